@@ -1,0 +1,147 @@
+/*
+ * drinpaint -- C ABI of the MI355X (gfx950) inpainting library.
+ *
+ * The library runs the forward pass of a windowed-attention transformer inpainting network
+ * on one GPU: it fills the private (masked) regions of each video frame with generated
+ * background and leaves every other pixel untouched.  The operation follows the thesis's
+ * problem statement for its inpainting stage (Methods, "Inpainting Manager"): the network
+ * receives a frame whose masked regions are set to 0 and returns the completed frame; the
+ * masked regions are the private objects cut out of the frame (Methods, "Object Control").
+ *
+ * Network (per clip of T frames, patch p, dim C, h heads, L blocks, MLP ratio r):
+ *   1. cut-out xc = frame with masked pixels set to 0; token flag = OR of the mask over the
+ *      token's p x p pixels;
+ *   2. patch embedding: Conv2d(3 -> C, kernel p, stride p);
+ *   3. L pre-LN blocks: multi-head self-attention inside non-overlapping windows of
+ *      win_t x win_h x win_w tokens (scaled dot product, as in the thesis's
+ *      "Performance Optimisations -- Inpainting Model"), then an exact-erf GELU MLP; only
+ *      flagged tokens are queries and are updated, keys/values are all window tokens;
+ *   4. final LayerNorm, ConvTranspose2d(C -> 3, kernel p, stride p), sigmoid;
+ *   5. composite: out = prediction where the mask is nonzero, else the input pixel, bit for
+ *      bit.
+ *
+ * Conventions shared by every call
+ *   - Every call returns a dr_status; nothing aborts or throws across the ABI.  After a
+ *     non-DR_OK status, dr_last_error(ctx) holds a message (per context, valid until the
+ *     next call on that context).
+ *   - Device pointers are plain HIP device addresses on the context's device, owned by the
+ *     caller.  Host pointers are marked "host".
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Work is
+ *     enqueued asynchronously on it; the caller synchronises.  Kernel faults surface as
+ *     DR_EHIP at a later call or at the caller's synchronisation.
+ *   - A context is not thread-safe: calls that overlap on one context race.
+ */
+#ifndef DRINPAINT_H
+#define DRINPAINT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DR_OK = 0,
+  DR_EINVAL = 1, /* bad argument: null pointer, bad enum, partial aliasing, no weights   */
+  DR_ESHAPE = 2, /* shape does not tile into whole windows / unsupported network shape   */
+  DR_ENOMEM = 3, /* device allocation failed or a footprint budget would be exceeded      */
+  DR_EHIP = 4,   /* a HIP runtime call or kernel launch failed                             */
+  DR_EBUSY = 5   /* resource in use (e.g. stream id still has work in flight)              */
+} dr_status;
+
+/* Arithmetic of the attention/MLP GEMMs.  DR_FP32: plain FP32 kernels, one per operation.
+ * DR_BF16: BF16 operands on MFMA with FP32 accumulation.  LayerNorm statistics, softmax
+ * max/sum, the residual stream, patch embedding and decoder stay FP32 in every mode. */
+typedef enum { DR_FP32 = 0, DR_BF16 = 1, DR_FP8 = 2 } dr_precision;
+
+/* Which tokens are attention queries and get updated.  DR_QUERY_MASKED: tokens whose patch
+ * holds a masked pixel.  DR_QUERY_ALL: every token (dense). */
+typedef enum { DR_QUERY_MASKED = 0, DR_QUERY_ALL = 1 } dr_query_set;
+
+typedef struct {
+  int32_t dim;       /* C, multiple of 64, <= 1024                                        */
+  int32_t heads;     /* h, dim / heads in {32, 64}                                        */
+  int32_t blocks;    /* L >= 1                                                            */
+  int32_t mlp_ratio; /* r >= 1                                                            */
+  int32_t patch;     /* p; only 4 is supported                                            */
+  int32_t win_h;     /* window height in tokens                                           */
+  int32_t win_w;     /* window width in tokens                                            */
+  int32_t win_t;     /* window length in frames; clips must have T == win_t               */
+} dr_netcfg;
+
+typedef struct dr_ctx dr_ctx;
+
+/* Create a context on HIP device `device` for network `cfg` (host pointer, copied).
+ * Checks the network shape (DR_ESHAPE if unsupported).  The context owns every buffer it
+ * allocates; release it with dr_destroy. */
+dr_status dr_create(dr_ctx** out, int device, const dr_netcfg* cfg);
+
+/* Load FP32 master weights from a host blob of `nbytes` bytes (not retained).  Blob layout
+ * (little endian): char magic[4] = "DRW1"; uint32 version = 1; dr_netcfg cfg; uint32 count;
+ * then `count` records {char name[48]; uint32 dtype (0 = f32); uint32 ndim; uint32 shape[4];
+ * uint64 offset; uint64 nbytes;}; data offsets are relative to the end of the table.  The
+ * tensors must be exactly the network's parameters, in order: embed.w [C,3,p,p] (OIHW),
+ * embed.b [C]; per block l: blk{l}.ln1.g, .ln1.b, .wq, .bq, .wk, .bk, .wv, .bv, .wo, .bo,
+ * .ln2.g, .ln2.b, .w1 [rC,C], .b1, .w2 [C,rC], .b2 (linear weights [out,in]); lnf.g, lnf.b,
+ * dec.w [C,3,p,p] (IOHW), dec.b [3].  Derived BF16 copies are built on the device.
+ * DR_EINVAL on a malformed blob or a config mismatch. */
+dr_status dr_load_weights(dr_ctx* ctx, const void* blob, size_t nbytes);
+
+/* Pre-allocate the workspace for clips of B x T x H x W so later dr_inpaint calls of that
+ * size (or smaller) allocate nothing.  dr_inpaint grows the workspace itself if needed. */
+dr_status dr_reserve(dr_ctx* ctx, int B, int T, int H, int W, dr_precision prec);
+
+/* Inpaint B clips of T frames.
+ *   frames: device f32 [B,T,H,W,3] (NHWC, values nominally in [0,1]).
+ *   masks:  device u8  [B,T,H,W], nonzero = private pixel to be filled.
+ *   out:    device f32 [B,T,H,W,3].  out == frames (in place) is allowed; any other overlap
+ *           of out with frames or masks is DR_EINVAL.
+ * Pixels whose mask is 0 are copied from `frames` bit for bit.  DR_ESHAPE unless
+ * T == win_t, H % (p*win_h) == 0 and W % (p*win_w) == 0.  DR_EINVAL without weights. */
+dr_status dr_inpaint(dr_ctx* ctx, const float* frames, const uint8_t* masks, float* out,
+                     int B, int T, int H, int W, dr_precision prec, dr_query_set qs,
+                     void* stream);
+
+/* Token gather of step 1 alone, for inspection and tests.  Token order is window-major:
+ * windows in (clip, frame-block, window-row, window-col) order, tokens inside a window in
+ * (frame, row, col) order.  Outputs (device): flag u8 [N] (N = B*T*H*W/p^2), idx int32 [N]
+ * whose first Nq entries list the flagged tokens in ascending order, woff int32 [nwin+1]
+ * (window w's queries are idx[woff[w] .. woff[w+1])), nq int32 [1] = Nq. */
+dr_status dr_gather_tokens(dr_ctx* ctx, const uint8_t* masks, int B, int T, int H, int W,
+                           dr_query_set qs, uint8_t* flag, int32_t* idx, int32_t* woff,
+                           int32_t* nq, void* stream);
+
+/* Per-kernel timing.  dr_profile(ctx, 1) makes every later launch record a HIP event pair
+ * on its stream; dr_profile_read synchronises on those events, writes the summed time in
+ * milliseconds and the launch count per stage into ms[] / count[] (host arrays of
+ * `nstage` entries, stage ids as listed by dr_stage_name), and clears the record.
+ * dr_profile(ctx, 0) stops recording. */
+dr_status dr_profile(dr_ctx* ctx, int enable);
+dr_status dr_profile_read(dr_ctx* ctx, double* ms, int64_t* count, int nstage);
+/* Name of stage id `stage` (static string), or NULL past the last stage. */
+const char* dr_stage_name(int stage);
+
+/* Inspection, for tests: copy the first `nbytes` of the named workspace buffer into device
+ * memory `dst` on `stream`.  Names: "x" (f32 residual [N,C], window-major), "u16", "q16",
+ * "o16" (bf16 [N,C]), "k16" (bf16 [win][head][Spad][dh]), "v16t" (bf16 [win][head][dh][Spad]),
+ * "h16" (bf16 [N,rC]), "u", "q", "o" (f32 [N,C]), "kv" (f32 [N,2C]), "h" (f32 [N,rC]),
+ * "flag" (u8 [N]), "idx" (int32 [N]), "nq" (int32).  DR_EINVAL for an unknown name or a
+ * size beyond the buffer. */
+dr_status dr_inspect(dr_ctx* ctx, const char* name, void* dst, size_t nbytes, void* stream);
+
+/* Inspection, for tests: key "blocks" = number of transformer blocks later dr_inpaint calls
+ * run (-1 = all); the output then is not the network's. */
+dr_status dr_debug_set(dr_ctx* ctx, const char* key, int64_t value);
+
+/* Message of the last failed call on `ctx` ("" if none).  ctx may be NULL (then the
+ * message of the last failed dr_create). */
+const char* dr_last_error(dr_ctx* ctx);
+
+/* Free everything the context owns.  Waits for the context's device to finish its work. */
+void dr_destroy(dr_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DRINPAINT_H */

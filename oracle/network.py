@@ -182,8 +182,9 @@ def composite(frames, masks, pred):
     return np.where(masks[..., None] != 0, pred, frames.astype(F64))
 
 
-def forward_detail(frames, masks, W, cfg, query_set="masked"):
-    """Run the whole clip-mode forward; returns a dict of the intermediate results."""
+def forward_detail(frames, masks, W, cfg, query_set="masked", keep_blocks=False):
+    """Run the whole clip-mode forward; returns a dict of the intermediate results (with the
+    per-block tensors under "blocks" when ``keep_blocks``)."""
     check_shape(frames, masks, cfg)
     p = cfg.patch
     xc = cut_out(frames, masks)
@@ -191,7 +192,7 @@ def forward_detail(frames, masks, W, cfg, query_set="masked"):
     upd = flags if query_set == "masked" else np.ones_like(flags)
     x0 = patch_embed(xc, W["embed.w"], W["embed.b"], p)
     x = x0
-    trace = []
+    trace = [] if keep_blocks else None
     for l in range(cfg.blocks):
         x = block(x, upd, W, l, cfg, trace)
     z = layer_norm(x, _w(W, "lnf.g"), _w(W, "lnf.b"))

@@ -1,0 +1,577 @@
+// Host side of the C ABI: context, weight blob loading, workspace, and the launch sequence
+// of the inpainting forward (see include/drinpaint.h for the contract of every call).
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dr_internal.h"
+
+namespace dr {
+bool attn_bf16_supported(int dh, int spad);
+}
+
+using namespace dr;
+
+static std::string g_create_err;
+
+static dr_status fail(dr_ctx* c, dr_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c)
+    c->err = buf;
+  else
+    g_create_err = buf;
+  return st;
+}
+
+#define HIP_OK(ctx, expr)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(ctx, DR_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+  } while (0)
+
+static const char* kStageNames[ST_COUNT] = {"tokens", "embed", "ln1",  "qkv",    "attn", "proj",
+                                            "ln2",    "fc1",   "fc2",  "mlp",    "decode", "copy"};
+
+// ------------------------------------------------------------------------------------------
+// small host helpers
+// ------------------------------------------------------------------------------------------
+static uint16_t host_f2bf(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+static bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+static hipError_t dmalloc(dr_ctx* c, void** p, size_t n, std::vector<void*>& list) {
+  *p = nullptr;
+  if (n == 0) n = 256;
+  hipError_t e = hipMalloc(p, n);
+  if (e == hipSuccess) list.push_back(*p);
+  return e;
+}
+
+// profiling brackets
+static void prof_begin(dr_ctx* c, int stage, hipStream_t s, hipEvent_t* a, hipEvent_t* b) {
+  *a = *b = nullptr;
+  if (!c->prof) return;
+  for (hipEvent_t* e : {a, b}) {
+    if (!c->event_pool.empty()) {
+      *e = c->event_pool.back();
+      c->event_pool.pop_back();
+    } else {
+      hipEventCreate(e);
+    }
+  }
+  hipEventRecord(*a, s);
+  (void)stage;
+}
+
+static void prof_end(dr_ctx* c, int stage, hipStream_t s, hipEvent_t a, hipEvent_t b) {
+  if (!c->prof || !a) return;
+  hipEventRecord(b, s);
+  c->recs.push_back({stage, a, b});
+}
+
+// ------------------------------------------------------------------------------------------
+// create / destroy
+// ------------------------------------------------------------------------------------------
+extern "C" dr_status dr_create(dr_ctx** out, int device, const dr_netcfg* cfg) {
+  if (!out || !cfg) return fail(nullptr, DR_EINVAL, "dr_create: null argument");
+  *out = nullptr;
+  const dr_netcfg& k = *cfg;
+  if (k.dim <= 0 || k.dim % 64 || k.dim > 1024)
+    return fail(nullptr, DR_ESHAPE, "dim must be a positive multiple of 64, at most 1024");
+  if (k.heads <= 0 || k.dim % k.heads) return fail(nullptr, DR_ESHAPE, "dim %% heads != 0");
+  const int dh = k.dim / k.heads;
+  if (dh != 32 && dh != 64) return fail(nullptr, DR_ESHAPE, "head dim must be 32 or 64");
+  if (k.blocks <= 0 || k.mlp_ratio <= 0) return fail(nullptr, DR_ESHAPE, "blocks and mlp_ratio must be >= 1");
+  if (k.patch != 4) return fail(nullptr, DR_ESHAPE, "only patch 4 is supported");
+  if (k.win_h <= 0 || k.win_w <= 0 || k.win_t <= 0) return fail(nullptr, DR_ESHAPE, "window extents must be >= 1");
+  const int S = k.win_h * k.win_w * k.win_t;
+  if (S > 320) return fail(nullptr, DR_ESHAPE, "window of %d tokens exceeds 320", S);
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return fail(nullptr, DR_EINVAL, "no HIP device %d", device);
+  dr_ctx* c = new dr_ctx();
+  c->device = device;
+  Net& n = c->net;
+  n.cfg = k;
+  n.C = k.dim;
+  n.R = k.dim * k.mlp_ratio;
+  n.dh = dh;
+  n.S = S;
+  n.Spad = (S + 15) / 16 * 16;
+  n.P = k.patch;
+  *out = c;
+  return DR_OK;
+}
+
+static void free_work(dr_ctx* c) {
+  for (void* p : c->work.allocs) hipFree(p);
+  c->work = Work();
+}
+
+extern "C" void dr_destroy(dr_ctx* c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  hipDeviceSynchronize();
+  free_work(c);
+  for (void* p : c->weight_allocs) hipFree(p);
+  for (auto& r : c->recs) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  for (auto e : c->event_pool) hipEventDestroy(e);
+  delete c;
+}
+
+extern "C" const char* dr_last_error(dr_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+extern "C" const char* dr_stage_name(int stage) {
+  return (stage >= 0 && stage < ST_COUNT) ? kStageNames[stage] : nullptr;
+}
+
+// ------------------------------------------------------------------------------------------
+// weights
+// ------------------------------------------------------------------------------------------
+struct BlobRec {
+  char name[48];
+  uint32_t dtype, ndim, shape[4];
+  uint64_t offset, nbytes;
+};
+
+extern "C" dr_status dr_load_weights(dr_ctx* c, const void* blob, size_t nbytes) {
+  if (!c || !blob) return fail(c, DR_EINVAL, "dr_load_weights: null argument");
+  const char* b = (const char*)blob;
+  const size_t head = 4 + 4 + sizeof(dr_netcfg) + 4;
+  if (nbytes < head || std::memcmp(b, "DRW1", 4) != 0) return fail(c, DR_EINVAL, "weight blob: bad magic");
+  uint32_t version, count;
+  dr_netcfg bc;
+  std::memcpy(&version, b + 4, 4);
+  std::memcpy(&bc, b + 8, sizeof bc);
+  std::memcpy(&count, b + 8 + sizeof bc, 4);
+  if (version != 1) return fail(c, DR_EINVAL, "weight blob: unsupported version %u", version);
+  if (std::memcmp(&bc, &c->net.cfg, sizeof bc) != 0)
+    return fail(c, DR_EINVAL, "weight blob: network config differs from the context's");
+  const Net& n = c->net;
+  const int C = n.C, R = n.R, L = n.cfg.blocks, P = n.P;
+  // expected tensors in order
+  struct Want { std::string name; std::vector<uint32_t> shape; };
+  std::vector<Want> want;
+  want.push_back({"embed.w", {(uint32_t)C, 3, (uint32_t)P, (uint32_t)P}});
+  want.push_back({"embed.b", {(uint32_t)C}});
+  for (int l = 0; l < L; ++l) {
+    const std::string p = "blk" + std::to_string(l) + ".";
+    const uint32_t c32 = C, r32 = R;
+    want.push_back({p + "ln1.g", {c32}});
+    want.push_back({p + "ln1.b", {c32}});
+    want.push_back({p + "wq", {c32, c32}});
+    want.push_back({p + "bq", {c32}});
+    want.push_back({p + "wk", {c32, c32}});
+    want.push_back({p + "bk", {c32}});
+    want.push_back({p + "wv", {c32, c32}});
+    want.push_back({p + "bv", {c32}});
+    want.push_back({p + "wo", {c32, c32}});
+    want.push_back({p + "bo", {c32}});
+    want.push_back({p + "ln2.g", {c32}});
+    want.push_back({p + "ln2.b", {c32}});
+    want.push_back({p + "w1", {r32, c32}});
+    want.push_back({p + "b1", {r32}});
+    want.push_back({p + "w2", {c32, r32}});
+    want.push_back({p + "b2", {c32}});
+  }
+  want.push_back({"lnf.g", {(uint32_t)C}});
+  want.push_back({"lnf.b", {(uint32_t)C}});
+  want.push_back({"dec.w", {(uint32_t)C, 3, (uint32_t)P, (uint32_t)P}});
+  want.push_back({"dec.b", {3}});
+  if (count != want.size())
+    return fail(c, DR_EINVAL, "weight blob: %u tensors, expected %zu", count, want.size());
+  const size_t table = head + (size_t)count * sizeof(BlobRec);
+  if (nbytes < table) return fail(c, DR_EINVAL, "weight blob: truncated table");
+  std::vector<const float*> src(count);
+  for (uint32_t i = 0; i < count; ++i) {
+    BlobRec r;
+    std::memcpy(&r, b + head + (size_t)i * sizeof(BlobRec), sizeof r);
+    r.name[47] = 0;
+    if (want[i].name != r.name) return fail(c, DR_EINVAL, "weight blob: tensor %u is '%s', expected '%s'", i, r.name, want[i].name.c_str());
+    if (r.dtype != 0) return fail(c, DR_EINVAL, "weight blob: '%s' is not f32", r.name);
+    if (r.ndim != want[i].shape.size()) return fail(c, DR_EINVAL, "weight blob: '%s' has wrong rank", r.name);
+    size_t elems = 1;
+    for (uint32_t d = 0; d < r.ndim; ++d) {
+      if (r.shape[d] != want[i].shape[d]) return fail(c, DR_EINVAL, "weight blob: '%s' has wrong shape", r.name);
+      elems *= r.shape[d];
+    }
+    if (r.nbytes != elems * 4 || table + r.offset + r.nbytes > nbytes || r.offset % 4)
+      return fail(c, DR_EINVAL, "weight blob: '%s' has a bad extent", r.name);
+    src[i] = reinterpret_cast<const float*>(b + table + r.offset);
+  }
+
+  // Host-side layout: f32 arena and bf16 arena, then one copy each.
+  std::vector<float> f;
+  std::vector<uint16_t> h16;
+  auto put = [&](const float* p, size_t nel) {
+    size_t off = f.size();
+    f.insert(f.end(), p, p + nel);
+    while (f.size() % 64) f.push_back(0.f);  // 256-byte alignment
+    return off;
+  };
+  auto put16 = [&](const std::vector<const float*>& parts, const std::vector<size_t>& nels) {
+    size_t off = h16.size();
+    for (size_t k = 0; k < parts.size(); ++k)
+      for (size_t e = 0; e < nels[k]; ++e) h16.push_back(host_f2bf(parts[k][e]));
+    while (h16.size() % 128) h16.push_back(0);
+    return off;
+  };
+  const size_t CC = (size_t)C * C, RC = (size_t)R * C;
+  // embed weight transposed to [48][C], row (ky*4+kx)*3+c
+  std::vector<float> ewT((size_t)48 * C), dw((size_t)C * 48);
+  const float* ew = src[0];
+  for (int o = 0; o < C; ++o)
+    for (int ch = 0; ch < 3; ++ch)
+      for (int ky = 0; ky < P; ++ky)
+        for (int kx = 0; kx < P; ++kx)
+          ewT[(size_t)((ky * P + kx) * 3 + ch) * C + o] = ew[((o * 3 + ch) * P + ky) * P + kx];
+  const float* dws = src[count - 2];
+  for (int ci = 0; ci < C; ++ci)
+    for (int ch = 0; ch < 3; ++ch)
+      for (int ky = 0; ky < P; ++ky)
+        for (int kx = 0; kx < P; ++kx)
+          dw[(size_t)ci * 48 + (ky * P + kx) * 3 + ch] = dws[((ci * 3 + ch) * P + ky) * P + kx];
+  struct Off { size_t v[32]; };
+  const size_t o_ewT = put(ewT.data(), ewT.size());
+  const size_t o_eb = put(src[1], C);
+  std::vector<Off> bo(L), b16(L);
+  for (int l = 0; l < L; ++l) {
+    const float* const* s = &src[2 + 16 * l];
+    Off& O = bo[l];
+    O.v[0] = put(s[0], C);   // ln1.g
+    O.v[1] = put(s[1], C);   // ln1.b
+    O.v[2] = put(s[2], CC);  // wq
+    O.v[3] = put(s[3], C);   // bq
+    O.v[4] = put(s[4], CC);  // wk
+    O.v[5] = put(s[5], C);   // bk
+    O.v[6] = put(s[6], CC);  // wv
+    O.v[7] = put(s[7], C);   // bv
+    O.v[8] = put(s[8], CC);  // wo
+    O.v[9] = put(s[9], C);   // bo
+    O.v[10] = put(s[10], C); // ln2.g
+    O.v[11] = put(s[11], C); // ln2.b
+    O.v[12] = put(s[12], RC);// w1
+    O.v[13] = put(s[13], R); // b1
+    O.v[14] = put(s[14], RC);// w2
+    O.v[15] = put(s[15], C); // b2
+    // [Wk; Wv] and [bq; bk; bv]
+    O.v[16] = f.size();
+    f.insert(f.end(), s[4], s[4] + CC);
+    f.insert(f.end(), s[6], s[6] + CC);
+    while (f.size() % 64) f.push_back(0.f);
+    O.v[17] = f.size();
+    f.insert(f.end(), s[5], s[5] + C);
+    f.insert(f.end(), s[7], s[7] + C);
+    while (f.size() % 64) f.push_back(0.f);
+    O.v[18] = f.size();
+    f.insert(f.end(), s[3], s[3] + C);
+    f.insert(f.end(), s[5], s[5] + C);
+    f.insert(f.end(), s[7], s[7] + C);
+    while (f.size() % 64) f.push_back(0.f);
+    Off& H = b16[l];
+    H.v[0] = put16({s[2], s[4], s[6]}, {CC, CC, CC});
+    H.v[1] = put16({s[8]}, {CC});
+    H.v[2] = put16({s[12]}, {RC});
+    H.v[3] = put16({s[14]}, {RC});
+  }
+  const size_t o_lnfg = put(src[count - 4], C);
+  const size_t o_lnfb = put(src[count - 3], C);
+  const size_t o_dw = put(dw.data(), dw.size());
+  const size_t o_db = put(src[count - 1], 3);
+
+  HIP_OK(c, hipSetDevice(c->device));
+  for (void* p : c->weight_allocs) hipFree(p);
+  c->weight_allocs.clear();
+  c->have_weights = false;
+  void *df = nullptr, *dh16 = nullptr;
+  if (dmalloc(c, &df, f.size() * 4, c->weight_allocs) != hipSuccess ||
+      dmalloc(c, &dh16, h16.size() * 2, c->weight_allocs) != hipSuccess)
+    return fail(c, DR_ENOMEM, "weights: device allocation failed");
+  HIP_OK(c, hipMemcpy(df, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+  HIP_OK(c, hipMemcpy(dh16, h16.data(), h16.size() * 2, hipMemcpyHostToDevice));
+  const float* F = (const float*)df;
+  const bf16* B16 = (const bf16*)dh16;
+  Net& nn = c->net;
+  nn.embed_wT = F + o_ewT;
+  nn.embed_b = F + o_eb;
+  nn.blk.assign(L, BlockW());
+  for (int l = 0; l < L; ++l) {
+    BlockW& w = nn.blk[l];
+    const Off& O = bo[l];
+    w.ln1g = F + O.v[0]; w.ln1b = F + O.v[1];
+    w.wq = F + O.v[2]; w.bq = F + O.v[3];
+    w.wk = F + O.v[4]; w.bk = F + O.v[5];
+    w.wv = F + O.v[6]; w.bv = F + O.v[7];
+    w.wo = F + O.v[8]; w.bo = F + O.v[9];
+    w.ln2g = F + O.v[10]; w.ln2b = F + O.v[11];
+    w.w1 = F + O.v[12]; w.b1 = F + O.v[13];
+    w.w2 = F + O.v[14]; w.b2 = F + O.v[15];
+    w.wkv = F + O.v[16]; w.bkv = F + O.v[17]; w.bqkv = F + O.v[18];
+    w.wqkv16 = B16 + b16[l].v[0];
+    w.wo16 = B16 + b16[l].v[1];
+    w.w116 = B16 + b16[l].v[2];
+    w.w216 = B16 + b16[l].v[3];
+  }
+  nn.lnfg = F + o_lnfg;
+  nn.lnfb = F + o_lnfb;
+  nn.dec_w = F + o_dw;
+  nn.dec_b = F + o_db;
+  c->have_weights = true;
+  return DR_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// shapes and workspace
+// ------------------------------------------------------------------------------------------
+static dr_status make_geo(dr_ctx* c, int B, int T, int H, int W, Geo& g) {
+  const dr_netcfg& k = c->net.cfg;
+  if (B <= 0 || T <= 0 || H <= 0 || W <= 0) return fail(c, DR_ESHAPE, "empty or negative shape");
+  if (T != k.win_t) return fail(c, DR_ESHAPE, "T=%d must equal the window length %d", T, k.win_t);
+  if (H % (k.patch * k.win_h) || W % (k.patch * k.win_w))
+    return fail(c, DR_ESHAPE, "H=%d, W=%d must be multiples of %d and %d", H, W, k.patch * k.win_h,
+                k.patch * k.win_w);
+  g.B = B; g.T = T; g.H = H; g.W = W; g.P = k.patch;
+  g.Ht = H / k.patch; g.Wt = W / k.patch;
+  g.wt = k.win_t; g.wh = k.win_h; g.ww = k.win_w;
+  g.nwh = g.Ht / k.win_h; g.nww = g.Wt / k.win_w;
+  g.S = c->net.S;
+  const long long N = (long long)B * T * g.Ht * g.Wt;
+  if (N > (1LL << 30)) return fail(c, DR_ESHAPE, "too many tokens");
+  g.N = (int)N;
+  g.nwin = g.N / g.S;
+  return DR_OK;
+}
+
+static dr_status reserve_geo(dr_ctx* c, const Geo& g) {
+  Work& w = c->work;
+  if ((size_t)g.N <= w.cap_tokens && (size_t)g.nwin <= w.cap_windows) return DR_OK;
+  HIP_OK(c, hipSetDevice(c->device));
+  HIP_OK(c, hipDeviceSynchronize());
+  free_work(c);
+  const Net& n = c->net;
+  const size_t N = g.N, C = n.C, R = n.R, nw = g.nwin;
+  const size_t kvlen = nw * n.cfg.heads * (size_t)n.Spad * n.dh;
+  void* p;
+#define ALLOC(field, bytes)                                                        \
+  do {                                                                             \
+    if (dmalloc(c, &p, (bytes), w.allocs) != hipSuccess) {                          \
+      free_work(c);                                                                \
+      return fail(c, DR_ENOMEM, "workspace: cannot allocate %zu bytes", (size_t)(bytes)); \
+    }                                                                              \
+    w.field = (decltype(w.field))p;                                                \
+  } while (0)
+  ALLOC(flag, N);
+  ALLOC(wcount, nw * 4);
+  ALLOC(woff, (nw + 1) * 4);
+  ALLOC(idx, N * 4);
+  ALLOC(nq, 256);
+  ALLOC(x, N * C * 4);
+  ALLOC(u, N * C * 4);
+  ALLOC(kv, N * 2 * C * 4);
+  ALLOC(q, N * C * 4);
+  ALLOC(o, N * C * 4);
+  ALLOC(h, N * R * 4);
+  ALLOC(u16, N * C * 2);
+  ALLOC(q16, N * C * 2);
+  ALLOC(k16, kvlen * 2);
+  ALLOC(v16t, kvlen * 2);
+  ALLOC(o16, N * C * 2);
+  ALLOC(h16, N * R * 2);
+#undef ALLOC
+  // padded key rows / columns of K and V^T must read as zero
+  HIP_OK(c, hipMemset(w.k16, 0, kvlen * 2));
+  HIP_OK(c, hipMemset(w.v16t, 0, kvlen * 2));
+  HIP_OK(c, hipDeviceSynchronize());
+  w.cap_tokens = N;
+  w.cap_windows = nw;
+  return DR_OK;
+}
+
+extern "C" dr_status dr_reserve(dr_ctx* c, int B, int T, int H, int W, dr_precision prec) {
+  if (!c) return DR_EINVAL;
+  if (prec != DR_FP32 && prec != DR_BF16) return fail(c, DR_EINVAL, "unsupported precision %d", (int)prec);
+  Geo g;
+  dr_status st = make_geo(c, B, T, H, W, g);
+  if (st != DR_OK) return st;
+  return reserve_geo(c, g);
+}
+
+// ------------------------------------------------------------------------------------------
+// forward
+// ------------------------------------------------------------------------------------------
+#define LAUNCH(stage, call)                                                     \
+  do {                                                                          \
+    hipEvent_t ea_, eb_;                                                        \
+    prof_begin(c, stage, s, &ea_, &eb_);                                        \
+    call;                                                                       \
+    hipError_t e_ = hipGetLastError();                                          \
+    if (e_ != hipSuccess)                                                       \
+      return fail(c, DR_EHIP, "launch of %s failed: %s", kStageNames[stage], hipGetErrorString(e_)); \
+    prof_end(c, stage, s, ea_, eb_);                                            \
+  } while (0)
+
+static dr_status run_tokens(dr_ctx* c, const Geo& g, const uint8_t* masks, int all, hipStream_t s) {
+  Work& w = c->work;
+  LAUNCH(ST_TOKENS, launch_token_flags(g, masks, all, w.flag, w.wcount, s));
+  LAUNCH(ST_TOKENS, launch_token_gather(g, w.flag, w.wcount, w.idx, w.woff, w.nq, s));
+  return DR_OK;
+}
+
+extern "C" dr_status dr_gather_tokens(dr_ctx* c, const uint8_t* masks, int B, int T, int H, int W,
+                                      dr_query_set qs, uint8_t* flag, int32_t* idx, int32_t* woff,
+                                      int32_t* nq, void* stream) {
+  if (!c || !masks || !flag || !idx || !woff || !nq) return fail(c, DR_EINVAL, "dr_gather_tokens: null argument");
+  if (qs != DR_QUERY_MASKED && qs != DR_QUERY_ALL) return fail(c, DR_EINVAL, "bad query set");
+  Geo g;
+  dr_status st = make_geo(c, B, T, H, W, g);
+  if (st != DR_OK) return st;
+  HIP_OK(c, hipSetDevice(c->device));
+  // wcount scratch comes from the workspace
+  st = reserve_geo(c, g);
+  if (st != DR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  LAUNCH(ST_TOKENS, launch_token_flags(g, masks, qs == DR_QUERY_ALL, flag, c->work.wcount, s));
+  LAUNCH(ST_TOKENS, launch_token_gather(g, flag, c->work.wcount, idx, woff, nq, s));
+  return DR_OK;
+}
+
+extern "C" dr_status dr_inpaint(dr_ctx* c, const float* frames, const uint8_t* masks, float* out,
+                                int B, int T, int H, int W, dr_precision prec, dr_query_set qs,
+                                void* stream) {
+  if (!c) return DR_EINVAL;
+  if (!frames || !masks || !out) return fail(c, DR_EINVAL, "dr_inpaint: null pointer");
+  if (!c->have_weights) return fail(c, DR_EINVAL, "dr_inpaint: no weights loaded");
+  if (prec != DR_FP32 && prec != DR_BF16) return fail(c, DR_EINVAL, "unsupported precision %d", (int)prec);
+  if (qs != DR_QUERY_MASKED && qs != DR_QUERY_ALL) return fail(c, DR_EINVAL, "bad query set");
+  Geo g;
+  dr_status st = make_geo(c, B, T, H, W, g);
+  if (st != DR_OK) return st;
+  const Net& n = c->net;
+  if (prec == DR_BF16 && !attn_bf16_supported(n.dh, n.Spad))
+    return fail(c, DR_ESHAPE, "BF16 attention has no kernel for %d-token windows", n.S);
+  const size_t npix = (size_t)B * T * H * W;
+  if (out != frames && ranges_overlap(out, npix * 12, frames, npix * 12))
+    return fail(c, DR_EINVAL, "out partially overlaps frames");
+  if (ranges_overlap(out, npix * 12, masks, npix)) return fail(c, DR_EINVAL, "out overlaps masks");
+  HIP_OK(c, hipSetDevice(c->device));
+  st = reserve_geo(c, g);
+  if (st != DR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Work& w = c->work;
+  const int C = n.C, R = n.R, N = g.N;
+  st = run_tokens(c, g, masks, qs == DR_QUERY_ALL, s);
+  if (st != DR_OK) return st;
+  LAUNCH(ST_EMBED, launch_embed(g, C, frames, masks, n.embed_wT, n.embed_b, w.x, s));
+  const int nblk = (c->debug_blocks >= 0 && c->debug_blocks < n.cfg.blocks) ? c->debug_blocks : n.cfg.blocks;
+  for (int l = 0; l < nblk; ++l) {
+    const BlockW& b = n.blk[l];
+    if (prec == DR_FP32) {
+      LAUNCH(ST_LN1, launch_ln_f32(w.x, nullptr, nullptr, N, C, b.ln1g, b.ln1b, w.u, s));
+      LAUNCH(ST_QKV, launch_gemm_f32(w.u, nullptr, nullptr, N, C, b.wkv, b.bkv, 2 * C, EPI_STORE, w.kv, nullptr, s));
+      LAUNCH(ST_QKV, launch_gemm_f32(w.u, w.idx, w.nq, N, C, b.wq, b.bq, C, EPI_STORE, w.q, nullptr, s));
+      LAUNCH(ST_ATTN, launch_attn_f32(g, C, n.cfg.heads, w.q, w.kv, w.woff, w.o, s));
+      LAUNCH(ST_PROJ, launch_gemm_f32(w.o, nullptr, w.nq, N, C, b.wo, b.bo, C, EPI_RESID, w.x, w.idx, s));
+      LAUNCH(ST_LN2, launch_ln_f32(w.x, w.idx, w.nq, N, C, b.ln2g, b.ln2b, w.u, s));
+      LAUNCH(ST_FC1, launch_gemm_f32(w.u, nullptr, w.nq, N, C, b.w1, b.b1, R, EPI_GELU, w.h, nullptr, s));
+      LAUNCH(ST_FC2, launch_gemm_f32(w.h, nullptr, w.nq, N, R, b.w2, b.b2, C, EPI_RESID, w.x, w.idx, s));
+    } else {
+      LAUNCH(ST_LN1, launch_ln_bf16(w.x, nullptr, nullptr, N, C, b.ln1g, b.ln1b, w.u16, s));
+      LAUNCH(ST_QKV, launch_qkv_bf16(g, C, n.cfg.heads, n.Spad, w.u16, w.flag, b.wqkv16, b.bqkv, w.q16, w.k16, w.v16t, s));
+      LAUNCH(ST_ATTN, launch_attn_bf16(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.v16t, w.idx, w.woff, w.o16, s));
+      LAUNCH(ST_PROJ, launch_gemm_bf16(w.o16, w.nq, N, C, b.wo16, b.bo, C, EPI_RESID, w.x, w.idx, s));
+      LAUNCH(ST_LN2, launch_ln_bf16(w.x, w.idx, w.nq, N, C, b.ln2g, b.ln2b, w.u16, s));
+      LAUNCH(ST_FC1, launch_gemm_bf16(w.u16, w.nq, N, C, b.w116, b.b1, R, EPI_GELU, w.h16, nullptr, s));
+      LAUNCH(ST_FC2, launch_gemm_bf16(w.h16, w.nq, N, R, b.w216, b.b2, C, EPI_RESID, w.x, w.idx, s));
+    }
+  }
+  LAUNCH(ST_DECODE, launch_decode(g, C, w.x, w.idx, w.nq, n.lnfg, n.lnfb, n.dec_w, n.dec_b, masks, out, s));
+  if (out != frames) LAUNCH(ST_COPY, launch_copy_unmasked(npix, frames, masks, out, s));
+  return DR_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// profiling
+// ------------------------------------------------------------------------------------------
+extern "C" dr_status dr_profile(dr_ctx* c, int enable) {
+  if (!c) return DR_EINVAL;
+  c->prof = enable != 0;
+  return DR_OK;
+}
+
+extern "C" dr_status dr_profile_read(dr_ctx* c, double* ms, int64_t* count, int nstage) {
+  if (!c || !ms || !count || nstage < 0) return fail(c, DR_EINVAL, "dr_profile_read: bad argument");
+  for (int i = 0; i < nstage; ++i) {
+    ms[i] = 0.0;
+    count[i] = 0;
+  }
+  HIP_OK(c, hipSetDevice(c->device));
+  dr_status st = DR_OK;
+  for (auto& r : c->recs) {
+    float t = 0.f;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+    if (e != hipSuccess && st == DR_OK) st = fail(c, DR_EHIP, "profile events: %s", hipGetErrorString(e));
+    if (r.stage < nstage) {
+      ms[r.stage] += t;
+      count[r.stage] += 1;
+    }
+    c->event_pool.push_back(r.a);
+    c->event_pool.push_back(r.b);
+  }
+  c->recs.clear();
+  return st;
+}
+
+// ------------------------------------------------------------------------------------------
+// inspection
+// ------------------------------------------------------------------------------------------
+extern "C" dr_status dr_inspect(dr_ctx* c, const char* name, void* dst, size_t nbytes, void* stream) {
+  if (!c || !name || !dst) return fail(c, DR_EINVAL, "dr_inspect: null argument");
+  const Work& w = c->work;
+  const size_t N = w.cap_tokens, C = c->net.C, R = c->net.R;
+  const size_t kvlen = w.cap_windows * c->net.cfg.heads * (size_t)c->net.Spad * c->net.dh;
+  struct Buf { const char* n; const void* p; size_t bytes; } bufs[] = {
+      {"x", w.x, N * C * 4},       {"u16", w.u16, N * C * 2}, {"q16", w.q16, N * C * 2},
+      {"k16", w.k16, kvlen * 2},   {"v16t", w.v16t, kvlen * 2}, {"o16", w.o16, N * C * 2},
+      {"h16", w.h16, N * R * 2},   {"u", w.u, N * C * 4},     {"kv", w.kv, N * 2 * C * 4},
+      {"q", w.q, N * C * 4},       {"o", w.o, N * C * 4},     {"h", w.h, N * R * 4},
+      {"flag", w.flag, N},         {"idx", w.idx, N * 4},     {"nq", w.nq, 4}};
+  for (const Buf& b : bufs) {
+    if (std::strcmp(b.n, name) == 0) {
+      if (!b.p) return fail(c, DR_EINVAL, "dr_inspect: no workspace yet");
+      if (nbytes > b.bytes) return fail(c, DR_EINVAL, "dr_inspect: %zu bytes requested, buffer has %zu", nbytes, b.bytes);
+      HIP_OK(c, hipMemcpyAsync(dst, b.p, nbytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+      return DR_OK;
+    }
+  }
+  return fail(c, DR_EINVAL, "dr_inspect: unknown buffer '%s'", name);
+}
+
+extern "C" dr_status dr_debug_set(dr_ctx* c, const char* key, int64_t value) {
+  if (!c || !key) return fail(c, DR_EINVAL, "dr_debug_set: null argument");
+  if (std::strcmp(key, "blocks") == 0) {
+    c->debug_blocks = (int)value;
+    return DR_OK;
+  }
+  return fail(c, DR_EINVAL, "dr_debug_set: unknown key '%s'", key);
+}

@@ -1,0 +1,160 @@
+// Internal declarations shared by the library's translation units (host side and device
+// helpers).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/drinpaint.h"
+
+namespace dr {
+
+typedef uint16_t bf16;  // raw bfloat16 bits
+
+// ------------------------------------------------------------------------------------------
+// Stages (profiling ids)
+// ------------------------------------------------------------------------------------------
+enum Stage {
+  ST_TOKENS = 0,  // token flags, per-window counts, gather lists
+  ST_EMBED,       // cut-out + patch embedding
+  ST_LN1,         // LayerNorm before attention
+  ST_QKV,         // Q/K/V projection
+  ST_ATTN,        // window attention
+  ST_PROJ,        // output projection + residual
+  ST_LN2,         // LayerNorm before the MLP
+  ST_FC1,         // first MLP linear + GELU
+  ST_FC2,         // second MLP linear + residual
+  ST_MLP,         // fused LN2 + MLP + residual
+  ST_DECODE,      // final LayerNorm + decoder + sigmoid + masked store
+  ST_COPY,        // unmasked pixels copied to the output
+  ST_COUNT
+};
+
+// ------------------------------------------------------------------------------------------
+// Device-side parameter views
+// ------------------------------------------------------------------------------------------
+struct BlockW {
+  const float *ln1g, *ln1b, *ln2g, *ln2b;
+  const float *wq, *wk, *wv, *wo, *w1, *w2;  // f32 [out, in]
+  const float *bq, *bk, *bv, *bo, *b1, *b2;
+  const float* wkv;                          // f32 [2C, C]  (Wk rows then Wv rows)
+  const float* bkv;                          // f32 [2C]
+  const float* bqkv;                         // f32 [3C]
+  const bf16* wqkv16;                        // bf16 [3C, C]
+  const bf16 *wo16, *w116, *w216;            // bf16 [out, in]
+};
+
+struct Net {
+  dr_netcfg cfg;
+  int C, R, dh, S, Spad, P;  // dim, hidden, head dim, window tokens, padded window, patch
+  const float* embed_wT;     // [48][C], row k = (ky*p + kx)*3 + c
+  const float* embed_b;      // [C]
+  std::vector<BlockW> blk;
+  const float *lnfg, *lnfb;
+  const float* dec_w;        // [C][48], column k = (ky*p + kx)*3 + ch
+  const float* dec_b;        // [3]
+};
+
+struct Work {
+  int B = 0, T = 0, H = 0, W = 0;
+  int N = 0, nwin = 0;
+  size_t cap_tokens = 0;  // capacity in tokens
+  size_t cap_windows = 0;
+  // token gather
+  uint8_t* flag = nullptr;
+  int32_t* wcount = nullptr;
+  int32_t* woff = nullptr;
+  int32_t* idx = nullptr;
+  int32_t* nq = nullptr;
+  // residual stream, FP32, window-major rows
+  float* x = nullptr;
+  // FP32 path scratch
+  float *u = nullptr, *kv = nullptr, *q = nullptr, *o = nullptr, *h = nullptr;
+  // BF16 path scratch
+  bf16 *u16 = nullptr, *q16 = nullptr, *k16 = nullptr, *v16t = nullptr, *o16 = nullptr,
+       *h16 = nullptr;
+  std::vector<void*> allocs;
+};
+
+}  // namespace dr
+
+struct dr_ctx {
+  int device = 0;
+  dr::Net net;
+  bool have_weights = false;
+  std::vector<void*> weight_allocs;
+  dr::Work work;
+  std::string err;
+  // profiling
+  bool prof = false;
+  int debug_blocks = -1;  // inspection: run only this many blocks (-1 = all)
+  struct Rec { int stage; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> event_pool;
+};
+
+namespace dr {
+
+// ------------------------------------------------------------------------------------------
+// Kernel launchers (one translation unit each; all enqueue on `s`, no synchronisation)
+// ------------------------------------------------------------------------------------------
+struct Geo {
+  int B, T, H, W;      // pixel shape
+  int Ht, Wt;          // token grid per frame
+  int nwh, nww;        // windows per frame (rows, cols)
+  int wt, wh, ww;      // window extent in tokens
+  int S, N, nwin;      // tokens per window, total tokens, total windows
+  int P;               // patch
+};
+
+// step 1 -- token flags and gather lists
+void launch_token_flags(const Geo& g, const uint8_t* masks, int all, uint8_t* flag,
+                        int32_t* wcount, hipStream_t s);
+void launch_token_gather(const Geo& g, const uint8_t* flag, const int32_t* wcount,
+                         int32_t* idx, int32_t* woff, int32_t* nq, hipStream_t s);
+// step 2 -- cut-out + patch embedding, x [N, C] f32 window-major
+void launch_embed(const Geo& g, int C, const float* frames, const uint8_t* masks,
+                  const float* wT, const float* b, float* x, hipStream_t s);
+// final step -- LN_f + decoder + sigmoid, masked pixels of flagged tokens written to out
+void launch_decode(const Geo& g, int C, const float* x, const int32_t* idx, const int32_t* nq,
+                   const float* lng, const float* lnb, const float* dw, const float* db,
+                   const uint8_t* masks, float* out, hipStream_t s);
+// unmasked pixels copied from frames to out (skipped when in place)
+void launch_copy_unmasked(size_t npix, const float* frames, const uint8_t* masks, float* out,
+                          hipStream_t s);
+
+// FP32 path
+void launch_ln_f32(const float* x, const int32_t* rows, const int32_t* nrows_dev, int nrows_max,
+                   int C, const float* g, const float* b, float* y, hipStream_t s);
+enum EpiKind { EPI_STORE = 0, EPI_GELU = 1, EPI_RESID = 2 };
+// Y = A[rows] W^T + bias, A f32 [*, K] (row stride K), W f32 [Nout, K].
+//   EPI_STORE: Y[r, :] stored to out (row stride Nout)
+//   EPI_GELU : GELU(Y) stored to out
+//   EPI_RESID: x[res_rows[r], :] += Y[r, :]  (out = x, row stride Nout)
+void launch_gemm_f32(const float* A, const int32_t* arows, const int32_t* m_dev, int m_max,
+                     int K, const float* W, const float* bias, int Nout, int epi, float* out,
+                     const int32_t* res_rows, hipStream_t s);
+void launch_attn_f32(const Geo& g, int C, int heads, const float* q, const float* kv,
+                     const int32_t* woff, float* o, hipStream_t s);
+
+// BF16 path
+void launch_ln_bf16(const float* x, const int32_t* rows, const int32_t* nrows_dev,
+                    int nrows_max, int C, const float* g, const float* b, bf16* y,
+                    hipStream_t s);
+void launch_qkv_bf16(const Geo& g, int C, int heads, int Spad, const bf16* u,
+                     const uint8_t* flag, const bf16* w, const float* bias, bf16* q, bf16* k,
+                     bf16* vt, hipStream_t s);
+void launch_gemm_bf16(const bf16* A, const int32_t* m_dev, int m_max, int K, const bf16* W,
+                      const float* bias, int Nout, int epi, void* out,
+                      const int32_t* res_rows, hipStream_t s);
+void launch_attn_bf16(const Geo& g, int C, int heads, int Spad, const bf16* q, const bf16* k,
+                      const bf16* vt, const int32_t* idx, const int32_t* woff, bf16* o,
+                      hipStream_t s);
+
+// weight preparation
+void launch_f32_to_bf16(const float* a, bf16* b, size_t n, hipStream_t s);
+
+}  // namespace dr

@@ -1,0 +1,454 @@
+// BF16 path on gfx950 matrix cores: v_mfma_f32_16x16x32_bf16 (FP32 accumulation) for the
+// Q/K/V projection, the output projection and both MLP linears, and a fused window-attention
+// kernel with K and V^T staged in LDS and the softmax max/sum in FP32 across lanes.
+//
+// MFMA 16x16x32 operand layout (wave64): lane l supplies row (l % 16) of A and column
+// (l % 16) of B, each with 8 consecutive k values; the k group is (l / 16).  The result lane
+// l holds C[4*(l/16) + i][l % 16], i = 0..3.  Only the pairing of A's and B's k slots matters
+// for the sum, so any k permutation applied to both operands alike is legal; the attention
+// kernel uses that to feed P straight from the score registers.
+//
+// Hazard rule.  The double-rate v_mfma_f32_16x16x32_bf16 keeps reading its A/B source VGPRs
+// for a few cycles after issue, and a VALU write to one of those VGPRs right after the issue
+// corrupts the product (seen as run-to-run differences of single output elements).  The
+// compiler does not pad that write-after-read case, so every group of these MFMAs is fenced:
+// scheduling barriers keep VALU code out of the group and an s_nop after the group gives the
+// last MFMA time to read its operands.  Inside a group, each MFMA waits for the matrix pipe,
+// which covers the operand reads of the one before it.  The attention kernel instead uses the
+// single-rate 16x16x16 form, whose operands are read at issue.
+#include "dr_device.h"
+#include "dr_internal.h"
+
+namespace dr {
+
+__device__ __forceinline__ f32x4_t mfma16(const bf16x8_t& a, const bf16x8_t& b, const f32x4_t& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Fences around a group of double-rate MFMAs (see the hazard rule above).
+__device__ __forceinline__ void mfma_group_begin() { __builtin_amdgcn_sched_barrier(0); }
+__device__ __forceinline__ void mfma_group_end() {
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("s_nop 7" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// k = 32 product from two single-rate 16x16x16 MFMAs (k slots 0-3, then 4-7).
+__device__ __forceinline__ f32x4_t mfma16_x2(const bf16x8_t& a, const bf16x8_t& b, const f32x4_t& c) {
+  const bf16x4_t a0 = {a[0], a[1], a[2], a[3]}, a1 = {a[4], a[5], a[6], a[7]};
+  const bf16x4_t b0 = {b[0], b[1], b[2], b[3]}, b1 = {b[4], b[5], b[6], b[7]};
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0, c, 0, 0, 0), 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x4_t mfma16k16(const bf16x4_t& a, const bf16x4_t& b, const f32x4_t& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+template <typename T, typename S>
+__device__ __forceinline__ T bitcast(const S& s) {
+  static_assert(sizeof(T) == sizeof(S), "size");
+  T t;
+  __builtin_memcpy(&t, &s, sizeof(T));
+  return t;
+}
+
+// ------------------------------------------------------------------------------------------
+// Tiled GEMM core.  Block = 256 threads = 4 waves in a 2 x 2 grid; block tile BM x BN
+// (tokens x output channels), each wave (BM/2) x (BN/2); BK = 64 per LDS stage, the next
+// stage prefetched into registers while the current one is multiplied.
+//
+// Orientation: with CH_ROWS = true the MFMA's A operand is the weight tile, so each lane ends
+// with 4 consecutive output channels of one token (row-major stores); with CH_ROWS = false
+// each lane ends with 4 consecutive tokens of one channel (used for V^T).
+// ------------------------------------------------------------------------------------------
+constexpr int BK = 64;
+constexpr int LDS_STRIDE = BK + 8;  // bf16 elements; 144 B rows keep ds_read_b128 conflict free
+
+template <int BM, int BN>
+struct GemmSmem {
+  bf16 a[2][BM][LDS_STRIDE];
+  bf16 w[2][BN][LDS_STRIDE];
+};
+
+template <int BM, int BN, bool CH_ROWS>
+__device__ __forceinline__ void gemm_tile(const bf16* __restrict__ A, int M, int m0, int K,
+                                          const bf16* __restrict__ W, int n0,
+                                          GemmSmem<BM, BN>& sm, f32x4_t (&acc)[BM / 32][BN / 32]) {
+  constexpr int TM = BM / 2, TN = BN / 2;        // wave tile
+  constexpr int FM = TM / 16, FN = TN / 16;      // 16x16 fragments per wave
+  constexpr int A_CHUNKS = BM * BK / 8 / 256;    // 16-byte chunks per thread
+  constexpr int W_CHUNKS = BN * BK / 8 / 256;
+  static_assert(A_CHUNKS >= 1 && W_CHUNKS >= 1, "tile too small");
+  const int t = threadIdx.x;
+  const int lane = t & 63, wv = t >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int l16 = lane & 15, kg = lane >> 4;
+
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+  uint4 ra[A_CHUNKS], rw[W_CHUNKS];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int c = 0; c < A_CHUNKS; ++c) {
+      const int id = t + 256 * c;
+      const int row = id >> 3, col = (id & 7) * 8;
+      const int m = m0 + row;
+      ra[c] = (m < M) ? *reinterpret_cast<const uint4*>(A + (size_t)m * K + k0 + col)
+                      : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int c = 0; c < W_CHUNKS; ++c) {
+      const int id = t + 256 * c;
+      const int row = id >> 3, col = (id & 7) * 8;
+      rw[c] = *reinterpret_cast<const uint4*>(W + (size_t)(n0 + row) * K + k0 + col);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int c = 0; c < A_CHUNKS; ++c) {
+      const int id = t + 256 * c;
+      *reinterpret_cast<uint4*>(&sm.a[buf][id >> 3][(id & 7) * 8]) = ra[c];
+    }
+#pragma unroll
+    for (int c = 0; c < W_CHUNKS; ++c) {
+      const int id = t + 256 * c;
+      *reinterpret_cast<uint4*>(&sm.w[buf][id >> 3][(id & 7) * 8]) = rw[c];
+    }
+  };
+
+  load(0);
+  stash(0);
+  __syncthreads();
+  const int nk = K / BK;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 32) {
+      bf16x8_t af[FM], wf[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+        af[i] = *reinterpret_cast<const bf16x8_t*>(&sm.a[buf][wm * TM + i * 16 + l16][kk + kg * 8]);
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        wf[j] = *reinterpret_cast<const bf16x8_t*>(&sm.w[buf][wn * TN + j * 16 + l16][kk + kg * 8]);
+      mfma_group_begin();
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = CH_ROWS ? mfma16(wf[j], af[i], acc[i][j]) : mfma16(af[i], wf[j], acc[i][j]);
+      mfma_group_end();
+    }
+    if (kt + 1 < nk) {
+      stash(buf ^ 1);
+      __syncthreads();
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Generic GEMM over compact rows: out = A W^T + bias with an epilogue.
+//   EPI_STORE: bf16 out[m, n];  EPI_GELU: bf16 GELU;  EPI_RESID: f32 x[res_rows[m], n] += y.
+// ------------------------------------------------------------------------------------------
+template <int BM, int BN>
+__global__ void __launch_bounds__(256) gemm_bf16_kernel(const bf16* __restrict__ A, const int32_t* __restrict__ m_dev,
+                                                        int m_max, int K, const bf16* __restrict__ W,
+                                                        const float* __restrict__ bias, int Nout, int epi,
+                                                        void* __restrict__ out, const int32_t* __restrict__ res_rows) {
+  __shared__ GemmSmem<BM, BN> sm;
+  const int M = m_dev ? m_dev[0] : m_max;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  if (m0 >= M) return;
+  f32x4_t acc[BM / 32][BN / 32];
+  gemm_tile<BM, BN, true>(A, M, m0, K, W, n0, sm, acc);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int l16 = lane & 15, kg = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < BM / 32; ++i) {
+    const int m = m0 + wm * (BM / 2) + i * 16 + l16;
+    if (m >= M) continue;
+#pragma unroll
+    for (int j = 0; j < BN / 32; ++j) {
+      const int n = n0 + wn * (BN / 2) + j * 16 + kg * 4;
+      const float4 b4 = *reinterpret_cast<const float4*>(bias + n);
+      float y0 = acc[i][j][0] + b4.x, y1 = acc[i][j][1] + b4.y;
+      float y2 = acc[i][j][2] + b4.z, y3 = acc[i][j][3] + b4.w;
+      if (epi == EPI_RESID) {
+        const int dst = res_rows ? res_rows[m] : m;
+        float4* p = reinterpret_cast<float4*>(static_cast<float*>(out) + (size_t)dst * Nout + n);
+        float4 xv = *p;
+        xv.x += y0; xv.y += y1; xv.z += y2; xv.w += y3;
+        *p = xv;
+      } else {
+        if (epi == EPI_GELU) {
+          y0 = gelu_erf(y0); y1 = gelu_erf(y1); y2 = gelu_erf(y2); y3 = gelu_erf(y3);
+        }
+        uint2 pk;
+        pk.x = pack_bf2(y0, y1);
+        pk.y = pack_bf2(y2, y3);
+        *reinterpret_cast<uint2*>(static_cast<bf16*>(out) + (size_t)m * Nout + n) = pk;
+      }
+    }
+  }
+}
+
+void launch_gemm_bf16(const bf16* A, const int32_t* m_dev, int m_max, int K, const bf16* W,
+                      const float* bias, int Nout, int epi, void* out, const int32_t* res_rows,
+                      hipStream_t s) {
+  if (m_max <= 0) return;
+  if (Nout % 128 == 0) {
+    dim3 grid((m_max + 127) / 128, Nout / 128);
+    gemm_bf16_kernel<128, 128><<<grid, 256, 0, s>>>(A, m_dev, m_max, K, W, bias, Nout, epi, out, res_rows);
+  } else {
+    dim3 grid((m_max + 127) / 128, Nout / 64);
+    gemm_bf16_kernel<128, 64><<<grid, 256, 0, s>>>(A, m_dev, m_max, K, W, bias, Nout, epi, out, res_rows);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Q/K/V projection over all N tokens: [N, C] x [3C, C]^T.  Column blocks in [0, C) are Q
+// (row-major [N, C]; skipped for row tiles without a flagged token), [C, 2C) are K stored
+// [win][head][Spad][dh], [2C, 3C) are V stored transposed [win][head][dh][Spad].
+// ------------------------------------------------------------------------------------------
+template <int BM, int BN>
+__global__ void __launch_bounds__(256) qkv_bf16_kernel(Geo g, int C, int heads, int Spad,
+                                                       const bf16* __restrict__ u, const uint8_t* __restrict__ flag,
+                                                       const bf16* __restrict__ W, const float* __restrict__ bias,
+                                                       bf16* __restrict__ q, bf16* __restrict__ k,
+                                                       bf16* __restrict__ vt) {
+  __shared__ GemmSmem<BM, BN> sm;
+  const int M = g.N;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int part = n0 / C;  // 0 = Q, 1 = K, 2 = V
+  if (part == 0) {
+    int any = 0;
+    for (int r = threadIdx.x; r < BM; r += 256)
+      if (m0 + r < M && flag[m0 + r]) any = 1;
+    if (!__syncthreads_or(any)) return;
+  }
+  const int dh = C / heads;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int l16 = lane & 15, kg = lane >> 4;
+  f32x4_t acc[BM / 32][BN / 32];
+  if (part < 2) {
+    gemm_tile<BM, BN, true>(u, M, m0, C, W, n0, sm, acc);
+#pragma unroll
+    for (int i = 0; i < BM / 32; ++i) {
+      const int m = m0 + wm * (BM / 2) + i * 16 + l16;
+      if (m >= M) continue;
+#pragma unroll
+      for (int j = 0; j < BN / 32; ++j) {
+        const int n = n0 + wn * (BN / 2) + j * 16 + kg * 4;
+        const float4 b4 = *reinterpret_cast<const float4*>(bias + n);
+        uint2 pk;
+        pk.x = pack_bf2(acc[i][j][0] + b4.x, acc[i][j][1] + b4.y);
+        pk.y = pack_bf2(acc[i][j][2] + b4.z, acc[i][j][3] + b4.w);
+        bf16* dst;
+        if (part == 0) {
+          dst = q + (size_t)m * C + n;
+        } else {
+          const int c = n - C, hh = c / dh, d = c - hh * dh;
+          const int w = m / g.S, s = m - w * g.S;
+          dst = k + (((size_t)w * heads + hh) * Spad + s) * dh + d;
+        }
+        *reinterpret_cast<uint2*>(dst) = pk;
+      }
+    }
+  } else {
+    gemm_tile<BM, BN, false>(u, M, m0, C, W, n0, sm, acc);
+#pragma unroll
+    for (int i = 0; i < BM / 32; ++i) {
+#pragma unroll
+      for (int j = 0; j < BN / 32; ++j) {
+        const int n = n0 + wn * (BN / 2) + j * 16 + l16;
+        const float bn = bias[n];
+        const int c = n - 2 * C, hh = c / dh, d = c - hh * dh;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int m = m0 + wm * (BM / 2) + i * 16 + kg * 4 + e;
+          if (m >= M) continue;
+          const int w = m / g.S, s = m - w * g.S;
+          vt[(((size_t)w * heads + hh) * dh + d) * Spad + s] = f2bf(acc[i][j][e] + bn);
+        }
+      }
+    }
+  }
+}
+
+void launch_qkv_bf16(const Geo& g, int C, int heads, int Spad, const bf16* u, const uint8_t* flag,
+                     const bf16* w, const float* bias, bf16* q, bf16* k, bf16* vt, hipStream_t s) {
+  if (C % 128 == 0) {
+    dim3 grid((g.N + 127) / 128, 3 * C / 128);
+    qkv_bf16_kernel<128, 128><<<grid, 256, 0, s>>>(g, C, heads, Spad, u, flag, w, bias, q, k, vt);
+  } else {
+    dim3 grid((g.N + 127) / 128, 3 * C / 64);
+    qkv_bf16_kernel<128, 64><<<grid, 256, 0, s>>>(g, C, heads, Spad, u, flag, w, bias, q, k, vt);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Window attention on MFMA.  Block = 4 waves = 64 queries of one (window, head); K and V^T of
+// the window/head are staged in LDS once.  Each wave: 16 queries.
+//   S^T tile (16 keys x 16 queries) = K_tile (16 x dh) . Q^T  -> lane l holds the scores of
+//   query l%16 for keys 16t + 4*(l/16) + i.  Softmax statistics stay FP32: max/sum over
+//   registers, then across the 4 lane groups with two xor shuffles.
+//   O^T (16 dh x 16 queries) = V^T (dh x keys) . P^T, with P taken from the score registers
+//   (the k slots of both operands use the same key permutation).
+// ------------------------------------------------------------------------------------------
+template <int DH, int NT>
+__global__ void __launch_bounds__(256) attn_bf16_kernel(Geo g, int C, int heads, const bf16* __restrict__ q,
+                                                        const bf16* __restrict__ kmat, const bf16* __restrict__ vt,
+                                                        const int32_t* __restrict__ idx,
+                                                        const int32_t* __restrict__ woff, bf16* __restrict__ o) {
+  constexpr int SP = NT * 16;           // padded window length
+  constexpr int KST = DH + 8;           // LDS row stride of K (bf16)
+  constexpr int VST = SP + 8;           // LDS row stride of V^T
+  __shared__ bf16 Ks[SP * KST];
+  __shared__ bf16 Vs[DH * VST];
+  const int w = blockIdx.x / heads, h = blockIdx.x - w * heads;
+  const int q0 = woff[w], nqw = woff[w + 1] - q0;
+  const int qbase = blockIdx.y * 64;
+  if (qbase >= nqw) return;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int l16 = lane & 15, kg = lane >> 4;
+
+  // stage K [SP][DH] and V^T [DH][SP] of (w, h)
+  const bf16* kg_ = kmat + ((size_t)w * heads + h) * SP * DH;
+  const bf16* vg_ = vt + ((size_t)w * heads + h) * DH * SP;
+  for (int c = t; c < SP * DH / 8; c += 256) {
+    const int row = c / (DH / 8), col = (c % (DH / 8)) * 8;
+    *reinterpret_cast<uint4*>(&Ks[row * KST + col]) = *reinterpret_cast<const uint4*>(kg_ + row * DH + col);
+  }
+  for (int c = t; c < DH * SP / 8; c += 256) {
+    const int row = c / (SP / 8), col = (c % (SP / 8)) * 8;
+    *reinterpret_cast<uint4*>(&Vs[row * VST + col]) = *reinterpret_cast<const uint4*>(vg_ + row * SP + col);
+  }
+  __syncthreads();
+
+  const int qi = qbase + wv * 16 + l16;  // this lane's query (column of S^T)
+  if (qbase + wv * 16 >= nqw) return;    // whole wave idle (no block barrier follows)
+  const bool valid = qi < nqw;
+  const int r = q0 + (valid ? qi : 0);
+  const int n = idx[r];
+
+  // Q^T operand: lane holds q[n][kk*32 + 8*kg .. +7]
+  bf16x8_t qf[DH / 32];
+#pragma unroll
+  for (int kk = 0; kk < DH / 32; ++kk) {
+    uint4 v = valid ? *reinterpret_cast<const uint4*>(q + (size_t)n * C + h * DH + kk * 32 + kg * 8)
+                    : make_uint4(0, 0, 0, 0);
+    qf[kk] = bitcast<bf16x8_t>(v);
+  }
+
+  const float sl2 = 1.4426950408889634f / sqrtf((float)DH);  // log2(e) / sqrt(dh)
+  float sc[NT][4];
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt) {
+    f32x4_t a = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < DH / 32; ++kk) {
+      const bf16x8_t kf = *reinterpret_cast<const bf16x8_t*>(&Ks[(tt * 16 + l16) * KST + kk * 32 + kg * 8]);
+      a = mfma16_x2(kf, qf[kk], a);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int key = tt * 16 + kg * 4 + i;
+      sc[tt][i] = key < g.S ? a[i] * sl2 : -INFINITY;
+    }
+  }
+  float mx = -INFINITY;
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) mx = fmaxf(mx, sc[tt][i]);
+  mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+  mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+  float sum = 0.f;
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float p = exp2f(sc[tt][i] - mx);
+      sc[tt][i] = p;
+      sum += p;
+    }
+  sum += __shfl_xor(sum, 16, 64);
+  sum += __shfl_xor(sum, 32, 64);
+  const float inv = 1.0f / sum;
+
+#pragma unroll
+  for (int dt = 0; dt < DH / 16; ++dt) {
+    f32x4_t a = {0.f, 0.f, 0.f, 0.f};
+    const bf16* vrow = &Vs[(dt * 16 + l16) * VST];
+#pragma unroll
+    for (int tt = 0; tt + 1 < NT; tt += 2) {
+      const uint2 v0 = *reinterpret_cast<const uint2*>(vrow + tt * 16 + kg * 4);
+      const uint2 v1 = *reinterpret_cast<const uint2*>(vrow + tt * 16 + 16 + kg * 4);
+      uint4 pv;
+      pv.x = pack_bf2(sc[tt][0], sc[tt][1]);
+      pv.y = pack_bf2(sc[tt][2], sc[tt][3]);
+      pv.z = pack_bf2(sc[tt + 1][0], sc[tt + 1][1]);
+      pv.w = pack_bf2(sc[tt + 1][2], sc[tt + 1][3]);
+      const uint4 vv = make_uint4(v0.x, v0.y, v1.x, v1.y);
+      a = mfma16_x2(bitcast<bf16x8_t>(vv), bitcast<bf16x8_t>(pv), a);
+    }
+    if (NT & 1) {
+      constexpr int tt = NT - 1;
+      const uint2 v0 = *reinterpret_cast<const uint2*>(vrow + tt * 16 + kg * 4);
+      uint2 pv;
+      pv.x = pack_bf2(sc[tt][0], sc[tt][1]);
+      pv.y = pack_bf2(sc[tt][2], sc[tt][3]);
+      a = mfma16k16(bitcast<bf16x4_t>(v0), bitcast<bf16x4_t>(pv), a);
+    }
+    if (valid) {
+      uint2 pk;
+      pk.x = pack_bf2(a[0] * inv, a[1] * inv);
+      pk.y = pack_bf2(a[2] * inv, a[3] * inv);
+      *reinterpret_cast<uint2*>(o + (size_t)r * C + h * DH + dt * 16 + kg * 4) = pk;
+    }
+  }
+}
+
+void launch_attn_bf16(const Geo& g, int C, int heads, int Spad, const bf16* q, const bf16* k,
+                      const bf16* vt, const int32_t* idx, const int32_t* woff, bf16* o, hipStream_t s) {
+  const int dh = C / heads;
+  dim3 grid(g.nwin * heads, (g.S + 63) / 64);
+  const int nt = Spad / 16;
+#define DR_ATTN_CASE(DH_, NT_)                                                          \
+  if (dh == DH_ && nt == NT_) {                                                         \
+    attn_bf16_kernel<DH_, NT_><<<grid, 256, 0, s>>>(g, C, heads, q, k, vt, idx, woff, o); \
+    return;                                                                             \
+  }
+  DR_ATTN_CASE(32, 4)
+  DR_ATTN_CASE(64, 4)
+  DR_ATTN_CASE(64, 15)
+  DR_ATTN_CASE(64, 19)
+  DR_ATTN_CASE(32, 15)
+  DR_ATTN_CASE(32, 19)
+#undef DR_ATTN_CASE
+}
+
+bool attn_bf16_supported(int dh, int spad) {
+  const int nt = spad / 16;
+  return (dh == 32 || dh == 64) && (nt == 4 || nt == 15 || nt == 19);
+}
+
+// ------------------------------------------------------------------------------------------
+__global__ void f32_to_bf16_kernel(const float* __restrict__ a, bf16* __restrict__ b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = f2bf(a[i]);
+}
+
+void launch_f32_to_bf16(const float* a, bf16* b, size_t n, hipStream_t s) {
+  size_t grid = (n + 255) / 256;
+  if (grid > 8192) grid = 8192;
+  if (grid) f32_to_bf16_kernel<<<(unsigned)grid, 256, 0, s>>>(a, b, n);
+}
+
+}  // namespace dr

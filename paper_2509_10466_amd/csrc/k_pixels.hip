@@ -1,0 +1,210 @@
+// Pixel-side steps of the path: cut-out + patch embedding (first step after the token
+// gather), and final LayerNorm + transposed-conv decoder + sigmoid + composite (last step).
+//
+// The network input is the frame with private pixels set to 0 (thesis, Methods,
+// "Inpainting Manager"); the output keeps every non-private pixel of the input and takes
+// generated content only inside the mask.  Both steps are FP32 in every precision mode:
+// together they are well under 1 % of the path's arithmetic.
+#include "dr_device.h"
+#include "dr_internal.h"
+
+namespace dr {
+
+__device__ __forceinline__ void token_coords(const Geo& g, int n, int& b, int& t, int& i, int& j) {
+  int w = n / g.S, s = n - w * g.S;
+  int v = w % g.nww;
+  int r = w / g.nww;
+  int u = r % g.nwh;
+  r /= g.nwh;
+  int nT = g.T / g.wt;
+  int a = r % nT;
+  b = r / nT;
+  int dj = s % g.ww;
+  int q = s / g.ww;
+  int di = q % g.wh;
+  int dt = q / g.wh;
+  t = a * g.wt + dt;
+  i = u * g.wh + di;
+  j = v * g.ww + dj;
+}
+
+// ------------------------------------------------------------------------------------------
+// Cut-out + patch embedding: x[n, o] = b[o] + sum_k wT[k, o] * patch_n[k],
+// k = (ky*4 + kx)*3 + c, patch value = 0 where the mask is set.  Block = C threads, 64
+// tokens per block; thread o keeps its 48 weights in registers.
+// ------------------------------------------------------------------------------------------
+constexpr int EMB_TOK = 64;
+
+__global__ void embed_kernel(Geo g, int C, const float* __restrict__ frames,
+                             const uint8_t* __restrict__ masks, const float* __restrict__ wT,
+                             const float* __restrict__ bias, float* __restrict__ x) {
+  __shared__ float P[EMB_TOK][48];
+  const int n0 = blockIdx.x * EMB_TOK;
+  for (int seg = threadIdx.x; seg < EMB_TOK * 4; seg += blockDim.x) {
+    const int tok = seg >> 2, ky = seg & 3;
+    const int n = n0 + tok;
+    float vals[12];
+    if (n < g.N) {
+      int b, t, i, j;
+      token_coords(g, n, b, t, i, j);
+      const size_t px = (((size_t)b * g.T + t) * g.H + 4 * i + ky) * g.W + 4 * j;
+      const float4* src = reinterpret_cast<const float4*>(frames + px * 3);
+      const float4 f0 = src[0], f1 = src[1], f2 = src[2];
+      const uint32_t m = *reinterpret_cast<const uint32_t*>(masks + px);
+      vals[0] = f0.x; vals[1] = f0.y; vals[2] = f0.z; vals[3] = f0.w;
+      vals[4] = f1.x; vals[5] = f1.y; vals[6] = f1.z; vals[7] = f1.w;
+      vals[8] = f2.x; vals[9] = f2.y; vals[10] = f2.z; vals[11] = f2.w;
+#pragma unroll
+      for (int kx = 0; kx < 4; ++kx) {
+        if ((m >> (8 * kx)) & 0xffu) {
+          vals[kx * 3 + 0] = 0.f;
+          vals[kx * 3 + 1] = 0.f;
+          vals[kx * 3 + 2] = 0.f;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) vals[k] = 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) P[tok][ky * 12 + k] = vals[k];
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < C; o += blockDim.x) {
+    float w[48];
+#pragma unroll
+    for (int k = 0; k < 48; ++k) w[k] = wT[k * C + o];
+    const float bo = bias[o];
+    const int ntok = min(EMB_TOK, g.N - n0);
+    for (int tok = 0; tok < ntok; ++tok) {
+      float acc = bo;
+#pragma unroll
+      for (int k = 0; k < 48; ++k) acc = fmaf(P[tok][k], w[k], acc);
+      x[(size_t)(n0 + tok) * C + o] = acc;
+    }
+  }
+}
+
+void launch_embed(const Geo& g, int C, const float* frames, const uint8_t* masks, const float* wT,
+                  const float* b, float* x, hipStream_t s) {
+  const int blocks = (g.N + EMB_TOK - 1) / EMB_TOK;
+  const int threads = C < 256 ? C : 256;
+  embed_kernel<<<blocks, threads, 0, s>>>(g, C, frames, masks, wT, b, x);
+}
+
+// ------------------------------------------------------------------------------------------
+// Final LayerNorm + decoder + sigmoid, then the masked pixels of each flagged token are
+// written.  One wavefront per flagged token; the decoder matrix [C][48] lives in LDS.
+// ------------------------------------------------------------------------------------------
+constexpr int DEC_GRID = 1024;
+
+__global__ void __launch_bounds__(256) decode_kernel(Geo g, int C, const float* __restrict__ x,
+                                                     const int32_t* __restrict__ idx,
+                                                     const int32_t* __restrict__ nq,
+                                                     const float* __restrict__ lng,
+                                                     const float* __restrict__ lnb,
+                                                     const float* __restrict__ dw,
+                                                     const float* __restrict__ db,
+                                                     const uint8_t* __restrict__ masks,
+                                                     float* __restrict__ out) {
+  extern __shared__ float sm[];
+  float* Wd = sm;                      // [C][48]
+  float* Z = sm + (size_t)C * 48;      // [4][C]
+  for (int e = threadIdx.x; e < C * 48; e += blockDim.x) Wd[e] = dw[e];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  float* z = Z + wv * C;
+  const int total = nq[0];
+  const int per = C / 64;
+  for (int r = blockIdx.x * 4 + wv; r < total; r += gridDim.x * 4) {
+    const int n = idx[r];
+    const float* xr = x + (size_t)n * C;
+    float v[16];
+    float s = 0.f;
+    for (int e = 0; e < per; ++e) {
+      v[e] = xr[lane + 64 * e];
+      s += v[e];
+    }
+    const float mean = wave_sum(s) / C;
+    float q = 0.f;
+    for (int e = 0; e < per; ++e) {
+      const float d = v[e] - mean;
+      q += d * d;
+    }
+    const float rstd = rsqrtf(wave_sum(q) / C + 1e-5f);
+    for (int e = 0; e < per; ++e) {
+      const int c = lane + 64 * e;
+      z[c] = (v[e] - mean) * rstd * lng[c] + lnb[c];
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane < 48) {
+      float acc = db[lane % 3];
+      for (int c = 0; c < C; ++c) acc = fmaf(z[c], Wd[c * 48 + lane], acc);
+      const float pred = 1.0f / (1.0f + expf(-acc));
+      int b, t, i, j;
+      token_coords(g, n, b, t, i, j);
+      const int pix = lane / 3, ch = lane - 3 * pix;
+      const int ky = pix >> 2, kx = pix & 3;
+      const size_t px = (((size_t)b * g.T + t) * g.H + 4 * i + ky) * g.W + 4 * j + kx;
+      if (masks[px]) out[px * 3 + ch] = pred;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+void launch_decode(const Geo& g, int C, const float* x, const int32_t* idx, const int32_t* nq,
+                   const float* lng, const float* lnb, const float* dw, const float* db,
+                   const uint8_t* masks, float* out, hipStream_t s) {
+  const size_t smem = (size_t)C * 48 * sizeof(float) + 4 * (size_t)C * sizeof(float);
+  int grid = (g.N + 3) / 4;
+  if (grid > DEC_GRID) grid = DEC_GRID;
+  static size_t granted = 0;
+  if (smem > 65536 && smem > granted) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(decode_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    granted = smem;
+  }
+  decode_kernel<<<grid, 256, smem, s>>>(g, C, x, idx, nq, lng, lnb, dw, db, masks, out);
+}
+
+// ------------------------------------------------------------------------------------------
+// out = frames wherever the mask is 0 (4 pixels per thread, vector loads and stores).
+// ------------------------------------------------------------------------------------------
+__global__ void copy_unmasked_kernel(size_t nquad, const float4* __restrict__ frames,
+                                     const uint32_t* __restrict__ masks, float4* __restrict__ out) {
+  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < nquad;
+       q += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t m = masks[q];
+    if (m == 0x01010101u) continue;
+    const float4 a = frames[3 * q], b = frames[3 * q + 1], c = frames[3 * q + 2];
+    if (m == 0) {
+      out[3 * q] = a;
+      out[3 * q + 1] = b;
+      out[3 * q + 2] = c;
+    } else {
+      float v[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
+      float* o = reinterpret_cast<float*>(out + 3 * q);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (((m >> (8 * k)) & 0xffu) == 0) {
+          o[3 * k] = v[3 * k];
+          o[3 * k + 1] = v[3 * k + 1];
+          o[3 * k + 2] = v[3 * k + 2];
+        }
+      }
+    }
+  }
+}
+
+void launch_copy_unmasked(size_t npix, const float* frames, const uint8_t* masks, float* out,
+                          hipStream_t s) {
+  const size_t nquad = npix / 4;
+  size_t grid = (nquad + 255) / 256;
+  if (grid > 4096) grid = 4096;
+  if (grid == 0) return;
+  copy_unmasked_kernel<<<(unsigned)grid, 256, 0, s>>>(nquad, reinterpret_cast<const float4*>(frames),
+                                                      reinterpret_cast<const uint32_t*>(masks),
+                                                      reinterpret_cast<float4*>(out));
+}
+
+}  // namespace dr

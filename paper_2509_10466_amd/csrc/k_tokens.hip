@@ -1,0 +1,109 @@
+// Step 1 of the path: token flags and the gather lists of query tokens.
+//
+// A token is flagged when any pixel of its p x p patch is private (OR rule), i.e. when the
+// cut-out of the private object (thesis, Methods, "Object Control") touches it.  Tokens are
+// numbered window-major: window w = ((b*nT + a)*nwh + u)*nww + v, and inside a window
+// s = (dt*wh + di)*ww + dj; token n = w*S + s.  All outputs are integers and are exact.
+#include "dr_device.h"
+#include "dr_internal.h"
+
+namespace dr {
+
+// Pixel offset (in pixels, not channels) of the top-left pixel of token n.
+__device__ __forceinline__ size_t token_pixel(const Geo& g, int n) {
+  int w = n / g.S, s = n - w * g.S;
+  int v = w % g.nww;
+  int r = w / g.nww;
+  int u = r % g.nwh;
+  r /= g.nwh;
+  int nT = g.T / g.wt;
+  int a = r % nT;
+  int b = r / nT;
+  int dj = s % g.ww;
+  int q = s / g.ww;
+  int di = q % g.wh;
+  int dt = q / g.wh;
+  int t = a * g.wt + dt, i = u * g.wh + di, j = v * g.ww + dj;
+  return (((size_t)b * g.T + t) * g.H + (size_t)g.P * i) * g.W + (size_t)g.P * j;
+}
+
+// One workgroup per window: flag its S tokens and count them.
+__global__ void __launch_bounds__(256) token_flags_kernel(Geo g, const uint8_t* __restrict__ masks,
+                                                          int all, uint8_t* __restrict__ flag,
+                                                          int32_t* __restrict__ wcount) {
+  __shared__ int cnt;
+  const int w = blockIdx.x;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  int local = 0;
+  for (int s = threadIdx.x; s < g.S; s += blockDim.x) {
+    const int n = w * g.S + s;
+    int f = 1;
+    if (!all) {
+      const size_t px = token_pixel(g, n);
+      uint32_t any = 0;
+      // p == 4 and W % 4 == 0: each patch row is one aligned 32-bit word of mask bytes.
+      for (int ky = 0; ky < 4; ++ky)
+        any |= *reinterpret_cast<const uint32_t*>(masks + px + (size_t)ky * g.W);
+      f = any != 0;
+    }
+    flag[n] = (uint8_t)f;
+    local += f;
+  }
+  if (local) atomicAdd(&cnt, local);
+  __syncthreads();
+  if (threadIdx.x == 0) wcount[w] = cnt;
+}
+
+// One workgroup per window: offset = flagged tokens in earlier windows, then an ordered
+// compaction of this window's flagged tokens into idx (ranks from wavefront ballots).
+__global__ void __launch_bounds__(256) token_gather_kernel(Geo g, const uint8_t* __restrict__ flag,
+                                                           const int32_t* __restrict__ wcount,
+                                                           int32_t* __restrict__ idx,
+                                                           int32_t* __restrict__ woff,
+                                                           int32_t* __restrict__ nq) {
+  __shared__ int red[4];
+  __shared__ int wave_tot[4];
+  const int w = blockIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int part = 0;
+  for (int k = threadIdx.x; k < w; k += blockDim.x) part += wcount[k];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o, 64);
+  if (lane == 0) red[wv] = part;
+  __syncthreads();
+  const int off = red[0] + red[1] + red[2] + red[3];
+  int running = 0;
+  for (int base = 0; base < g.S; base += 256) {
+    const int s = base + threadIdx.x;
+    const int f = (s < g.S) ? flag[w * g.S + s] : 0;
+    const unsigned long long bal = __ballot(f);
+    const int below = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wave_tot[wv] = __popcll(bal);
+    __syncthreads();
+    int before = running;
+    for (int k = 0; k < wv; ++k) before += wave_tot[k];
+    if (f) idx[off + before + below] = w * g.S + s;
+    running += wave_tot[0] + wave_tot[1] + wave_tot[2] + wave_tot[3];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    woff[w] = off;
+    if (w == g.nwin - 1) {
+      woff[g.nwin] = off + running;
+      nq[0] = off + running;
+    }
+  }
+}
+
+void launch_token_flags(const Geo& g, const uint8_t* masks, int all, uint8_t* flag,
+                        int32_t* wcount, hipStream_t s) {
+  token_flags_kernel<<<g.nwin, 256, 0, s>>>(g, masks, all, flag, wcount);
+}
+
+void launch_token_gather(const Geo& g, const uint8_t* flag, const int32_t* wcount, int32_t* idx,
+                         int32_t* woff, int32_t* nq, hipStream_t s) {
+  token_gather_kernel<<<g.nwin, 256, 0, s>>>(g, flag, wcount, idx, woff, nq);
+}
+
+}  // namespace dr

@@ -1,0 +1,204 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import drsynth
+from oracle import network as on
+from tests.gpu_util import TOL, case_inputs, compare, sample_windows
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+_ENGINES = {}
+
+
+def engine(cfg, seed=0, qk_std=None):
+    from paper_2509_10466_amd import Inpainter
+    key = (cfg, seed, qk_std)
+    if key not in _ENGINES:
+        W = drsynth.make_weights(cfg, seed, qk_std=qk_std)
+        _ENGINES[key] = (Inpainter(cfg, W), W)
+    return _ENGINES[key]
+
+
+def run(eng, frames, masks, precision, query_set="masked"):
+    f = torch.from_numpy(frames).cuda()
+    m = torch.from_numpy(masks).cuda()
+    out = eng(f, m, precision, query_set)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+# ------------------------------------------------------------------------------------------
+# step 1: token gather, bit-exact
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["tiny64", "mid", "mid_b2", "clip240"])
+@pytest.mark.parametrize("qs", ["masked", "all"])
+def test_gather_bit_exact(dev, case, qs):
+    cfg, frames, masks = case_inputs(case)
+    _say(f"[gather] case={case} qs={qs} shape={masks.shape}")
+    eng, _ = engine(cfg)
+    flag, idx, woff = eng.gather_tokens(torch.from_numpy(masks).cuda(), qs)
+    torch.cuda.synchronize()
+    rf, ri, rw = on.gather_lists(masks, cfg, qs)
+    assert np.array_equal(flag.cpu().numpy(), rf)
+    assert np.array_equal(idx.cpu().numpy(), ri)
+    assert np.array_equal(woff.cpu().numpy(), rw)
+
+
+@pytest.mark.parametrize("fill", [0, 1, 255])
+def test_gather_degenerate_masks(dev, fill):
+    cfg, frames, masks = case_inputs("mid")
+    masks = np.full_like(masks, fill)
+    _say(f"[gather-degenerate] fill={fill}")
+    eng, _ = engine(cfg)
+    flag, idx, woff = eng.gather_tokens(torch.from_numpy(masks).cuda())
+    N = flag.numel()
+    if fill == 0:
+        assert idx.numel() == 0 and int(woff.abs().sum()) == 0 and int(flag.sum()) == 0
+    else:
+        assert np.array_equal(idx.cpu().numpy(), np.arange(N, dtype=np.int32))
+
+
+# ------------------------------------------------------------------------------------------
+# whole forward against the oracle
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["tiny64", "mid", "mid_b2"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("qs", ["masked", "all"])
+def test_forward_parity_small(dev, case, precision, qs):
+    cfg, frames, masks = case_inputs(case)
+    _say(f"[forward] case={case} prec={precision} qs={qs} shape={frames.shape}")
+    eng, W = engine(cfg)
+    out = run(eng, frames, masks, precision, qs)
+    ref = on.forward(frames, masks, W, cfg, qs)
+    mx, n = compare(out, ref, frames, masks, TOL[precision])
+    _say(f"    max abs err {mx:.3e} over {n} in-mask values")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_forward_parity_stress_weights(dev, precision):
+    """Peaked softmax (Wq, Wk drawn with std 0.2) exercises the max subtraction."""
+    cfg, frames, masks = case_inputs("mid")
+    _say(f"[stress] prec={precision}")
+    eng, W = engine(cfg, seed=1, qk_std=0.2)
+    out = run(eng, frames, masks, precision)
+    ref = on.forward(frames, masks, W, cfg)
+    compare(out, ref, frames, masks, TOL[precision])
+
+
+@pytest.mark.parametrize("case", ["clip240", "clip720"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_forward_parity_full_size_sampled(dev, case, precision):
+    """Full-size clip on the GPU; the oracle recomputes sampled windows from their pixel
+    footprints (outputs of a window depend on its footprint only)."""
+    cfg, frames, masks = case_inputs(case)
+    _say(f"[full-size] case={case} prec={precision} shape={frames.shape}")
+    eng, W = engine(cfg)
+    out = run(eng, frames, masks, precision)
+    inside = np.repeat(masks[..., None] != 0, 3, axis=-1)
+    assert np.array_equal(out[~inside], frames[~inside])
+    worst = 0.0
+    for b, rs, cs in sample_windows(cfg, masks, k=8):
+        ref = on.forward(frames[b:b + 1, :, rs, cs], masks[b:b + 1, :, rs, cs], W, cfg)
+        mx, _ = compare(out[b:b + 1, :, rs, cs], ref, frames[b:b + 1, :, rs, cs],
+                        masks[b:b + 1, :, rs, cs], TOL[precision])
+        worst = max(worst, mx)
+    _say(f"    worst sampled max abs err {worst:.3e}")
+
+
+# ------------------------------------------------------------------------------------------
+# properties that hold at any size
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_empty_mask_returns_input(dev, precision):
+    cfg, frames, masks = case_inputs("mid")
+    masks = np.zeros_like(masks)
+    eng, _ = engine(cfg)
+    out = run(eng, frames, masks, precision)
+    assert np.array_equal(out, frames)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_full_mask_equals_dense(dev, precision):
+    cfg, frames, masks = case_inputs("mid")
+    masks = np.ones_like(masks)
+    eng, _ = engine(cfg)
+    a = run(eng, frames, masks, precision, "masked")
+    b = run(eng, frames, masks, precision, "all")
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_in_place_and_determinism(dev, precision):
+    cfg, frames, masks = case_inputs("clip240")
+    eng, _ = engine(cfg)
+    a = run(eng, frames, masks, precision)
+    for rep in range(4):
+        b = run(eng, frames, masks, precision)
+        assert np.array_equal(a, b), f"run {rep + 2} differs from run 1"
+    f = torch.from_numpy(frames).cuda()
+    m = torch.from_numpy(masks).cuda()
+    eng(f, m, precision, out=f)
+    torch.cuda.synchronize()
+    assert np.array_equal(f.cpu().numpy(), a)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_batch_independence_bitwise(dev, precision):
+    cfg, frames, masks = case_inputs("mid_b2")
+    eng, _ = engine(cfg)
+    both = run(eng, frames, masks, precision)
+    for b in range(2):
+        one = run(eng, frames[b:b + 1].copy(), masks[b:b + 1].copy(), precision)
+        assert np.array_equal(one, both[b:b + 1])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_window_locality_bitwise(dev, precision):
+    cfg, frames, masks = case_inputs("clip240")
+    eng, _ = engine(cfg)
+    a = run(eng, frames, masks, precision)
+    f2, m2 = frames.copy(), masks.copy()
+    ph, pw = cfg.patch * cfg.win_h, cfg.patch * cfg.win_w
+    # change everything outside the window (u=2, v=3)
+    rs, cs = slice(2 * ph, 3 * ph), slice(3 * pw, 4 * pw)
+    keep_f, keep_m = frames[:, :, rs, cs].copy(), masks[:, :, rs, cs].copy()
+    f2 = np.random.default_rng(1).random(f2.shape).astype(np.float32)
+    m2 = (np.random.default_rng(2).random(m2.shape) < 0.3).astype(np.uint8)
+    f2[:, :, rs, cs], m2[:, :, rs, cs] = keep_f, keep_m
+    b = run(eng, f2, m2, precision)
+    assert np.array_equal(a[:, :, rs, cs], b[:, :, rs, cs])
+
+
+def test_bad_shapes_and_aliasing(dev):
+    from paper_2509_10466_amd._lib import DrError
+    cfg, frames, masks = case_inputs("mid")
+    eng, _ = engine(cfg)
+    f = torch.from_numpy(frames).cuda()
+    m = torch.from_numpy(masks).cuda()
+    with pytest.raises(DrError, match="DR_ESHAPE"):
+        eng(f[:, :4].contiguous(), m[:, :4].contiguous())
+    with pytest.raises(DrError, match="DR_ESHAPE"):
+        eng(f[:, :, :36].contiguous(), m[:, :, :36].contiguous())
+    big = torch.zeros(f.numel() * 2, device=f.device)
+    view = big[7: 7 + f.numel()].view(f.shape)
+    big[: f.numel()].view(f.shape).copy_(f)
+    with pytest.raises(DrError, match="DR_EINVAL"):
+        eng(big[: f.numel()].view(f.shape), m, out=view)
