@@ -124,7 +124,7 @@ const char* dr_stage_name(int stage);
 
 /* Inspection, for tests: copy the first `nbytes` of the named workspace buffer into device
  * memory `dst` on `stream`.  Names: "x" (f32 residual [N,C], window-major), "u16", "q16",
- * "o16" (bf16 [N,C]), "k16" (bf16 [win][head][Spad][dh]), "v16t" (bf16 [win][head][dh][Spad]),
+ * "o16" (bf16 [N,C]), "k16", "v16" (bf16 [win][head][Spad][dh]),
  * "h16" (bf16 [N,rC]), "u", "q", "o" (f32 [N,C]), "kv" (f32 [N,2C]), "h" (f32 [N,rC]),
  * "flag" (u8 [N]), "idx" (int32 [N]), "nq" (int32).  DR_EINVAL for an unknown name or a
  * size beyond the buffer. */

@@ -164,7 +164,7 @@ def block(x, upd, W, l, cfg, trace=None):
                _w(W, p + "b1"))
     x2 = x1 + linear(gelu(h), _w(W, p + "w2"), _w(W, p + "b2"))
     if trace is not None:
-        trace.append(dict(u=u, q=q, k=k, v=v, o=o, probs=probs, x1=x1, h=h, x2=x2))
+        trace.append(dict(x=x, u=u, q=q, k=k, v=v, o=o, probs=probs, x1=x1, h=h, x2=x2))
     return np.where(upd[..., None], x2, x)
 
 

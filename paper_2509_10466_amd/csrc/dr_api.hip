@@ -394,13 +394,13 @@ static dr_status reserve_geo(dr_ctx* c, const Geo& g) {
   ALLOC(u16, N * C * 2);
   ALLOC(q16, N * C * 2);
   ALLOC(k16, kvlen * 2);
-  ALLOC(v16t, kvlen * 2);
+  ALLOC(v16, kvlen * 2);
   ALLOC(o16, N * C * 2);
   ALLOC(h16, N * R * 2);
 #undef ALLOC
   // padded key rows / columns of K and V^T must read as zero
   HIP_OK(c, hipMemset(w.k16, 0, kvlen * 2));
-  HIP_OK(c, hipMemset(w.v16t, 0, kvlen * 2));
+  HIP_OK(c, hipMemset(w.v16, 0, kvlen * 2));
   HIP_OK(c, hipDeviceSynchronize());
   w.cap_tokens = N;
   w.cap_windows = nw;
@@ -495,12 +495,10 @@ extern "C" dr_status dr_inpaint(dr_ctx* c, const float* frames, const uint8_t* m
       LAUNCH(ST_FC1, launch_gemm_f32(w.u, nullptr, w.nq, N, C, b.w1, b.b1, R, EPI_GELU, w.h, nullptr, s));
       LAUNCH(ST_FC2, launch_gemm_f32(w.h, nullptr, w.nq, N, R, b.w2, b.b2, C, EPI_RESID, w.x, w.idx, s));
     } else {
-      LAUNCH(ST_LN1, launch_ln_bf16(w.x, nullptr, nullptr, N, C, b.ln1g, b.ln1b, w.u16, s));
-      LAUNCH(ST_QKV, launch_qkv_bf16(g, C, n.cfg.heads, n.Spad, w.u16, w.flag, b.wqkv16, b.bqkv, w.q16, w.k16, w.v16t, s));
-      LAUNCH(ST_ATTN, launch_attn_bf16(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.v16t, w.idx, w.woff, w.o16, s));
+      LAUNCH(ST_QKV, launch_ln_qkv_bf16(g, C, n.cfg.heads, n.Spad, w.x, w.flag, w.wcount, b.ln1g, b.ln1b, b.wqkv16, b.bqkv, w.q16, w.k16, w.v16, s));
+      LAUNCH(ST_ATTN, launch_attn_bf16(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.v16, w.idx, w.woff, w.o16, s));
       LAUNCH(ST_PROJ, launch_gemm_bf16(w.o16, w.nq, N, C, b.wo16, b.bo, C, EPI_RESID, w.x, w.idx, s));
-      LAUNCH(ST_LN2, launch_ln_bf16(w.x, w.idx, w.nq, N, C, b.ln2g, b.ln2b, w.u16, s));
-      LAUNCH(ST_FC1, launch_gemm_bf16(w.u16, w.nq, N, C, b.w116, b.b1, R, EPI_GELU, w.h16, nullptr, s));
+      LAUNCH(ST_FC1, launch_ln_fc1_bf16(N, C, R, w.x, w.idx, w.nq, b.ln2g, b.ln2b, b.w116, b.b1, w.h16, s));
       LAUNCH(ST_FC2, launch_gemm_bf16(w.h16, w.nq, N, R, b.w216, b.b2, C, EPI_RESID, w.x, w.idx, s));
     }
   }
@@ -552,7 +550,7 @@ extern "C" dr_status dr_inspect(dr_ctx* c, const char* name, void* dst, size_t n
   const size_t kvlen = w.cap_windows * c->net.cfg.heads * (size_t)c->net.Spad * c->net.dh;
   struct Buf { const char* n; const void* p; size_t bytes; } bufs[] = {
       {"x", w.x, N * C * 4},       {"u16", w.u16, N * C * 2}, {"q16", w.q16, N * C * 2},
-      {"k16", w.k16, kvlen * 2},   {"v16t", w.v16t, kvlen * 2}, {"o16", w.o16, N * C * 2},
+      {"k16", w.k16, kvlen * 2},   {"v16", w.v16, kvlen * 2}, {"o16", w.o16, N * C * 2},
       {"h16", w.h16, N * R * 2},   {"u", w.u, N * C * 4},     {"kv", w.kv, N * 2 * C * 4},
       {"q", w.q, N * C * 4},       {"o", w.o, N * C * 4},     {"h", w.h, N * R * 4},
       {"flag", w.flag, N},         {"idx", w.idx, N * 4},     {"nq", w.nq, 4}};

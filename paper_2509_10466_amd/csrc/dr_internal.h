@@ -74,7 +74,7 @@ struct Work {
   // FP32 path scratch
   float *u = nullptr, *kv = nullptr, *q = nullptr, *o = nullptr, *h = nullptr;
   // BF16 path scratch
-  bf16 *u16 = nullptr, *q16 = nullptr, *k16 = nullptr, *v16t = nullptr, *o16 = nullptr,
+  bf16 *u16 = nullptr, *q16 = nullptr, *k16 = nullptr, *v16 = nullptr, *o16 = nullptr,
        *h16 = nullptr;
   std::vector<void*> allocs;
 };
@@ -144,14 +144,20 @@ void launch_attn_f32(const Geo& g, int C, int heads, const float* q, const float
 void launch_ln_bf16(const float* x, const int32_t* rows, const int32_t* nrows_dev,
                     int nrows_max, int C, const float* g, const float* b, bf16* y,
                     hipStream_t s);
-void launch_qkv_bf16(const Geo& g, int C, int heads, int Spad, const bf16* u,
-                     const uint8_t* flag, const bf16* w, const float* bias, bf16* q, bf16* k,
-                     bf16* vt, hipStream_t s);
+// LN1 fused into the Q/K/V projection: q [N, C]; k, v [win][head][Spad][dh].
+void launch_ln_qkv_bf16(const Geo& g, int C, int heads, int Spad, const float* x,
+                        const uint8_t* flag, const int32_t* wcount, const float* lng,
+                        const float* lnb, const bf16* w, const float* bias, bf16* q, bf16* k,
+                        bf16* v, hipStream_t s);
+// LN2 fused into the first MLP linear + GELU over the gathered rows x[idx[r]]: h [Nq, R].
+void launch_ln_fc1_bf16(int m_max, int C, int R, const float* x, const int32_t* idx,
+                        const int32_t* nq, const float* lng, const float* lnb, const bf16* w,
+                        const float* bias, bf16* h, hipStream_t s);
 void launch_gemm_bf16(const bf16* A, const int32_t* m_dev, int m_max, int K, const bf16* W,
                       const float* bias, int Nout, int epi, void* out,
                       const int32_t* res_rows, hipStream_t s);
 void launch_attn_bf16(const Geo& g, int C, int heads, int Spad, const bf16* q, const bf16* k,
-                      const bf16* vt, const int32_t* idx, const int32_t* woff, bf16* o,
+                      const bf16* v, const int32_t* idx, const int32_t* woff, bf16* o,
                       hipStream_t s);
 
 // weight preparation

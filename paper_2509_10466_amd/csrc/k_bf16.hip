@@ -201,100 +201,282 @@ void launch_gemm_bf16(const bf16* A, const int32_t* m_dev, int m_max, int K, con
                       const float* bias, int Nout, int epi, void* out, const int32_t* res_rows,
                       hipStream_t s) {
   if (m_max <= 0) return;
+  // 64-row tiles: the gathered row count is often only a few thousand
   if (Nout % 128 == 0) {
-    dim3 grid((m_max + 127) / 128, Nout / 128);
-    gemm_bf16_kernel<128, 128><<<grid, 256, 0, s>>>(A, m_dev, m_max, K, W, bias, Nout, epi, out, res_rows);
+    dim3 grid((m_max + 63) / 64, Nout / 128);
+    gemm_bf16_kernel<64, 128><<<grid, 256, 0, s>>>(A, m_dev, m_max, K, W, bias, Nout, epi, out, res_rows);
   } else {
-    dim3 grid((m_max + 127) / 128, Nout / 64);
-    gemm_bf16_kernel<128, 64><<<grid, 256, 0, s>>>(A, m_dev, m_max, K, W, bias, Nout, epi, out, res_rows);
+    dim3 grid((m_max + 63) / 64, Nout / 64);
+    gemm_bf16_kernel<64, 64><<<grid, 256, 0, s>>>(A, m_dev, m_max, K, W, bias, Nout, epi, out, res_rows);
   }
 }
 
 // ------------------------------------------------------------------------------------------
-// Q/K/V projection over all N tokens: [N, C] x [3C, C]^T.  Column blocks in [0, C) are Q
-// (row-major [N, C]; skipped for row tiles without a flagged token), [C, 2C) are K stored
-// [win][head][Spad][dh], [2C, 3C) are V stored transposed [win][head][dh][Spad].
+// LayerNorm-fused panel GEMM.  Block = 512 threads = 8 waves in 2 (rows) x 4 (columns); block
+// tile 128 rows x BN output columns, wave tile 64 x BN/4.  The prologue normalises the block's
+// 128 rows of the FP32 residual stream (one wavefront per row, FP32 statistics, biased
+// variance, eps 1e-5) straight into a bf16 A panel holding the full K = C in LDS; the weight
+// tile [BN][K] then streams through a two-stage LDS ring, the next stage prefetched into
+// registers while the current one is multiplied.  Rows come from x[rows[r]] (gathered) or
+// x[r]; the first *m_dev (or m_max) rows are valid.
 // ------------------------------------------------------------------------------------------
-template <int BM, int BN>
-__global__ void __launch_bounds__(256) qkv_bf16_kernel(Geo g, int C, int heads, int Spad,
-                                                       const bf16* __restrict__ u, const uint8_t* __restrict__ flag,
-                                                       const bf16* __restrict__ W, const float* __restrict__ bias,
-                                                       bf16* __restrict__ q, bf16* __restrict__ k,
-                                                       bf16* __restrict__ vt) {
-  __shared__ GemmSmem<BM, BN> sm;
-  const int M = g.N;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-  const int part = n0 / C;  // 0 = Q, 1 = K, 2 = V
-  if (part == 0) {
-    int any = 0;
-    for (int r = threadIdx.x; r < BM; r += 256)
-      if (m0 + r < M && flag[m0 + r]) any = 1;
-    if (!__syncthreads_or(any)) return;
-  }
-  const int dh = C / heads;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int wm = wv >> 1, wn = wv & 1;
+constexpr int PANEL_M = 128;
+constexpr int PANEL_THREADS = 512;
+
+template <int BN>
+__host__ __device__ constexpr size_t panel_smem_bytes(int K) {
+  return (size_t)PANEL_M * (K + 8) * 2 + (size_t)2 * BN * LDS_STRIDE * 2;
+}
+
+template <int BN, class Epi>
+__device__ __forceinline__ void panel_gemm(const float* __restrict__ x, const int32_t* __restrict__ rows,
+                                           int M, int m0, int K, const float* __restrict__ lng,
+                                           const float* __restrict__ lnb, const bf16* __restrict__ W, int n0,
+                                           bf16* smem, Epi& epi) {
+  constexpr int FN = BN / 64;              // 16-wide fragments per wave in N
+  constexpr int W_CHUNKS = BN * BK / 8 / PANEL_THREADS;
+  static_assert(FN >= 1 && W_CHUNKS >= 1, "panel tile too small");
+  const int KS = K + 8;                    // A panel row stride (bf16)
+  bf16* apanel = smem;
+  bf16* wst = smem + (size_t)PANEL_M * KS;  // [2][BN][LDS_STRIDE]
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int wm = wv >> 2, wn = wv & 3;
   const int l16 = lane & 15, kg = lane >> 4;
-  f32x4_t acc[BM / 32][BN / 32];
-  if (part < 2) {
-    gemm_tile<BM, BN, true>(u, M, m0, C, W, n0, sm, acc);
+
+  uint4 rw[W_CHUNKS];
+  auto load_w = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < BM / 32; ++i) {
-      const int m = m0 + wm * (BM / 2) + i * 16 + l16;
-      if (m >= M) continue;
-#pragma unroll
-      for (int j = 0; j < BN / 32; ++j) {
-        const int n = n0 + wn * (BN / 2) + j * 16 + kg * 4;
-        const float4 b4 = *reinterpret_cast<const float4*>(bias + n);
-        uint2 pk;
-        pk.x = pack_bf2(acc[i][j][0] + b4.x, acc[i][j][1] + b4.y);
-        pk.y = pack_bf2(acc[i][j][2] + b4.z, acc[i][j][3] + b4.w);
-        bf16* dst;
-        if (part == 0) {
-          dst = q + (size_t)m * C + n;
-        } else {
-          const int c = n - C, hh = c / dh, d = c - hh * dh;
-          const int w = m / g.S, s = m - w * g.S;
-          dst = k + (((size_t)w * heads + hh) * Spad + s) * dh + d;
-        }
-        *reinterpret_cast<uint2*>(dst) = pk;
-      }
+    for (int c = 0; c < W_CHUNKS; ++c) {
+      const int id = t + PANEL_THREADS * c;
+      rw[c] = *reinterpret_cast<const uint4*>(W + (size_t)(n0 + (id >> 3)) * K + k0 + (id & 7) * 8);
     }
-  } else {
-    gemm_tile<BM, BN, false>(u, M, m0, C, W, n0, sm, acc);
+  };
+  auto stash_w = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < BM / 32; ++i) {
-#pragma unroll
-      for (int j = 0; j < BN / 32; ++j) {
-        const int n = n0 + wn * (BN / 2) + j * 16 + l16;
-        const float bn = bias[n];
-        const int c = n - 2 * C, hh = c / dh, d = c - hh * dh;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int m = m0 + wm * (BM / 2) + i * 16 + kg * 4 + e;
-          if (m >= M) continue;
-          const int w = m / g.S, s = m - w * g.S;
-          vt[(((size_t)w * heads + hh) * dh + d) * Spad + s] = f2bf(acc[i][j][e] + bn);
-        }
-      }
+    for (int c = 0; c < W_CHUNKS; ++c) {
+      const int id = t + PANEL_THREADS * c;
+      *reinterpret_cast<uint4*>(wst + ((size_t)buf * BN + (id >> 3)) * LDS_STRIDE + (id & 7) * 8) = rw[c];
     }
+  };
+  load_w(0);
+
+  // LayerNorm prologue: wave wv normalises rows wv, wv + 8, ...
+  const int per = K / 64;
+  for (int r = wv; r < PANEL_M; r += PANEL_THREADS / 64) {
+    const int m = m0 + r;
+    bf16* arow = apanel + (size_t)r * KS;
+    if (m < M) {
+      const float* xr = x + (size_t)(rows ? rows[m] : m) * K;
+      float v[16];
+      float sum = 0.f;
+      for (int e = 0; e < per; ++e) {
+        v[e] = xr[lane + 64 * e];
+        sum += v[e];
+      }
+      const float mean = wave_sum(sum) / K;
+      float sq = 0.f;
+      for (int e = 0; e < per; ++e) {
+        const float d = v[e] - mean;
+        sq += d * d;
+      }
+      const float rstd = rsqrtf(wave_sum(sq) / K + 1e-5f);
+      for (int e = 0; e < per; ++e) {
+        const int c = lane + 64 * e;
+        arow[c] = f2bf((v[e] - mean) * rstd * lng[c] + lnb[c]);
+      }
+    } else {
+      for (int e = 0; e < per; ++e) arow[lane + 64 * e] = 0;
+    }
+  }
+  stash_w(0);
+  __syncthreads();
+
+  f32x4_t acc[4][FN];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+  const int nk = K / BK;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load_w((kt + 1) * BK);
+    const bf16* wb = wst + (size_t)buf * BN * LDS_STRIDE;
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 32) {
+      bf16x8_t af[4], wf[FN];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        af[i] = *reinterpret_cast<const bf16x8_t*>(apanel + (size_t)(wm * 64 + i * 16 + l16) * KS + kt * BK + kk + kg * 8);
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        wf[j] = *reinterpret_cast<const bf16x8_t*>(wb + (size_t)(wn * (BN / 4) + j * 16 + l16) * LDS_STRIDE + kk + kg * 8);
+      mfma_group_begin();
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = mfma16(wf[j], af[i], acc[i][j]);
+      mfma_group_end();
+    }
+    if (kt + 1 < nk) {
+      stash_w(buf ^ 1);
+      __syncthreads();
+    }
+  }
+  // lane holds output channels n .. n+3 of token m
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int m = m0 + wm * 64 + i * 16 + l16;
+    if (m >= M) continue;
+#pragma unroll
+    for (int j = 0; j < FN; ++j) epi(m, n0 + wn * (BN / 4) + j * 16 + kg * 4, acc[i][j]);
   }
 }
 
-void launch_qkv_bf16(const Geo& g, int C, int heads, int Spad, const bf16* u, const uint8_t* flag,
-                     const bf16* w, const float* bias, bf16* q, bf16* k, bf16* vt, hipStream_t s) {
-  if (C % 128 == 0) {
-    dim3 grid((g.N + 127) / 128, 3 * C / 128);
-    qkv_bf16_kernel<128, 128><<<grid, 256, 0, s>>>(g, C, heads, Spad, u, flag, w, bias, q, k, vt);
-  } else {
-    dim3 grid((g.N + 127) / 128, 3 * C / 64);
-    qkv_bf16_kernel<128, 64><<<grid, 256, 0, s>>>(g, C, heads, Spad, u, flag, w, bias, q, k, vt);
+// Q/K/V epilogue: columns [0, C) -> Q rows [N, C]; [C, 2C) -> K, [2C, 3C) -> V, both
+// [win][head][Spad][dh].
+struct QkvEpi {
+  const float* bias;
+  bf16 *q, *k, *v;
+  int C, dh, heads, Spad, S;
+  __device__ __forceinline__ void operator()(int m, int n, const f32x4_t& a) const {
+    const float4 b4 = *reinterpret_cast<const float4*>(bias + n);
+    uint2 pk;
+    pk.x = pack_bf2(a[0] + b4.x, a[1] + b4.y);
+    pk.y = pack_bf2(a[2] + b4.z, a[3] + b4.w);
+    bf16* dst;
+    if (n < C) {
+      dst = q + (size_t)m * C + n;
+    } else {
+      const int part = n < 2 * C ? 1 : 2;
+      const int c = n - part * C, hh = c / dh, d = c - hh * dh;
+      const int w = m / S, s = m - w * S;
+      dst = (part == 1 ? k : v) + (((size_t)w * heads + hh) * Spad + s) * dh + d;
+    }
+    *reinterpret_cast<uint2*>(dst) = pk;
   }
+};
+
+// LN1 + Q/K/V over all N tokens.  Column blocks of Q run only for row tiles holding a
+// flagged token; K/V blocks only for row tiles touching a window that has queries (keys and
+// values of a window without queries are never read).
+template <int BN>
+__global__ void __launch_bounds__(PANEL_THREADS) ln_qkv_kernel(Geo g, int C, int heads, int Spad,
+                                                               const float* __restrict__ x,
+                                                               const uint8_t* __restrict__ flag,
+                                                               const int32_t* __restrict__ wcount,
+                                                               const float* __restrict__ lng,
+                                                               const float* __restrict__ lnb,
+                                                               const bf16* __restrict__ W,
+                                                               const float* __restrict__ bias, bf16* q,
+                                                               bf16* k, bf16* v) {
+  extern __shared__ __align__(16) bf16 smem_panel[];
+  const int M = g.N;
+  const int n0 = blockIdx.x * BN, m0 = blockIdx.y * PANEL_M;
+  const bool is_q = n0 < C;
+  int need = 0;
+  if (threadIdx.x < PANEL_M && m0 + threadIdx.x < M) {
+    const int m = m0 + threadIdx.x;
+    need = is_q ? flag[m] != 0 : wcount[m / g.S] > 0;
+  }
+  if (!__syncthreads_or(need)) return;
+  QkvEpi epi{bias, q, k, v, C, C / heads, heads, Spad, g.S};
+  panel_gemm<BN>(x, nullptr, M, m0, C, lng, lnb, W, n0, smem_panel, epi);
+}
+
+template <class K>
+static void allow_smem(K kernel, size_t bytes) {
+  if (bytes > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)bytes);
+}
+
+template <int BN>
+static void qkv_launch(const Geo& g, int C, int heads, int Spad, const float* x, const uint8_t* flag,
+                       const int32_t* wcount, const float* lng, const float* lnb, const bf16* w,
+                       const float* bias, bf16* q, bf16* k, bf16* v, hipStream_t s) {
+  const size_t smem = panel_smem_bytes<BN>(C);
+  static size_t granted = 0;
+  if (smem > granted) {
+    allow_smem(ln_qkv_kernel<BN>, smem);
+    granted = smem;
+  }
+  dim3 grid(3 * C / BN, (g.N + PANEL_M - 1) / PANEL_M);
+  ln_qkv_kernel<BN><<<grid, PANEL_THREADS, smem, s>>>(g, C, heads, Spad, x, flag, wcount, lng, lnb, w, bias, q, k, v);
+}
+
+void launch_ln_qkv_bf16(const Geo& g, int C, int heads, int Spad, const float* x, const uint8_t* flag,
+                        const int32_t* wcount, const float* lng, const float* lnb, const bf16* w,
+                        const float* bias, bf16* q, bf16* k, bf16* v, hipStream_t s) {
+  if (C % 256 == 0 && panel_smem_bytes<256>(C) <= 160 * 1024)
+    qkv_launch<256>(g, C, heads, Spad, x, flag, wcount, lng, lnb, w, bias, q, k, v, s);
+  else if (C % 128 == 0)
+    qkv_launch<128>(g, C, heads, Spad, x, flag, wcount, lng, lnb, w, bias, q, k, v, s);
+  else
+    qkv_launch<64>(g, C, heads, Spad, x, flag, wcount, lng, lnb, w, bias, q, k, v, s);
+}
+
+// GELU epilogue: h[m, n] = bf16(GELU(acc + b)).
+struct GeluEpi {
+  const float* bias;
+  bf16* h;
+  int R;
+  __device__ __forceinline__ void operator()(int m, int n, const f32x4_t& a) const {
+    const float4 b4 = *reinterpret_cast<const float4*>(bias + n);
+    uint2 pk;
+    pk.x = pack_bf2(gelu_erf(a[0] + b4.x), gelu_erf(a[1] + b4.y));
+    pk.y = pack_bf2(gelu_erf(a[2] + b4.z), gelu_erf(a[3] + b4.w));
+    *reinterpret_cast<uint2*>(h + (size_t)m * R + n) = pk;
+  }
+};
+
+// LN2 + first MLP linear + GELU over the gathered query rows x[idx[r]], r < *nq.
+template <int BN>
+__global__ void __launch_bounds__(PANEL_THREADS) ln_fc1_kernel(int C, int R, const float* __restrict__ x,
+                                                               const int32_t* __restrict__ idx,
+                                                               const int32_t* __restrict__ nq,
+                                                               const float* __restrict__ lng,
+                                                               const float* __restrict__ lnb,
+                                                               const bf16* __restrict__ W,
+                                                               const float* __restrict__ bias, bf16* h) {
+  extern __shared__ __align__(16) bf16 smem_panel[];
+  const int M = nq[0];
+  const int n0 = blockIdx.x * BN, m0 = blockIdx.y * PANEL_M;
+  if (m0 >= M) return;
+  GeluEpi epi{bias, h, R};
+  panel_gemm<BN>(x, idx, M, m0, C, lng, lnb, W, n0, smem_panel, epi);
+}
+
+template <int BN>
+static void fc1_launch(int m_max, int C, int R, const float* x, const int32_t* idx, const int32_t* nq,
+                       const float* lng, const float* lnb, const bf16* w, const float* bias, bf16* h,
+                       hipStream_t s) {
+  const size_t smem = panel_smem_bytes<BN>(C);
+  static size_t granted = 0;
+  if (smem > granted) {
+    allow_smem(ln_fc1_kernel<BN>, smem);
+    granted = smem;
+  }
+  dim3 grid(R / BN, (m_max + PANEL_M - 1) / PANEL_M);
+  ln_fc1_kernel<BN><<<grid, PANEL_THREADS, smem, s>>>(C, R, x, idx, nq, lng, lnb, w, bias, h);
+}
+
+void launch_ln_fc1_bf16(int m_max, int C, int R, const float* x, const int32_t* idx, const int32_t* nq,
+                        const float* lng, const float* lnb, const bf16* w, const float* bias, bf16* h,
+                        hipStream_t s) {
+  if (m_max <= 0) return;
+  if (R % 256 == 0 && panel_smem_bytes<256>(C) <= 160 * 1024)
+    fc1_launch<256>(m_max, C, R, x, idx, nq, lng, lnb, w, bias, h, s);
+  else if (R % 128 == 0)
+    fc1_launch<128>(m_max, C, R, x, idx, nq, lng, lnb, w, bias, h, s);
+  else
+    fc1_launch<64>(m_max, C, R, x, idx, nq, lng, lnb, w, bias, h, s);
 }
 
 // ------------------------------------------------------------------------------------------
-// Window attention on MFMA.  Block = 4 waves = 64 queries of one (window, head); K and V^T of
-// the window/head are staged in LDS once.  Each wave: 16 queries.
+// Window attention on MFMA.  Block = 4 waves = 64 queries of one (window, head); K and V of
+// the window/head ([Spad][dh] each in global memory) are staged in LDS once, V transposed to
+// V^T [dh][keys] on the way in.  Each wave: 16 queries.
 //   S^T tile (16 keys x 16 queries) = K_tile (16 x dh) . Q^T  -> lane l holds the scores of
 //   query l%16 for keys 16t + 4*(l/16) + i.  Softmax statistics stay FP32: max/sum over
 //   registers, then across the 4 lane groups with two xor shuffles.
@@ -303,12 +485,13 @@ void launch_qkv_bf16(const Geo& g, int C, int heads, int Spad, const bf16* u, co
 // ------------------------------------------------------------------------------------------
 template <int DH, int NT>
 __global__ void __launch_bounds__(256) attn_bf16_kernel(Geo g, int C, int heads, const bf16* __restrict__ q,
-                                                        const bf16* __restrict__ kmat, const bf16* __restrict__ vt,
+                                                        const bf16* __restrict__ kmat, const bf16* __restrict__ vmat,
                                                         const int32_t* __restrict__ idx,
                                                         const int32_t* __restrict__ woff, bf16* __restrict__ o) {
   constexpr int SP = NT * 16;           // padded window length
   constexpr int KST = DH + 8;           // LDS row stride of K (bf16)
-  constexpr int VST = SP + 8;           // LDS row stride of V^T
+  constexpr int VST = SP + 4;           // LDS row stride of V^T (122 dwords per 240 keys: rows
+                                        // spread over distinct bank pairs, 8-byte aligned)
   __shared__ bf16 Ks[SP * KST];
   __shared__ bf16 Vs[DH * VST];
   const int w = blockIdx.x / heads, h = blockIdx.x - w * heads;
@@ -320,14 +503,20 @@ __global__ void __launch_bounds__(256) attn_bf16_kernel(Geo g, int C, int heads,
 
   // stage K [SP][DH] and V^T [DH][SP] of (w, h)
   const bf16* kg_ = kmat + ((size_t)w * heads + h) * SP * DH;
-  const bf16* vg_ = vt + ((size_t)w * heads + h) * DH * SP;
+  const bf16* vg_ = vmat + ((size_t)w * heads + h) * SP * DH;
   for (int c = t; c < SP * DH / 8; c += 256) {
     const int row = c / (DH / 8), col = (c % (DH / 8)) * 8;
     *reinterpret_cast<uint4*>(&Ks[row * KST + col]) = *reinterpret_cast<const uint4*>(kg_ + row * DH + col);
   }
-  for (int c = t; c < DH * SP / 8; c += 256) {
-    const int row = c / (SP / 8), col = (c % (SP / 8)) * 8;
-    *reinterpret_cast<uint4*>(&Vs[row * VST + col]) = *reinterpret_cast<const uint4*>(vg_ + row * SP + col);
+  for (int c = t; c < SP * DH / 8; c += 256) {
+    const int key = c / (DH / 8), d0 = (c % (DH / 8)) * 8;
+    const uint4 v = *reinterpret_cast<const uint4*>(vg_ + key * DH + d0);
+    const uint32_t wds[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      Vs[(d0 + 2 * e) * VST + key] = (bf16)(wds[e] & 0xffffu);
+      Vs[(d0 + 2 * e + 1) * VST + key] = (bf16)(wds[e] >> 16);
+    }
   }
   __syncthreads();
 

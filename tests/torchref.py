@@ -16,6 +16,15 @@ def _t(a):
 
 
 def reference_forward(frames, masks, W, cfg, query_set="masked"):
+    """(out, pred, flags) as numpy arrays; W holds numpy arrays."""
+    Wt = {k: _t(v) for k, v in W.items()}
+    out, pred, flags = reference_forward_t(frames, masks, Wt, cfg, query_set)
+    return out.detach().numpy(), pred.detach().numpy(), flags.numpy()
+
+
+def reference_forward_t(frames, masks, params, cfg, query_set="masked"):
+    """Same as reference_forward on torch FP64 parameter tensors (autograd-ready)."""
+    W = params
     fr = _t(frames)
     m = torch.from_numpy(np.asarray(masks) != 0)
     B, T, H, Wd, _ = fr.shape
@@ -24,7 +33,7 @@ def reference_forward(frames, masks, W, cfg, query_set="masked"):
     dh = C // heads
     xc = fr.masked_fill(m[..., None], 0.0)
     img = xc.reshape(B * T, H, Wd, 3).permute(0, 3, 1, 2)
-    x = F.conv2d(img, _t(W["embed.w"]), _t(W["embed.b"]), stride=p)  # [BT, C, Ht, Wt]
+    x = F.conv2d(img, W["embed.w"], W["embed.b"], stride=p)  # [BT, C, Ht, Wt]
     x = x.permute(0, 2, 3, 1).reshape(B, T * Ht * Wt, C)
     flags = F.max_pool2d(m.reshape(B * T, 1, H, Wd).double(), p).reshape(B, T * Ht * Wt) > 0
     upd = flags if query_set == "masked" else torch.ones_like(flags)
@@ -38,7 +47,7 @@ def reference_forward(frames, masks, W, cfg, query_set="masked"):
         return z.reshape(B, -1, heads, dh).transpose(1, 2)
 
     for l in range(cfg.blocks):
-        g = lambda n: _t(W[f"blk{l}.{n}"])  # noqa: E731
+        g = lambda n: W[f"blk{l}.{n}"]  # noqa: E731
         u = F.layer_norm(x, (C,), g("ln1.g"), g("ln1.b"), eps=1e-5)
         q = F.linear(u, g("wq"), g("bq"))
         k = F.linear(u, g("wk"), g("bk"))
@@ -50,9 +59,9 @@ def reference_forward(frames, masks, W, cfg, query_set="masked"):
         x2 = x1 + F.linear(hdn, g("w2"), g("b2"))
         x = torch.where(upd[..., None], x2, x)
 
-    z = F.layer_norm(x, (C,), _t(W["lnf.g"]), _t(W["lnf.b"]), eps=1e-5)
+    z = F.layer_norm(x, (C,), W["lnf.g"], W["lnf.b"], eps=1e-5)
     z = z.reshape(B * T, Ht, Wt, C).permute(0, 3, 1, 2)
-    pred = torch.sigmoid(F.conv_transpose2d(z, _t(W["dec.w"]), _t(W["dec.b"]), stride=p))
+    pred = torch.sigmoid(F.conv_transpose2d(z, W["dec.w"], W["dec.b"], stride=p))
     pred = pred.permute(0, 2, 3, 1).reshape(B, T, H, Wd, 3)
     out = torch.where(m[..., None], pred, fr)
-    return out.numpy(), pred.numpy(), flags.reshape(B, T, Ht, Wt).numpy()
+    return out, pred, flags.reshape(B, T, Ht, Wt)
