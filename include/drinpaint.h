@@ -51,8 +51,11 @@ typedef enum {
 } dr_status;
 
 /* Arithmetic of the attention/MLP GEMMs.  DR_FP32: plain FP32 kernels, one per operation.
- * DR_BF16: BF16 operands on MFMA with FP32 accumulation.  LayerNorm statistics, softmax
- * max/sum, the residual stream, patch embedding and decoder stay FP32 in every mode. */
+ * DR_BF16: BF16 operands on MFMA with FP32 accumulation.  DR_FP8: the Q/K/V, projection and
+ * MLP GEMMs take OCP e4m3 operands with per-tensor scales (amax/448; weights fixed at load,
+ * activations from the current call) and FP32 accumulation, attention stays BF16; needs dim
+ * and hidden width multiples of 128.  LayerNorm statistics, softmax max/sum, the residual
+ * stream, patch embedding and decoder stay FP32 in every mode. */
 typedef enum { DR_FP32 = 0, DR_BF16 = 1, DR_FP8 = 2 } dr_precision;
 
 /* Which tokens are attention queries and get updated.  DR_QUERY_MASKED: tokens whose patch
@@ -133,6 +136,55 @@ dr_status dr_inspect(dr_ctx* ctx, const char* name, void* dst, size_t nbytes, vo
 /* Inspection, for tests: key "blocks" = number of transformer blocks later dr_inpaint calls
  * run (-1 = all); the output then is not the network's. */
 dr_status dr_debug_set(dr_ctx* ctx, const char* key, int64_t value);
+
+/* Test hook of the FP8 path's quantiser: out[i] = e4m3(in[i] / scale) (OCP e4m3, round to
+ * nearest even, clamped to +-448), device pointers, n elements. */
+dr_status dr_fp8_encode(dr_ctx* ctx, const float* in, uint8_t* out, size_t n, float scale,
+                        void* stream);
+
+/* ---- Stream mode (one new frame per call, per-stream memory of past frames) -------------
+ * Each stream keeps, per transformer block, the keys/values of its last win_t - 1 frames on
+ * the device (the thesis's memory tensors kept from previous outputs, Methods, "Inpainting
+ * Manager"); a new frame's flagged tokens attend to their spatial window (win_h x win_w
+ * tokens) in those frames and in the new frame, then the new frame's K/V replace the oldest.
+ * The first frames of a stream use the frames available.  BF16 only. */
+
+/* Footprint budget in bytes for all open streams' caches (0 = unlimited, the default). */
+dr_status dr_set_budget(dr_ctx* ctx, size_t bytes);
+/* Device bytes a stream of H x W frames holds while open. */
+size_t dr_stream_footprint(dr_ctx* ctx, int H, int W);
+/* Open a stream of H x W frames (H, W multiples of the window's pixel size); *sid receives
+ * its id.  DR_ENOMEM if its footprint does not fit the budget (admit it later). */
+dr_status dr_stream_open(dr_ctx* ctx, int H, int W, int32_t* sid);
+/* Close a stream (waits for the device) and release its memory. */
+dr_status dr_stream_close(dr_ctx* ctx, int32_t sid);
+/* Inpaint the newest frame of n (1..16) distinct streams of one resolution in one batch.
+ * sids: host array; frames, masks, outs: host arrays of device pointers to f32 [H,W,3],
+ * u8 [H,W], f32 [H,W,3] (out must not overlap frame or mask).  Asynchronous on `stream`;
+ * prec must be DR_BF16.  A stream must not appear in two overlapping calls. */
+dr_status dr_stream_step(dr_ctx* ctx, int n, const int32_t* sids, const float* const* frames,
+                         const uint8_t* const* masks, float* const* outs, dr_precision prec,
+                         dr_query_set qs, void* stream);
+
+/* ---- Serving loop ---------------------------------------------------------------------
+ * A persistent native thread that batches submitted requests continuously: per resolution
+ * class it launches the oldest pending requests (at most one per stream, up to max_batch)
+ * whenever that class's executor (own workspace and HIP stream) is idle, so classes overlap
+ * on the device and new requests join as soon as their class frees up.  Latency of a request
+ * = completion (event observed by the loop) - submission. */
+typedef struct dr_server dr_server;
+dr_status dr_server_create(dr_ctx* ctx, int max_batch, dr_server** out);
+/* Queue one frame of an open stream; device buffers must stay valid until it completes. */
+dr_status dr_server_submit(dr_server* srv, int32_t sid, const float* frame,
+                           const uint8_t* mask, float* out, uint64_t* ticket);
+/* Move up to `max` completed requests into host arrays (status may be NULL; a nonzero status
+ * is the dr_status of a failed batch, latency -1).  *n_done receives the count. */
+dr_status dr_server_poll(dr_server* srv, uint64_t* tickets, double* latency_ms,
+                         int32_t* status, int max, int* n_done);
+/* Batches launched, requests launched, requests still pending (any pointer may be NULL). */
+dr_status dr_server_stats(dr_server* srv, int64_t* batches, int64_t* requests, int* pending);
+/* Finish all queued work, stop the thread and free the executors. */
+void dr_server_destroy(dr_server* srv);
 
 /* Message of the last failed call on `ctx` ("" if none).  ctx may be NULL (then the
  * message of the last failed dr_create). */

@@ -58,6 +58,17 @@ def load():
         "dr_stage_name": (ct.c_char_p, [I]),
         "dr_inspect": (I, [P, ct.c_char_p, P, Z, P]),
         "dr_debug_set": (I, [P, ct.c_char_p, ct.c_int64]),
+        "dr_fp8_encode": (I, [P, P, P, Z, ct.c_float, P]),
+        "dr_set_budget": (I, [P, Z]),
+        "dr_stream_footprint": (Z, [P, I, I]),
+        "dr_stream_open": (I, [P, I, I, ct.POINTER(ct.c_int32)]),
+        "dr_stream_close": (I, [P, ct.c_int32]),
+        "dr_stream_step": (I, [P, I, P, P, P, P, I, I, P]),
+        "dr_server_create": (I, [P, I, ct.POINTER(P)]),
+        "dr_server_submit": (I, [P, ct.c_int32, P, P, P, ct.POINTER(ct.c_uint64)]),
+        "dr_server_poll": (I, [P, P, P, P, I, ct.POINTER(I)]),
+        "dr_server_stats": (I, [P, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64), ct.POINTER(I)]),
+        "dr_server_destroy": (None, [P]),
         "dr_last_error": (ct.c_char_p, [P]),
         "dr_destroy": (None, [P]),
     }

@@ -95,6 +95,15 @@ class Inpainter:
         _lib.check(self.lib, self._ctx, st)
         return dst
 
+    def fp8_encode(self, values: torch.Tensor, scale: float, stream=None) -> torch.Tensor:
+        """e4m3 codes (uint8) of values / scale, as the FP8 path quantises."""
+        if not values.is_cuda or values.dtype != torch.float32 or not values.is_contiguous():
+            raise ValueError("values must be a contiguous float32 device tensor")
+        out = torch.empty(values.shape, dtype=torch.uint8, device=values.device)
+        st = self.lib.dr_fp8_encode(self._ctx, _ptr(values), _ptr(out), values.numel(), scale, _stream(stream))
+        _lib.check(self.lib, self._ctx, st)
+        return out
+
     def debug_set(self, key: str, value: int):
         _lib.check(self.lib, self._ctx, self.lib.dr_debug_set(self._ctx, key.encode(), value))
 
@@ -109,6 +118,42 @@ class Inpainter:
         cnt = (ct.c_int64 * n)()
         _lib.check(self.lib, self._ctx, self.lib.dr_profile_read(self._ctx, ms, cnt, n))
         return {self.stages[i]: (ms[i], cnt[i]) for i in range(n) if cnt[i]}
+
+    # ---- stream mode ------------------------------------------------------------------
+    def set_budget(self, nbytes: int):
+        _lib.check(self.lib, self._ctx, self.lib.dr_set_budget(self._ctx, int(nbytes)))
+
+    def stream_footprint(self, H: int, W: int) -> int:
+        return int(self.lib.dr_stream_footprint(self._ctx, H, W))
+
+    def stream_open(self, H: int, W: int) -> int:
+        sid = ct.c_int32()
+        _lib.check(self.lib, self._ctx, self.lib.dr_stream_open(self._ctx, H, W, ct.byref(sid)))
+        return sid.value
+
+    def stream_close(self, sid: int):
+        _lib.check(self.lib, self._ctx, self.lib.dr_stream_close(self._ctx, sid))
+
+    def stream_step(self, sids, frames, masks, outs=None, query_set: str = "masked", stream=None):
+        """Inpaint the newest frame [H,W,3] of each stream in ``sids`` (one batch)."""
+        n = len(sids)
+        if not (len(frames) == len(masks) == n):
+            raise ValueError("one frame and one mask per stream")
+        for f, m in zip(frames, masks):
+            if not (f.is_cuda and m.is_cuda and f.dtype == torch.float32 and m.dtype == torch.uint8
+                    and f.is_contiguous() and m.is_contiguous() and f.dim() == 3 and f.shape[-1] == 3
+                    and m.shape == f.shape[:-1]):
+                raise ValueError("frames must be contiguous f32 [H,W,3] and masks u8 [H,W] device tensors")
+        if outs is None:
+            outs = [torch.empty_like(f) for f in frames]
+        sid_arr = (ct.c_int32 * n)(*sids)
+        fp = (ct.c_void_p * n)(*[f.data_ptr() for f in frames])
+        mp = (ct.c_void_p * n)(*[m.data_ptr() for m in masks])
+        op = (ct.c_void_p * n)(*[o.data_ptr() for o in outs])
+        st = self.lib.dr_stream_step(self._ctx, n, sid_arr, fp, mp, op, _lib.PRECISION["bf16"],
+                                     _lib.QUERY_SET[query_set], _stream(stream))
+        _lib.check(self.lib, self._ctx, st)
+        return outs
 
     def close(self):
         if self._ctx:
@@ -131,3 +176,44 @@ def inpaint(frames, masks, weights, cfg, precision: str = "bf16", query_set: str
         return out
     finally:
         eng.close()
+
+
+class Server:
+    """The library's native serving loop on one Inpainter context."""
+
+    def __init__(self, eng: Inpainter, max_batch: int = 16):
+        self.eng = eng
+        self.lib = eng.lib
+        self._srv = ct.c_void_p()
+        _lib.check(self.lib, eng._ctx, self.lib.dr_server_create(eng._ctx, max_batch, ct.byref(self._srv)))
+
+    def submit(self, sid: int, frame: torch.Tensor, mask: torch.Tensor, out: torch.Tensor) -> int:
+        t = ct.c_uint64()
+        st = self.lib.dr_server_submit(self._srv, sid, _ptr(frame), _ptr(mask), _ptr(out), ct.byref(t))
+        _lib.check(self.lib, self.eng._ctx, st)
+        return t.value
+
+    def poll(self, max_n: int = 4096):
+        """[(ticket, latency_ms, status)] of requests completed since the last poll."""
+        tk = (ct.c_uint64 * max_n)()
+        lat = (ct.c_double * max_n)()
+        sts = (ct.c_int32 * max_n)()
+        n = ct.c_int()
+        _lib.check(self.lib, self.eng._ctx, self.lib.dr_server_poll(self._srv, tk, lat, sts, max_n, ct.byref(n)))
+        return [(tk[i], lat[i], sts[i]) for i in range(n.value)]
+
+    def stats(self):
+        b, r, p = ct.c_int64(), ct.c_int64(), ct.c_int()
+        _lib.check(self.lib, self.eng._ctx, self.lib.dr_server_stats(self._srv, ct.byref(b), ct.byref(r), ct.byref(p)))
+        return {"batches": b.value, "requests": r.value, "pending": p.value}
+
+    def close(self):
+        if self._srv:
+            self.lib.dr_server_destroy(self._srv)
+            self._srv = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,5 +1,7 @@
 // Host side of the C ABI: context, weight blob loading, workspace, and the launch sequence
 // of the inpainting forward (see include/drinpaint.h for the contract of every call).
+#include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -12,21 +14,40 @@ namespace dr {
 bool attn_bf16_supported(int dh, int spad);
 }
 
+static float host_amax(const float* p, size_t n) {
+  float m = 0.f;
+  for (size_t i = 0; i < n; ++i) m = std::max(m, std::fabs(p[i]));
+  return m;
+}
+
 using namespace dr;
 
 static std::string g_create_err;
 
-static dr_status fail(dr_ctx* c, dr_status st, const char* fmt, ...) {
+static dr_status vfail(dr_ctx* c, dr_status st, const char* fmt, va_list ap) {
   char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
   vsnprintf(buf, sizeof buf, fmt, ap);
-  va_end(ap);
   if (c)
     c->err = buf;
   else
     g_create_err = buf;
   return st;
+}
+
+static dr_status fail(dr_ctx* c, dr_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  dr_status r = vfail(c, st, fmt, ap);
+  va_end(ap);
+  return r;
+}
+
+dr_status dr::dr_fail(dr_ctx* c, dr_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  dr_status r = vfail(c, st, fmt, ap);
+  va_end(ap);
+  return r;
 }
 
 #define HIP_OK(ctx, expr)                                                              \
@@ -36,7 +57,7 @@ static dr_status fail(dr_ctx* c, dr_status st, const char* fmt, ...) {
       return fail(ctx, DR_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));        \
   } while (0)
 
-static const char* kStageNames[ST_COUNT] = {"tokens", "embed", "ln1",  "qkv",    "attn", "proj",
+const char* const dr::kStageNames[ST_COUNT] = {"tokens", "embed", "ln1",  "qkv",    "attn", "proj",
                                             "ln2",    "fc1",   "fc2",  "mlp",    "decode", "copy"};
 
 // ------------------------------------------------------------------------------------------
@@ -65,7 +86,7 @@ static hipError_t dmalloc(dr_ctx* c, void** p, size_t n, std::vector<void*>& lis
 }
 
 // profiling brackets
-static void prof_begin(dr_ctx* c, int stage, hipStream_t s, hipEvent_t* a, hipEvent_t* b) {
+void dr::dr_prof_begin(dr_ctx* c, hipStream_t s, hipEvent_t* a, hipEvent_t* b) {
   *a = *b = nullptr;
   if (!c->prof) return;
   for (hipEvent_t* e : {a, b}) {
@@ -77,10 +98,9 @@ static void prof_begin(dr_ctx* c, int stage, hipStream_t s, hipEvent_t* a, hipEv
     }
   }
   hipEventRecord(*a, s);
-  (void)stage;
 }
 
-static void prof_end(dr_ctx* c, int stage, hipStream_t s, hipEvent_t a, hipEvent_t b) {
+void dr::dr_prof_end(dr_ctx* c, int stage, hipStream_t s, hipEvent_t a, hipEvent_t b) {
   if (!c->prof || !a) return;
   hipEventRecord(b, s);
   c->recs.push_back({stage, a, b});
@@ -120,16 +140,26 @@ extern "C" dr_status dr_create(dr_ctx** out, int device, const dr_netcfg* cfg) {
   return DR_OK;
 }
 
-static void free_work(dr_ctx* c) {
-  for (void* p : c->work.allocs) hipFree(p);
-  c->work = Work();
+void dr::dr_free_work(Work& w) {
+  for (void* p : w.allocs) hipFree(p);
+  w = Work();
 }
+
+static void free_work(dr_ctx* c) { dr_free_work(c->work); }
 
 extern "C" void dr_destroy(dr_ctx* c) {
   if (!c) return;
   hipSetDevice(c->device);
   hipDeviceSynchronize();
   free_work(c);
+  for (auto& kv : c->swork) {
+    dr_free_work(*kv.second);
+    delete kv.second;
+  }
+  for (auto& kv : c->streams) {
+    hipFree(kv.second.kc);
+    hipFree(kv.second.vc);
+  }
   for (void* p : c->weight_allocs) hipFree(p);
   for (auto& r : c->recs) {
     hipEventDestroy(r.a);
@@ -336,6 +366,44 @@ extern "C" dr_status dr_load_weights(dr_ctx* c, const void* blob, size_t nbytes)
   nn.lnfb = F + o_lnfb;
   nn.dec_w = F + o_dw;
   nn.dec_b = F + o_db;
+
+  // FP8 e4m3 copies of the GEMM weights, one scale per tensor (amax / 448)
+  if (fp8_supported(C, R)) {
+    const size_t per_blk = 3 * CC + CC + RC + RC;
+    void *d8 = nullptr, *dsc = nullptr;
+    if (dmalloc(c, &d8, per_blk * L, c->weight_allocs) != hipSuccess ||
+        dmalloc(c, &dsc, (size_t)L * 8 * 4, c->weight_allocs) != hipSuccess)
+      return fail(c, DR_ENOMEM, "weights: device allocation failed");
+    std::vector<float> sc((size_t)L * 8, 1.f);
+    uint8_t* q8 = (uint8_t*)d8;
+    for (int l = 0; l < L; ++l) {
+      const float* const* sp = &src[2 + 16 * l];
+      BlockW& w = nn.blk[l];
+      uint8_t* base = q8 + per_blk * l;
+      const float* dev[6] = {w.wq, w.wk, w.wv, w.wo, w.w1, w.w2};
+      const float* hst[6] = {sp[2], sp[4], sp[6], sp[8], sp[12], sp[14]};
+      const size_t nel[6] = {CC, CC, CC, CC, RC, RC};
+      size_t off = 0;
+      for (int k = 0; k < 6; ++k) {
+        const float am = host_amax(hst[k], nel[k]);
+        const float s8 = am > 0.f ? am / 448.0f : 1.0f;
+        sc[(size_t)l * 8 + k] = s8;
+        launch_quantize_fp8(dev[k], base + off, nel[k], 1.0f / s8, nullptr);
+        off += nel[k];
+      }
+      w.wqkv8 = base;
+      w.wo8 = base + 3 * CC;
+      w.w18 = base + 4 * CC;
+      w.w28 = base + 4 * CC + RC;
+      w.wscale8 = (const float*)dsc + (size_t)l * 8;
+      w.so8 = sc[(size_t)l * 8 + 3];
+      w.s18 = sc[(size_t)l * 8 + 4];
+      w.s28 = sc[(size_t)l * 8 + 5];
+    }
+    HIP_OK(c, hipGetLastError());
+    HIP_OK(c, hipMemcpy(dsc, sc.data(), sc.size() * 4, hipMemcpyHostToDevice));
+    HIP_OK(c, hipDeviceSynchronize());
+  }
   c->have_weights = true;
   return DR_OK;
 }
@@ -343,18 +411,18 @@ extern "C" dr_status dr_load_weights(dr_ctx* c, const void* blob, size_t nbytes)
 // ------------------------------------------------------------------------------------------
 // shapes and workspace
 // ------------------------------------------------------------------------------------------
-static dr_status make_geo(dr_ctx* c, int B, int T, int H, int W, Geo& g) {
+dr_status dr::dr_make_geo(dr_ctx* c, int B, int T, int H, int W, int wt, Geo& g) {
   const dr_netcfg& k = c->net.cfg;
   if (B <= 0 || T <= 0 || H <= 0 || W <= 0) return fail(c, DR_ESHAPE, "empty or negative shape");
-  if (T != k.win_t) return fail(c, DR_ESHAPE, "T=%d must equal the window length %d", T, k.win_t);
+  if (T != wt) return fail(c, DR_ESHAPE, "T=%d must equal the window length %d", T, wt);
   if (H % (k.patch * k.win_h) || W % (k.patch * k.win_w))
     return fail(c, DR_ESHAPE, "H=%d, W=%d must be multiples of %d and %d", H, W, k.patch * k.win_h,
                 k.patch * k.win_w);
   g.B = B; g.T = T; g.H = H; g.W = W; g.P = k.patch;
   g.Ht = H / k.patch; g.Wt = W / k.patch;
-  g.wt = k.win_t; g.wh = k.win_h; g.ww = k.win_w;
+  g.wt = wt; g.wh = k.win_h; g.ww = k.win_w;
   g.nwh = g.Ht / k.win_h; g.nww = g.Wt / k.win_w;
-  g.S = c->net.S;
+  g.S = wt * k.win_h * k.win_w;
   const long long N = (long long)B * T * g.Ht * g.Wt;
   if (N > (1LL << 30)) return fail(c, DR_ESHAPE, "too many tokens");
   g.N = (int)N;
@@ -362,12 +430,15 @@ static dr_status make_geo(dr_ctx* c, int B, int T, int H, int W, Geo& g) {
   return DR_OK;
 }
 
-static dr_status reserve_geo(dr_ctx* c, const Geo& g) {
-  Work& w = c->work;
-  if ((size_t)g.N <= w.cap_tokens && (size_t)g.nwin <= w.cap_windows) return DR_OK;
+static dr_status make_geo(dr_ctx* c, int B, int T, int H, int W, Geo& g) {
+  return dr_make_geo(c, B, T, H, W, c->net.cfg.win_t, g);
+}
+
+dr_status dr::dr_reserve_work(dr_ctx* c, Work& w, const Geo& g, bool stream_mode) {
+  if ((size_t)g.N <= w.cap_tokens && (size_t)g.nwin <= w.cap_windows && w.stream_mode == stream_mode) return DR_OK;
   HIP_OK(c, hipSetDevice(c->device));
   HIP_OK(c, hipDeviceSynchronize());
-  free_work(c);
+  dr_free_work(w);
   const Net& n = c->net;
   const size_t N = g.N, C = n.C, R = n.R, nw = g.nwin;
   const size_t kvlen = nw * n.cfg.heads * (size_t)n.Spad * n.dh;
@@ -375,7 +446,7 @@ static dr_status reserve_geo(dr_ctx* c, const Geo& g) {
 #define ALLOC(field, bytes)                                                        \
   do {                                                                             \
     if (dmalloc(c, &p, (bytes), w.allocs) != hipSuccess) {                          \
-      free_work(c);                                                                \
+      dr_free_work(w);                                                             \
       return fail(c, DR_ENOMEM, "workspace: cannot allocate %zu bytes", (size_t)(bytes)); \
     }                                                                              \
     w.field = (decltype(w.field))p;                                                \
@@ -386,30 +457,41 @@ static dr_status reserve_geo(dr_ctx* c, const Geo& g) {
   ALLOC(idx, N * 4);
   ALLOC(nq, 256);
   ALLOC(x, N * C * 4);
-  ALLOC(u, N * C * 4);
-  ALLOC(kv, N * 2 * C * 4);
-  ALLOC(q, N * C * 4);
-  ALLOC(o, N * C * 4);
-  ALLOC(h, N * R * 4);
-  ALLOC(u16, N * C * 2);
   ALLOC(q16, N * C * 2);
-  ALLOC(k16, kvlen * 2);
-  ALLOC(v16, kvlen * 2);
   ALLOC(o16, N * C * 2);
   ALLOC(h16, N * R * 2);
+  ALLOC(amax, (size_t)n.cfg.blocks * 4 * 4);
+  if (stream_mode) {
+    const size_t npix = N * 16;  // 4 x 4 pixels per token
+    ALLOC(fst, npix * 12);
+    ALLOC(mst, npix);
+    ALLOC(ost, npix * 12);
+  } else {
+    ALLOC(u, N * C * 4);
+    ALLOC(kv, N * 2 * C * 4);
+    ALLOC(q, N * C * 4);
+    ALLOC(o, N * C * 4);
+    ALLOC(h, N * R * 4);
+    ALLOC(u16, N * C * 2);
+    ALLOC(k16, kvlen * 2);
+    ALLOC(v16, kvlen * 2);
+    // padded key rows of K and V must read as zero
+    HIP_OK(c, hipMemset(w.k16, 0, kvlen * 2));
+    HIP_OK(c, hipMemset(w.v16, 0, kvlen * 2));
+  }
 #undef ALLOC
-  // padded key rows / columns of K and V^T must read as zero
-  HIP_OK(c, hipMemset(w.k16, 0, kvlen * 2));
-  HIP_OK(c, hipMemset(w.v16, 0, kvlen * 2));
   HIP_OK(c, hipDeviceSynchronize());
   w.cap_tokens = N;
   w.cap_windows = nw;
+  w.stream_mode = stream_mode;
   return DR_OK;
 }
 
+static dr_status reserve_geo(dr_ctx* c, const Geo& g) { return dr_reserve_work(c, c->work, g, false); }
+
 extern "C" dr_status dr_reserve(dr_ctx* c, int B, int T, int H, int W, dr_precision prec) {
   if (!c) return DR_EINVAL;
-  if (prec != DR_FP32 && prec != DR_BF16) return fail(c, DR_EINVAL, "unsupported precision %d", (int)prec);
+  if (prec != DR_FP32 && prec != DR_BF16 && prec != DR_FP8) return fail(c, DR_EINVAL, "unsupported precision %d", (int)prec);
   Geo g;
   dr_status st = make_geo(c, B, T, H, W, g);
   if (st != DR_OK) return st;
@@ -422,12 +504,12 @@ extern "C" dr_status dr_reserve(dr_ctx* c, int B, int T, int H, int W, dr_precis
 #define LAUNCH(stage, call)                                                     \
   do {                                                                          \
     hipEvent_t ea_, eb_;                                                        \
-    prof_begin(c, stage, s, &ea_, &eb_);                                        \
+    dr_prof_begin(c, s, &ea_, &eb_);                                            \
     call;                                                                       \
     hipError_t e_ = hipGetLastError();                                          \
     if (e_ != hipSuccess)                                                       \
       return fail(c, DR_EHIP, "launch of %s failed: %s", kStageNames[stage], hipGetErrorString(e_)); \
-    prof_end(c, stage, s, ea_, eb_);                                            \
+    dr_prof_end(c, stage, s, ea_, eb_);                                         \
   } while (0)
 
 static dr_status run_tokens(dr_ctx* c, const Geo& g, const uint8_t* masks, int all, hipStream_t s) {
@@ -461,14 +543,16 @@ extern "C" dr_status dr_inpaint(dr_ctx* c, const float* frames, const uint8_t* m
   if (!c) return DR_EINVAL;
   if (!frames || !masks || !out) return fail(c, DR_EINVAL, "dr_inpaint: null pointer");
   if (!c->have_weights) return fail(c, DR_EINVAL, "dr_inpaint: no weights loaded");
-  if (prec != DR_FP32 && prec != DR_BF16) return fail(c, DR_EINVAL, "unsupported precision %d", (int)prec);
+  if (prec != DR_FP32 && prec != DR_BF16 && prec != DR_FP8) return fail(c, DR_EINVAL, "unsupported precision %d", (int)prec);
   if (qs != DR_QUERY_MASKED && qs != DR_QUERY_ALL) return fail(c, DR_EINVAL, "bad query set");
   Geo g;
   dr_status st = make_geo(c, B, T, H, W, g);
   if (st != DR_OK) return st;
   const Net& n = c->net;
-  if (prec == DR_BF16 && !attn_bf16_supported(n.dh, n.Spad))
+  if (prec != DR_FP32 && !attn_bf16_supported(n.dh, n.Spad))
     return fail(c, DR_ESHAPE, "BF16 attention has no kernel for %d-token windows", n.S);
+  if (prec == DR_FP8 && !fp8_supported(n.C, n.R))
+    return fail(c, DR_ESHAPE, "the FP8 path needs dim and hidden width multiples of 128");
   const size_t npix = (size_t)B * T * H * W;
   if (out != frames && ranges_overlap(out, npix * 12, frames, npix * 12))
     return fail(c, DR_EINVAL, "out partially overlaps frames");
@@ -482,6 +566,7 @@ extern "C" dr_status dr_inpaint(dr_ctx* c, const float* frames, const uint8_t* m
   st = run_tokens(c, g, masks, qs == DR_QUERY_ALL, s);
   if (st != DR_OK) return st;
   LAUNCH(ST_EMBED, launch_embed(g, C, frames, masks, n.embed_wT, n.embed_b, w.x, s));
+  if (prec == DR_FP8) LAUNCH(ST_LN1, launch_zero_f32(w.amax, 4 * n.cfg.blocks, s));
   const int nblk = (c->debug_blocks >= 0 && c->debug_blocks < n.cfg.blocks) ? c->debug_blocks : n.cfg.blocks;
   for (int l = 0; l < nblk; ++l) {
     const BlockW& b = n.blk[l];
@@ -494,9 +579,18 @@ extern "C" dr_status dr_inpaint(dr_ctx* c, const float* frames, const uint8_t* m
       LAUNCH(ST_LN2, launch_ln_f32(w.x, w.idx, w.nq, N, C, b.ln2g, b.ln2b, w.u, s));
       LAUNCH(ST_FC1, launch_gemm_f32(w.u, nullptr, w.nq, N, C, b.w1, b.b1, R, EPI_GELU, w.h, nullptr, s));
       LAUNCH(ST_FC2, launch_gemm_f32(w.h, nullptr, w.nq, N, R, b.w2, b.b2, C, EPI_RESID, w.x, w.idx, s));
+    } else if (prec == DR_FP8) {
+      float* am = w.amax + 4 * l;  // [0] LN1 out, [1] O, [2] LN2 out, [3] h
+      LAUNCH(ST_LN1, launch_ln_amax(w.x, nullptr, nullptr, N, w.wcount, g.S, C, b.ln1g, b.ln1b, am + 0, s));
+      LAUNCH(ST_QKV, launch_ln_qkv_fp8(g, C, n.cfg.heads, n.Spad, w.x, w.flag, w.wcount, b.ln1g, b.ln1b, b.wqkv8, b.wscale8, b.bqkv, am + 0, w.q16, w.k16, w.v16, s));
+      LAUNCH(ST_ATTN, launch_attn_bf16(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.v16, w.idx, w.woff, w.o16, am + 1, s));
+      LAUNCH(ST_PROJ, launch_gemm_fp8_resid(w.o16, w.nq, N, C, b.wo8, b.so8, am + 1, b.bo, C, w.x, w.idx, s));
+      LAUNCH(ST_LN2, launch_ln_amax(w.x, w.idx, w.nq, N, nullptr, g.S, C, b.ln2g, b.ln2b, am + 2, s));
+      LAUNCH(ST_FC1, launch_ln_fc1_fp8(N, C, R, w.x, w.idx, w.nq, b.ln2g, b.ln2b, b.w18, b.s18, b.b1, am + 2, w.h16, am + 3, s));
+      LAUNCH(ST_FC2, launch_gemm_fp8_resid(w.h16, w.nq, N, R, b.w28, b.s28, am + 3, b.b2, C, w.x, w.idx, s));
     } else {
       LAUNCH(ST_QKV, launch_ln_qkv_bf16(g, C, n.cfg.heads, n.Spad, w.x, w.flag, w.wcount, b.ln1g, b.ln1b, b.wqkv16, b.bqkv, w.q16, w.k16, w.v16, s));
-      LAUNCH(ST_ATTN, launch_attn_bf16(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.v16, w.idx, w.woff, w.o16, s));
+      LAUNCH(ST_ATTN, launch_attn_bf16(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.v16, w.idx, w.woff, w.o16, nullptr, s));
       LAUNCH(ST_PROJ, launch_gemm_bf16(w.o16, w.nq, N, C, b.wo16, b.bo, C, EPI_RESID, w.x, w.idx, s));
       LAUNCH(ST_FC1, launch_ln_fc1_bf16(N, C, R, w.x, w.idx, w.nq, b.ln2g, b.ln2b, b.w116, b.b1, w.h16, s));
       LAUNCH(ST_FC2, launch_gemm_bf16(w.h16, w.nq, N, R, b.w216, b.b2, C, EPI_RESID, w.x, w.idx, s));
@@ -572,4 +666,12 @@ extern "C" dr_status dr_debug_set(dr_ctx* c, const char* key, int64_t value) {
     return DR_OK;
   }
   return fail(c, DR_EINVAL, "dr_debug_set: unknown key '%s'", key);
+}
+
+extern "C" dr_status dr_fp8_encode(dr_ctx* c, const float* in, uint8_t* out, size_t n, float scale, void* stream) {
+  if (!c || !in || !out || !(scale > 0.f)) return fail(c, DR_EINVAL, "dr_fp8_encode: bad argument");
+  HIP_OK(c, hipSetDevice(c->device));
+  launch_quantize_fp8(in, out, n, 1.0f / scale, (hipStream_t)stream);
+  HIP_OK(c, hipGetLastError());
+  return DR_OK;
 }

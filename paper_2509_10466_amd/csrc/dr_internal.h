@@ -5,7 +5,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
+#include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/drinpaint.h"
@@ -45,6 +48,10 @@ struct BlockW {
   const float* bqkv;                         // f32 [3C]
   const bf16* wqkv16;                        // bf16 [3C, C]
   const bf16 *wo16, *w116, *w216;            // bf16 [out, in]
+  const uint8_t* wqkv8;                      // e4m3 [3C, C] (Wq, Wk, Wv each / own scale)
+  const uint8_t *wo8, *w18, *w28;            // e4m3 [out, in]
+  const float* wscale8;                      // device: s_q, s_k, s_v
+  float so8, s18, s28;                       // host copies of the other weight scales
 };
 
 struct Net {
@@ -76,9 +83,44 @@ struct Work {
   // BF16 path scratch
   bf16 *u16 = nullptr, *q16 = nullptr, *k16 = nullptr, *v16 = nullptr, *o16 = nullptr,
        *h16 = nullptr;
+  float* amax = nullptr;  // FP8 activation amax slots [blocks][4]
+  // stream mode: contiguous staging of the batch's frames, masks and outputs
+  float* fst = nullptr;
+  uint8_t* mst = nullptr;
+  float* ost = nullptr;
+  bool stream_mode = false;
   std::vector<void*> allocs;
 };
 
+// Stream mode: one ring of win_t K/V slots per stream; slot j, block l starts at element
+// (j * blocks + l) * blk_elems, each block holding [win_f][head][S_f][dh] bf16.
+constexpr int STREAM_MAXB = 16;
+struct StreamTable {
+  bf16* k[STREAM_MAXB];     // cache base of request r, advanced to the current block (slot 0)
+  bf16* v[STREAM_MAXB];
+  int head[STREAM_MAXB];    // slot receiving the new frame
+  int npast[STREAM_MAXB];   // cached past frames (<= T - 1)
+  long long slot_stride;    // elements between slots
+  int T;                    // slots in the ring
+};
+
+struct FramePtrs {          // per-request device buffers of a stream-mode batch
+  const float* f[STREAM_MAXB];
+  const uint8_t* m[STREAM_MAXB];
+  float* o[STREAM_MAXB];
+  int n;
+};
+
+}  // namespace dr
+
+namespace dr {
+struct StreamSt {
+  int H = 0, W = 0;
+  bf16* kc = nullptr;
+  bf16* vc = nullptr;
+  int head = 0, npast = 0;
+  size_t bytes = 0;
+};
 }  // namespace dr
 
 struct dr_ctx {
@@ -94,6 +136,13 @@ struct dr_ctx {
   struct Rec { int stage; hipEvent_t a, b; };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> event_pool;
+  // stream mode
+  std::mutex smu;                                   // guards streams, budget, swork
+  std::map<int, dr::StreamSt> streams;
+  int next_sid = 1;
+  size_t budget = 0;                                // 0 = no limit
+  size_t used = 0;                                  // bytes of open streams' caches
+  std::map<std::pair<int, int>, dr::Work*> swork;   // stream-mode workspaces by (H, W)
 };
 
 namespace dr {
@@ -156,11 +205,50 @@ void launch_ln_fc1_bf16(int m_max, int C, int R, const float* x, const int32_t* 
 void launch_gemm_bf16(const bf16* A, const int32_t* m_dev, int m_max, int K, const bf16* W,
                       const float* bias, int Nout, int epi, void* out,
                       const int32_t* res_rows, hipStream_t s);
+// amax_o (nullable): max |O| of the call is max-reduced into *amax_o (FP8 path)
 void launch_attn_bf16(const Geo& g, int C, int heads, int Spad, const bf16* q, const bf16* k,
                       const bf16* v, const int32_t* idx, const int32_t* woff, bf16* o,
-                      hipStream_t s);
+                      float* amax_o, hipStream_t s);
+
+// FP8 path (OCP e4m3 operands, per-tensor scales s = amax/448, FP32 accumulation)
+bool fp8_supported(int C, int R);
+void launch_quantize_fp8(const float* in, uint8_t* out, size_t n, float inv_scale, hipStream_t s);
+void launch_zero_f32(float* p, int n, hipStream_t s);
+void launch_ln_amax(const float* x, const int32_t* rows, const int32_t* nrows_dev, int nrows_max,
+                    const int32_t* wcount, int S, int C, const float* g, const float* b, float* slot,
+                    hipStream_t s);
+void launch_ln_qkv_fp8(const Geo& g, int C, int heads, int Spad, const float* x,
+                       const uint8_t* flag, const int32_t* wcount, const float* lng,
+                       const float* lnb, const uint8_t* w, const float* wscale, const float* bias,
+                       const float* amax_u, bf16* q, bf16* k, bf16* v, hipStream_t s);
+void launch_ln_fc1_fp8(int m_max, int C, int R, const float* x, const int32_t* idx,
+                       const int32_t* nq, const float* lng, const float* lnb, const uint8_t* w,
+                       float s_w, const float* bias, const float* amax_u, bf16* h, float* amax_h,
+                       hipStream_t s);
+void launch_gemm_fp8_resid(const bf16* A, const int32_t* m_dev, int m_max, int K,
+                           const uint8_t* W, float s_w, const float* amax_a, const float* bias,
+                           int Nout, float* x, const int32_t* res_rows, hipStream_t s);
 
 // weight preparation
 void launch_f32_to_bf16(const float* a, bf16* b, size_t n, hipStream_t s);
+
+// stream mode
+void launch_gather_frames(const FramePtrs& p, size_t npix, float* fst, uint8_t* mst, hipStream_t s);
+void launch_scatter_frames(const FramePtrs& p, size_t npix, const float* ost, hipStream_t s);
+void launch_ln_qkv_stream(const Geo& g, int C, int heads, const float* x, const uint8_t* flag,
+                          const float* lng, const float* lnb, const bf16* w, const float* bias,
+                          bf16* q, const StreamTable& tab, hipStream_t s);
+void launch_attn_stream(const StreamTable& tab, const Geo& g, int C, int heads, int Spad,
+                        const bf16* q, const int32_t* idx, const int32_t* woff, bf16* o,
+                        hipStream_t s);
+
+// host helpers shared by the API translation units
+dr_status dr_fail(dr_ctx* c, dr_status st, const char* fmt, ...);
+dr_status dr_make_geo(dr_ctx* c, int B, int T, int H, int W, int wt, Geo& g);
+dr_status dr_reserve_work(dr_ctx* c, Work& w, const Geo& g, bool stream_mode);
+void dr_free_work(Work& w);
+void dr_prof_begin(dr_ctx* c, hipStream_t s, hipEvent_t* a, hipEvent_t* b);
+void dr_prof_end(dr_ctx* c, int stage, hipStream_t s, hipEvent_t a, hipEvent_t b);
+extern const char* const kStageNames[];
 
 }  // namespace dr

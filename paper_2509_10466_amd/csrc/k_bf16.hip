@@ -416,6 +416,81 @@ void launch_ln_qkv_bf16(const Geo& g, int C, int heads, int Spad, const float* x
     qkv_launch<64>(g, C, heads, Spad, x, flag, wcount, lng, lnb, w, bias, q, k, v, s);
 }
 
+// Stream-mode Q/K/V epilogue: Q rows into the batch buffer; K and V of every token into the
+// current ring slot of its request's cache ([win_f][head][S_f][dh] per block and slot).
+struct StreamQkvEpi {
+  const float* bias;
+  bf16* q;
+  StreamTable tab;
+  int C, dh, heads, Sf, nwin_f;
+  __device__ __forceinline__ void operator()(int m, int n, const f32x4_t& a) const {
+    const float4 b4 = *reinterpret_cast<const float4*>(bias + n);
+    uint2 pk;
+    pk.x = pack_bf2(a[0] + b4.x, a[1] + b4.y);
+    pk.y = pack_bf2(a[2] + b4.z, a[3] + b4.w);
+    bf16* dst;
+    if (n < C) {
+      dst = q + (size_t)m * C + n;
+    } else {
+      const int part = n < 2 * C ? 1 : 2;
+      const int c = n - part * C, hh = c / dh, d = c - hh * dh;
+      const int w = m / Sf, s = m - w * Sf;
+      const int r = w / nwin_f, wl = w - r * nwin_f;
+      dst = (part == 1 ? tab.k[r] : tab.v[r]) + (size_t)tab.head[r] * tab.slot_stride +
+            (((size_t)wl * heads + hh) * Sf + s) * dh + d;
+    }
+    *reinterpret_cast<uint2*>(dst) = pk;
+  }
+};
+
+// LN1 + Q/K/V for a batch of new frames: K/V of every token (later frames may query any
+// window), Q only for row tiles holding a flagged token.
+template <int BN>
+__global__ void __launch_bounds__(PANEL_THREADS) ln_qkv_stream_kernel(Geo g, int C, int heads,
+                                                                      const float* __restrict__ x,
+                                                                      const uint8_t* __restrict__ flag,
+                                                                      const float* __restrict__ lng,
+                                                                      const float* __restrict__ lnb,
+                                                                      const bf16* __restrict__ W,
+                                                                      const float* __restrict__ bias, bf16* q,
+                                                                      StreamTable tab) {
+  extern __shared__ __align__(16) bf16 smem_panel[];
+  const int M = g.N;
+  const int n0 = blockIdx.x * BN, m0 = blockIdx.y * PANEL_M;
+  if (n0 < C) {
+    int need = 0;
+    if (threadIdx.x < PANEL_M && m0 + threadIdx.x < M) need = flag[m0 + threadIdx.x] != 0;
+    if (!__syncthreads_or(need)) return;
+  }
+  StreamQkvEpi epi{bias, q, tab, C, C / heads, heads, g.S, g.nwh * g.nww};
+  panel_gemm<BN>(x, nullptr, M, m0, C, lng, lnb, W, n0, smem_panel, epi);
+}
+
+template <int BN>
+static void qkv_stream_launch(const Geo& g, int C, int heads, const float* x, const uint8_t* flag,
+                              const float* lng, const float* lnb, const bf16* w, const float* bias, bf16* q,
+                              const StreamTable& tab, hipStream_t s) {
+  const size_t smem = panel_smem_bytes<BN>(C);
+  static size_t granted = 0;
+  if (smem > granted) {
+    allow_smem(ln_qkv_stream_kernel<BN>, smem);
+    granted = smem;
+  }
+  dim3 grid(3 * C / BN, (g.N + PANEL_M - 1) / PANEL_M);
+  ln_qkv_stream_kernel<BN><<<grid, PANEL_THREADS, smem, s>>>(g, C, heads, x, flag, lng, lnb, w, bias, q, tab);
+}
+
+void launch_ln_qkv_stream(const Geo& g, int C, int heads, const float* x, const uint8_t* flag, const float* lng,
+                          const float* lnb, const bf16* w, const float* bias, bf16* q, const StreamTable& tab,
+                          hipStream_t s) {
+  if (C % 256 == 0 && panel_smem_bytes<256>(C) <= 160 * 1024)
+    qkv_stream_launch<256>(g, C, heads, x, flag, lng, lnb, w, bias, q, tab, s);
+  else if (C % 128 == 0)
+    qkv_stream_launch<128>(g, C, heads, x, flag, lng, lnb, w, bias, q, tab, s);
+  else
+    qkv_stream_launch<64>(g, C, heads, x, flag, lng, lnb, w, bias, q, tab, s);
+}
+
 // GELU epilogue: h[m, n] = bf16(GELU(acc + b)).
 struct GeluEpi {
   const float* bias;
@@ -484,42 +559,47 @@ void launch_ln_fc1_bf16(int m_max, int C, int R, const float* x, const int32_t* 
 //   (the k slots of both operands use the same key permutation).
 // ------------------------------------------------------------------------------------------
 template <int DH, int NT>
-__global__ void __launch_bounds__(256) attn_bf16_kernel(Geo g, int C, int heads, const bf16* __restrict__ q,
-                                                        const bf16* __restrict__ kmat, const bf16* __restrict__ vmat,
-                                                        const int32_t* __restrict__ idx,
-                                                        const int32_t* __restrict__ woff, bf16* __restrict__ o) {
-  constexpr int SP = NT * 16;           // padded window length
-  constexpr int KST = DH + 8;           // LDS row stride of K (bf16)
-  constexpr int VST = SP + 4;           // LDS row stride of V^T (122 dwords per 240 keys: rows
-                                        // spread over distinct bank pairs, 8-byte aligned)
-  __shared__ bf16 Ks[SP * KST];
-  __shared__ bf16 Vs[DH * VST];
-  const int w = blockIdx.x / heads, h = blockIdx.x - w * heads;
-  const int q0 = woff[w], nqw = woff[w + 1] - q0;
-  const int qbase = blockIdx.y * 64;
-  if (qbase >= nqw) return;
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int l16 = lane & 15, kg = lane >> 4;
+struct AttnTile {
+  static constexpr int SP = NT * 16;   // padded window length
+  static constexpr int KST = DH + 8;   // LDS row stride of K (bf16)
+  static constexpr int VST = SP + 4;   // LDS row stride of V^T: rows spread over distinct bank
+                                       // pairs, 8-byte aligned
+};
 
-  // stage K [SP][DH] and V^T [DH][SP] of (w, h)
-  const bf16* kg_ = kmat + ((size_t)w * heads + h) * SP * DH;
-  const bf16* vg_ = vmat + ((size_t)w * heads + h) * SP * DH;
-  for (int c = t; c < SP * DH / 8; c += 256) {
+// Stage `nrows` keys/values (rows of [.][DH] in global memory) into LDS rows row0.. of K and
+// columns row0.. of V^T.
+template <int DH, int NT>
+__device__ __forceinline__ void attn_stage(bf16* Ks, bf16* Vs, const bf16* __restrict__ kg_,
+                                           const bf16* __restrict__ vg_, int row0, int nrows) {
+  using AT = AttnTile<DH, NT>;
+  const int t = threadIdx.x;
+  for (int c = t; c < nrows * DH / 8; c += 256) {
     const int row = c / (DH / 8), col = (c % (DH / 8)) * 8;
-    *reinterpret_cast<uint4*>(&Ks[row * KST + col]) = *reinterpret_cast<const uint4*>(kg_ + row * DH + col);
+    *reinterpret_cast<uint4*>(&Ks[(row0 + row) * AT::KST + col]) = *reinterpret_cast<const uint4*>(kg_ + row * DH + col);
   }
-  for (int c = t; c < SP * DH / 8; c += 256) {
+  for (int c = t; c < nrows * DH / 8; c += 256) {
     const int key = c / (DH / 8), d0 = (c % (DH / 8)) * 8;
     const uint4 v = *reinterpret_cast<const uint4*>(vg_ + key * DH + d0);
     const uint32_t wds[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      Vs[(d0 + 2 * e) * VST + key] = (bf16)(wds[e] & 0xffffu);
-      Vs[(d0 + 2 * e + 1) * VST + key] = (bf16)(wds[e] >> 16);
+      Vs[(d0 + 2 * e) * AT::VST + row0 + key] = (bf16)(wds[e] & 0xffffu);
+      Vs[(d0 + 2 * e + 1) * AT::VST + row0 + key] = (bf16)(wds[e] >> 16);
     }
   }
-  __syncthreads();
+}
 
+// Queries of one (window, head, 64-query tile) against the S keys staged in LDS (rows >= S of
+// K and columns >= S of V^T must be finite; their scores are masked to -inf).
+template <int DH, int NT>
+__device__ __forceinline__ void attn_compute(const bf16* Ks, const bf16* Vs, int S, int C, int h,
+                                             const bf16* __restrict__ q, const int32_t* __restrict__ idx,
+                                             int q0, int nqw, int qbase, bf16* __restrict__ o,
+                                             float* __restrict__ amax_o) {
+  constexpr int KST = AttnTile<DH, NT>::KST;
+  constexpr int VST = AttnTile<DH, NT>::VST;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int l16 = lane & 15, kg = lane >> 4;
   const int qi = qbase + wv * 16 + l16;  // this lane's query (column of S^T)
   if (qbase + wv * 16 >= nqw) return;    // whole wave idle (no block barrier follows)
   const bool valid = qi < nqw;
@@ -548,7 +628,7 @@ __global__ void __launch_bounds__(256) attn_bf16_kernel(Geo g, int C, int heads,
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int key = tt * 16 + kg * 4 + i;
-      sc[tt][i] = key < g.S ? a[i] * sl2 : -INFINITY;
+      sc[tt][i] = key < S ? a[i] * sl2 : -INFINITY;
     }
   }
   float mx = -INFINITY;
@@ -570,6 +650,7 @@ __global__ void __launch_bounds__(256) attn_bf16_kernel(Geo g, int C, int heads,
   sum += __shfl_xor(sum, 16, 64);
   sum += __shfl_xor(sum, 32, 64);
   const float inv = 1.0f / sum;
+  float omax = 0.f;
 
 #pragma unroll
   for (int dt = 0; dt < DH / 16; ++dt) {
@@ -600,19 +681,99 @@ __global__ void __launch_bounds__(256) attn_bf16_kernel(Geo g, int C, int heads,
       pk.x = pack_bf2(a[0] * inv, a[1] * inv);
       pk.y = pack_bf2(a[2] * inv, a[3] * inv);
       *reinterpret_cast<uint2*>(o + (size_t)r * C + h * DH + dt * 16 + kg * 4) = pk;
+      omax = fmaxf(omax, fmaxf(fmaxf(fabsf(a[0]), fabsf(a[1])), fmaxf(fabsf(a[2]), fabsf(a[3]))) * inv);
     }
+  }
+  if (amax_o) {
+    // max |O| of this wave into the per-call slot (non-negative floats order like their bits)
+    const float wmx = wave_max(omax);
+    if (lane == 0 && wmx > 0.f) atomicMax(reinterpret_cast<unsigned int*>(amax_o), __float_as_uint(wmx));
   }
 }
 
+template <int DH, int NT>
+__global__ void __launch_bounds__(256) attn_bf16_kernel(Geo g, int C, int heads, const bf16* __restrict__ q,
+                                                        const bf16* __restrict__ kmat, const bf16* __restrict__ vmat,
+                                                        const int32_t* __restrict__ idx,
+                                                        const int32_t* __restrict__ woff, bf16* __restrict__ o,
+                                                        float* __restrict__ amax_o) {
+  using AT = AttnTile<DH, NT>;
+  __shared__ bf16 Ks[AT::SP * AT::KST];
+  __shared__ bf16 Vs[DH * AT::VST];
+  const int w = blockIdx.x / heads, h = blockIdx.x - w * heads;
+  const int q0 = woff[w], nqw = woff[w + 1] - q0;
+  const int qbase = blockIdx.y * 64;
+  if (qbase >= nqw) return;
+  // K and V of (w, h) hold SP rows, the pad rows zero in memory
+  attn_stage<DH, NT>(Ks, Vs, kmat + ((size_t)w * heads + h) * AT::SP * DH, vmat + ((size_t)w * heads + h) * AT::SP * DH,
+                     0, AT::SP);
+  __syncthreads();
+  attn_compute<DH, NT>(Ks, Vs, g.S, C, h, q, idx, q0, nqw, qbase, o, amax_o);
+}
+
+// Stream mode: the keys of window (request r, window wl) are the window's rows in the
+// request's cached frames (oldest first) followed by the new frame, each frame block being
+// S_f = wh*ww rows of a ring slot [win_f][head][S_f][dh].
+template <int DH, int NT>
+__global__ void __launch_bounds__(256) attn_stream_kernel(StreamTable tab, int C, int heads, int Sf, int nwin_f,
+                                                          const bf16* __restrict__ q, const int32_t* __restrict__ idx,
+                                                          const int32_t* __restrict__ woff, bf16* __restrict__ o) {
+  using AT = AttnTile<DH, NT>;
+  __shared__ bf16 Ks[AT::SP * AT::KST];
+  __shared__ bf16 Vs[DH * AT::VST];
+  const int w = blockIdx.x / heads, h = blockIdx.x - w * heads;
+  const int q0 = woff[w], nqw = woff[w + 1] - q0;
+  const int qbase = blockIdx.y * 64;
+  if (qbase >= nqw) return;
+  const int r = w / nwin_f, wl = w - r * nwin_f;
+  const int np = tab.npast[r], hd = tab.head[r];
+  const size_t off = ((size_t)wl * heads + h) * Sf * DH;
+  for (int j = 0; j <= np; ++j) {
+    const int slot = (hd - np + j + tab.T) % tab.T;
+    attn_stage<DH, NT>(Ks, Vs, tab.k[r] + (size_t)slot * tab.slot_stride + off,
+                       tab.v[r] + (size_t)slot * tab.slot_stride + off, j * Sf, Sf);
+  }
+  const int S = (np + 1) * Sf;
+  // zero the pad keys (rows of K, columns of V^T) so that P = 0 meets finite values
+  for (int e = threadIdx.x; e < (AT::SP - S) * DH; e += 256) {
+    const int row = S + e / DH, d = e % DH;
+    Ks[row * AT::KST + d] = 0;
+    Vs[d * AT::VST + row] = 0;
+  }
+  __syncthreads();
+  attn_compute<DH, NT>(Ks, Vs, S, C, h, q, idx, q0, nqw, qbase, o, nullptr);
+}
+
 void launch_attn_bf16(const Geo& g, int C, int heads, int Spad, const bf16* q, const bf16* k,
-                      const bf16* vt, const int32_t* idx, const int32_t* woff, bf16* o, hipStream_t s) {
+                      const bf16* vt, const int32_t* idx, const int32_t* woff, bf16* o, float* amax_o,
+                      hipStream_t s) {
   const int dh = C / heads;
   dim3 grid(g.nwin * heads, (g.S + 63) / 64);
   const int nt = Spad / 16;
 #define DR_ATTN_CASE(DH_, NT_)                                                          \
   if (dh == DH_ && nt == NT_) {                                                         \
-    attn_bf16_kernel<DH_, NT_><<<grid, 256, 0, s>>>(g, C, heads, q, k, vt, idx, woff, o); \
+    attn_bf16_kernel<DH_, NT_><<<grid, 256, 0, s>>>(g, C, heads, q, k, vt, idx, woff, o, amax_o); \
     return;                                                                             \
+  }
+  DR_ATTN_CASE(32, 4)
+  DR_ATTN_CASE(64, 4)
+  DR_ATTN_CASE(64, 15)
+  DR_ATTN_CASE(64, 19)
+  DR_ATTN_CASE(32, 15)
+  DR_ATTN_CASE(32, 19)
+#undef DR_ATTN_CASE
+}
+
+void launch_attn_stream(const StreamTable& tab, const Geo& g, int C, int heads, int Spad, const bf16* q,
+                        const int32_t* idx, const int32_t* woff, bf16* o, hipStream_t s) {
+  const int dh = C / heads;
+  dim3 grid(g.nwin * heads, (g.S + 63) / 64);
+  const int nt = Spad / 16;
+  const int nwin_f = g.nwh * g.nww;
+#define DR_ATTN_CASE(DH_, NT_)                                                                      \
+  if (dh == DH_ && nt == NT_) {                                                                     \
+    attn_stream_kernel<DH_, NT_><<<grid, 256, 0, s>>>(tab, C, heads, g.S, nwin_f, q, idx, woff, o); \
+    return;                                                                                         \
   }
   DR_ATTN_CASE(32, 4)
   DR_ATTN_CASE(64, 4)

@@ -208,3 +208,50 @@ void launch_copy_unmasked(size_t npix, const float* frames, const uint8_t* masks
 }
 
 }  // namespace dr
+
+namespace dr {
+
+// ------------------------------------------------------------------------------------------
+// Stream mode: copy the batch's per-request frames and masks into contiguous staging buffers
+// (request-major), and the staged outputs back.  One grid row per request, float4 / u32
+// accesses (each frame holds a multiple of 4 pixels).
+// ------------------------------------------------------------------------------------------
+__global__ void gather_frames_kernel(FramePtrs p, size_t nquad, float4* __restrict__ fst,
+                                     uint32_t* __restrict__ mst) {
+  const int r = blockIdx.y;
+  const float4* f = reinterpret_cast<const float4*>(p.f[r]);
+  const uint32_t* m = reinterpret_cast<const uint32_t*>(p.m[r]);
+  float4* fo = fst + (size_t)r * nquad * 3;
+  uint32_t* mo = mst + (size_t)r * nquad;
+  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < nquad; q += (size_t)gridDim.x * blockDim.x) {
+    fo[3 * q] = f[3 * q];
+    fo[3 * q + 1] = f[3 * q + 1];
+    fo[3 * q + 2] = f[3 * q + 2];
+    mo[q] = m[q];
+  }
+}
+
+__global__ void scatter_frames_kernel(FramePtrs p, size_t nquad, const float4* __restrict__ ost) {
+  const int r = blockIdx.y;
+  float4* o = reinterpret_cast<float4*>(p.o[r]);
+  const float4* src = ost + (size_t)r * nquad * 3;
+  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < 3 * nquad; q += (size_t)gridDim.x * blockDim.x)
+    o[q] = src[q];
+}
+
+void launch_gather_frames(const FramePtrs& p, size_t npix, float* fst, uint8_t* mst, hipStream_t s) {
+  const size_t nquad = npix / 4;
+  unsigned gx = (unsigned)((nquad + 255) / 256);
+  if (gx > 512) gx = 512;
+  gather_frames_kernel<<<dim3(gx, p.n), 256, 0, s>>>(p, nquad, reinterpret_cast<float4*>(fst),
+                                                     reinterpret_cast<uint32_t*>(mst));
+}
+
+void launch_scatter_frames(const FramePtrs& p, size_t npix, const float* ost, hipStream_t s) {
+  const size_t nquad = npix / 4;
+  unsigned gx = (unsigned)((3 * nquad + 255) / 256);
+  if (gx > 512) gx = 512;
+  scatter_frames_kernel<<<dim3(gx, p.n), 256, 0, s>>>(p, nquad, reinterpret_cast<const float4*>(ost));
+}
+
+}  // namespace dr
