@@ -186,6 +186,28 @@ dr_status dr_server_stats(dr_server* srv, int64_t* batches, int64_t* requests, i
 /* Finish all queued work, stop the thread and free the executors. */
 void dr_server_destroy(dr_server* srv);
 
+/* ---- Training (FP32) --------------------------------------------------------------------
+ * Parameters are addressed as one flat f32 vector in the blob order of dr_load_weights
+ * (embed.w OIHW, embed.b, per block ln1.g ... b2, lnf.g, lnf.b, dec.w IOHW, dec.b). */
+size_t dr_param_count(dr_ctx* ctx);
+/* Forward of B clips (as dr_inpaint, masked queries) keeping the activations the reverse
+ * pass needs (per block: block input, LN1 output, K/V, Q, attention output and row max/sum,
+ * post-projection rows, LN2 output, MLP pre-activation) in the context.  pred: device f32
+ * [B,T,H,W,3], the sigmoid output of the decoder at every pixel (before the composite). */
+dr_status dr_train_forward(dr_ctx* ctx, const float* frames, const uint8_t* masks, float* pred,
+                           int B, int T, int H, int W, void* stream);
+/* Reverse pass of the last dr_train_forward: dpred = dL/dpred (device, layout of pred);
+ * grads: device f32 [dr_param_count] receives dL/dparams.  Attention probabilities are
+ * recomputed from Q, K and the saved row statistics.  Token reductions run in fixed chunks,
+ * so the result is deterministic. */
+dr_status dr_train_backward(dr_ctx* ctx, const float* dpred, float* grads, void* stream);
+/* Training loss (thesis, Methods, "Model Training -- Loss"): loss[0] = w_in * mean over
+ * masked pixel-channel values |pred - gt| + w_out * mean over the others (an empty region adds
+ * 0); dpred (may be NULL) receives dL/dpred with sign(0) = 0.  Device pointers; npix pixels. */
+dr_status dr_l1_loss(dr_ctx* ctx, const float* pred, const float* gt, const uint8_t* masks,
+                     size_t npix, float w_in, float w_out, float* loss, float* dpred,
+                     void* stream);
+
 /* Message of the last failed call on `ctx` ("" if none).  ctx may be NULL (then the
  * message of the last failed dr_create). */
 const char* dr_last_error(dr_ctx* ctx);

@@ -69,6 +69,10 @@ def load():
         "dr_server_poll": (I, [P, P, P, P, I, ct.POINTER(I)]),
         "dr_server_stats": (I, [P, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64), ct.POINTER(I)]),
         "dr_server_destroy": (None, [P]),
+        "dr_param_count": (Z, [P]),
+        "dr_train_forward": (I, [P, P, P, P, I, I, I, I, P]),
+        "dr_train_backward": (I, [P, P, P, P]),
+        "dr_l1_loss": (I, [P, P, P, P, Z, ct.c_float, ct.c_float, P, P, P]),
         "dr_last_error": (ct.c_char_p, [P]),
         "dr_destroy": (None, [P]),
     }

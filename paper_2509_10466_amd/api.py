@@ -7,6 +7,7 @@ from __future__ import annotations
 
 import ctypes as ct
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -119,6 +120,51 @@ class Inpainter:
         _lib.check(self.lib, self._ctx, self.lib.dr_profile_read(self._ctx, ms, cnt, n))
         return {self.stages[i]: (ms[i], cnt[i]) for i in range(n) if cnt[i]}
 
+    # ---- training ---------------------------------------------------------------------
+    def param_count(self) -> int:
+        return int(self.lib.dr_param_count(self._ctx))
+
+    def load_params(self, flat: torch.Tensor):
+        """Replace the weights from a flat FP32 parameter vector (blob order)."""
+        names = wblob.param_names(self.cfg)
+        shapes = dict(_shapes(self.cfg))
+        host = flat.detach().float().cpu().numpy()
+        W, o = {}, 0
+        for n in names:
+            size = int(np.prod(shapes[n]))
+            W[n] = host[o:o + size].reshape(shapes[n])
+            o += size
+        blob = wblob.pack(self.cfg, W)
+        buf = ct.create_string_buffer(blob, len(blob))
+        _lib.check(self.lib, self._ctx, self.lib.dr_load_weights(self._ctx, buf, len(blob)))
+
+    def train_forward(self, frames: torch.Tensor, masks: torch.Tensor, stream=None) -> torch.Tensor:
+        """Decoder prediction at every pixel [B,T,H,W,3] (before the composite), keeping the
+        activations for train_backward."""
+        self._check_inputs(frames, masks)
+        pred = torch.empty_like(frames)
+        B, T, H, W, _ = frames.shape
+        st = self.lib.dr_train_forward(self._ctx, _ptr(frames), _ptr(masks), _ptr(pred), B, T, H, W, _stream(stream))
+        _lib.check(self.lib, self._ctx, st)
+        return pred
+
+    def train_backward(self, dpred: torch.Tensor, stream=None) -> torch.Tensor:
+        """dL/dparams (flat FP32, blob order) of the last train_forward."""
+        dpred = dpred.contiguous().float()
+        grads = torch.empty(self.param_count(), dtype=torch.float32, device=dpred.device)
+        st = self.lib.dr_train_backward(self._ctx, _ptr(dpred), _ptr(grads), _stream(stream))
+        _lib.check(self.lib, self._ctx, st)
+        return grads
+
+    def l1_loss(self, pred, gt, masks, w_in: float = 1.0, w_out: float = 0.1, stream=None):
+        """(loss [1] device tensor, dL/dpred)."""
+        loss = torch.empty(1, dtype=torch.float32, device=pred.device)
+        dpred = torch.empty_like(pred)
+        st = self.lib.dr_l1_loss(self._ctx, _ptr(pred), _ptr(gt), _ptr(masks), masks.numel(), w_in, w_out,
+                                 _ptr(loss), _ptr(dpred), _stream(stream))
+        _lib.check(self.lib, self._ctx, st)
+        return loss, dpred
+
     # ---- stream mode ------------------------------------------------------------------
     def set_budget(self, nbytes: int):
         _lib.check(self.lib, self._ctx, self.lib.dr_set_budget(self._ctx, int(nbytes)))
@@ -217,3 +263,48 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def _shapes(cfg):
+    C, p, R = cfg.dim, cfg.patch, cfg.mlp_ratio * cfg.dim
+    out = [("embed.w", (C, 3, p, p)), ("embed.b", (C,))]
+    for l in range(cfg.blocks):
+        b = f"blk{l}."
+        out += [(b + "ln1.g", (C,)), (b + "ln1.b", (C,)), (b + "wq", (C, C)), (b + "bq", (C,)),
+                (b + "wk", (C, C)), (b + "bk", (C,)), (b + "wv", (C, C)), (b + "bv", (C,)),
+                (b + "wo", (C, C)), (b + "bo", (C,)), (b + "ln2.g", (C,)), (b + "ln2.b", (C,)),
+                (b + "w1", (R, C)), (b + "b1", (R,)), (b + "w2", (C, R)), (b + "b2", (C,))]
+    return out + [("lnf.g", (C,)), ("lnf.b", (C,)), ("dec.w", (C, 3, p, p)), ("dec.b", (3,))]
+
+
+def flatten_params(cfg, weights) -> torch.Tensor:
+    """Flat FP32 parameter vector (blob order) from a name -> array mapping."""
+    return torch.cat([torch.as_tensor(np.asarray(weights[n], np.float32)).reshape(-1) for n, _ in _shapes(cfg)])
+
+
+def unflatten_params(cfg, flat):
+    """name -> view of a flat parameter vector."""
+    out, o = {}, 0
+    for n, shp in _shapes(cfg):
+        size = int(np.prod(shp))
+        out[n] = flat[o:o + size].reshape(shp)
+        o += size
+    return out
+
+
+class InpaintFn(torch.autograd.Function):
+    """pred = network(frames, masks; params) with the library's hand-written backward.
+
+    ``params`` is the flat FP32 parameter vector (blob order); the prediction is the decoder
+    output at every pixel, before the composite (the training loss is taken on it)."""
+
+    @staticmethod
+    def forward(ctx, frames, masks, params, eng):
+        eng.load_params(params)
+        pred = eng.train_forward(frames.contiguous(), masks.contiguous())
+        ctx.eng = eng
+        return pred
+
+    @staticmethod
+    def backward(ctx, dpred):
+        return None, None, ctx.eng.train_backward(dpred), None

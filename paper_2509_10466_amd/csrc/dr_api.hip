@@ -1,6 +1,7 @@
 // Host side of the C ABI: context, weight blob loading, workspace, and the launch sequence
 // of the inpainting forward (see include/drinpaint.h for the contract of every call).
 #include <algorithm>
+#include <initializer_list>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -152,6 +153,7 @@ extern "C" void dr_destroy(dr_ctx* c) {
   hipSetDevice(c->device);
   hipDeviceSynchronize();
   free_work(c);
+  dr_train_release(c);
   for (auto& kv : c->swork) {
     dr_free_work(*kv.second);
     delete kv.second;
@@ -318,6 +320,26 @@ extern "C" dr_status dr_load_weights(dr_ctx* c, const void* blob, size_t nbytes)
     f.insert(f.end(), s[5], s[5] + C);
     f.insert(f.end(), s[7], s[7] + C);
     while (f.size() % 64) f.push_back(0.f);
+    // transposes: T[i][o] = W[o][i] for W [out][in]
+    auto putT = [&](std::initializer_list<const float*> parts, int out_each, int in) {
+      const size_t off = f.size();
+      const int nparts = (int)parts.size();
+      const int out_total = out_each * nparts;
+      f.resize(off + (size_t)in * out_total);
+      int pi = 0;
+      for (const float* wsrc : parts) {
+        for (int o = 0; o < out_each; ++o)
+          for (int i = 0; i < in; ++i) f[off + (size_t)i * out_total + pi * out_each + o] = wsrc[(size_t)o * in + i];
+        ++pi;
+      }
+      while (f.size() % 64) f.push_back(0.f);
+      return off;
+    };
+    O.v[19] = putT({s[2]}, C, C);         // Wq^T
+    O.v[20] = putT({s[4], s[6]}, C, C);   // [Wk; Wv]^T  [C][2C]
+    O.v[21] = putT({s[8]}, C, C);         // Wo^T
+    O.v[22] = putT({s[12]}, R, C);        // W1^T [C][R]
+    O.v[23] = putT({s[14]}, C, R);        // W2^T [R][C]
     Off& H = b16[l];
     H.v[0] = put16({s[2], s[4], s[6]}, {CC, CC, CC});
     H.v[1] = put16({s[8]}, {CC});
@@ -357,6 +379,7 @@ extern "C" dr_status dr_load_weights(dr_ctx* c, const void* blob, size_t nbytes)
     w.w1 = F + O.v[12]; w.b1 = F + O.v[13];
     w.w2 = F + O.v[14]; w.b2 = F + O.v[15];
     w.wkv = F + O.v[16]; w.bkv = F + O.v[17]; w.bqkv = F + O.v[18];
+    w.wqT = F + O.v[19]; w.wkvT = F + O.v[20]; w.woT = F + O.v[21]; w.w1T = F + O.v[22]; w.w2T = F + O.v[23];
     w.wqkv16 = B16 + b16[l].v[0];
     w.wo16 = B16 + b16[l].v[1];
     w.w116 = B16 + b16[l].v[2];

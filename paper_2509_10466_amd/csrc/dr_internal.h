@@ -52,6 +52,8 @@ struct BlockW {
   const uint8_t *wo8, *w18, *w28;            // e4m3 [out, in]
   const float* wscale8;                      // device: s_q, s_k, s_v
   float so8, s18, s28;                       // host copies of the other weight scales
+  // transposed FP32 copies for the input gradients of the backward pass ([in, out])
+  const float *wqT, *wkvT, *woT, *w1T, *w2T;  // [C,C], [C,2C], [C,C], [C,R], [R,C]
 };
 
 struct Net {
@@ -143,6 +145,7 @@ struct dr_ctx {
   size_t budget = 0;                                // 0 = no limit
   size_t used = 0;                                  // bytes of open streams' caches
   std::map<std::pair<int, int>, dr::Work*> swork;   // stream-mode workspaces by (H, W)
+  void* train = nullptr;                            // training workspace (activations, scratch)
 };
 
 namespace dr {
@@ -247,6 +250,7 @@ dr_status dr_fail(dr_ctx* c, dr_status st, const char* fmt, ...);
 dr_status dr_make_geo(dr_ctx* c, int B, int T, int H, int W, int wt, Geo& g);
 dr_status dr_reserve_work(dr_ctx* c, Work& w, const Geo& g, bool stream_mode);
 void dr_free_work(Work& w);
+void dr_train_release(dr_ctx* c);
 void dr_prof_begin(dr_ctx* c, hipStream_t s, hipEvent_t* a, hipEvent_t* b);
 void dr_prof_end(dr_ctx* c, int stage, hipStream_t s, hipEvent_t a, hipEvent_t b);
 extern const char* const kStageNames[];

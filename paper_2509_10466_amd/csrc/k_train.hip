@@ -1,0 +1,574 @@
+// Training kernels (FP32): the pieces of the hand-written reverse pass of the inpainting
+// network.  Weight gradients are reductions over tokens; they are computed deterministically
+// (fixed chunks of rows, then the chunk partials summed in order), so a gradient does not
+// depend on launch timing or on which other clips share the batch.
+#include "dr_device.h"
+#include "dr_internal.h"
+
+namespace dr {
+
+constexpr int RED_CHUNK = 2048;  // rows per partial of a token reduction
+
+// ------------------------------------------------------------------------------------------
+// Y[r, :] = X[rows[r], :] for r < *n (gather of residual rows)
+// ------------------------------------------------------------------------------------------
+__global__ void gather_rows_kernel(const float* __restrict__ X, const int32_t* __restrict__ rows,
+                                   const int32_t* __restrict__ n_dev, int n_max, int C, float* __restrict__ Y) {
+  const int n = n_dev ? n_dev[0] : n_max;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < (size_t)n * C; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t r = e / C, c = e - r * C;
+    Y[e] = X[(size_t)rows[r] * C + c];
+  }
+}
+
+void launch_gather_rows(const float* X, const int32_t* rows, const int32_t* n_dev, int n_max, int C, float* Y,
+                        hipStream_t s) {
+  size_t grid = ((size_t)n_max * C + 255) / 256;
+  if (grid > 8192) grid = 8192;
+  if (grid) gather_rows_kernel<<<(unsigned)grid, 256, 0, s>>>(X, rows, n_dev, n_max, C, Y);
+}
+
+// X[rows[r], :] = Y[r, :] (scatter-replace)
+__global__ void scatter_rows_kernel(const float* __restrict__ Y, const int32_t* __restrict__ rows,
+                                    const int32_t* __restrict__ n_dev, int C, float* __restrict__ X) {
+  const int n = n_dev[0];
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < (size_t)n * C; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t r = e / C, c = e - r * C;
+    X[(size_t)rows[r] * C + c] = Y[e];
+  }
+}
+
+void launch_scatter_rows(const float* Y, const int32_t* rows, const int32_t* n_dev, int n_max, int C, float* X,
+                         hipStream_t s) {
+  size_t grid = ((size_t)n_max * C + 255) / 256;
+  if (grid > 8192) grid = 8192;
+  if (grid) scatter_rows_kernel<<<(unsigned)grid, 256, 0, s>>>(Y, rows, n_dev, C, X);
+}
+
+// ------------------------------------------------------------------------------------------
+// elementwise: a = GELU(h);  dh = da * GELU'(h),  GELU'(z) = Phi(z) + z phi(z)
+// ------------------------------------------------------------------------------------------
+__global__ void gelu_fwd_kernel(const float* __restrict__ h, const int32_t* __restrict__ n_dev, int R,
+                                float* __restrict__ a) {
+  const size_t n = (size_t)n_dev[0] * R;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+    a[e] = gelu_erf(h[e]);
+}
+
+__global__ void gelu_bwd_kernel(const float* __restrict__ h, const float* __restrict__ da,
+                                const int32_t* __restrict__ n_dev, int R, float* __restrict__ dh) {
+  const size_t n = (size_t)n_dev[0] * R;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const float z = h[e];
+    const float cdf = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
+    const float pdf = 0.3989422804014327f * expf(-0.5f * z * z);
+    dh[e] = da[e] * (cdf + z * pdf);
+  }
+}
+
+void launch_gelu_fwd(const float* h, const int32_t* n_dev, int n_max, int R, float* a, hipStream_t s) {
+  size_t grid = ((size_t)n_max * R + 255) / 256;
+  if (grid > 8192) grid = 8192;
+  if (grid) gelu_fwd_kernel<<<(unsigned)grid, 256, 0, s>>>(h, n_dev, R, a);
+}
+
+void launch_gelu_bwd(const float* h, const float* da, const int32_t* n_dev, int n_max, int R, float* dh,
+                     hipStream_t s) {
+  size_t grid = ((size_t)n_max * R + 255) / 256;
+  if (grid > 8192) grid = 8192;
+  if (grid) gelu_bwd_kernel<<<(unsigned)grid, 256, 0, s>>>(h, da, n_dev, R, dh);
+}
+
+// ------------------------------------------------------------------------------------------
+// Window attention forward (FP32) that also saves each query row's max m and sum l of
+// exp(s - m) per head: stats[r * heads + h] = (m, l).  Same arithmetic as the inference
+// kernel of the FP32 path.
+// ------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) attn_f32_save_kernel(Geo g, int C, int heads, const float* __restrict__ q,
+                                                            const float* __restrict__ kv,
+                                                            const int32_t* __restrict__ woff, float* __restrict__ o,
+                                                            float2* __restrict__ stats) {
+  __shared__ float qs[4][64];
+  __shared__ float ps[4][320];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int w = blockIdx.x / heads, h = blockIdx.x - w * heads;
+  const int j = blockIdx.y * 4 + wv;
+  const int q0 = woff[w], nqw = woff[w + 1] - q0;
+  if (j >= nqw) return;
+  const int dh = C / heads;
+  const int r = q0 + j;
+  const float scale = rsqrtf((float)dh);
+  if (lane < dh) qs[wv][lane] = q[(size_t)r * C + h * dh + lane];
+  __builtin_amdgcn_wave_barrier();
+  const float* kbase = kv + (size_t)w * g.S * 2 * C + h * dh;
+  float mx = -INFINITY;
+  for (int s = lane; s < g.S; s += 64) {
+    const float* kr = kbase + (size_t)s * 2 * C;
+    float d = 0.f;
+    for (int e = 0; e < dh; ++e) d = fmaf(qs[wv][e], kr[e], d);
+    d *= scale;
+    ps[wv][s] = d;
+    mx = fmaxf(mx, d);
+  }
+  mx = wave_max(mx);
+  float sum = 0.f;
+  for (int s = lane; s < g.S; s += 64) {
+    const float e = expf(ps[wv][s] - mx);
+    ps[wv][s] = e;
+    sum += e;
+  }
+  sum = wave_sum(sum);
+  __builtin_amdgcn_wave_barrier();
+  if (lane < dh) {
+    const float* vbase = kbase + C + lane;
+    float acc = 0.f;
+    for (int s = 0; s < g.S; ++s) acc = fmaf(ps[wv][s], vbase[(size_t)s * 2 * C], acc);
+    o[(size_t)r * C + h * dh + lane] = acc / sum;
+  }
+  if (lane == 0) stats[(size_t)r * heads + h] = make_float2(mx, sum);
+}
+
+void launch_attn_f32_save(const Geo& g, int C, int heads, const float* q, const float* kv, const int32_t* woff,
+                          float* o, float2* stats, hipStream_t s) {
+  dim3 grid(g.nwin * heads, (g.S + 3) / 4);
+  attn_f32_save_kernel<<<grid, 256, 0, s>>>(g, C, heads, q, kv, woff, o, stats);
+}
+
+// ------------------------------------------------------------------------------------------
+// Attention backward, part 1: one wavefront per (query, head).  P is recomputed from Q, K and
+// the saved row statistics, P_s = exp(q.k_s / sqrt(dh) - m) / l.  Then dP_s = dO . v_s,
+// D = sum_s P_s dP_s (= dO . O), dS_s = P_s (dP_s - D), dq = sum_s dS_s k_s / sqrt(dh).
+// P and dS are written for part 2 ([Nq][heads][S]).
+// ------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) attn_bwd_q_kernel(Geo g, int C, int heads, const float* __restrict__ q,
+                                                         const float* __restrict__ kv, const float* __restrict__ dout,
+                                                         const float2* __restrict__ stats,
+                                                         const int32_t* __restrict__ woff, float* __restrict__ dq,
+                                                         float* __restrict__ P, float* __restrict__ dS) {
+  __shared__ float qs[4][64];
+  __shared__ float dos[4][64];
+  __shared__ float ds_[4][320];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int w = blockIdx.x / heads, h = blockIdx.x - w * heads;
+  const int j = blockIdx.y * 4 + wv;
+  const int q0 = woff[w], nqw = woff[w + 1] - q0;
+  if (j >= nqw) return;
+  const int dh = C / heads;
+  const int r = q0 + j;
+  const float scale = rsqrtf((float)dh);
+  if (lane < dh) {
+    qs[wv][lane] = q[(size_t)r * C + h * dh + lane];
+    dos[wv][lane] = dout[(size_t)r * C + h * dh + lane];
+  }
+  __builtin_amdgcn_wave_barrier();
+  const float2 st = stats[(size_t)r * heads + h];
+  const float* kbase = kv + (size_t)w * g.S * 2 * C + h * dh;
+  float* prow = P + ((size_t)r * heads + h) * g.S;
+  float* dsrow = dS + ((size_t)r * heads + h) * g.S;
+  float dsum = 0.f;
+  for (int s = lane; s < g.S; s += 64) {
+    const float* kr = kbase + (size_t)s * 2 * C;
+    const float* vr = kr + C;
+    float d = 0.f, dp = 0.f;
+    for (int e = 0; e < dh; ++e) {
+      d = fmaf(qs[wv][e], kr[e], d);
+      dp = fmaf(dos[wv][e], vr[e], dp);
+    }
+    const float p = expf(d * scale - st.x) / st.y;
+    prow[s] = p;
+    ds_[wv][s] = dp;
+    dsum += p * dp;
+  }
+  dsum = wave_sum(dsum);
+  __builtin_amdgcn_wave_barrier();
+  for (int s = lane; s < g.S; s += 64) {
+    const float v = prow[s] * (ds_[wv][s] - dsum);
+    ds_[wv][s] = v;
+    dsrow[s] = v;
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (lane < dh) {
+    float acc = 0.f;
+    for (int s = 0; s < g.S; ++s) acc = fmaf(ds_[wv][s], kbase[(size_t)s * 2 * C + lane], acc);
+    dq[(size_t)r * C + h * dh + lane] = acc * scale;
+  }
+}
+
+void launch_attn_bwd_q(const Geo& g, int C, int heads, const float* q, const float* kv, const float* dout,
+                       const float2* stats, const int32_t* woff, float* dq, float* P, float* dS, hipStream_t s) {
+  dim3 grid(g.nwin * heads, (g.S + 3) / 4);
+  attn_bwd_q_kernel<<<grid, 256, 0, s>>>(g, C, heads, q, kv, dout, stats, woff, dq, P, dS);
+}
+
+// ------------------------------------------------------------------------------------------
+// Attention backward, part 2: per (window, head), thread per (key s, channel d):
+//   dK[s, d] = sum_j dS[j, s] q[j, d] / sqrt(dh),  dV[s, d] = sum_j P[j, s] dO[j, d]
+// over the window's queries j (in order).  dkv rows [N][2C]: dK in [0, C), dV in [C, 2C);
+// windows without queries get zeros.
+// ------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) attn_bwd_kv_kernel(Geo g, int C, int heads, const float* __restrict__ q,
+                                                          const float* __restrict__ dout, const float* __restrict__ P,
+                                                          const float* __restrict__ dS,
+                                                          const int32_t* __restrict__ woff, float* __restrict__ dkv) {
+  const int w = blockIdx.x / heads, h = blockIdx.x - w * heads;
+  const int dh = C / heads;
+  const int q0 = woff[w], nqw = woff[w + 1] - q0;
+  const float scale = rsqrtf((float)dh);
+  for (int e = blockIdx.y * blockDim.x + threadIdx.x; e < g.S * dh; e += gridDim.y * blockDim.x) {
+    const int s = e / dh, d = e - s * dh;
+    float ak = 0.f, av = 0.f;
+    for (int j = 0; j < nqw; ++j) {
+      const size_t r = (size_t)(q0 + j);
+      const size_t pi = (r * heads + h) * g.S + s;
+      ak = fmaf(dS[pi], q[r * C + h * dh + d], ak);
+      av = fmaf(P[pi], dout[r * C + h * dh + d], av);
+    }
+    float* row = dkv + ((size_t)w * g.S + s) * 2 * C + h * dh + d;
+    row[0] = ak * scale;
+    row[C] = av;
+  }
+}
+
+void launch_attn_bwd_kv(const Geo& g, int C, int heads, const float* q, const float* dout, const float* P,
+                        const float* dS, const int32_t* woff, float* dkv, hipStream_t s) {
+  const int dh = C / heads;
+  dim3 grid(g.nwin * heads, (g.S * dh + 255) / 256);
+  attn_bwd_kv_kernel<<<grid, 256, 0, s>>>(g, C, heads, q, dout, P, dS, woff, dkv);
+}
+
+// ------------------------------------------------------------------------------------------
+// LayerNorm backward, one wavefront per row r < *n (or n_max): rows of x at rows[r] (or r);
+// dx[r] = rstd * (dxh - mean(dxh) - xh * mean(dxh * xh)), dxh = dy * gamma, written or added
+// (accumulate) at dst row (rows ? rows[r] : r) or compact r (dst_compact).  dgamma/dbeta
+// partials per block of 64 rows: part[blk][0..C) = sum dy*xh, part[blk][C..2C) = sum dy.
+// ------------------------------------------------------------------------------------------
+constexpr int LNB_ROWS = 64;
+
+__global__ void __launch_bounds__(256) ln_bwd_kernel(const float* __restrict__ x, const int32_t* __restrict__ rows,
+                                                     const int32_t* __restrict__ n_dev, int n_max, int C,
+                                                     const float* __restrict__ g, const float* __restrict__ dy,
+                                                     float* __restrict__ dx, int accumulate, int dst_compact,
+                                                     float* __restrict__ part) {
+  extern __shared__ float red[];  // [4][2C]
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int n = n_dev ? n_dev[0] : n_max;
+  const int per = C / 64;
+  float pg[16], pb[16];
+  for (int e = 0; e < per; ++e) pg[e] = pb[e] = 0.f;
+  for (int rr = 0; rr < LNB_ROWS / 4; ++rr) {
+    const int r = blockIdx.x * LNB_ROWS + rr * 4 + wv;
+    if (r >= n) break;
+    const size_t src = rows ? (size_t)rows[r] : (size_t)r;
+    const float* xr = x + src * C;
+    const float* dyr = dy + (size_t)r * C;
+    float v[16], d[16];
+    float s = 0.f;
+    for (int e = 0; e < per; ++e) {
+      v[e] = xr[lane + 64 * e];
+      s += v[e];
+    }
+    const float mean = wave_sum(s) / C;
+    float q = 0.f;
+    for (int e = 0; e < per; ++e) {
+      const float t = v[e] - mean;
+      q += t * t;
+    }
+    const float rstd = rsqrtf(wave_sum(q) / C + 1e-5f);
+    float s1 = 0.f, s2 = 0.f;
+    for (int e = 0; e < per; ++e) {
+      const int c = lane + 64 * e;
+      const float xh = (v[e] - mean) * rstd;
+      const float dyv = dyr[c];
+      d[e] = dyv * g[c];
+      s1 += d[e];
+      s2 += d[e] * xh;
+      pg[e] += dyv * xh;
+      pb[e] += dyv;
+      v[e] = xh;
+    }
+    s1 = wave_sum(s1) / C;
+    s2 = wave_sum(s2) / C;
+    float* out = dx + (dst_compact ? (size_t)r : src) * C;
+    for (int e = 0; e < per; ++e) {
+      const int c = lane + 64 * e;
+      const float val = rstd * (d[e] - s1 - v[e] * s2);
+      out[c] = accumulate ? out[c] + val : val;
+    }
+  }
+  // fixed-order block reduction of the dgamma / dbeta partials
+  for (int e = 0; e < per; ++e) {
+    red[wv * 2 * C + lane + 64 * e] = pg[e];
+    red[wv * 2 * C + C + lane + 64 * e] = pb[e];
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < 2 * C; c += blockDim.x)
+    part[(size_t)blockIdx.x * 2 * C + c] = red[c] + red[2 * C + c] + red[4 * C + c] + red[6 * C + c];
+}
+
+void launch_ln_bwd(const float* x, const int32_t* rows, const int32_t* n_dev, int n_max, int C, const float* g,
+                   const float* dy, float* dx, int accumulate, int dst_compact, float* part, hipStream_t s) {
+  const int blocks = (n_max + LNB_ROWS - 1) / LNB_ROWS;
+  if (blocks <= 0) return;
+  ln_bwd_kernel<<<blocks, 256, 4 * 2 * C * sizeof(float), s>>>(x, rows, n_dev, n_max, C, g, dy, dx, accumulate,
+                                                              dst_compact, part);
+}
+
+int ln_bwd_blocks(int n_max) { return (n_max + LNB_ROWS - 1) / LNB_ROWS; }
+
+// out[c] (+)= sum over b < nparts of part[b][c] (in order)
+__global__ void sum_parts_kernel(const float* __restrict__ part, int nparts, int width, float* __restrict__ out,
+                                 int accumulate) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= width) return;
+  float acc = 0.f;
+  for (int b = 0; b < nparts; ++b) acc += part[(size_t)b * width + c];
+  out[c] = accumulate ? out[c] + acc : acc;
+}
+
+void launch_sum_parts(const float* part, int nparts, int width, float* out, int accumulate, hipStream_t s) {
+  if (width <= 0) return;
+  sum_parts_kernel<<<(width + 255) / 256, 256, 0, s>>>(part, nparts, width, out, accumulate);
+}
+
+// ------------------------------------------------------------------------------------------
+// Token reductions.  TN product: out[i][j] = sum_m A[arow(m)][i] * B[brow(m)][j], m < *M (or
+// M_max), A row stride lda, B row stride ldb, i < I, j < J.  Partials per chunk of RED_CHUNK
+// rows: part[chunk][i][j]; a 64 x 64 output tile per block, 4 x 4 per thread.
+// Column sums: out[j] = sum_m B[m][j] (same chunking).
+// ------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) tn_partial_kernel(const float* __restrict__ A, const int32_t* __restrict__ arow,
+                                                         int lda, const float* __restrict__ B,
+                                                         const int32_t* __restrict__ brow, int ldb,
+                                                         const int32_t* __restrict__ M_dev, int M_max, int I, int J,
+                                                         float* __restrict__ part) {
+  __shared__ float As[16][64];
+  __shared__ float Bs[16][64];
+  const int M = M_dev ? M_dev[0] : M_max;
+  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64, chunk = blockIdx.z;
+  const int m_begin = chunk * RED_CHUNK;
+  const int m_end = min(M, m_begin + RED_CHUNK);
+  const int t = threadIdx.x, ty = t >> 4, tx = t & 15;
+  float acc[4][4] = {};
+  for (int m0 = m_begin; m0 < m_end; m0 += 16) {
+    // 16 rows x 64 columns of A and of B: 1024 values each, 4 per thread
+    for (int e = t; e < 1024; e += 256) {
+      const int rr = e >> 6, cc = e & 63;
+      const int m = m0 + rr;
+      float av = 0.f, bv = 0.f;
+      if (m < m_end) {
+        const size_t ra = arow ? (size_t)arow[m] : (size_t)m;
+        const size_t rb = brow ? (size_t)brow[m] : (size_t)m;
+        if (i0 + cc < I) av = A[ra * lda + i0 + cc];
+        if (j0 + cc < J) bv = B[rb * ldb + j0 + cc];
+      }
+      As[rr][cc] = av;
+      Bs[rr][cc] = bv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      float a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = As[k][ty + 16 * u];
+        b[u] = Bs[k][tx + 16 * u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fmaf(a[u], b[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+  float* P = part + (size_t)chunk * I * J;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = i0 + ty + 16 * u;
+    if (i >= I) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int j = j0 + tx + 16 * v;
+      if (j < J) P[(size_t)i * J + j] = acc[u][v];
+    }
+  }
+}
+
+int tn_chunks(int M_max) { return (M_max + RED_CHUNK - 1) / RED_CHUNK; }
+
+void launch_tn_partial(const float* A, const int32_t* arow, int lda, const float* B, const int32_t* brow, int ldb,
+                       const int32_t* M_dev, int M_max, int I, int J, float* part, hipStream_t s) {
+  const int chunks = tn_chunks(M_max);
+  if (chunks <= 0) return;
+  dim3 grid((I + 63) / 64, (J + 63) / 64, chunks);
+  tn_partial_kernel<<<grid, 256, 0, s>>>(A, arow, lda, B, brow, ldb, M_dev, M_max, I, J, part);
+}
+
+__global__ void colsum_partial_kernel(const float* __restrict__ B, int ldb, const int32_t* __restrict__ M_dev,
+                                      int M_max, int J, float* __restrict__ part) {
+  const int M = M_dev ? M_dev[0] : M_max;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int chunk = blockIdx.y;
+  if (j >= J) return;
+  const int m_end = min(M, (chunk + 1) * RED_CHUNK);
+  float acc = 0.f;
+  for (int m = chunk * RED_CHUNK; m < m_end; ++m) acc += B[(size_t)m * ldb + j];
+  part[(size_t)chunk * J + j] = acc;
+}
+
+void launch_colsum_partial(const float* B, int ldb, const int32_t* M_dev, int M_max, int J, float* part,
+                           hipStream_t s) {
+  const int chunks = tn_chunks(M_max);
+  if (chunks <= 0) return;
+  colsum_partial_kernel<<<dim3((J + 255) / 256, chunks), 256, 0, s>>>(B, ldb, M_dev, M_max, J, part);
+}
+
+// ------------------------------------------------------------------------------------------
+// Pixel-side pieces.  Patches of the cut-out input [N][48] (k = (ky*4 + kx)*3 + c), and the
+// decoder's pre-activation gradient per token: dyt[n][k] = dpred * pred * (1 - pred) at the
+// token's pixels.  Also the full-frame decoder (all tokens) for the training forward:
+// pred = sigmoid(z W_dec + b) written to every pixel.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ size_t tok_pixel(const Geo& g, int n) {
+  int w = n / g.S, s = n - w * g.S;
+  int v = w % g.nww;
+  int r = w / g.nww;
+  int u = r % g.nwh;
+  r /= g.nwh;
+  int nT = g.T / g.wt;
+  int a = r % nT;
+  int b = r / nT;
+  int dj = s % g.ww;
+  int q = s / g.ww;
+  int di = q % g.wh;
+  int dt = q / g.wh;
+  int t = a * g.wt + dt, i = u * g.wh + di, j = v * g.ww + dj;
+  return (((size_t)b * g.T + t) * g.H + (size_t)4 * i) * g.W + (size_t)4 * j;
+}
+
+__global__ void patches_kernel(Geo g, const float* __restrict__ frames, const uint8_t* __restrict__ masks,
+                               float* __restrict__ P) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < (size_t)g.N * 48; e += (size_t)gridDim.x * blockDim.x) {
+    const int n = (int)(e / 48), k = (int)(e % 48);
+    const int pix = k / 3, c = k - 3 * pix, ky = pix >> 2, kx = pix & 3;
+    const size_t px = tok_pixel(g, n) + (size_t)ky * g.W + kx;
+    P[e] = masks[px] ? 0.f : frames[px * 3 + c];
+  }
+}
+
+void launch_patches(const Geo& g, const float* frames, const uint8_t* masks, float* P, hipStream_t s) {
+  size_t grid = ((size_t)g.N * 48 + 255) / 256;
+  if (grid > 8192) grid = 8192;
+  patches_kernel<<<(unsigned)grid, 256, 0, s>>>(g, frames, masks, P);
+}
+
+__global__ void decoder_full_kernel(Geo g, int C, const float* __restrict__ z, const float* __restrict__ dw,
+                                    const float* __restrict__ db, float* __restrict__ pred) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < (size_t)g.N * 48; e += (size_t)gridDim.x * blockDim.x) {
+    const int n = (int)(e / 48), k = (int)(e % 48);
+    const int pix = k / 3, c = k - 3 * pix, ky = pix >> 2, kx = pix & 3;
+    const float* zr = z + (size_t)n * C;
+    float acc = db[c];
+    for (int i = 0; i < C; ++i) acc = fmaf(zr[i], dw[i * 48 + k], acc);
+    const size_t px = tok_pixel(g, n) + (size_t)ky * g.W + kx;
+    pred[px * 3 + c] = 1.0f / (1.0f + expf(-acc));
+  }
+}
+
+void launch_decoder_full(const Geo& g, int C, const float* z, const float* dw, const float* db, float* pred,
+                         hipStream_t s) {
+  size_t grid = ((size_t)g.N * 48 + 255) / 256;
+  if (grid > 16384) grid = 16384;
+  decoder_full_kernel<<<(unsigned)grid, 256, 0, s>>>(g, C, z, dw, db, pred);
+}
+
+__global__ void dec_grad_tok_kernel(Geo g, const float* __restrict__ pred, const float* __restrict__ dpred,
+                                    float* __restrict__ dyt) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < (size_t)g.N * 48; e += (size_t)gridDim.x * blockDim.x) {
+    const int n = (int)(e / 48), k = (int)(e % 48);
+    const int pix = k / 3, c = k - 3 * pix, ky = pix >> 2, kx = pix & 3;
+    const size_t i = (tok_pixel(g, n) + (size_t)ky * g.W + kx) * 3 + c;
+    const float p = pred[i];
+    dyt[e] = dpred[i] * p * (1.0f - p);
+  }
+}
+
+void launch_dec_grad_tok(const Geo& g, const float* pred, const float* dpred, float* dyt, hipStream_t s) {
+  size_t grid = ((size_t)g.N * 48 + 255) / 256;
+  if (grid > 8192) grid = 8192;
+  dec_grad_tok_kernel<<<(unsigned)grid, 256, 0, s>>>(g, pred, dpred, dyt);
+}
+
+// ------------------------------------------------------------------------------------------
+// L1 training loss: L = w_in mean_{m!=0}|pred - gt| + w_out mean_{m==0}|pred - gt| over
+// pixel-channel values, and dL/dpred = w * sign(pred - gt) / count (sign(0) = 0; an empty
+// region contributes nothing).  Two passes: counts and partial sums per block (fixed order),
+// then the gradient.  acc[0..3] = (sum_in, sum_out, n_in, n_out) after the reduction.
+// ------------------------------------------------------------------------------------------
+constexpr int L1_BLOCKS = 1024;
+
+__global__ void l1_partial_kernel(const float* __restrict__ pred, const float* __restrict__ gt,
+                                  const uint8_t* __restrict__ masks, size_t npix, float* __restrict__ part) {
+  __shared__ float sh[4][256];
+  float si = 0.f, so = 0.f, ni = 0.f, no = 0.f;
+  for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < npix; p += (size_t)gridDim.x * blockDim.x) {
+    const bool in = masks[p] != 0;
+    float e = 0.f;
+    for (int c = 0; c < 3; ++c) e += fabsf(pred[3 * p + c] - gt[3 * p + c]);
+    if (in) {
+      si += e;
+      ni += 3.f;
+    } else {
+      so += e;
+      no += 3.f;
+    }
+  }
+  sh[0][threadIdx.x] = si;
+  sh[1][threadIdx.x] = so;
+  sh[2][threadIdx.x] = ni;
+  sh[3][threadIdx.x] = no;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st)
+      for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void l1_final_kernel(const float* __restrict__ part, int nb, float w_in, float w_out,
+                                float* __restrict__ acc, float* __restrict__ loss) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s[4] = {0, 0, 0, 0};
+  for (int b = 0; b < nb; ++b)
+    for (int k = 0; k < 4; ++k) s[k] += part[b * 4 + k];
+  for (int k = 0; k < 4; ++k) acc[k] = (float)s[k];
+  double L = 0.0;
+  if (s[2] > 0) L += w_in * s[0] / s[2];
+  if (s[3] > 0) L += w_out * s[1] / s[3];
+  loss[0] = (float)L;
+}
+
+__global__ void l1_grad_kernel(const float* __restrict__ pred, const float* __restrict__ gt,
+                               const uint8_t* __restrict__ masks, size_t npix, float w_in, float w_out,
+                               const float* __restrict__ acc, float* __restrict__ dpred) {
+  const float gi = acc[2] > 0.f ? w_in / acc[2] : 0.f;
+  const float go = acc[3] > 0.f ? w_out / acc[3] : 0.f;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < 3 * npix; e += (size_t)gridDim.x * blockDim.x) {
+    const float d = pred[e] - gt[e];
+    const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
+    dpred[e] = sg * (masks[e / 3] ? gi : go);
+  }
+}
+
+void launch_l1_loss(const float* pred, const float* gt, const uint8_t* masks, size_t npix, float w_in, float w_out,
+                    float* part, float* acc, float* loss, float* dpred, hipStream_t s) {
+  l1_partial_kernel<<<L1_BLOCKS, 256, 0, s>>>(pred, gt, masks, npix, part);
+  l1_final_kernel<<<1, 64, 0, s>>>(part, L1_BLOCKS, w_in, w_out, acc, loss);
+  if (dpred) {
+    size_t grid = (3 * npix + 255) / 256;
+    if (grid > 8192) grid = 8192;
+    l1_grad_kernel<<<(unsigned)grid, 256, 0, s>>>(pred, gt, masks, npix, w_in, w_out, acc, dpred);
+  }
+}
+
+}  // namespace dr
