@@ -27,11 +27,13 @@ PEAK = {"bf16": 2500.0, "fp8": 5000.0, "fp32": 157.3}  # dense TFLOP/s, MI355X
 HBM_PEAK = 8000.0  # GB/s
 
 
-def stage_flops(stage, cfg, N, Nq):
-    """Algorithmic FLOPs of one launch of each stage (padding and skipped work not counted)."""
+def stage_flops(stage, cfg, N, Nq, Na):
+    """Algorithmic FLOPs of one launch of each stage (padding and skipped work not counted):
+    N tokens, Nq query tokens, Na tokens in windows that have queries (only their keys and
+    values are ever read)."""
     C, R, S = cfg.dim, cfg.dim * cfg.mlp_ratio, cfg.window_tokens
     return {
-        "qkv": 2 * N * C * 2 * C + 2 * Nq * C * C,
+        "qkv": 2 * Na * C * 2 * C + 2 * Nq * C * C,
         "attn": 4 * Nq * S * C,
         "proj": 2 * Nq * C * C,
         "fc1": 2 * Nq * C * R,
@@ -107,7 +109,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--fp32-steps", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp8"])
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this path has no multi-GPU mode "
@@ -131,6 +135,10 @@ def main():
     clips = [(torch.from_numpy(f).cuda(), torch.from_numpy(m).cuda()) for f, m, _ in host]
     p = cfg.patch
     tok_cov = [float(m.reshape(B, T, H // p, p, Wd // p, p).any(axis=(3, 5)).mean()) for _, m, _ in host]
+    act_cov = []  # fraction of windows holding a query token (from the library's own gather)
+    for _, m in clips:
+        _, _, woff = eng.gather_tokens(m)
+        act_cov.append(float((torch.diff(woff) > 0).float().mean()))
     pix_cov = [float(m.mean()) for _, m, _ in host]
     N = B * T * (H // p) * (Wd // p)
 
@@ -144,12 +152,13 @@ def main():
     prof = profile_path(eng, clips, args.precision, len(clips) * 2, torch)
     nsteps_prof = len(clips) * 2
     mean_nq = float(np.mean([tc * N for tc in tok_cov]))
+    mean_na = float(np.mean([ac * N for ac in act_cov]))
     best = None
     for st, (ms, cnt) in prof.items():
         if best is None or ms > best[1]:
             best = (st, ms, cnt)
     st, ms, cnt = best
-    fl = stage_flops(st, cfg, N, mean_nq)
+    fl = stage_flops(st, cfg, N, mean_nq, mean_na)
     avg_s = ms / cnt / 1e3
     if fl is not None:
         ach = fl / avg_s / 1e12
@@ -161,6 +170,13 @@ def main():
                 "frac": None, "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2), "launches": cnt}
     stages = {k: {"ms_per_step": round(v[0] / nsteps_prof, 4), "launches_per_step": v[1] / nsteps_prof}
               for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])}
+
+    if args.calib_copy:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
 
     cpu = None
     if not args.no_cpu:
@@ -186,6 +202,7 @@ def main():
             "clips": "10 seeded Perlin+moving-object clips, random-walk stroke masks dilated 7 px, cycled",
             "pixel_coverage_mean": round(float(np.mean(pix_cov)), 4),
             "token_coverage_mean": round(float(np.mean(tok_cov)), 4),
+            "active_window_fraction_mean": round(float(np.mean(act_cov)), 4),
         },
         "p50_ms_per_clip": round(float(np.percentile(lat, 50)), 4),
         "p99_ms_per_clip": round(float(np.percentile(lat, 99)), 4),

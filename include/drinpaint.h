@@ -134,7 +134,9 @@ const char* dr_stage_name(int stage);
 dr_status dr_inspect(dr_ctx* ctx, const char* name, void* dst, size_t nbytes, void* stream);
 
 /* Inspection, for tests: key "blocks" = number of transformer blocks later dr_inpaint calls
- * run (-1 = all); the output then is not the network's. */
+ * run (-1 = all; the output then is not the network's); key "graphs" = 0 launches every
+ * kernel directly instead of replaying the per-block sequence as a HIP graph (default 1:
+ * the first call of a shape runs directly, the second captures, later ones replay). */
 dr_status dr_debug_set(dr_ctx* ctx, const char* key, int64_t value);
 
 /* Test hook of the FP8 path's quantiser: out[i] = e4m3(in[i] / scale) (OCP e4m3, round to

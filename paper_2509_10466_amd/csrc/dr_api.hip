@@ -146,13 +146,24 @@ void dr::dr_free_work(Work& w) {
   w = Work();
 }
 
-static void free_work(dr_ctx* c) { dr_free_work(c->work); }
+static void invalidate_graphs(dr_ctx* c) {
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+  c->graph_seen.clear();
+  c->graph_epoch++;
+}
+
+static void free_work(dr_ctx* c) {
+  invalidate_graphs(c);
+  dr_free_work(c->work);
+}
 
 extern "C" void dr_destroy(dr_ctx* c) {
   if (!c) return;
   hipSetDevice(c->device);
   hipDeviceSynchronize();
   free_work(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   dr_train_release(c);
   for (auto& kv : c->swork) {
     dr_free_work(*kv.second);
@@ -352,6 +363,8 @@ extern "C" dr_status dr_load_weights(dr_ctx* c, const void* blob, size_t nbytes)
   const size_t o_db = put(src[count - 1], 3);
 
   HIP_OK(c, hipSetDevice(c->device));
+  HIP_OK(c, hipDeviceSynchronize());
+  invalidate_graphs(c);
   for (void* p : c->weight_allocs) hipFree(p);
   c->weight_allocs.clear();
   c->have_weights = false;
@@ -510,7 +523,12 @@ dr_status dr::dr_reserve_work(dr_ctx* c, Work& w, const Geo& g, bool stream_mode
   return DR_OK;
 }
 
-static dr_status reserve_geo(dr_ctx* c, const Geo& g) { return dr_reserve_work(c, c->work, g, false); }
+static dr_status reserve_geo(dr_ctx* c, const Geo& g) {
+  const bool grows = !((size_t)g.N <= c->work.cap_tokens && (size_t)g.nwin <= c->work.cap_windows &&
+                       !c->work.stream_mode);
+  if (grows) invalidate_graphs(c);
+  return dr_reserve_work(c, c->work, g, false);
+}
 
 extern "C" dr_status dr_reserve(dr_ctx* c, int B, int T, int H, int W, dr_precision prec) {
   if (!c) return DR_EINVAL;
@@ -560,6 +578,50 @@ extern "C" dr_status dr_gather_tokens(dr_ctx* c, const uint8_t* masks, int B, in
   return DR_OK;
 }
 
+// The per-block launch sequence.  It reads only the workspace and the weights, so the same
+// sequence can be captured once per shape into a HIP graph and replayed.
+static dr_status run_blocks(dr_ctx* c, const Geo& g, dr_precision prec, hipStream_t s) {
+  const Net& n = c->net;
+  Work& w = c->work;
+  const int C = n.C, R = n.R, N = g.N;
+  const int nblk = (c->debug_blocks >= 0 && c->debug_blocks < n.cfg.blocks) ? c->debug_blocks : n.cfg.blocks;
+  for (int l = 0; l < nblk; ++l) {
+    const BlockW& b = n.blk[l];
+    if (prec == DR_FP32) {
+      LAUNCH(ST_LN1, launch_ln_f32(w.x, nullptr, nullptr, N, C, b.ln1g, b.ln1b, w.u, s));
+      LAUNCH(ST_QKV, launch_gemm_f32(w.u, nullptr, nullptr, N, C, b.wkv, b.bkv, 2 * C, EPI_STORE, w.kv, nullptr, s));
+      LAUNCH(ST_QKV, launch_gemm_f32(w.u, w.idx, w.nq, N, C, b.wq, b.bq, C, EPI_STORE, w.q, nullptr, s));
+      LAUNCH(ST_ATTN, launch_attn_f32(g, C, n.cfg.heads, w.q, w.kv, w.woff, w.o, s));
+      LAUNCH(ST_PROJ, launch_gemm_f32(w.o, nullptr, w.nq, N, C, b.wo, b.bo, C, EPI_RESID, w.x, w.idx, s));
+      LAUNCH(ST_LN2, launch_ln_f32(w.x, w.idx, w.nq, N, C, b.ln2g, b.ln2b, w.u, s));
+      LAUNCH(ST_FC1, launch_gemm_f32(w.u, nullptr, w.nq, N, C, b.w1, b.b1, R, EPI_GELU, w.h, nullptr, s));
+      LAUNCH(ST_FC2, launch_gemm_f32(w.h, nullptr, w.nq, N, R, b.w2, b.b2, C, EPI_RESID, w.x, w.idx, s));
+    } else if (prec == DR_FP8) {
+      float* am = w.amax + 4 * l;  // [0] LN1 out, [1] O, [2] LN2 out, [3] h
+      LAUNCH(ST_LN1, launch_ln_amax(w.x, nullptr, nullptr, N, w.wcount, g.S, C, b.ln1g, b.ln1b, am + 0, s));
+      LAUNCH(ST_QKV, launch_ln_qkv_fp8(g, C, n.cfg.heads, n.Spad, w.x, w.flag, w.wcount, b.ln1g, b.ln1b, b.wqkv8, b.wscale8, b.bqkv, am + 0, w.q16, w.k16, w.v16, s));
+      LAUNCH(ST_ATTN, launch_attn_bf16(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.v16, w.idx, w.woff, w.o16, am + 1, s));
+      LAUNCH(ST_PROJ, launch_gemm_fp8_resid(w.o16, w.nq, N, C, b.wo8, b.so8, am + 1, b.bo, C, w.x, w.idx, s));
+      LAUNCH(ST_LN2, launch_ln_amax(w.x, w.idx, w.nq, N, nullptr, g.S, C, b.ln2g, b.ln2b, am + 2, s));
+      LAUNCH(ST_FC1, launch_ln_fc1_fp8(N, C, R, w.x, w.idx, w.nq, b.ln2g, b.ln2b, b.w18, b.s18, b.b1, am + 2, w.h16, am + 3, s));
+      LAUNCH(ST_FC2, launch_gemm_fp8_resid(w.h16, w.nq, N, R, b.w28, b.s28, am + 3, b.b2, C, w.x, w.idx, s));
+    } else {
+      LAUNCH(ST_QKV, launch_ln_qkv_bf16(g, C, n.cfg.heads, n.Spad, w.x, w.flag, w.wcount, b.ln1g, b.ln1b, b.wqkv16, b.bqkv, w.q16, w.k16, w.v16, s));
+      LAUNCH(ST_ATTN, launch_attn_bf16(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.v16, w.idx, w.woff, w.o16, nullptr, s));
+      LAUNCH(ST_PROJ, launch_gemm_bf16(w.o16, w.nq, N, C, b.wo16, b.bo, C, EPI_RESID, w.x, w.idx, s));
+      LAUNCH(ST_FC1, launch_ln_fc1_bf16(N, C, R, w.x, w.idx, w.nq, b.ln2g, b.ln2b, b.w116, b.b1, w.h16, s));
+      LAUNCH(ST_FC2, launch_gemm_bf16(w.h16, w.nq, N, R, b.w216, b.b2, C, EPI_RESID, w.x, w.idx, s));
+    }
+  }
+  return DR_OK;
+}
+
+static std::string graph_key(const Geo& g, dr_precision prec) {
+  char buf[128];
+  snprintf(buf, sizeof buf, "%d,%d,%d,%d,%d,%d", g.B, g.T, g.H, g.W, (int)prec, 0);
+  return buf;
+}
+
 extern "C" dr_status dr_inpaint(dr_ctx* c, const float* frames, const uint8_t* masks, float* out,
                                 int B, int T, int H, int W, dr_precision prec, dr_query_set qs,
                                 void* stream) {
@@ -590,35 +652,40 @@ extern "C" dr_status dr_inpaint(dr_ctx* c, const float* frames, const uint8_t* m
   if (st != DR_OK) return st;
   LAUNCH(ST_EMBED, launch_embed(g, C, frames, masks, n.embed_wT, n.embed_b, w.x, s));
   if (prec == DR_FP8) LAUNCH(ST_LN1, launch_zero_f32(w.amax, 4 * n.cfg.blocks, s));
-  const int nblk = (c->debug_blocks >= 0 && c->debug_blocks < n.cfg.blocks) ? c->debug_blocks : n.cfg.blocks;
-  for (int l = 0; l < nblk; ++l) {
-    const BlockW& b = n.blk[l];
-    if (prec == DR_FP32) {
-      LAUNCH(ST_LN1, launch_ln_f32(w.x, nullptr, nullptr, N, C, b.ln1g, b.ln1b, w.u, s));
-      LAUNCH(ST_QKV, launch_gemm_f32(w.u, nullptr, nullptr, N, C, b.wkv, b.bkv, 2 * C, EPI_STORE, w.kv, nullptr, s));
-      LAUNCH(ST_QKV, launch_gemm_f32(w.u, w.idx, w.nq, N, C, b.wq, b.bq, C, EPI_STORE, w.q, nullptr, s));
-      LAUNCH(ST_ATTN, launch_attn_f32(g, C, n.cfg.heads, w.q, w.kv, w.woff, w.o, s));
-      LAUNCH(ST_PROJ, launch_gemm_f32(w.o, nullptr, w.nq, N, C, b.wo, b.bo, C, EPI_RESID, w.x, w.idx, s));
-      LAUNCH(ST_LN2, launch_ln_f32(w.x, w.idx, w.nq, N, C, b.ln2g, b.ln2b, w.u, s));
-      LAUNCH(ST_FC1, launch_gemm_f32(w.u, nullptr, w.nq, N, C, b.w1, b.b1, R, EPI_GELU, w.h, nullptr, s));
-      LAUNCH(ST_FC2, launch_gemm_f32(w.h, nullptr, w.nq, N, R, b.w2, b.b2, C, EPI_RESID, w.x, w.idx, s));
-    } else if (prec == DR_FP8) {
-      float* am = w.amax + 4 * l;  // [0] LN1 out, [1] O, [2] LN2 out, [3] h
-      LAUNCH(ST_LN1, launch_ln_amax(w.x, nullptr, nullptr, N, w.wcount, g.S, C, b.ln1g, b.ln1b, am + 0, s));
-      LAUNCH(ST_QKV, launch_ln_qkv_fp8(g, C, n.cfg.heads, n.Spad, w.x, w.flag, w.wcount, b.ln1g, b.ln1b, b.wqkv8, b.wscale8, b.bqkv, am + 0, w.q16, w.k16, w.v16, s));
-      LAUNCH(ST_ATTN, launch_attn_bf16(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.v16, w.idx, w.woff, w.o16, am + 1, s));
-      LAUNCH(ST_PROJ, launch_gemm_fp8_resid(w.o16, w.nq, N, C, b.wo8, b.so8, am + 1, b.bo, C, w.x, w.idx, s));
-      LAUNCH(ST_LN2, launch_ln_amax(w.x, w.idx, w.nq, N, nullptr, g.S, C, b.ln2g, b.ln2b, am + 2, s));
-      LAUNCH(ST_FC1, launch_ln_fc1_fp8(N, C, R, w.x, w.idx, w.nq, b.ln2g, b.ln2b, b.w18, b.s18, b.b1, am + 2, w.h16, am + 3, s));
-      LAUNCH(ST_FC2, launch_gemm_fp8_resid(w.h16, w.nq, N, R, b.w28, b.s28, am + 3, b.b2, C, w.x, w.idx, s));
+  dr_status br = DR_OK;
+  const bool graphable = c->use_graphs && !c->prof && c->debug_blocks < 0;
+  if (graphable) {
+    const std::string key = graph_key(g, prec) + "#" + std::to_string(c->graph_epoch);
+    auto it = c->graphs.find(key);
+    if (it != c->graphs.end()) {
+      HIP_OK(c, hipGraphLaunch(it->second, s));
+    } else if (!c->graph_seen.count(key)) {
+      // first call of this shape runs eagerly (and sets kernel attributes); the next one
+      // captures
+      c->graph_seen.insert(key);
+      br = run_blocks(c, g, prec, s);
     } else {
-      LAUNCH(ST_QKV, launch_ln_qkv_bf16(g, C, n.cfg.heads, n.Spad, w.x, w.flag, w.wcount, b.ln1g, b.ln1b, b.wqkv16, b.bqkv, w.q16, w.k16, w.v16, s));
-      LAUNCH(ST_ATTN, launch_attn_bf16(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.v16, w.idx, w.woff, w.o16, nullptr, s));
-      LAUNCH(ST_PROJ, launch_gemm_bf16(w.o16, w.nq, N, C, b.wo16, b.bo, C, EPI_RESID, w.x, w.idx, s));
-      LAUNCH(ST_FC1, launch_ln_fc1_bf16(N, C, R, w.x, w.idx, w.nq, b.ln2g, b.ln2b, b.w116, b.b1, w.h16, s));
-      LAUNCH(ST_FC2, launch_gemm_bf16(w.h16, w.nq, N, R, b.w216, b.b2, C, EPI_RESID, w.x, w.idx, s));
+      if (!c->cap_stream) HIP_OK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+      HIP_OK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+      br = run_blocks(c, g, prec, c->cap_stream);
+      hipGraph_t graph = nullptr;
+      hipError_t ec = hipStreamEndCapture(c->cap_stream, &graph);
+      if (br != DR_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return br;
+      }
+      if (ec != hipSuccess) return fail(c, DR_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
+      hipGraphExec_t exec = nullptr;
+      ec = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ec != hipSuccess) return fail(c, DR_EHIP, "graph instantiation failed: %s", hipGetErrorString(ec));
+      c->graphs[key] = exec;
+      HIP_OK(c, hipGraphLaunch(exec, s));
     }
+  } else {
+    br = run_blocks(c, g, prec, s);
   }
+  if (br != DR_OK) return br;
   LAUNCH(ST_DECODE, launch_decode(g, C, w.x, w.idx, w.nq, n.lnfg, n.lnfb, n.dec_w, n.dec_b, masks, out, s));
   if (out != frames) LAUNCH(ST_COPY, launch_copy_unmasked(npix, frames, masks, out, s));
   return DR_OK;
@@ -686,6 +753,10 @@ extern "C" dr_status dr_debug_set(dr_ctx* c, const char* key, int64_t value) {
   if (!c || !key) return fail(c, DR_EINVAL, "dr_debug_set: null argument");
   if (std::strcmp(key, "blocks") == 0) {
     c->debug_blocks = (int)value;
+    return DR_OK;
+  }
+  if (std::strcmp(key, "graphs") == 0) {
+    c->use_graphs = value != 0;
     return DR_OK;
   }
   return fail(c, DR_EINVAL, "dr_debug_set: unknown key '%s'", key);

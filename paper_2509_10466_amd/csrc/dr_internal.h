@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <map>
 #include <mutex>
+#include <set>
 #include <string>
 #include <utility>
 #include <vector>
@@ -146,6 +147,12 @@ struct dr_ctx {
   size_t used = 0;                                  // bytes of open streams' caches
   std::map<std::pair<int, int>, dr::Work*> swork;   // stream-mode workspaces by (H, W)
   void* train = nullptr;                            // training workspace (activations, scratch)
+  // HIP graphs of the per-block launch sequence, per shape and precision
+  bool use_graphs = true;
+  int graph_epoch = 0;                              // bumped when weights or workspace move
+  std::map<std::string, hipGraphExec_t> graphs;
+  std::set<std::string> graph_seen;
+  hipStream_t cap_stream = nullptr;
 };
 
 namespace dr {

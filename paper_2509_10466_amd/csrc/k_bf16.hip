@@ -228,6 +228,97 @@ __host__ __device__ constexpr size_t panel_smem_bytes(int K) {
   return (size_t)PANEL_M * (K + 8) * 2 + (size_t)2 * BN * LDS_STRIDE * 2;
 }
 
+constexpr int LN_BATCH = 8;
+
+// 128 panel rows -> LayerNorm -> bf16; K = 64 * KPER channels; lane owns channels lane + 64 e.
+template <int KPER>
+__device__ __forceinline__ void ln_rows_to_panel(const float* __restrict__ x, const int32_t* __restrict__ rows,
+                                                 int M, int m0, const float* __restrict__ lng,
+                                                 const float* __restrict__ lnb, bf16* apanel, int KS) {
+  constexpr int K = 64 * KPER;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  float g[KPER], b[KPER];
+#pragma unroll
+  for (int e = 0; e < KPER; ++e) {
+    g[e] = lng[lane + 64 * e];
+    b[e] = lnb[lane + 64 * e];
+  }
+  for (int r0 = wv; r0 < PANEL_M; r0 += LN_BATCH * (PANEL_THREADS / 64)) {
+    float v[LN_BATCH][KPER];
+#pragma unroll
+    for (int j = 0; j < LN_BATCH; ++j) {
+      const int r = r0 + j * (PANEL_THREADS / 64);
+      const int m = m0 + r;
+      if (r < PANEL_M && m < M) {
+        const float* xr = x + (size_t)(rows ? rows[m] : m) * K;
+#pragma unroll
+        for (int e = 0; e < KPER; ++e) v[j][e] = xr[lane + 64 * e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < KPER; ++e) v[j][e] = 0.f;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < LN_BATCH; ++j) {
+      const int r = r0 + j * (PANEL_THREADS / 64);
+      if (r >= PANEL_M) break;
+      bf16* arow = apanel + (size_t)r * KS;
+      if (m0 + r >= M) {
+#pragma unroll
+        for (int e = 0; e < KPER; ++e) arow[lane + 64 * e] = 0;
+        continue;
+      }
+      float sum = 0.f;
+#pragma unroll
+      for (int e = 0; e < KPER; ++e) sum += v[j][e];
+      const float mean = wave_sum(sum) / K;
+      float sq = 0.f;
+#pragma unroll
+      for (int e = 0; e < KPER; ++e) {
+        const float d = v[j][e] - mean;
+        sq += d * d;
+      }
+      const float rstd = rsqrtf(wave_sum(sq) / K + 1e-5f);
+#pragma unroll
+      for (int e = 0; e < KPER; ++e) arow[lane + 64 * e] = f2bf((v[j][e] - mean) * rstd * g[e] + b[e]);
+    }
+  }
+}
+
+// any K (multiple of 64, at most 1024): one row at a time
+__device__ __forceinline__ void ln_rows_to_panel_any(const float* __restrict__ x, const int32_t* __restrict__ rows,
+                                                     int M, int m0, int K, const float* __restrict__ lng,
+                                                     const float* __restrict__ lnb, bf16* apanel, int KS) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int per = K / 64;
+  for (int r = wv; r < PANEL_M; r += PANEL_THREADS / 64) {
+    const int m = m0 + r;
+    bf16* arow = apanel + (size_t)r * KS;
+    if (m < M) {
+      const float* xr = x + (size_t)(rows ? rows[m] : m) * K;
+      float v[16];
+      float sum = 0.f;
+      for (int e = 0; e < per; ++e) {
+        v[e] = xr[lane + 64 * e];
+        sum += v[e];
+      }
+      const float mean = wave_sum(sum) / K;
+      float sq = 0.f;
+      for (int e = 0; e < per; ++e) {
+        const float d = v[e] - mean;
+        sq += d * d;
+      }
+      const float rstd = rsqrtf(wave_sum(sq) / K + 1e-5f);
+      for (int e = 0; e < per; ++e) {
+        const int c = lane + 64 * e;
+        arow[c] = f2bf((v[e] - mean) * rstd * lng[c] + lnb[c]);
+      }
+    } else {
+      for (int e = 0; e < per; ++e) arow[lane + 64 * e] = 0;
+    }
+  }
+}
+
 template <int BN, class Epi>
 __device__ __forceinline__ void panel_gemm(const float* __restrict__ x, const int32_t* __restrict__ rows,
                                            int M, int m0, int K, const float* __restrict__ lng,
@@ -260,33 +351,14 @@ __device__ __forceinline__ void panel_gemm(const float* __restrict__ x, const in
   };
   load_w(0);
 
-  // LayerNorm prologue: wave wv normalises rows wv, wv + 8, ...
-  const int per = K / 64;
-  for (int r = wv; r < PANEL_M; r += PANEL_THREADS / 64) {
-    const int m = m0 + r;
-    bf16* arow = apanel + (size_t)r * KS;
-    if (m < M) {
-      const float* xr = x + (size_t)(rows ? rows[m] : m) * K;
-      float v[16];
-      float sum = 0.f;
-      for (int e = 0; e < per; ++e) {
-        v[e] = xr[lane + 64 * e];
-        sum += v[e];
-      }
-      const float mean = wave_sum(sum) / K;
-      float sq = 0.f;
-      for (int e = 0; e < per; ++e) {
-        const float d = v[e] - mean;
-        sq += d * d;
-      }
-      const float rstd = rsqrtf(wave_sum(sq) / K + 1e-5f);
-      for (int e = 0; e < per; ++e) {
-        const int c = lane + 64 * e;
-        arow[c] = f2bf((v[e] - mean) * rstd * lng[c] + lnb[c]);
-      }
-    } else {
-      for (int e = 0; e < per; ++e) arow[lane + 64 * e] = 0;
-    }
+  // LayerNorm prologue: wave wv normalises rows wv, wv + 8, ... in batches of LN_BATCH rows
+  // whose loads are all issued before the first reduction (hides the load latency).
+  switch (K / 64) {
+    case 1: ln_rows_to_panel<1>(x, rows, M, m0, lng, lnb, apanel, KS); break;
+    case 2: ln_rows_to_panel<2>(x, rows, M, m0, lng, lnb, apanel, KS); break;
+    case 4: ln_rows_to_panel<4>(x, rows, M, m0, lng, lnb, apanel, KS); break;
+    case 6: ln_rows_to_panel<6>(x, rows, M, m0, lng, lnb, apanel, KS); break;
+    default: ln_rows_to_panel_any(x, rows, M, m0, K, lng, lnb, apanel, KS); break;
   }
   stash_w(0);
   __syncthreads();

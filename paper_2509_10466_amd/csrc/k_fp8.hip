@@ -143,6 +143,59 @@ __host__ __device__ constexpr size_t f8_panel_smem(int K) {
   return (size_t)F8_PANEL_M * (K + 16) + (size_t)2 * BN * F8_WST;
 }
 
+constexpr int F8_LN_BATCH = 8;
+
+template <int PER2>
+__device__ __forceinline__ void f8_ln_rows(const float* __restrict__ x, const int32_t* __restrict__ rows, int M,
+                                           int m0, const float* __restrict__ lng, const float* __restrict__ lnb,
+                                           float inv_sa, uint8_t* apanel, int KS) {
+  constexpr int K = 128 * PER2;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int r0 = wv; r0 < F8_PANEL_M; r0 += F8_LN_BATCH * (F8_THREADS / 64)) {
+    float2 v[F8_LN_BATCH][PER2];
+#pragma unroll
+    for (int j = 0; j < F8_LN_BATCH; ++j) {
+      const int m = m0 + r0 + j * (F8_THREADS / 64);
+      if (m < M) {
+        const float* xr = x + (size_t)(rows ? rows[m] : m) * K;
+#pragma unroll
+        for (int e = 0; e < PER2; ++e) v[j][e] = *reinterpret_cast<const float2*>(xr + 2 * lane + 128 * e);
+      } else {
+#pragma unroll
+        for (int e = 0; e < PER2; ++e) v[j][e] = make_float2(0.f, 0.f);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < F8_LN_BATCH; ++j) {
+      const int r = r0 + j * (F8_THREADS / 64);
+      uint8_t* arow = apanel + (size_t)r * KS;
+      if (m0 + r >= M) {
+#pragma unroll
+        for (int e = 0; e < PER2; ++e) *reinterpret_cast<uint16_t*>(arow + 2 * lane + 128 * e) = 0;
+        continue;
+      }
+      float sum = 0.f;
+#pragma unroll
+      for (int e = 0; e < PER2; ++e) sum += v[j][e].x + v[j][e].y;
+      const float mean = wave_sum(sum) / K;
+      float sq = 0.f;
+#pragma unroll
+      for (int e = 0; e < PER2; ++e) {
+        const float d0 = v[j][e].x - mean, d1 = v[j][e].y - mean;
+        sq += d0 * d0 + d1 * d1;
+      }
+      const float rstd = rsqrtf(wave_sum(sq) / K + 1e-5f);
+#pragma unroll
+      for (int e = 0; e < PER2; ++e) {
+        const int c = 2 * lane + 128 * e;
+        const float y0 = ((v[j][e].x - mean) * rstd * lng[c] + lnb[c]) * inv_sa;
+        const float y1 = ((v[j][e].y - mean) * rstd * lng[c + 1] + lnb[c + 1]) * inv_sa;
+        *reinterpret_cast<uint16_t*>(arow + c) = (uint16_t)f32x2_to_fp8(y0, y1);
+      }
+    }
+  }
+}
+
 template <int BN, class Epi>
 __device__ __forceinline__ void f8_panel_gemm(const float* __restrict__ x, const int32_t* __restrict__ rows, int M,
                                               int m0, int K, const float* __restrict__ lng,
@@ -175,35 +228,15 @@ __device__ __forceinline__ void f8_panel_gemm(const float* __restrict__ x, const
   };
   load_w(0);
 
-  // LayerNorm prologue: lane handles channel pairs (2*lane + 128*e, +1)
-  const int per2 = K / 128;
-  for (int r = wv; r < F8_PANEL_M; r += F8_THREADS / 64) {
-    const int m = m0 + r;
-    uint8_t* arow = apanel + (size_t)r * KS;
-    if (m < M) {
-      const float* xr = x + (size_t)(rows ? rows[m] : m) * K;
-      float2 v[8];
-      float sum = 0.f;
-      for (int e = 0; e < per2; ++e) {
-        v[e] = *reinterpret_cast<const float2*>(xr + 2 * lane + 128 * e);
-        sum += v[e].x + v[e].y;
-      }
-      const float mean = wave_sum(sum) / K;
-      float sq = 0.f;
-      for (int e = 0; e < per2; ++e) {
-        const float d0 = v[e].x - mean, d1 = v[e].y - mean;
-        sq += d0 * d0 + d1 * d1;
-      }
-      const float rstd = rsqrtf(wave_sum(sq) / K + 1e-5f);
-      for (int e = 0; e < per2; ++e) {
-        const int c = 2 * lane + 128 * e;
-        const float y0 = ((v[e].x - mean) * rstd * lng[c] + lnb[c]) * inv_sa;
-        const float y1 = ((v[e].y - mean) * rstd * lng[c + 1] + lnb[c + 1]) * inv_sa;
-        *reinterpret_cast<uint16_t*>(arow + c) = (uint16_t)f32x2_to_fp8(y0, y1);
-      }
-    } else {
-      for (int e = 0; e < per2; ++e) *reinterpret_cast<uint16_t*>(arow + 2 * lane + 128 * e) = 0;
-    }
+  // LayerNorm prologue: lane handles channel pairs (2*lane + 128*e, +1); rows in batches whose
+  // loads are issued before the first reduction
+  switch (K / 128) {
+    case 1: f8_ln_rows<1>(x, rows, M, m0, lng, lnb, inv_sa, apanel, KS); break;
+    case 2: f8_ln_rows<2>(x, rows, M, m0, lng, lnb, inv_sa, apanel, KS); break;
+    case 3: f8_ln_rows<3>(x, rows, M, m0, lng, lnb, inv_sa, apanel, KS); break;
+    case 4: f8_ln_rows<4>(x, rows, M, m0, lng, lnb, inv_sa, apanel, KS); break;
+    case 6: f8_ln_rows<6>(x, rows, M, m0, lng, lnb, inv_sa, apanel, KS); break;
+    default: f8_ln_rows<8>(x, rows, M, m0, lng, lnb, inv_sa, apanel, KS); break;
   }
   stash_w(0);
   __syncthreads();

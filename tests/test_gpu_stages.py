@@ -1,0 +1,58 @@
+"""Stage-level parity: the residual stream after the patch embedding and after each block,
+read back through the inspection entry point, against the oracle's intermediates."""
+import numpy as np
+import pytest
+
+import drsynth
+from oracle import network as on
+from tests.gpu_util import case_inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _x_after(eng, cfg, frames, masks, nblocks, precision):
+    f = torch.from_numpy(frames).cuda()
+    m = torch.from_numpy(masks).cuda()
+    eng.debug_set("blocks", nblocks)
+    eng(f, m, precision)
+    torch.cuda.synchronize()
+    B, T, H, W, _ = frames.shape
+    N = B * T * (H // 4) * (W // 4)
+    x = eng.inspect("x", N * cfg.dim * 4).view(torch.float32).reshape(N, cfg.dim).cpu().numpy()
+    eng.debug_set("blocks", -1)
+    return x
+
+
+def _window_major(xgrid, cfg):
+    return on.to_windows(xgrid, cfg).reshape(-1, cfg.dim)
+
+
+@pytest.mark.parametrize("case", ["tiny64", "mid"])
+@pytest.mark.parametrize("precision,tol", [("fp32", 2e-5), ("bf16", 3e-2)])
+def test_residual_stream_per_block(dev, case, precision, tol):
+    from paper_2509_10466_amd import Inpainter
+    cfg, frames, masks = case_inputs(case)
+    W = drsynth.make_weights(cfg, 0)
+    eng = Inpainter(cfg, W)
+    d = on.forward_detail(frames, masks, W, cfg, keep_blocks=True)
+    ref0 = _window_major(d["x0"], cfg)
+    x0 = _x_after(eng, cfg, frames, masks, 0, precision)
+    np.testing.assert_allclose(x0, ref0, rtol=0, atol=2e-5)  # embedding is FP32 in every mode
+    flags = _window_major(d["flags"][..., None].astype(np.float64), cfg)[:, 0] > 0
+    for l in range(cfg.blocks):
+        ref = _window_major(on.from_windows(on.to_windows(d["blocks"][l]["x2"], cfg), cfg), cfg)
+        ref = np.where(flags[:, None], ref, ref0)  # unflagged tokens keep their embedding
+        x = _x_after(eng, cfg, frames, masks, l + 1, precision)
+        assert np.array_equal(x[~flags], x0[~flags]), "unflagged tokens changed"
+        scale = np.abs(ref[flags]).max()
+        err = np.abs(x[flags] - ref[flags]).max()
+        assert err <= tol * max(scale, 1.0), (l, err, scale)
+    eng.close()
