@@ -158,6 +158,9 @@ size_t dr_stream_footprint(dr_ctx* ctx, int H, int W);
 /* Open a stream of H x W frames (H, W multiples of the window's pixel size); *sid receives
  * its id.  DR_ENOMEM if its footprint does not fit the budget (admit it later). */
 dr_status dr_stream_open(dr_ctx* ctx, int H, int W, int32_t* sid);
+/* As dr_stream_open with `slots` past frames kept (the thesis's memory slots, 0..win_t-1;
+ * dr_stream_open keeps win_t - 1).  Footprint scales with slots + 1. */
+dr_status dr_stream_open_slots(dr_ctx* ctx, int H, int W, int slots, int32_t* sid);
 /* Close a stream (waits for the device) and release its memory. */
 dr_status dr_stream_close(dr_ctx* ctx, int32_t sid);
 /* Inpaint the newest frame of n (1..16) distinct streams of one resolution in one batch.

@@ -27,10 +27,14 @@ F64 = np.float64
 
 
 class StreamState:
-    """Per-stream cache: kv[l] is a list (oldest first) of (K, V), each [Ht, Wt, C]."""
+    """Per-stream cache: kv[l] is a list (oldest first) of (K, V), each [Ht, Wt, C].  ``slots``
+    is the number of past frames kept (the thesis's memory slots m); default win_t - 1."""
 
-    def __init__(self, cfg):
+    def __init__(self, cfg, slots=None):
         self.cfg = cfg
+        self.slots = cfg.win_t - 1 if slots is None else int(slots)
+        if not 0 <= self.slots <= cfg.win_t - 1:
+            raise ValueError("slots must be in [0, win_t - 1]")
         self.kv = [[] for _ in range(cfg.blocks)]
 
 
@@ -83,7 +87,7 @@ def step(state: StreamState, frame, mask, W, cfg, query_set="masked"):
         new_kv.append((k, v))
     for l in range(cfg.blocks):
         state.kv[l].append(new_kv[l])
-        if len(state.kv[l]) > cfg.win_t - 1:
+        while len(state.kv[l]) > state.slots:
             state.kv[l].pop(0)
     z = on.layer_norm(x, np.asarray(W["lnf.g"], F64), np.asarray(W["lnf.b"], F64))
     pred = on.sigmoid(on.decode_logits(z[None, None], W["dec.w"], W["dec.b"], p))[0, 0]
@@ -106,7 +110,7 @@ def _cross_attention(q, k, v, heads):
     return o.transpose(0, 2, 1, 3).reshape(*lead, Sq, C)
 
 
-def run_stream(frames, masks, W, cfg, query_set="masked"):
+def run_stream(frames, masks, W, cfg, query_set="masked", slots=None):
     """Replay a whole stream: frames [T, H, W, 3], masks [T, H, W] -> outputs [T, H, W, 3]."""
-    st = StreamState(cfg)
+    st = StreamState(cfg, slots)
     return np.stack([step(st, frames[t], masks[t], W, cfg, query_set)[0] for t in range(len(frames))])

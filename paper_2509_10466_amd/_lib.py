@@ -62,6 +62,7 @@ def load():
         "dr_set_budget": (I, [P, Z]),
         "dr_stream_footprint": (Z, [P, I, I]),
         "dr_stream_open": (I, [P, I, I, ct.POINTER(ct.c_int32)]),
+        "dr_stream_open_slots": (I, [P, I, I, I, ct.POINTER(ct.c_int32)]),
         "dr_stream_close": (I, [P, ct.c_int32]),
         "dr_stream_step": (I, [P, I, P, P, P, P, I, I, P]),
         "dr_server_create": (I, [P, I, ct.POINTER(P)]),

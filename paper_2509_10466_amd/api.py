@@ -172,9 +172,14 @@ class Inpainter:
     def stream_footprint(self, H: int, W: int) -> int:
         return int(self.lib.dr_stream_footprint(self._ctx, H, W))
 
-    def stream_open(self, H: int, W: int) -> int:
+    def stream_open(self, H: int, W: int, slots: int | None = None) -> int:
+        """Open a stream of H x W frames keeping `slots` past frames (default win_t - 1)."""
         sid = ct.c_int32()
-        _lib.check(self.lib, self._ctx, self.lib.dr_stream_open(self._ctx, H, W, ct.byref(sid)))
+        if slots is None:
+            st = self.lib.dr_stream_open(self._ctx, H, W, ct.byref(sid))
+        else:
+            st = self.lib.dr_stream_open_slots(self._ctx, H, W, int(slots), ct.byref(sid))
+        _lib.check(self.lib, self._ctx, st)
         return sid.value
 
     def stream_close(self, sid: int):

@@ -102,9 +102,9 @@ struct StreamTable {
   bf16* k[STREAM_MAXB];     // cache base of request r, advanced to the current block (slot 0)
   bf16* v[STREAM_MAXB];
   int head[STREAM_MAXB];    // slot receiving the new frame
-  int npast[STREAM_MAXB];   // cached past frames (<= T - 1)
+  int npast[STREAM_MAXB];   // cached past frames (<= ring - 1)
+  int T[STREAM_MAXB];       // frames in the request's ring (memory slots + 1)
   long long slot_stride;    // elements between slots
-  int T;                    // slots in the ring
 };
 
 struct FramePtrs {          // per-request device buffers of a stream-mode batch
@@ -119,6 +119,7 @@ struct FramePtrs {          // per-request device buffers of a stream-mode batch
 namespace dr {
 struct StreamSt {
   int H = 0, W = 0;
+  int slots = 0;        // past frames kept (memory slots); the ring holds slots + 1 frames
   bf16* kc = nullptr;
   bf16* vc = nullptr;
   int head = 0, npast = 0;

@@ -49,9 +49,9 @@ namespace dr {
 bool attn_bf16_supported(int dh, int spad);
 }
 
-static size_t stream_bytes(const dr_ctx* c, int H, int W) {
+static size_t stream_bytes(const dr_ctx* c, int H, int W, int slots) {
   const size_t tok = (size_t)(H / c->net.P) * (W / c->net.P);
-  return (size_t)2 * c->net.cfg.win_t * c->net.cfg.blocks * tok * c->net.C * 2;
+  return (size_t)2 * (slots + 1) * c->net.cfg.blocks * tok * c->net.C * 2;
 }
 
 static dr_status check_frame_shape(dr_ctx* c, int H, int W) {
@@ -69,13 +69,17 @@ extern "C" dr_status dr_set_budget(dr_ctx* c, size_t bytes) {
   return DR_OK;
 }
 
-extern "C" size_t dr_stream_footprint(dr_ctx* c, int H, int W) { return c ? stream_bytes(c, H, W) : 0; }
+extern "C" size_t dr_stream_footprint(dr_ctx* c, int H, int W) {
+  return c ? stream_bytes(c, H, W, c->net.cfg.win_t - 1) : 0;
+}
 
-extern "C" dr_status dr_stream_open(dr_ctx* c, int H, int W, int32_t* sid) {
+extern "C" dr_status dr_stream_open_slots(dr_ctx* c, int H, int W, int slots, int32_t* sid) {
   if (!c || !sid) return dr_fail(c, DR_EINVAL, "dr_stream_open: null argument");
+  if (slots < 0 || slots > c->net.cfg.win_t - 1)
+    return dr_fail(c, DR_EINVAL, "memory slots must be in [0, %d]", c->net.cfg.win_t - 1);
   dr_status st = check_frame_shape(c, H, W);
   if (st != DR_OK) return st;
-  const size_t bytes = stream_bytes(c, H, W);
+  const size_t bytes = stream_bytes(c, H, W, slots);
   std::lock_guard<std::mutex> lk(c->smu);
   if (c->budget && c->used + bytes > c->budget)
     return dr_fail(c, DR_ENOMEM, "stream of %zu bytes exceeds the budget (%zu of %zu in use)", bytes, c->used,
@@ -84,6 +88,7 @@ extern "C" dr_status dr_stream_open(dr_ctx* c, int H, int W, int32_t* sid) {
   StreamSt s;
   s.H = H;
   s.W = W;
+  s.slots = slots;
   s.bytes = bytes;
   if (hipMalloc(&s.kc, bytes / 2) != hipSuccess) return dr_fail(c, DR_ENOMEM, "stream cache allocation failed");
   if (hipMalloc(&s.vc, bytes / 2) != hipSuccess) {
@@ -95,6 +100,11 @@ extern "C" dr_status dr_stream_open(dr_ctx* c, int H, int W, int32_t* sid) {
   c->used += bytes;
   *sid = id;
   return DR_OK;
+}
+
+extern "C" dr_status dr_stream_open(dr_ctx* c, int H, int W, int32_t* sid) {
+  if (!c) return DR_EINVAL;
+  return dr_stream_open_slots(c, H, W, c->net.cfg.win_t - 1, sid);
 }
 
 extern "C" dr_status dr_stream_close(dr_ctx* c, int32_t sid) {
@@ -157,9 +167,9 @@ static dr_status stream_step_locked(dr_ctx* c, Work& w, int n, const int32_t* si
       tab.v[r] = st[r]->vc + (size_t)l * blk_elems;
       tab.head[r] = st[r]->head;
       tab.npast[r] = st[r]->npast;
+      tab.T[r] = st[r]->slots + 1;
     }
     tab.slot_stride = (long long)L * blk_elems;
-    tab.T = net.cfg.win_t;
     LAUNCH(ST_QKV, launch_ln_qkv_stream(g, C, net.cfg.heads, w.x, w.flag, b.ln1g, b.ln1b, b.wqkv16, b.bqkv, w.q16, tab, s));
     LAUNCH(ST_ATTN, launch_attn_stream(tab, g, C, net.cfg.heads, net.Spad, w.q16, w.idx, w.woff, w.o16, s));
     LAUNCH(ST_PROJ, launch_gemm_bf16(w.o16, w.nq, N, C, b.wo16, b.bo, C, EPI_RESID, w.x, w.idx, s));
@@ -171,8 +181,8 @@ static dr_status stream_step_locked(dr_ctx* c, Work& w, int n, const int32_t* si
   LAUNCH(ST_COPY, launch_scatter_frames(fp, npix, w.ost, s));
   // the new frame now occupies the head slot
   for (int r = 0; r < n; ++r) {
-    st[r]->head = (st[r]->head + 1) % net.cfg.win_t;
-    st[r]->npast = std::min(st[r]->npast + 1, net.cfg.win_t - 1);
+    st[r]->head = (st[r]->head + 1) % (st[r]->slots + 1);
+    st[r]->npast = std::min(st[r]->npast + 1, st[r]->slots);
   }
   return DR_OK;
 }

@@ -801,7 +801,7 @@ __global__ void __launch_bounds__(256) attn_stream_kernel(StreamTable tab, int C
   const int np = tab.npast[r], hd = tab.head[r];
   const size_t off = ((size_t)wl * heads + h) * Sf * DH;
   for (int j = 0; j <= np; ++j) {
-    const int slot = (hd - np + j + tab.T) % tab.T;
+    const int slot = (hd - np + j + tab.T[r]) % tab.T[r];
     attn_stage<DH, NT>(Ks, Vs, tab.k[r] + (size_t)slot * tab.slot_stride + off,
                        tab.v[r] + (size_t)slot * tab.slot_stride + off, j * Sf, Sf);
   }

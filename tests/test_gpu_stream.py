@@ -137,3 +137,18 @@ def test_server_results_equal_direct_steps(eng):
             assert np.array_equal(outs[k][t].cpu().numpy(), ref[k][t]), (k, t)
     for k in sids:
         eng.stream_close(sids[k])
+
+
+@pytest.mark.parametrize("slots", [1, 2, 3])
+def test_stream_memory_slots_match_oracle(eng, slots):
+    f, m = video(21 + slots, 5)
+    sid = eng.stream_open(40, 72, slots=slots)
+    st = ost.StreamState(MID, slots)
+    for t in range(5):
+        out = _step(eng, [sid], [f[t]], [m[t]])[0]
+        ref, _ = ost.step(st, f[t], m[t], eng.W, MID)
+        inside = np.repeat(m[t][..., None] != 0, 3, -1)
+        assert np.array_equal(out[~inside], f[t][~inside])
+        if inside.any():
+            assert float(np.abs(out[inside] - ref[inside]).max()) <= TOL["bf16"], (slots, t)
+    eng.stream_close(sid)

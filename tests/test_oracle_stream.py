@@ -76,3 +76,22 @@ def test_stream_is_causal_and_differs_from_clip_mode():
     assert not np.allclose(outs[-1], clip[-1], atol=1e-6)
     # outside the mask the input is returned bit for bit
     assert np.array_equal(outs[:, :, :][m == 0], f[m == 0].astype(np.float64))
+
+
+def test_memory_slots_bound_the_history():
+    """With m memory slots, frames older than m steps no longer matter; m = 0 is per-frame."""
+    cfg = SCFG
+    W = drsynth.make_weights(cfg, 1, std=0.2)
+    f, m = _frames(5, T=3)
+    m[-1, 3:11, 5:17] = 1
+    f2 = f.copy()
+    f2[0] = 0.25
+    a = ost.run_stream(f, m, W, cfg, slots=1)
+    b = ost.run_stream(f2, m, W, cfg, slots=1)
+    assert np.array_equal(a[-1], b[-1])  # frame 0 dropped by frame 2
+    c = ost.run_stream(f2, m, W, cfg, slots=2)
+    assert not np.array_equal(a[-1], c[-1])
+    single = drsynth.NetCfg(**{**SCFG.__dict__, "win_t": 1})
+    z = ost.run_stream(f, m, W, cfg, slots=0)[-1]
+    ref = on.forward(f[None, -1:], m[None, -1:], W, single)[0, 0]
+    np.testing.assert_allclose(z, ref, rtol=0, atol=1e-13)
