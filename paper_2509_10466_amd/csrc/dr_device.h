@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
+#include <utility>
 
 namespace dr {
 
@@ -13,8 +15,22 @@ typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef uint16_t u16x8_t __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));  // 16-byte load/store unit
 
 constexpr int WAVE = 64;
+
+// Compile-time loop: f(std::integral_constant<int, i>) for i = 0 .. N-1.  Register arrays
+// indexed only through it keep constant indices from the first optimisation pass on, so they
+// stay in VGPRs (a runtime-indexed array can be placed in scratch or LDS, which turns every
+// register prefetch into a round trip through memory).
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 // float -> bfloat16 bits, round to nearest even; NaN stays NaN.
 __device__ __forceinline__ uint16_t f2bf(float f) {

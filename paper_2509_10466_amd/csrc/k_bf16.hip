@@ -89,34 +89,30 @@ __device__ __forceinline__ void gemm_tile(const bf16* __restrict__ A, int M, int
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
-  uint4 ra[A_CHUNKS], rw[W_CHUNKS];
+  u32x4_t ra[A_CHUNKS], rw[W_CHUNKS];
   auto load = [&](int k0) {
-#pragma unroll
-    for (int c = 0; c < A_CHUNKS; ++c) {
+    static_for<A_CHUNKS>([&](auto c) {
       const int id = t + 256 * c;
       const int row = id >> 3, col = (id & 7) * 8;
       const int m = m0 + row;
-      ra[c] = (m < M) ? *reinterpret_cast<const uint4*>(A + (size_t)m * K + k0 + col)
-                      : make_uint4(0, 0, 0, 0);
-    }
-#pragma unroll
-    for (int c = 0; c < W_CHUNKS; ++c) {
+      ra[c] = (m < M) ? *reinterpret_cast<const u32x4_t*>(A + (size_t)m * K + k0 + col)
+                      : u32x4_t{0u, 0u, 0u, 0u};
+    });
+    static_for<W_CHUNKS>([&](auto c) {
       const int id = t + 256 * c;
       const int row = id >> 3, col = (id & 7) * 8;
-      rw[c] = *reinterpret_cast<const uint4*>(W + (size_t)(n0 + row) * K + k0 + col);
-    }
+      rw[c] = *reinterpret_cast<const u32x4_t*>(W + (size_t)(n0 + row) * K + k0 + col);
+    });
   };
   auto stash = [&](int buf) {
-#pragma unroll
-    for (int c = 0; c < A_CHUNKS; ++c) {
+    static_for<A_CHUNKS>([&](auto c) {
       const int id = t + 256 * c;
-      *reinterpret_cast<uint4*>(&sm.a[buf][id >> 3][(id & 7) * 8]) = ra[c];
-    }
-#pragma unroll
-    for (int c = 0; c < W_CHUNKS; ++c) {
+      *reinterpret_cast<u32x4_t*>(&sm.a[buf][id >> 3][(id & 7) * 8]) = ra[c];
+    });
+    static_for<W_CHUNKS>([&](auto c) {
       const int id = t + 256 * c;
-      *reinterpret_cast<uint4*>(&sm.w[buf][id >> 3][(id & 7) * 8]) = rw[c];
-    }
+      *reinterpret_cast<u32x4_t*>(&sm.w[buf][id >> 3][(id & 7) * 8]) = rw[c];
+    });
   };
 
   load(0);
@@ -334,20 +330,18 @@ __device__ __forceinline__ void panel_gemm(const float* __restrict__ x, const in
   const int wm = wv >> 2, wn = wv & 3;
   const int l16 = lane & 15, kg = lane >> 4;
 
-  uint4 rw[W_CHUNKS];
+  u32x4_t rw[W_CHUNKS];
   auto load_w = [&](int k0) {
-#pragma unroll
-    for (int c = 0; c < W_CHUNKS; ++c) {
+    static_for<W_CHUNKS>([&](auto c) {
       const int id = t + PANEL_THREADS * c;
-      rw[c] = *reinterpret_cast<const uint4*>(W + (size_t)(n0 + (id >> 3)) * K + k0 + (id & 7) * 8);
-    }
+      rw[c] = *reinterpret_cast<const u32x4_t*>(W + (size_t)(n0 + (id >> 3)) * K + k0 + (id & 7) * 8);
+    });
   };
   auto stash_w = [&](int buf) {
-#pragma unroll
-    for (int c = 0; c < W_CHUNKS; ++c) {
+    static_for<W_CHUNKS>([&](auto c) {
       const int id = t + PANEL_THREADS * c;
-      *reinterpret_cast<uint4*>(wst + ((size_t)buf * BN + (id >> 3)) * LDS_STRIDE + (id & 7) * 8) = rw[c];
-    }
+      *reinterpret_cast<u32x4_t*>(wst + ((size_t)buf * BN + (id >> 3)) * LDS_STRIDE + (id & 7) * 8) = rw[c];
+    });
   };
   load_w(0);
 
@@ -488,6 +482,17 @@ void launch_ln_qkv_bf16(const Geo& g, int C, int heads, int Spad, const float* x
     qkv_launch<64>(g, C, heads, Spad, x, flag, wcount, lng, lnb, w, bias, q, k, v, s);
 }
 
+// Entry r of a per-request table held in the kernel arguments, read through selects: a
+// runtime index into the argument struct would copy the whole table to scratch memory.
+template <class T>
+__device__ __forceinline__ T pick(const T (&a)[STREAM_MAXB], int r) {
+  T v = a[0];
+  static_for<STREAM_MAXB>([&](auto i) {
+    if (i == r) v = a[i];
+  });
+  return v;
+}
+
 // Stream-mode Q/K/V epilogue: Q rows into the batch buffer; K and V of every token into the
 // current ring slot of its request's cache ([win_f][head][S_f][dh] per block and slot).
 struct StreamQkvEpi {
@@ -508,7 +513,7 @@ struct StreamQkvEpi {
       const int c = n - part * C, hh = c / dh, d = c - hh * dh;
       const int w = m / Sf, s = m - w * Sf;
       const int r = w / nwin_f, wl = w - r * nwin_f;
-      dst = (part == 1 ? tab.k[r] : tab.v[r]) + (size_t)tab.head[r] * tab.slot_stride +
+      dst = (part == 1 ? pick(tab.k, r) : pick(tab.v, r)) + (size_t)pick(tab.head, r) * tab.slot_stride +
             (((size_t)wl * heads + hh) * Sf + s) * dh + d;
     }
     *reinterpret_cast<uint2*>(dst) = pk;
@@ -798,12 +803,14 @@ __global__ void __launch_bounds__(256) attn_stream_kernel(StreamTable tab, int C
   const int qbase = blockIdx.y * 64;
   if (qbase >= nqw) return;
   const int r = w / nwin_f, wl = w - r * nwin_f;
-  const int np = tab.npast[r], hd = tab.head[r];
+  const int np = pick(tab.npast, r), hd = pick(tab.head, r), nT = pick(tab.T, r);
+  const bf16* kr = pick(tab.k, r);
+  const bf16* vr = pick(tab.v, r);
   const size_t off = ((size_t)wl * heads + h) * Sf * DH;
   for (int j = 0; j <= np; ++j) {
-    const int slot = (hd - np + j + tab.T[r]) % tab.T[r];
-    attn_stage<DH, NT>(Ks, Vs, tab.k[r] + (size_t)slot * tab.slot_stride + off,
-                       tab.v[r] + (size_t)slot * tab.slot_stride + off, j * Sf, Sf);
+    const int slot = (hd - np + j + nT) % nT;
+    attn_stage<DH, NT>(Ks, Vs, kr + (size_t)slot * tab.slot_stride + off, vr + (size_t)slot * tab.slot_stride + off,
+                       j * Sf, Sf);
   }
   const int S = (np + 1) * Sf;
   // zero the pad keys (rows of K, columns of V^T) so that P = 0 meets finite values

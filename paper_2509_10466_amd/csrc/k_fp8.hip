@@ -211,19 +211,19 @@ __device__ __forceinline__ void f8_panel_gemm(const float* __restrict__ x, const
   const int wm = wv >> 2, wn = wv & 3;
   const int l16 = lane & 15, kg = lane >> 4;
 
-  uint4 rw[W_CHUNKS];
+  u32x4_t rw[W_CHUNKS];
   auto load_w = [&](int k0) {
 #pragma unroll
     for (int c = 0; c < W_CHUNKS; ++c) {
       const int id = t + F8_THREADS * c;
-      rw[c] = *reinterpret_cast<const uint4*>(W + (size_t)(n0 + (id >> 3)) * K + k0 + (id & 7) * 16);
+      rw[c] = *reinterpret_cast<const u32x4_t*>(W + (size_t)(n0 + (id >> 3)) * K + k0 + (id & 7) * 16);
     }
   };
   auto stash_w = [&](int buf) {
 #pragma unroll
     for (int c = 0; c < W_CHUNKS; ++c) {
       const int id = t + F8_THREADS * c;
-      *reinterpret_cast<uint4*>(wst + ((size_t)buf * BN + (id >> 3)) * F8_WST + (id & 7) * 16) = rw[c];
+      *reinterpret_cast<u32x4_t*>(wst + ((size_t)buf * BN + (id >> 3)) * F8_WST + (id & 7) * 16) = rw[c];
     }
   };
   load_w(0);
@@ -464,16 +464,16 @@ __global__ void __launch_bounds__(256) gemm_fp8_resid_kernel(const bf16* __restr
   const int l16 = lane & 15, kg = lane >> 4;
   // A stage: 64 rows x 128 k = 1024 chunks of 8 bf16 -> 4 per thread; W stage: 128 rows x
   // 128 B = 1024 chunks of 16 B -> 4 per thread
-  uint4 ra[4], rw[4];
+  u32x4_t ra[4], rw[4];
   auto load = [&](int k0) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int id = t + 256 * c;
       const int row = id >> 4, col = (id & 15) * 8;
       const int m = m0 + row;
-      ra[c] = m < M ? *reinterpret_cast<const uint4*>(A + (size_t)m * K + k0 + col) : make_uint4(0, 0, 0, 0);
+      ra[c] = m < M ? *reinterpret_cast<const u32x4_t*>(A + (size_t)m * K + k0 + col) : u32x4_t{0u, 0u, 0u, 0u};
       const int wr = id >> 3, wc = (id & 7) * 16;
-      rw[c] = *reinterpret_cast<const uint4*>(W + (size_t)(n0 + wr) * K + k0 + wc);
+      rw[c] = *reinterpret_cast<const u32x4_t*>(W + (size_t)(n0 + wr) * K + k0 + wc);
     }
   };
   auto stash = [&](int buf) {
@@ -489,7 +489,7 @@ __global__ void __launch_bounds__(256) gemm_fp8_resid_kernel(const bf16* __restr
            (f32x2_to_fp8(bf2f(w4[3] & 0xffff) * inv_sa, bf2f(w4[3] >> 16) * inv_sa) << 16);
       *reinterpret_cast<uint2*>(&As[buf][row][col]) = make_uint2(lo, hi);
       const int wr = id >> 3, wc = (id & 7) * 16;
-      *reinterpret_cast<uint4*>(&Ws[buf][wr][wc]) = rw[c];
+      *reinterpret_cast<u32x4_t*>(&Ws[buf][wr][wc]) = rw[c];
     }
   };
   f32x4_t acc[2][4];
