@@ -356,7 +356,52 @@ extern "C" dr_status dr_load_weights(dr_ctx* c, const void* blob, size_t nbytes)
     H.v[1] = put16({s[8]}, {CC});
     H.v[2] = put16({s[12]}, {RC});
     H.v[3] = put16({s[14]}, {RC});
+    // LayerNorm affine parts folded into the next linear: appends W diag(g) to wf and
+    // b + W beta to bf for W [outs][in] (double accumulation for the bias)
+    auto fold = [](const float* wsrc, const float* bias, int outs, int in, const float* g, const float* beta,
+                   std::vector<float>& wf, std::vector<float>& bf) {
+      for (int o = 0; o < outs; ++o) {
+        double acc = bias[o];
+        for (int i = 0; i < in; ++i) {
+          wf.push_back(wsrc[(size_t)o * in + i] * g[i]);
+          acc += (double)wsrc[(size_t)o * in + i] * beta[i];
+        }
+        bf.push_back((float)acc);
+      }
+    };
+    std::vector<float> wf, bf;
+    fold(s[2], s[3], C, C, s[0], s[1], wf, bf);  // Q
+    fold(s[4], s[5], C, C, s[0], s[1], wf, bf);  // K
+    fold(s[6], s[7], C, C, s[0], s[1], wf, bf);  // V
+    H.v[4] = put16({wf.data()}, {wf.size()});
+    O.v[24] = put(bf.data(), bf.size());
+    wf.clear();
+    bf.clear();
+    fold(s[12], s[13], R, C, s[10], s[11], wf, bf);  // first MLP linear
+    H.v[5] = put16({wf.data()}, {wf.size()});
+    O.v[25] = put(bf.data(), bf.size());
   }
+  // embedding weight [C][64] (k = (ky*P + kx)*3 + c, zero-padded) and the decoder with the
+  // final LayerNorm folded in: Wd'[k][c] = gf[c] Wd[c][k], bd'[k] = bd[k % 3] + sum_c bf[c] Wd[c][k]
+  std::vector<float> ew64((size_t)C * 64, 0.f), dwf((size_t)48 * C), dbf(48);
+  for (int o = 0; o < C; ++o)
+    for (int k = 0; k < 48; ++k) ew64[(size_t)o * 64 + k] = ewT[(size_t)k * C + o];
+  {
+    const float* gf = src[count - 4];
+    const float* btf = src[count - 3];
+    const float* db = src[count - 1];
+    for (int k = 0; k < 48; ++k) {
+      double acc = db[k % 3];
+      for (int ci = 0; ci < C; ++ci) {
+        dwf[(size_t)k * C + ci] = gf[ci] * dw[(size_t)ci * 48 + k];
+        acc += (double)btf[ci] * dw[(size_t)ci * 48 + k];
+      }
+      dbf[k] = (float)acc;
+    }
+  }
+  const size_t o16_ew = put16({ew64.data()}, {ew64.size()});
+  const size_t o16_dw = put16({dwf.data()}, {dwf.size()});
+  const size_t o_dbf = put(dbf.data(), dbf.size());
   const size_t o_lnfg = put(src[count - 4], C);
   const size_t o_lnfb = put(src[count - 3], C);
   const size_t o_dw = put(dw.data(), dw.size());
@@ -397,7 +442,14 @@ extern "C" dr_status dr_load_weights(dr_ctx* c, const void* blob, size_t nbytes)
     w.wo16 = B16 + b16[l].v[1];
     w.w116 = B16 + b16[l].v[2];
     w.w216 = B16 + b16[l].v[3];
+    w.wqkvf16 = B16 + b16[l].v[4];
+    w.w1f16 = B16 + b16[l].v[5];
+    w.bqkvf = F + O.v[24];
+    w.b1f = F + O.v[25];
   }
+  nn.embed_wT16 = B16 + o16_ew;
+  nn.dec_wf16 = B16 + o16_dw;
+  nn.dec_bf = F + o_dbf;
   nn.lnfg = F + o_lnfg;
   nn.lnfb = F + o_lnfb;
   nn.dec_w = F + o_dw;
@@ -496,6 +548,8 @@ dr_status dr::dr_reserve_work(dr_ctx* c, Work& w, const Geo& g, bool stream_mode
   ALLOC(q16, N * C * 2);
   ALLOC(o16, N * C * 2);
   ALLOC(h16, N * R * 2);
+  ALLOC(u16, N * C * 2);
+  ALLOC(xh, N * C * 2);
   ALLOC(amax, (size_t)n.cfg.blocks * 4 * 4);
   if (stream_mode) {
     const size_t npix = N * 16;  // 4 x 4 pixels per token
@@ -508,7 +562,6 @@ dr_status dr::dr_reserve_work(dr_ctx* c, Work& w, const Geo& g, bool stream_mode
     ALLOC(q, N * C * 4);
     ALLOC(o, N * C * 4);
     ALLOC(h, N * R * 4);
-    ALLOC(u16, N * C * 2);
     ALLOC(k16, kvlen * 2);
     ALLOC(v16, kvlen * 2);
     // padded key rows of K and V must read as zero
@@ -606,11 +659,13 @@ static dr_status run_blocks(dr_ctx* c, const Geo& g, dr_precision prec, hipStrea
       LAUNCH(ST_FC1, launch_ln_fc1_fp8(N, C, R, w.x, w.idx, w.nq, b.ln2g, b.ln2b, b.w18, b.s18, b.b1, am + 2, w.h16, am + 3, s));
       LAUNCH(ST_FC2, launch_gemm_fp8_resid(w.h16, w.nq, N, R, b.w28, b.s28, am + 3, b.b2, C, w.x, w.idx, s));
     } else {
-      LAUNCH(ST_QKV, launch_ln_qkv_bf16(g, C, n.cfg.heads, n.Spad, w.x, w.flag, w.wcount, b.ln1g, b.ln1b, b.wqkv16, b.bqkv, w.q16, w.k16, w.v16, s));
+      // x^ (normalised rows) feeds Q/K/V; the projection leaves x1^ of the query rows in u16
+      // for the MLP; the second MLP linear refreshes x^ of the query rows
+      LAUNCH(ST_QKV, launch_qkv_bf16(g, C, n.cfg.heads, n.Spad, w.xh, w.flag, w.wcount, b.wqkvf16, b.bqkvf, w.q16, w.k16, w.v16, s));
       LAUNCH(ST_ATTN, launch_attn_bf16(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.v16, w.idx, w.woff, w.o16, nullptr, s));
-      LAUNCH(ST_PROJ, launch_gemm_bf16(w.o16, w.nq, N, C, b.wo16, b.bo, C, EPI_RESID, w.x, w.idx, s));
-      LAUNCH(ST_FC1, launch_ln_fc1_bf16(N, C, R, w.x, w.idx, w.nq, b.ln2g, b.ln2b, b.w116, b.b1, w.h16, s));
-      LAUNCH(ST_FC2, launch_gemm_bf16(w.h16, w.nq, N, R, b.w216, b.b2, C, EPI_RESID, w.x, w.idx, s));
+      LAUNCH(ST_PROJ, launch_resid_ln_bf16(N, w.nq, C, C, w.o16, b.wo16, b.bo, w.x, w.idx, w.u16, nullptr, s));
+      LAUNCH(ST_FC1, launch_fc1_bf16(N, w.nq, C, R, w.u16, b.w1f16, b.b1f, w.h16, s));
+      LAUNCH(ST_FC2, launch_resid_ln_bf16(N, w.nq, C, R, w.h16, b.w216, b.b2, w.x, w.idx, w.xh, w.idx, s));
     }
   }
   return DR_OK;
@@ -636,6 +691,8 @@ extern "C" dr_status dr_inpaint(dr_ctx* c, const float* frames, const uint8_t* m
   const Net& n = c->net;
   if (prec != DR_FP32 && !attn_bf16_supported(n.dh, n.Spad))
     return fail(c, DR_ESHAPE, "BF16 attention has no kernel for %d-token windows", n.S);
+  if (prec == DR_BF16 && (!resid_ln_supported(n.C) || n.cfg.patch != 4))
+    return fail(c, DR_ESHAPE, "the BF16 path needs dim 64, 128, 256 or 384 and patch 4");
   if (prec == DR_FP8 && !fp8_supported(n.C, n.R))
     return fail(c, DR_ESHAPE, "the FP8 path needs dim and hidden width multiples of 128");
   const size_t npix = (size_t)B * T * H * W;
@@ -650,7 +707,10 @@ extern "C" dr_status dr_inpaint(dr_ctx* c, const float* frames, const uint8_t* m
   const int C = n.C, R = n.R, N = g.N;
   st = run_tokens(c, g, masks, qs == DR_QUERY_ALL, s);
   if (st != DR_OK) return st;
-  LAUNCH(ST_EMBED, launch_embed(g, C, frames, masks, n.embed_wT, n.embed_b, w.x, s));
+  if (prec == DR_BF16)
+    LAUNCH(ST_EMBED, launch_embed_bf16(g, C, frames, masks, n.embed_wT16, n.embed_b, w.x, w.xh, s));
+  else
+    LAUNCH(ST_EMBED, launch_embed(g, C, frames, masks, n.embed_wT, n.embed_b, w.x, s));
   if (prec == DR_FP8) LAUNCH(ST_LN1, launch_zero_f32(w.amax, 4 * n.cfg.blocks, s));
   dr_status br = DR_OK;
   const bool graphable = c->use_graphs && !c->prof && c->debug_blocks < 0;
@@ -686,7 +746,10 @@ extern "C" dr_status dr_inpaint(dr_ctx* c, const float* frames, const uint8_t* m
     br = run_blocks(c, g, prec, s);
   }
   if (br != DR_OK) return br;
-  LAUNCH(ST_DECODE, launch_decode(g, C, w.x, w.idx, w.nq, n.lnfg, n.lnfb, n.dec_w, n.dec_b, masks, out, s));
+  if (prec == DR_BF16)
+    LAUNCH(ST_DECODE, launch_decode_bf16(g, C, w.xh, w.idx, w.nq, n.dec_wf16, n.dec_bf, masks, out, s));
+  else
+    LAUNCH(ST_DECODE, launch_decode(g, C, w.x, w.idx, w.nq, n.lnfg, n.lnfb, n.dec_w, n.dec_b, masks, out, s));
   if (out != frames) LAUNCH(ST_COPY, launch_copy_unmasked(npix, frames, masks, out, s));
   return DR_OK;
 }
@@ -733,7 +796,7 @@ extern "C" dr_status dr_inspect(dr_ctx* c, const char* name, void* dst, size_t n
   const size_t N = w.cap_tokens, C = c->net.C, R = c->net.R;
   const size_t kvlen = w.cap_windows * c->net.cfg.heads * (size_t)c->net.Spad * c->net.dh;
   struct Buf { const char* n; const void* p; size_t bytes; } bufs[] = {
-      {"x", w.x, N * C * 4},       {"u16", w.u16, N * C * 2}, {"q16", w.q16, N * C * 2},
+      {"x", w.x, N * C * 4},       {"xh", w.xh, N * C * 2},     {"u16", w.u16, N * C * 2}, {"q16", w.q16, N * C * 2},
       {"k16", w.k16, kvlen * 2},   {"v16", w.v16, kvlen * 2}, {"o16", w.o16, N * C * 2},
       {"h16", w.h16, N * R * 2},   {"u", w.u, N * C * 4},     {"kv", w.kv, N * 2 * C * 4},
       {"q", w.q, N * C * 4},       {"o", w.o, N * C * 4},     {"h", w.h, N * R * 4},

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/drinpaint.h"
+#include "dr_device.h"
 
 namespace dr {
 
@@ -49,6 +50,10 @@ struct BlockW {
   const float* bqkv;                         // f32 [3C]
   const bf16* wqkv16;                        // bf16 [3C, C]
   const bf16 *wo16, *w116, *w216;            // bf16 [out, in]
+  // LayerNorm affine parts folded into the following linear (BF16 path):
+  // W' = W diag(g), b' = b + W beta
+  const bf16 *wqkvf16, *w1f16;               // bf16 [3C, C], [R, C]
+  const float *bqkvf, *b1f;                  // f32 [3C], [R]
   const uint8_t* wqkv8;                      // e4m3 [3C, C] (Wq, Wk, Wv each / own scale)
   const uint8_t *wo8, *w18, *w28;            // e4m3 [out, in]
   const float* wscale8;                      // device: s_q, s_k, s_v
@@ -66,6 +71,9 @@ struct Net {
   const float *lnfg, *lnfb;
   const float* dec_w;        // [C][48], column k = (ky*p + kx)*3 + ch
   const float* dec_b;        // [3]
+  const bf16* embed_wT16;    // bf16 [C][64]: embedding weight, k = (ky*p + kx)*3 + c, zero-padded
+  const bf16* dec_wf16;      // bf16 [48][C]: decoder weight with the final LayerNorm gain folded in
+  const float* dec_bf;       // f32 [48]: decoder bias + final LayerNorm shift through the decoder
 };
 
 struct Work {
@@ -83,7 +91,9 @@ struct Work {
   float* x = nullptr;
   // FP32 path scratch
   float *u = nullptr, *kv = nullptr, *q = nullptr, *o = nullptr, *h = nullptr;
-  // BF16 path scratch
+  // BF16 path: normalised residual rows x^ (window-major, all tokens)
+  bf16* xh = nullptr;
+  // BF16 path scratch (u16: normalised rows after the projection, compact)
   bf16 *u16 = nullptr, *q16 = nullptr, *k16 = nullptr, *v16 = nullptr, *o16 = nullptr,
        *h16 = nullptr;
   float* amax = nullptr;  // FP8 activation amax slots [blocks][4]
@@ -106,6 +116,17 @@ struct StreamTable {
   int T[STREAM_MAXB];       // frames in the request's ring (memory slots + 1)
   long long slot_stride;    // elements between slots
 };
+
+// Entry r of a per-request table held in kernel arguments, read through selects: a runtime
+// index into the argument struct would copy the whole table to scratch memory.
+template <class T>
+__device__ __forceinline__ T pick(const T (&a)[STREAM_MAXB], int r) {
+  T v = a[0];
+  static_for<STREAM_MAXB>([&](auto i) {
+    if (i == r) v = a[i];
+  });
+  return v;
+}
 
 struct FramePtrs {          // per-request device buffers of a stream-mode batch
   const float* f[STREAM_MAXB];
@@ -201,21 +222,8 @@ void launch_attn_f32(const Geo& g, int C, int heads, const float* q, const float
                      const int32_t* woff, float* o, hipStream_t s);
 
 // BF16 path
-void launch_ln_bf16(const float* x, const int32_t* rows, const int32_t* nrows_dev,
-                    int nrows_max, int C, const float* g, const float* b, bf16* y,
-                    hipStream_t s);
 // LN1 fused into the Q/K/V projection: q [N, C]; k, v [win][head][Spad][dh].
-void launch_ln_qkv_bf16(const Geo& g, int C, int heads, int Spad, const float* x,
-                        const uint8_t* flag, const int32_t* wcount, const float* lng,
-                        const float* lnb, const bf16* w, const float* bias, bf16* q, bf16* k,
-                        bf16* v, hipStream_t s);
 // LN2 fused into the first MLP linear + GELU over the gathered rows x[idx[r]]: h [Nq, R].
-void launch_ln_fc1_bf16(int m_max, int C, int R, const float* x, const int32_t* idx,
-                        const int32_t* nq, const float* lng, const float* lnb, const bf16* w,
-                        const float* bias, bf16* h, hipStream_t s);
-void launch_gemm_bf16(const bf16* A, const int32_t* m_dev, int m_max, int K, const bf16* W,
-                      const float* bias, int Nout, int epi, void* out,
-                      const int32_t* res_rows, hipStream_t s);
 // amax_o (nullable): max |O| of the call is max-reduced into *amax_o (FP8 path)
 void launch_attn_bf16(const Geo& g, int C, int heads, int Spad, const bf16* q, const bf16* k,
                       const bf16* v, const int32_t* idx, const int32_t* woff, bf16* o,
@@ -241,14 +249,25 @@ void launch_gemm_fp8_resid(const bf16* A, const int32_t* m_dev, int m_max, int K
                            int Nout, float* x, const int32_t* res_rows, hipStream_t s);
 
 // weight preparation
-void launch_f32_to_bf16(const float* a, bf16* b, size_t n, hipStream_t s);
+void launch_embed_bf16(const Geo& g, int C, const float* frames, const uint8_t* masks, const bf16* wT16,
+                       const float* b, float* x, bf16* xh, hipStream_t s);
+void launch_decode_bf16(const Geo& g, int C, const bf16* xh, const int32_t* idx, const int32_t* nq,
+                        const bf16* wd16, const float* bd, const uint8_t* masks, float* out, hipStream_t s);
+void launch_qkv_bf16(const Geo& g, int C, int heads, int Spad, const bf16* xh, const uint8_t* flag,
+                     const int32_t* wcount, const bf16* w, const float* bias, bf16* q, bf16* k, bf16* v,
+                     hipStream_t s);
+void launch_qkv_stream(const Geo& g, int C, int heads, const bf16* xh, const uint8_t* flag, const bf16* w,
+                       const float* bias, bf16* q, const StreamTable& tab, hipStream_t s);
+void launch_fc1_bf16(int m_max, const int32_t* m_dev, int C, int R, const bf16* u2, const bf16* w,
+                     const float* bias, bf16* h, hipStream_t s);
+bool resid_ln_supported(int C);
+void launch_resid_ln_bf16(int m_max, const int32_t* m_dev, int C, int K, const bf16* A, const bf16* w,
+                          const float* bias, float* x, const int32_t* rows, bf16* xh, const int32_t* hrows,
+                          hipStream_t s);
 
 // stream mode
 void launch_gather_frames(const FramePtrs& p, size_t npix, float* fst, uint8_t* mst, hipStream_t s);
 void launch_scatter_frames(const FramePtrs& p, size_t npix, const float* ost, hipStream_t s);
-void launch_ln_qkv_stream(const Geo& g, int C, int heads, const float* x, const uint8_t* flag,
-                          const float* lng, const float* lnb, const bf16* w, const float* bias,
-                          bf16* q, const StreamTable& tab, hipStream_t s);
 void launch_attn_stream(const StreamTable& tab, const Geo& g, int C, int heads, int Spad,
                         const bf16* q, const int32_t* idx, const int32_t* woff, bf16* o,
                         hipStream_t s);

@@ -129,6 +129,8 @@ static dr_status stream_step_locked(dr_ctx* c, Work& w, int n, const int32_t* si
   if (!c->have_weights) return dr_fail(c, DR_EINVAL, "no weights loaded");
   const Net& net = c->net;
   if (!attn_bf16_supported(net.dh, net.Spad)) return dr_fail(c, DR_ESHAPE, "no attention kernel for this window");
+  if (!resid_ln_supported(net.C) || net.cfg.patch != 4)
+    return dr_fail(c, DR_ESHAPE, "stream mode needs dim 64, 128, 256 or 384 and patch 4");
   std::vector<StreamSt*> st(n);
   for (int r = 0; r < n; ++r) {
     auto it = c->streams.find(sids[r]);
@@ -158,7 +160,7 @@ static dr_status stream_step_locked(dr_ctx* c, Work& w, int n, const int32_t* si
   LAUNCH(ST_COPY, launch_gather_frames(fp, npix, w.fst, w.mst, s));
   LAUNCH(ST_TOKENS, launch_token_flags(g, w.mst, qs == DR_QUERY_ALL, w.flag, w.wcount, s));
   LAUNCH(ST_TOKENS, launch_token_gather(g, w.flag, w.wcount, w.idx, w.woff, w.nq, s));
-  LAUNCH(ST_EMBED, launch_embed(g, C, w.fst, w.mst, net.embed_wT, net.embed_b, w.x, s));
+  LAUNCH(ST_EMBED, launch_embed_bf16(g, C, w.fst, w.mst, net.embed_wT16, net.embed_b, w.x, w.xh, s));
   for (int l = 0; l < L; ++l) {
     const BlockW& b = net.blk[l];
     StreamTable tab{};
@@ -170,13 +172,13 @@ static dr_status stream_step_locked(dr_ctx* c, Work& w, int n, const int32_t* si
       tab.T[r] = st[r]->slots + 1;
     }
     tab.slot_stride = (long long)L * blk_elems;
-    LAUNCH(ST_QKV, launch_ln_qkv_stream(g, C, net.cfg.heads, w.x, w.flag, b.ln1g, b.ln1b, b.wqkv16, b.bqkv, w.q16, tab, s));
+    LAUNCH(ST_QKV, launch_qkv_stream(g, C, net.cfg.heads, w.xh, w.flag, b.wqkvf16, b.bqkvf, w.q16, tab, s));
     LAUNCH(ST_ATTN, launch_attn_stream(tab, g, C, net.cfg.heads, net.Spad, w.q16, w.idx, w.woff, w.o16, s));
-    LAUNCH(ST_PROJ, launch_gemm_bf16(w.o16, w.nq, N, C, b.wo16, b.bo, C, EPI_RESID, w.x, w.idx, s));
-    LAUNCH(ST_FC1, launch_ln_fc1_bf16(N, C, R, w.x, w.idx, w.nq, b.ln2g, b.ln2b, b.w116, b.b1, w.h16, s));
-    LAUNCH(ST_FC2, launch_gemm_bf16(w.h16, w.nq, N, R, b.w216, b.b2, C, EPI_RESID, w.x, w.idx, s));
+    LAUNCH(ST_PROJ, launch_resid_ln_bf16(N, w.nq, C, C, w.o16, b.wo16, b.bo, w.x, w.idx, w.u16, nullptr, s));
+    LAUNCH(ST_FC1, launch_fc1_bf16(N, w.nq, C, R, w.u16, b.w1f16, b.b1f, w.h16, s));
+    LAUNCH(ST_FC2, launch_resid_ln_bf16(N, w.nq, C, R, w.h16, b.w216, b.b2, w.x, w.idx, w.xh, w.idx, s));
   }
-  LAUNCH(ST_DECODE, launch_decode(g, C, w.x, w.idx, w.nq, net.lnfg, net.lnfb, net.dec_w, net.dec_b, w.mst, w.ost, s));
+  LAUNCH(ST_DECODE, launch_decode_bf16(g, C, w.xh, w.idx, w.nq, net.dec_wf16, net.dec_bf, w.mst, w.ost, s));
   LAUNCH(ST_COPY, launch_copy_unmasked(npix * n, w.fst, w.mst, w.ost, s));
   LAUNCH(ST_COPY, launch_scatter_frames(fp, npix, w.ost, s));
   // the new frame now occupies the head slot

@@ -55,11 +55,6 @@ void launch_ln_f32(const float* x, const int32_t* rows, const int32_t* nrows_dev
   ln_kernel<float><<<(nrows_max + 3) / 4, 256, 0, s>>>(x, rows, nrows_dev, nrows_max, C, g, b, y);
 }
 
-void launch_ln_bf16(const float* x, const int32_t* rows, const int32_t* nrows_dev, int nrows_max,
-                    int C, const float* g, const float* b, bf16* y, hipStream_t s) {
-  if (nrows_max <= 0) return;
-  ln_kernel<bf16><<<(nrows_max + 3) / 4, 256, 0, s>>>(x, rows, nrows_dev, nrows_max, C, g, b, y);
-}
 
 // ------------------------------------------------------------------------------------------
 // SIMT GEMM: Y[m, n] = sum_k A[arow(m), k] * W[n, k] + bias[n]; 64x64 tile, BK = 16,

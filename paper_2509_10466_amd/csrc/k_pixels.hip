@@ -168,6 +168,171 @@ void launch_decode(const Geo& g, int C, const float* x, const int32_t* idx, cons
 }
 
 // ------------------------------------------------------------------------------------------
+// BF16 mode: patch embedding and decoder on MFMA (v_mfma_f32_16x16x32_bf16, FP32
+// accumulation).  Each wavefront handles 16 tokens; lane l works on token l % 16 and k chunk
+// l / 16 of each 32-wide k slice (the operand layout of the GEMM core), so a wavefront holds
+// every channel of its tokens and the row statistics need no block-level exchange.
+// ------------------------------------------------------------------------------------------
+
+// 8 consecutive cut-out patch values k0 .. k0+7 (k = (ky*4 + kx)*3 + c, zero for k >= 48) of
+// token (b, t, i, j), as bf16.
+__device__ __forceinline__ bf16x8_t patch_chunk(const Geo& g, const float* __restrict__ frames,
+                                                const uint8_t* __restrict__ masks, int b, int t, int i, int j,
+                                                int k0, bool ok) {
+  bf16x8_t v;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int k = k0 + e;
+    float f = 0.f;
+    if (ok && k < 48) {
+      const int ky = k / 12, kx = (k % 12) / 3, ch = k % 3;
+      const size_t px = (((size_t)b * g.T + t) * g.H + 4 * i + ky) * g.W + 4 * j + kx;
+      f = masks[px] ? 0.f : frames[px * 3 + ch];
+    }
+    v[e] = __builtin_bit_cast(__bf16, f2bf(f));
+  }
+  return v;
+}
+
+// x = patch W_e^T + b_e (FP32 residual) and x^ = normalise(x) (bf16).  wT16: [C][64] bf16,
+// the embedding weight with k padded to 64.
+template <int C>
+__global__ void __launch_bounds__(256) embed_bf16_kernel(Geo g, const float* __restrict__ frames,
+                                                         const uint8_t* __restrict__ masks,
+                                                         const bf16* __restrict__ wT16, const float* __restrict__ bias,
+                                                         float* __restrict__ x, bf16* __restrict__ xh) {
+  constexpr int FN = C / 16;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int l16 = lane & 15, kg = lane >> 4;
+  const int n = (blockIdx.x * 4 + wv) * 16 + l16;
+  const bool ok = n < g.N;
+  int b = 0, t = 0, i = 0, j = 0;
+  if (ok) token_coords(g, n, b, t, i, j);
+  const bf16x8_t p0 = patch_chunk(g, frames, masks, b, t, i, j, 8 * kg, ok);
+  const bf16x8_t p1 = patch_chunk(g, frames, masks, b, t, i, j, 32 + 8 * kg, ok);
+  f32x4_t acc[FN];
+  float sum = 0.f;
+#pragma unroll
+  for (int f = 0; f < FN; ++f) {
+    const bf16* wr = wT16 + (size_t)(16 * f + l16) * 64 + 8 * kg;
+    const bf16x8_t w0 = *reinterpret_cast<const bf16x8_t*>(wr);
+    const bf16x8_t w1 = *reinterpret_cast<const bf16x8_t*>(wr + 32);
+    f32x4_t a = {0.f, 0.f, 0.f, 0.f};
+    __builtin_amdgcn_sched_barrier(0);
+    a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, p0, a, 0, 0, 0);
+    a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, p1, a, 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("s_nop 7" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+    const float4 b4 = *reinterpret_cast<const float4*>(bias + 16 * f + 4 * kg);
+    a[0] += b4.x; a[1] += b4.y; a[2] += b4.z; a[3] += b4.w;
+    acc[f] = a;
+    sum += (a[0] + a[1]) + (a[2] + a[3]);
+  }
+  sum += __shfl_xor(sum, 16, 64);
+  sum += __shfl_xor(sum, 32, 64);
+  const float mean = sum * (1.0f / C);
+  float sq = 0.f;
+#pragma unroll
+  for (int f = 0; f < FN; ++f)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float d = acc[f][e] - mean;
+      sq += d * d;
+    }
+  sq += __shfl_xor(sq, 16, 64);
+  sq += __shfl_xor(sq, 32, 64);
+  const float rstd = rsqrtf(sq * (1.0f / C) + 1e-5f);
+  if (!ok) return;
+#pragma unroll
+  for (int f = 0; f < FN; ++f) {
+    const int c = 16 * f + 4 * kg;
+    const f32x4_t& a = acc[f];
+    *reinterpret_cast<float4*>(x + (size_t)n * C + c) = make_float4(a[0], a[1], a[2], a[3]);
+    uint2 pk;
+    pk.x = pack_bf2((a[0] - mean) * rstd, (a[1] - mean) * rstd);
+    pk.y = pack_bf2((a[2] - mean) * rstd, (a[3] - mean) * rstd);
+    *reinterpret_cast<uint2*>(xh + (size_t)n * C + c) = pk;
+  }
+}
+
+void launch_embed_bf16(const Geo& g, int C, const float* frames, const uint8_t* masks, const bf16* wT16,
+                       const float* b, float* x, bf16* xh, hipStream_t s) {
+  const int blocks = (g.N + 63) / 64;
+  if (blocks == 0) return;
+  switch (C) {
+    case 64: embed_bf16_kernel<64><<<blocks, 256, 0, s>>>(g, frames, masks, wT16, b, x, xh); break;
+    case 128: embed_bf16_kernel<128><<<blocks, 256, 0, s>>>(g, frames, masks, wT16, b, x, xh); break;
+    case 256: embed_bf16_kernel<256><<<blocks, 256, 0, s>>>(g, frames, masks, wT16, b, x, xh); break;
+    case 384: embed_bf16_kernel<384><<<blocks, 256, 0, s>>>(g, frames, masks, wT16, b, x, xh); break;
+    default: break;  // rejected by the caller (resid_ln_supported)
+  }
+}
+
+// Decoder on x^ with the final LayerNorm's affine part folded in: logits[k] = bd'[k] +
+// sum_c x^[c] Wd'[k][c] (Wd' [48][C] bf16, bd' [48] FP32), sigmoid, and the masked pixels of
+// each flagged token written.  Output fragment f of lane l holds k = 16 f + 4 (l / 16) + e of
+// token l % 16.
+template <int C>
+__global__ void __launch_bounds__(256) decode_bf16_kernel(Geo g, const bf16* __restrict__ xh,
+                                                          const int32_t* __restrict__ idx,
+                                                          const int32_t* __restrict__ nq,
+                                                          const bf16* __restrict__ wd16, const float* __restrict__ bd,
+                                                          const uint8_t* __restrict__ masks, float* __restrict__ out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int l16 = lane & 15, kg = lane >> 4;
+  const int total = nq[0];
+  for (int r0 = (blockIdx.x * 4 + wv) * 16; r0 < total; r0 += gridDim.x * 64) {
+    const int r = r0 + l16;
+    const bool ok = r < total;
+    const int n = ok ? idx[r] : 0;
+    f32x4_t acc[3] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+    for (int kk = 0; kk < C / 32; ++kk) {
+      const bf16x8_t z = ok ? *reinterpret_cast<const bf16x8_t*>(xh + (size_t)n * C + kk * 32 + 8 * kg)
+                            : bf16x8_t{};
+      bf16x8_t w[3];
+#pragma unroll
+      for (int f = 0; f < 3; ++f)
+        w[f] = *reinterpret_cast<const bf16x8_t*>(wd16 + (size_t)(16 * f + l16) * C + kk * 32 + 8 * kg);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int f = 0; f < 3; ++f) acc[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[f], z, acc[f], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      asm volatile("s_nop 7" ::: "memory");
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (!ok) continue;
+    int b, t, i, j;
+    token_coords(g, n, b, t, i, j);
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int k = 16 * f + 4 * kg + e;
+        const int pix = k / 3, ch = k - 3 * pix;
+        const int ky = pix >> 2, kx = pix & 3;
+        const size_t px = (((size_t)b * g.T + t) * g.H + 4 * i + ky) * g.W + 4 * j + kx;
+        if (masks[px]) out[px * 3 + ch] = 1.0f / (1.0f + expf(-(acc[f][e] + bd[k])));
+      }
+  }
+}
+
+void launch_decode_bf16(const Geo& g, int C, const bf16* xh, const int32_t* idx, const int32_t* nq,
+                        const bf16* wd16, const float* bd, const uint8_t* masks, float* out, hipStream_t s) {
+  int grid = (g.N + 63) / 64;
+  if (grid > DEC_GRID) grid = DEC_GRID;
+  if (grid == 0) return;
+  switch (C) {
+    case 64: decode_bf16_kernel<64><<<grid, 256, 0, s>>>(g, xh, idx, nq, wd16, bd, masks, out); break;
+    case 128: decode_bf16_kernel<128><<<grid, 256, 0, s>>>(g, xh, idx, nq, wd16, bd, masks, out); break;
+    case 256: decode_bf16_kernel<256><<<grid, 256, 0, s>>>(g, xh, idx, nq, wd16, bd, masks, out); break;
+    case 384: decode_bf16_kernel<384><<<grid, 256, 0, s>>>(g, xh, idx, nq, wd16, bd, masks, out); break;
+    default: break;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // out = frames wherever the mask is 0 (4 pixels per thread, vector loads and stores).
 // ------------------------------------------------------------------------------------------
 __global__ void copy_unmasked_kernel(size_t nquad, const float4* __restrict__ frames,
