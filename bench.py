@@ -38,7 +38,7 @@ def stage_flops(stage, cfg, N, Nq, Na):
         "proj": 2 * Nq * C * C,
         "fc1": 2 * Nq * C * R,
         "fc2": 2 * Nq * R * C,
-        "mlp": 4 * Nq * C * R,
+        "mlp": 2 * Nq * C * C + 4 * Nq * C * R,  # fused projection + MLP
         "embed": 2 * N * 48 * C,
         "decode": 2 * Nq * C * 48,
     }.get(stage)

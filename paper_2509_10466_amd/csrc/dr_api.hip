@@ -663,9 +663,13 @@ static dr_status run_blocks(dr_ctx* c, const Geo& g, dr_precision prec, hipStrea
       // for the MLP; the second MLP linear refreshes x^ of the query rows
       LAUNCH(ST_QKV, launch_qkv_bf16(g, C, n.cfg.heads, n.Spad, w.xh, w.flag, w.wcount, b.wqkvf16, b.bqkvf, w.q16, w.k16, w.v16, s));
       LAUNCH(ST_ATTN, launch_attn_bf16(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.v16, w.idx, w.woff, w.o16, nullptr, s));
-      LAUNCH(ST_PROJ, launch_resid_ln_bf16(N, w.nq, C, C, w.o16, b.wo16, b.bo, w.x, w.idx, w.u16, nullptr, s));
-      LAUNCH(ST_FC1, launch_fc1_bf16(N, w.nq, C, R, w.u16, b.w1f16, b.b1f, w.h16, s));
-      LAUNCH(ST_FC2, launch_resid_ln_bf16(N, w.nq, C, R, w.h16, b.w216, b.b2, w.x, w.idx, w.xh, w.idx, s));
+      if (mlp_block_supported(C, R)) {
+        LAUNCH(ST_MLP, launch_mlp_block_bf16(N, w.nq, C, w.o16, w.idx, b.wo16, b.bo, b.w1f16, b.b1f, b.w216, b.b2, w.x, w.xh, s));
+      } else {
+        LAUNCH(ST_PROJ, launch_resid_ln_bf16(N, w.nq, C, C, w.o16, b.wo16, b.bo, w.x, w.idx, w.u16, nullptr, s));
+        LAUNCH(ST_FC1, launch_fc1_bf16(N, w.nq, C, R, w.u16, b.w1f16, b.b1f, w.h16, s));
+        LAUNCH(ST_FC2, launch_resid_ln_bf16(N, w.nq, C, R, w.h16, b.w216, b.b2, w.x, w.idx, w.xh, w.idx, s));
+      }
     }
   }
   return DR_OK;

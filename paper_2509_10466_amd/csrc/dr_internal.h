@@ -32,7 +32,7 @@ enum Stage {
   ST_LN2,         // LayerNorm before the MLP
   ST_FC1,         // first MLP linear + GELU
   ST_FC2,         // second MLP linear + residual
-  ST_MLP,         // fused LN2 + MLP + residual
+  ST_MLP,         // fused projection + residual + MLP + residual (BF16)
   ST_DECODE,      // final LayerNorm + decoder + sigmoid + masked store
   ST_COPY,        // unmasked pixels copied to the output
   ST_COUNT
@@ -261,6 +261,10 @@ void launch_qkv_stream(const Geo& g, int C, int heads, const bf16* xh, const uin
 void launch_fc1_bf16(int m_max, const int32_t* m_dev, int C, int R, const bf16* u2, const bf16* w,
                      const float* bias, bf16* h, hipStream_t s);
 bool resid_ln_supported(int C);
+bool mlp_block_supported(int C, int R);
+void launch_mlp_block_bf16(int m_max, const int32_t* m_dev, int C, const bf16* o, const int32_t* rows,
+                           const bf16* wo, const float* bo, const bf16* w1, const float* b1, const bf16* w2,
+                           const float* b2, float* x, bf16* xh, hipStream_t s);
 void launch_resid_ln_bf16(int m_max, const int32_t* m_dev, int C, int K, const bf16* A, const bf16* w,
                           const float* bias, float* x, const int32_t* rows, bf16* xh, const int32_t* hrows,
                           hipStream_t s);

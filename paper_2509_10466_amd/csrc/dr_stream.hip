@@ -174,9 +174,13 @@ static dr_status stream_step_locked(dr_ctx* c, Work& w, int n, const int32_t* si
     tab.slot_stride = (long long)L * blk_elems;
     LAUNCH(ST_QKV, launch_qkv_stream(g, C, net.cfg.heads, w.xh, w.flag, b.wqkvf16, b.bqkvf, w.q16, tab, s));
     LAUNCH(ST_ATTN, launch_attn_stream(tab, g, C, net.cfg.heads, net.Spad, w.q16, w.idx, w.woff, w.o16, s));
-    LAUNCH(ST_PROJ, launch_resid_ln_bf16(N, w.nq, C, C, w.o16, b.wo16, b.bo, w.x, w.idx, w.u16, nullptr, s));
-    LAUNCH(ST_FC1, launch_fc1_bf16(N, w.nq, C, R, w.u16, b.w1f16, b.b1f, w.h16, s));
-    LAUNCH(ST_FC2, launch_resid_ln_bf16(N, w.nq, C, R, w.h16, b.w216, b.b2, w.x, w.idx, w.xh, w.idx, s));
+    if (mlp_block_supported(C, R)) {
+      LAUNCH(ST_MLP, launch_mlp_block_bf16(N, w.nq, C, w.o16, w.idx, b.wo16, b.bo, b.w1f16, b.b1f, b.w216, b.b2, w.x, w.xh, s));
+    } else {
+      LAUNCH(ST_PROJ, launch_resid_ln_bf16(N, w.nq, C, C, w.o16, b.wo16, b.bo, w.x, w.idx, w.u16, nullptr, s));
+      LAUNCH(ST_FC1, launch_fc1_bf16(N, w.nq, C, R, w.u16, b.w1f16, b.b1f, w.h16, s));
+      LAUNCH(ST_FC2, launch_resid_ln_bf16(N, w.nq, C, R, w.h16, b.w216, b.b2, w.x, w.idx, w.xh, w.idx, s));
+    }
   }
   LAUNCH(ST_DECODE, launch_decode_bf16(g, C, w.xh, w.idx, w.nq, net.dec_wf16, net.dec_bf, w.mst, w.ost, s));
   LAUNCH(ST_COPY, launch_copy_unmasked(npix * n, w.fst, w.mst, w.ost, s));

@@ -45,14 +45,14 @@ __device__ __forceinline__ void mfma_fence_end() {
   __builtin_amdgcn_sched_barrier(0);
 }
 
-// Wait until at most N of this wavefront's vector-memory loads are outstanding, then the
-// block barrier.  Written as one asm statement with a memory clobber so that the compiler
-// neither adds a full vmcnt(0) wait (as a fenced __syncthreads would) nor moves LDS reads
-// across the barrier.
+// Wait until at most N of this wavefront's vector-memory operations are outstanding and its
+// LDS operations are done, then the block barrier.  Written as one asm statement with a
+// memory clobber so that the compiler neither adds a full vmcnt(0) wait (as a fenced
+// __syncthreads would) nor moves LDS accesses across the barrier.
 template <int N>
 __device__ __forceinline__ void vm_wait_barrier() {
   static_assert(N >= 0 && N < 64, "vmcnt range");
-  asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(N) : "memory");
+  asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
 }
 
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }

@@ -309,4 +309,294 @@ void launch_resid_ln_bf16(int m_max, const int32_t* m_dev, int C, int K, const b
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// Fused post-attention block over 64 query rows (compact rows r, token idx[r]):
+//   x1 = x + o W_o^T + b_o        u2 = normalise(x1)
+//   h  = GELU(u2 W1'^T + b1')     (hidden chunks of HC columns)
+//   x2 = x1 + h W_2^T + b_2       x^ = normalise(x2)
+// u2 and h never leave LDS: the o rows are loaded once into a resident A tile that u2 then
+// overwrites, each hidden chunk is written to LDS by the GELU epilogue and immediately
+// consumed by the second linear.  Only the weights stream, through a 3-stage ring whose
+// stages are, in order: the C/64 k-blocks of W_o; then per hidden chunk j the C/64 k-blocks
+// of W1' rows [j*HC, (j+1)*HC) followed by the HC/64 k-blocks of W_2 columns of chunk j.
+// All four wavefronts sit side by side (each C/4 output channels, all 64 rows).
+// ------------------------------------------------------------------------------------------
+template <int C_, int HC_>
+struct MlpCfg {
+  static constexpr int C = C_, HC = HC_, BM = 64, R = 4 * C, ST = 3;
+  static constexpr int SLOT_ROWS = C > HC ? C : HC;
+  static constexpr int SLOT = SLOT_ROWS * 64;          // bf16 elements per ring slot
+  static constexpr int NKC = C / 64, NKH = HC / 64;    // k blocks of C- and HC-wide operands
+  static constexpr int NCH = R / HC;                   // hidden chunks
+  static constexpr int PER_CHUNK = NKC + NKH;
+  static constexpr int NSTAGE = NKC + NCH * PER_CHUNK;
+  static constexpr int FN_C = C / 64, FN_H = HC / 64;  // 16-wide fragments per wavefront
+  static constexpr size_t RING = (size_t)ST * SLOT, ARES = (size_t)NKC * BM * 64, HRES = (size_t)NKH * BM * 64;
+  static constexpr size_t FLOATS = 2 * (size_t)C + R + 2 * 4 * BM;  // b_o, b1', b_2, row sums
+  static constexpr size_t LDS_BYTES = (RING + ARES + HRES) * 2 + FLOATS * 4;
+  static_assert(C % 64 == 0 && HC % 64 == 0 && R % HC == 0, "shapes");
+  static_assert(LDS_BYTES <= 160 * 1024, "LDS");
+};
+
+// One 64-wide k block: acc[i][j] += A[16i + l16][k] W[wn*16*FN + 16j + l16][k], A and W in
+// the swizzled 64-column LDS layout.
+template <int FN>
+__device__ __forceinline__ void mfma_block(const bf16* As, const bf16* Ws, f32x4_t (&acc)[4][FN]) {
+  const int lane = threadIdx.x & 63, wn = threadIdx.x >> 6;
+  const int l16 = lane & 15, kg = lane >> 4;
+  bf16x8_t af[2][4], wf[2][FN];
+  static_for<2>([&](auto kk) {
+    static_for<4>([&](auto i) {
+      const int row = 16 * i + l16;
+      af[kk][i] = *reinterpret_cast<const bf16x8_t*>(As + row * 64 + (((4 * kk + kg) ^ lds_swz(row)) * 8));
+    });
+    static_for<FN>([&](auto j) {
+      const int row = wn * 16 * FN + 16 * j + l16;
+      wf[kk][j] = *reinterpret_cast<const bf16x8_t*>(Ws + row * 64 + (((4 * kk + kg) ^ lds_swz(row)) * 8));
+    });
+  });
+  static_for<2>([&](auto kk) {
+    mfma_fence_begin();
+    static_for<4>([&](auto i) {
+      static_for<FN>([&](auto j) { acc[i][j] = mfma_bf16_16x16x32(wf[kk][j], af[kk][i], acc[i][j]); });
+    });
+    mfma_fence_end();
+  });
+}
+
+// Element offset of (row r, column c) in a resident [k block][64 rows][64] swizzled tile.
+__device__ __forceinline__ int res_off(int r, int c) {
+  return (c >> 6) * (64 * 64) + r * 64 + ((((c & 63) >> 3) ^ lds_swz(r)) << 3) + (c & 7);
+}
+
+// Residual + row normalisation for the [64][C] accumulators (4 wavefronts side by side):
+// acc += bias + x[dst]; x[dst] = acc; returns the row statistics through mean/rstd.
+template <int FN, int C>
+__device__ __forceinline__ void resid_rows(f32x4_t (&acc)[4][FN], const float* sbias, float* __restrict__ x,
+                                           const int (&dst)[4], float (*red)[4][64], float (&mean)[4],
+                                           float (&rstd)[4]) {
+  const int lane = threadIdx.x & 63, wn = threadIdx.x >> 6;
+  const int l16 = lane & 15, kg = lane >> 4;
+  float part[4];
+  static_for<4>([&](auto i) {
+    float sum = 0.f;
+    static_for<FN>([&](auto j) {
+      const int n = wn * 16 * FN + 16 * j + 4 * kg;
+      float4 xo = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (dst[i] >= 0) xo = *reinterpret_cast<const float4*>(x + (size_t)dst[i] * C + n);
+      f32x4_t& a = acc[i][j];
+      a[0] += sbias[n] + xo.x;
+      a[1] += sbias[n + 1] + xo.y;
+      a[2] += sbias[n + 2] + xo.z;
+      a[3] += sbias[n + 3] + xo.w;
+      if (dst[i] >= 0) *reinterpret_cast<float4*>(x + (size_t)dst[i] * C + n) = make_float4(a[0], a[1], a[2], a[3]);
+      sum += (a[0] + a[1]) + (a[2] + a[3]);
+    });
+    sum += __shfl_xor(sum, 16, 64);
+    sum += __shfl_xor(sum, 32, 64);
+    part[i] = sum;
+  });
+  if (kg == 0) static_for<4>([&](auto i) { red[0][wn][16 * i + l16] = part[i]; });
+  lds_barrier();
+  static_for<4>([&](auto i) {
+    const int r = 16 * i + l16;
+    mean[i] = ((red[0][0][r] + red[0][1][r]) + (red[0][2][r] + red[0][3][r])) * (1.0f / C);
+    float sq = 0.f;
+    static_for<FN>([&](auto j) {
+      static_for<4>([&](auto e) {
+        const float d = acc[i][j][int(e)] - mean[i];
+        sq += d * d;
+      });
+    });
+    sq += __shfl_xor(sq, 16, 64);
+    sq += __shfl_xor(sq, 32, 64);
+    part[i] = sq;
+  });
+  if (kg == 0) static_for<4>([&](auto i) { red[1][wn][16 * i + l16] = part[i]; });
+  lds_barrier();
+  static_for<4>([&](auto i) {
+    const int r = 16 * i + l16;
+    const float var = ((red[1][0][r] + red[1][1][r]) + (red[1][2][r] + red[1][3][r])) * (1.0f / C);
+    rstd[i] = rsqrtf(var + 1e-5f);
+  });
+}
+
+template <class MC>
+__global__ void __launch_bounds__(256) mlp_block_kernel(const int32_t* __restrict__ m_dev,
+                                                        const bf16* __restrict__ o, const int32_t* __restrict__ rows,
+                                                        const bf16* __restrict__ Wo, const float* __restrict__ bo,
+                                                        const bf16* __restrict__ W1, const float* __restrict__ b1,
+                                                        const bf16* __restrict__ W2, const float* __restrict__ b2,
+                                                        float* __restrict__ x, bf16* __restrict__ xh) {
+  constexpr int C = MC::C, HC = MC::HC, R = MC::R, BM = MC::BM;
+  extern __shared__ __align__(16) bf16 lds[];
+  bf16* ring = lds;
+  bf16* ares = lds + MC::RING;
+  bf16* hres = ares + MC::ARES;
+  float* sbo = reinterpret_cast<float*>(hres + MC::HRES);
+  float* sb1 = sbo + C;
+  float* sb2 = sb1 + R;
+  float(*red)[4][64] = reinterpret_cast<float(*)[4][64]>(sb2 + C);
+
+  const int M = m_dev[0];
+  const int m0 = blockIdx.x * BM;
+  if (m0 >= M) return;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int l16 = lane & 15, kg = lane >> 4;
+
+  for (int i = t; i < C; i += 256) {
+    sbo[i] = bo[i];
+    sb2[i] = b2[i];
+  }
+  for (int i = t; i < R; i += 256) sb1[i] = b1[i];
+  // o rows -> resident A tile (rows >= M read row M-1; their results are never stored)
+  static_for<MC::NKC>([&](auto kb) {
+    static_for<2>([&](auto c) {
+      const int g8 = wv + 4 * c;
+      const int row = g8 * 8 + (lane >> 3);
+      const int m = min(m0 + row, M - 1);
+      dma16(o + (size_t)m * C + 64 * kb + ((lane & 7) ^ lds_swz(row)) * 8, ares + kb * BM * 64 + g8 * 512);
+    });
+  });
+  // weight stages
+  auto stage_rows = [](int s) {
+    if (s < MC::NKC) return C;
+    const int q = s - MC::NKC, tt = q % MC::PER_CHUNK;
+    return tt < MC::NKC ? HC : C;
+  };
+  auto issue = [&](int s) {
+    const bf16* base;
+    int rows_s, ld;
+    if (s < MC::NKC) {
+      base = Wo + 64 * s;
+      rows_s = C;
+      ld = C;
+    } else {
+      const int q = s - MC::NKC, j = q / MC::PER_CHUNK, tt = q - j * MC::PER_CHUNK;
+      if (tt < MC::NKC) {
+        base = W1 + (size_t)j * HC * C + 64 * tt;
+        rows_s = HC;
+        ld = C;
+      } else {
+        base = W2 + j * HC + 64 * (tt - MC::NKC);
+        rows_s = C;
+        ld = R;
+      }
+    }
+    bf16* dst = ring + (s % MC::ST) * MC::SLOT;
+    static_for<MC::SLOT_ROWS / 32>([&](auto c) {
+      const int g8 = wv + 4 * c;
+      if (g8 * 8 < rows_s) {  // uniform per wavefront
+        const int row = g8 * 8 + (lane >> 3);
+        dma16(base + (size_t)row * ld + ((lane & 7) ^ lds_swz(row)) * 8, dst + g8 * 512);
+      }
+    });
+  };
+  issue(0);
+  issue(1);
+
+  int dst[4];
+  static_for<4>([&](auto i) {
+    const int m = m0 + 16 * i + l16;
+    dst[i] = m < M ? rows[m] : -1;
+  });
+  f32x4_t acc[4][MC::FN_C], hacc[4][MC::FN_H];
+  static_for<4>([&](auto i) {
+    static_for<MC::FN_C>([&](auto j) { acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f}; });
+    static_for<MC::FN_H>([&](auto j) { hacc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f}; });
+  });
+  float mean[4], rstd[4];
+  // Before multiplying stage s: wait until it has landed (at most the next stage's loads
+  // outstanding, or none after a stretch of other vector-memory traffic), then queue s + 2.
+  bool drained = true;  // the bias loads and row indices above are vector-memory reads
+  auto enter = [&](int s) {
+    if (drained || s + 1 >= MC::NSTAGE)
+      vm_wait_barrier<0>();
+    else if (stage_rows(s + 1) == C)
+      vm_wait_barrier<C / 32>();
+    else
+      vm_wait_barrier<HC / 32>();
+    drained = false;
+    if (s + 2 < MC::NSTAGE) issue(s + 2);
+    return ring + (s % MC::ST) * MC::SLOT;
+  };
+  int s = 0;
+  for (int kb = 0; kb < MC::NKC; ++kb, ++s) mfma_block<MC::FN_C>(ares + kb * BM * 64, enter(s), acc);
+  // x1 = x + o W_o^T + b_o; u2 = normalise(x1) into the resident tile (every wavefront has
+  // finished reading o there: resid_rows passes two block barriers)
+  resid_rows<MC::FN_C, C>(acc, sbo, x, dst, red, mean, rstd);
+  static_for<4>([&](auto i) {
+    const int r = 16 * i + l16;
+    static_for<MC::FN_C>([&](auto j) {
+      const int n = wv * 16 * MC::FN_C + 16 * j + 4 * kg;
+      const f32x4_t& a = acc[i][j];
+      uint2 pk;
+      pk.x = pack_bf2((a[0] - mean[i]) * rstd[i], (a[1] - mean[i]) * rstd[i]);
+      pk.y = pack_bf2((a[2] - mean[i]) * rstd[i], (a[3] - mean[i]) * rstd[i]);
+      *reinterpret_cast<uint2*>(ares + res_off(r, n)) = pk;
+      acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    });
+  });
+  drained = true;  // x was read and written
+  for (int j = 0; j < MC::NCH; ++j) {
+    for (int kb = 0; kb < MC::NKC; ++kb, ++s) mfma_block<MC::FN_H>(ares + kb * BM * 64, enter(s), hacc);
+    // hidden chunk j: GELU into the H tile (its previous contents were consumed before this
+    // stage's barrier)
+    static_for<4>([&](auto i) {
+      const int r = 16 * i + l16;
+      static_for<MC::FN_H>([&](auto jj) {
+        const int c = wv * 16 * MC::FN_H + 16 * jj + 4 * kg;
+        const float* bb = sb1 + j * HC + c;
+        const f32x4_t& a = hacc[i][jj];
+        uint2 pk;
+        pk.x = pack_bf2(gelu_erf(a[0] + bb[0]), gelu_erf(a[1] + bb[1]));
+        pk.y = pack_bf2(gelu_erf(a[2] + bb[2]), gelu_erf(a[3] + bb[3]));
+        *reinterpret_cast<uint2*>(hres + res_off(r, c)) = pk;
+        hacc[i][jj] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+      });
+    });
+    for (int kb = 0; kb < MC::NKH; ++kb, ++s) mfma_block<MC::FN_C>(hres + kb * BM * 64, enter(s), acc);
+  }
+  // x2 = x1 + h W_2^T + b_2 (x1 was stored by this thread above); x^ = normalise(x2)
+  resid_rows<MC::FN_C, C>(acc, sb2, x, dst, red, mean, rstd);
+  static_for<4>([&](auto i) {
+    if (dst[i] >= 0)
+      static_for<MC::FN_C>([&](auto j) {
+        const int n = wv * 16 * MC::FN_C + 16 * j + 4 * kg;
+        const f32x4_t& a = acc[i][j];
+        uint2 pk;
+        pk.x = pack_bf2((a[0] - mean[i]) * rstd[i], (a[1] - mean[i]) * rstd[i]);
+        pk.y = pack_bf2((a[2] - mean[i]) * rstd[i], (a[3] - mean[i]) * rstd[i]);
+        *reinterpret_cast<uint2*>(xh + (size_t)dst[i] * C + n) = pk;
+      });
+  });
+}
+
+template <class MC>
+static void mlp_launch(int m_max, const int32_t* m_dev, const bf16* o, const int32_t* rows, const bf16* wo,
+                       const float* bo, const bf16* w1, const float* b1, const bf16* w2, const float* b2, float* x,
+                       bf16* xh, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    allow_lds(mlp_block_kernel<MC>, MC::LDS_BYTES);
+    attr = true;
+  }
+  mlp_block_kernel<MC><<<(m_max + MC::BM - 1) / MC::BM, 256, MC::LDS_BYTES, s>>>(m_dev, o, rows, wo, bo, w1, b1, w2,
+                                                                                  b2, x, xh);
+}
+
+bool mlp_block_supported(int C, int R) { return R == 4 * C && (C == 64 || C == 128 || C == 256); }
+
+void launch_mlp_block_bf16(int m_max, const int32_t* m_dev, int C, const bf16* o, const int32_t* rows,
+                           const bf16* wo, const float* bo, const bf16* w1, const float* b1, const bf16* w2,
+                           const float* b2, float* x, bf16* xh, hipStream_t s) {
+  if (m_max <= 0) return;
+  switch (C) {
+    case 64: mlp_launch<MlpCfg<64, 128>>(m_max, m_dev, o, rows, wo, bo, w1, b1, w2, b2, x, xh, s); break;
+    case 128: mlp_launch<MlpCfg<128, 128>>(m_max, m_dev, o, rows, wo, bo, w1, b1, w2, b2, x, xh, s); break;
+    case 256: mlp_launch<MlpCfg<256, 128>>(m_max, m_dev, o, rows, wo, bo, w1, b1, w2, b2, x, xh, s); break;
+    default: break;  // rejected by the caller (mlp_block_supported)
+  }
+}
+
 }  // namespace dr
