@@ -10,11 +10,11 @@
 // stage kt is multiplied; a wavefront waits for its own loads of stage kt with an explicit
 // vmcnt and the block barrier then makes every wavefront's loads visible.
 //
-// LDS layout: the 16-byte chunk c of row r sits at chunk position c ^ swz(r) with
-// swz(r) = (r ^ (r >> 3)) & 7.  The MFMA operand reads fetch 16 consecutive rows at one
-// logical chunk; with this swizzle those 16 reads cover all 8 chunk positions of each
-// 8-row half and both 128-byte halves of a 256-byte bank window, so no two lanes of a
-// read group share a bank.  The loads apply the same swizzle to the global addresses.
+// LDS layout: the 16-byte chunk c of row r sits at chunk position c ^ (r & 7).  The MFMA
+// operand reads fetch 16 consecutive rows at one logical chunk; measured on gfx950 with the
+// SQ_LDS_BANK_CONFLICT counter, this XOR pattern reads those 16 rows without bank conflicts
+// (unswizzled 128-byte rows, 144-byte padded rows and an XOR with (r ^ (r >> 3)) & 7 all
+// conflict).  The loads apply the same swizzle to the global addresses.
 //
 // MFMA operands: lane l supplies row (l % 16) of each operand with k values 8*(l/16)..+7 of
 // the 32-wide k slice.  The W fragment is the MFMA's A operand, so result lane l holds output
@@ -32,7 +32,7 @@ namespace dr {
 
 typedef uint16_t bf16_t;
 
-__device__ __forceinline__ int lds_swz(int row) { return (row ^ (row >> 3)) & 7; }
+__device__ __forceinline__ int lds_swz(int row) { return row & 7; }
 
 __device__ __forceinline__ f32x4_t mfma_bf16_16x16x32(const bf16x8_t& a, const bf16x8_t& b, const f32x4_t& c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);

@@ -319,11 +319,17 @@ void launch_resid_ln_bf16(int m_max, const int32_t* m_dev, int C, int K, const b
 // consumed by the second linear.  Only the weights stream, through a 3-stage ring whose
 // stages are, in order: the C/64 k-blocks of W_o; then per hidden chunk j the C/64 k-blocks
 // of W1' rows [j*HC, (j+1)*HC) followed by the HC/64 k-blocks of W_2 columns of chunk j.
-// All four wavefronts sit side by side (each C/4 output channels, all 64 rows).
+// Block = 512 threads = 8 wavefronts in 2 (rows) x 4 (columns): the block needs most of the
+// LDS, so it runs alone on its CU, and two wavefronts per SIMD keep the matrix pipe fed
+// while the other waits on LDS or the barrier.
 // ------------------------------------------------------------------------------------------
+constexpr int MLP_THREADS = 512;
+
 template <int C_, int HC_>
 struct MlpCfg {
   static constexpr int C = C_, HC = HC_, BM = 64, R = 4 * C, ST = 3;
+  static constexpr int WM = 2, WN = 4, TM = BM / WM;   // wavefront grid; rows per wavefront
+  static constexpr int FM = TM / 16;
   static constexpr int SLOT_ROWS = C > HC ? C : HC;
   static constexpr int SLOT = SLOT_ROWS * 64;          // bf16 elements per ring slot
   static constexpr int NKC = C / 64, NKH = HC / 64;    // k blocks of C- and HC-wide operands
@@ -332,22 +338,23 @@ struct MlpCfg {
   static constexpr int NSTAGE = NKC + NCH * PER_CHUNK;
   static constexpr int FN_C = C / 64, FN_H = HC / 64;  // 16-wide fragments per wavefront
   static constexpr size_t RING = (size_t)ST * SLOT, ARES = (size_t)NKC * BM * 64, HRES = (size_t)NKH * BM * 64;
-  static constexpr size_t FLOATS = 2 * (size_t)C + R + 2 * 4 * BM;  // b_o, b1', b_2, row sums
+  static constexpr size_t FLOATS = 2 * (size_t)C + R + 2 * WN * BM;  // b_o, b1', b_2, row sums
   static constexpr size_t LDS_BYTES = (RING + ARES + HRES) * 2 + FLOATS * 4;
-  static_assert(C % 64 == 0 && HC % 64 == 0 && R % HC == 0, "shapes");
+  static_assert(C % 64 == 0 && HC % 64 == 0 && R % HC == 0 && C % 64 == 0, "shapes");
   static_assert(LDS_BYTES <= 160 * 1024, "LDS");
 };
 
-// One 64-wide k block: acc[i][j] += A[16i + l16][k] W[wn*16*FN + 16j + l16][k], A and W in
-// the swizzled 64-column LDS layout.
-template <int FN>
-__device__ __forceinline__ void mfma_block(const bf16* As, const bf16* Ws, f32x4_t (&acc)[4][FN]) {
-  const int lane = threadIdx.x & 63, wn = threadIdx.x >> 6;
+// One 64-wide k block: acc[i][j] += A[wm*TM + 16i + l16][k] W[wn*16*FN + 16j + l16][k], A and
+// W in the swizzled 64-column LDS layout.
+template <class MC, int FN>
+__device__ __forceinline__ void mfma_block(const bf16* As, const bf16* Ws, f32x4_t (&acc)[MC::FM][FN]) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wm = wv / MC::WN, wn = wv % MC::WN;
   const int l16 = lane & 15, kg = lane >> 4;
-  bf16x8_t af[2][4], wf[2][FN];
+  bf16x8_t af[2][MC::FM], wf[2][FN];
   static_for<2>([&](auto kk) {
-    static_for<4>([&](auto i) {
-      const int row = 16 * i + l16;
+    static_for<MC::FM>([&](auto i) {
+      const int row = wm * MC::TM + 16 * i + l16;
       af[kk][i] = *reinterpret_cast<const bf16x8_t*>(As + row * 64 + (((4 * kk + kg) ^ lds_swz(row)) * 8));
     });
     static_for<FN>([&](auto j) {
@@ -357,7 +364,7 @@ __device__ __forceinline__ void mfma_block(const bf16* As, const bf16* Ws, f32x4
   });
   static_for<2>([&](auto kk) {
     mfma_fence_begin();
-    static_for<4>([&](auto i) {
+    static_for<MC::FM>([&](auto i) {
       static_for<FN>([&](auto j) { acc[i][j] = mfma_bf16_16x16x32(wf[kk][j], af[kk][i], acc[i][j]); });
     });
     mfma_fence_end();
@@ -369,16 +376,19 @@ __device__ __forceinline__ int res_off(int r, int c) {
   return (c >> 6) * (64 * 64) + r * 64 + ((((c & 63) >> 3) ^ lds_swz(r)) << 3) + (c & 7);
 }
 
-// Residual + row normalisation for the [64][C] accumulators (4 wavefronts side by side):
-// acc += bias + x[dst]; x[dst] = acc; returns the row statistics through mean/rstd.
-template <int FN, int C>
-__device__ __forceinline__ void resid_rows(f32x4_t (&acc)[4][FN], const float* sbias, float* __restrict__ x,
-                                           const int (&dst)[4], float (*red)[4][64], float (&mean)[4],
-                                           float (&rstd)[4]) {
-  const int lane = threadIdx.x & 63, wn = threadIdx.x >> 6;
+// Residual + row normalisation for the [64][C] accumulators: acc += bias + x[dst];
+// x[dst] = acc; the row statistics come back through mean/rstd.  The four column
+// wavefronts of a row group exchange partial sums through red[2][WN][64].
+template <class MC>
+__device__ __forceinline__ void resid_rows(f32x4_t (&acc)[MC::FM][MC::FN_C], const float* sbias,
+                                           float* __restrict__ x, const int (&dst)[MC::FM], float (*red)[MC::WN][64],
+                                           float (&mean)[MC::FM], float (&rstd)[MC::FM]) {
+  constexpr int C = MC::C, FN = MC::FN_C;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wm = wv / MC::WN, wn = wv % MC::WN;
   const int l16 = lane & 15, kg = lane >> 4;
-  float part[4];
-  static_for<4>([&](auto i) {
+  float part[MC::FM];
+  static_for<MC::FM>([&](auto i) {
     float sum = 0.f;
     static_for<FN>([&](auto j) {
       const int n = wn * 16 * FN + 16 * j + 4 * kg;
@@ -396,10 +406,10 @@ __device__ __forceinline__ void resid_rows(f32x4_t (&acc)[4][FN], const float* s
     sum += __shfl_xor(sum, 32, 64);
     part[i] = sum;
   });
-  if (kg == 0) static_for<4>([&](auto i) { red[0][wn][16 * i + l16] = part[i]; });
+  if (kg == 0) static_for<MC::FM>([&](auto i) { red[0][wn][wm * MC::TM + 16 * i + l16] = part[i]; });
   lds_barrier();
-  static_for<4>([&](auto i) {
-    const int r = 16 * i + l16;
+  static_for<MC::FM>([&](auto i) {
+    const int r = wm * MC::TM + 16 * i + l16;
     mean[i] = ((red[0][0][r] + red[0][1][r]) + (red[0][2][r] + red[0][3][r])) * (1.0f / C);
     float sq = 0.f;
     static_for<FN>([&](auto j) {
@@ -412,23 +422,24 @@ __device__ __forceinline__ void resid_rows(f32x4_t (&acc)[4][FN], const float* s
     sq += __shfl_xor(sq, 32, 64);
     part[i] = sq;
   });
-  if (kg == 0) static_for<4>([&](auto i) { red[1][wn][16 * i + l16] = part[i]; });
+  if (kg == 0) static_for<MC::FM>([&](auto i) { red[1][wn][wm * MC::TM + 16 * i + l16] = part[i]; });
   lds_barrier();
-  static_for<4>([&](auto i) {
-    const int r = 16 * i + l16;
+  static_for<MC::FM>([&](auto i) {
+    const int r = wm * MC::TM + 16 * i + l16;
     const float var = ((red[1][0][r] + red[1][1][r]) + (red[1][2][r] + red[1][3][r])) * (1.0f / C);
     rstd[i] = rsqrtf(var + 1e-5f);
   });
 }
 
 template <class MC>
-__global__ void __launch_bounds__(256) mlp_block_kernel(const int32_t* __restrict__ m_dev,
-                                                        const bf16* __restrict__ o, const int32_t* __restrict__ rows,
-                                                        const bf16* __restrict__ Wo, const float* __restrict__ bo,
-                                                        const bf16* __restrict__ W1, const float* __restrict__ b1,
-                                                        const bf16* __restrict__ W2, const float* __restrict__ b2,
-                                                        float* __restrict__ x, bf16* __restrict__ xh) {
-  constexpr int C = MC::C, HC = MC::HC, R = MC::R, BM = MC::BM;
+__global__ void __launch_bounds__(MLP_THREADS) mlp_block_kernel(const int32_t* __restrict__ m_dev,
+                                                                const bf16* __restrict__ o,
+                                                                const int32_t* __restrict__ rows,
+                                                                const bf16* __restrict__ Wo, const float* __restrict__ bo,
+                                                                const bf16* __restrict__ W1, const float* __restrict__ b1,
+                                                                const bf16* __restrict__ W2, const float* __restrict__ b2,
+                                                                float* __restrict__ x, bf16* __restrict__ xh) {
+  constexpr int C = MC::C, HC = MC::HC, R = MC::R, BM = MC::BM, NW = MLP_THREADS / 64;
   extern __shared__ __align__(16) bf16 lds[];
   bf16* ring = lds;
   bf16* ares = lds + MC::RING;
@@ -436,32 +447,31 @@ __global__ void __launch_bounds__(256) mlp_block_kernel(const int32_t* __restric
   float* sbo = reinterpret_cast<float*>(hres + MC::HRES);
   float* sb1 = sbo + C;
   float* sb2 = sb1 + R;
-  float(*red)[4][64] = reinterpret_cast<float(*)[4][64]>(sb2 + C);
+  float(*red)[MC::WN][64] = reinterpret_cast<float(*)[MC::WN][64]>(sb2 + C);
 
   const int M = m_dev[0];
   const int m0 = blockIdx.x * BM;
   if (m0 >= M) return;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int wm = wv / MC::WN, wn = wv % MC::WN;
   const int l16 = lane & 15, kg = lane >> 4;
 
-  for (int i = t; i < C; i += 256) {
+  for (int i = t; i < C; i += MLP_THREADS) {
     sbo[i] = bo[i];
     sb2[i] = b2[i];
   }
-  for (int i = t; i < R; i += 256) sb1[i] = b1[i];
-  // o rows -> resident A tile (rows >= M read row M-1; their results are never stored)
+  for (int i = t; i < R; i += MLP_THREADS) sb1[i] = b1[i];
+  // o rows -> resident A tile (rows >= M read row M-1; their results are never stored):
+  // 8 rows per load, 8 row groups per k block, one group per wavefront
   static_for<MC::NKC>([&](auto kb) {
-    static_for<2>([&](auto c) {
-      const int g8 = wv + 4 * c;
-      const int row = g8 * 8 + (lane >> 3);
-      const int m = min(m0 + row, M - 1);
-      dma16(o + (size_t)m * C + 64 * kb + ((lane & 7) ^ lds_swz(row)) * 8, ares + kb * BM * 64 + g8 * 512);
-    });
+    const int row = wv * 8 + (lane >> 3);
+    const int m = min(m0 + row, M - 1);
+    dma16(o + (size_t)m * C + 64 * kb + ((lane & 7) ^ lds_swz(row)) * 8, ares + kb * BM * 64 + wv * 512);
   });
-  // weight stages
+  // weight stages: stage s holds rows [0, stage_rows(s)) of 64 k columns
   auto stage_rows = [](int s) {
     if (s < MC::NKC) return C;
-    const int q = s - MC::NKC, tt = q % MC::PER_CHUNK;
+    const int tt = (s - MC::NKC) % MC::PER_CHUNK;
     return tt < MC::NKC ? HC : C;
   };
   auto issue = [&](int s) {
@@ -484,8 +494,8 @@ __global__ void __launch_bounds__(256) mlp_block_kernel(const int32_t* __restric
       }
     }
     bf16* dst = ring + (s % MC::ST) * MC::SLOT;
-    static_for<MC::SLOT_ROWS / 32>([&](auto c) {
-      const int g8 = wv + 4 * c;
+    static_for<MC::SLOT_ROWS / (8 * NW)>([&](auto c) {
+      const int g8 = wv + NW * c;
       if (g8 * 8 < rows_s) {  // uniform per wavefront
         const int row = g8 * 8 + (lane >> 3);
         dma16(base + (size_t)row * ld + ((lane & 7) ^ lds_swz(row)) * 8, dst + g8 * 512);
@@ -495,17 +505,17 @@ __global__ void __launch_bounds__(256) mlp_block_kernel(const int32_t* __restric
   issue(0);
   issue(1);
 
-  int dst[4];
-  static_for<4>([&](auto i) {
-    const int m = m0 + 16 * i + l16;
+  int dst[MC::FM];
+  static_for<MC::FM>([&](auto i) {
+    const int m = m0 + wm * MC::TM + 16 * i + l16;
     dst[i] = m < M ? rows[m] : -1;
   });
-  f32x4_t acc[4][MC::FN_C], hacc[4][MC::FN_H];
-  static_for<4>([&](auto i) {
+  f32x4_t acc[MC::FM][MC::FN_C], hacc[MC::FM][MC::FN_H];
+  static_for<MC::FM>([&](auto i) {
     static_for<MC::FN_C>([&](auto j) { acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f}; });
     static_for<MC::FN_H>([&](auto j) { hacc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f}; });
   });
-  float mean[4], rstd[4];
+  float mean[MC::FM], rstd[MC::FM];
   // Before multiplying stage s: wait until it has landed (at most the next stage's loads
   // outstanding, or none after a stretch of other vector-memory traffic), then queue s + 2.
   bool drained = true;  // the bias loads and row indices above are vector-memory reads
@@ -513,22 +523,22 @@ __global__ void __launch_bounds__(256) mlp_block_kernel(const int32_t* __restric
     if (drained || s + 1 >= MC::NSTAGE)
       vm_wait_barrier<0>();
     else if (stage_rows(s + 1) == C)
-      vm_wait_barrier<C / 32>();
+      vm_wait_barrier<C / (8 * NW)>();
     else
-      vm_wait_barrier<HC / 32>();
+      vm_wait_barrier<HC / (8 * NW)>();
     drained = false;
     if (s + 2 < MC::NSTAGE) issue(s + 2);
     return ring + (s % MC::ST) * MC::SLOT;
   };
   int s = 0;
-  for (int kb = 0; kb < MC::NKC; ++kb, ++s) mfma_block<MC::FN_C>(ares + kb * BM * 64, enter(s), acc);
+  for (int kb = 0; kb < MC::NKC; ++kb, ++s) mfma_block<MC, MC::FN_C>(ares + kb * BM * 64, enter(s), acc);
   // x1 = x + o W_o^T + b_o; u2 = normalise(x1) into the resident tile (every wavefront has
   // finished reading o there: resid_rows passes two block barriers)
-  resid_rows<MC::FN_C, C>(acc, sbo, x, dst, red, mean, rstd);
-  static_for<4>([&](auto i) {
-    const int r = 16 * i + l16;
+  resid_rows<MC>(acc, sbo, x, dst, red, mean, rstd);
+  static_for<MC::FM>([&](auto i) {
+    const int r = wm * MC::TM + 16 * i + l16;
     static_for<MC::FN_C>([&](auto j) {
-      const int n = wv * 16 * MC::FN_C + 16 * j + 4 * kg;
+      const int n = wn * 16 * MC::FN_C + 16 * j + 4 * kg;
       const f32x4_t& a = acc[i][j];
       uint2 pk;
       pk.x = pack_bf2((a[0] - mean[i]) * rstd[i], (a[1] - mean[i]) * rstd[i]);
@@ -539,13 +549,13 @@ __global__ void __launch_bounds__(256) mlp_block_kernel(const int32_t* __restric
   });
   drained = true;  // x was read and written
   for (int j = 0; j < MC::NCH; ++j) {
-    for (int kb = 0; kb < MC::NKC; ++kb, ++s) mfma_block<MC::FN_H>(ares + kb * BM * 64, enter(s), hacc);
+    for (int kb = 0; kb < MC::NKC; ++kb, ++s) mfma_block<MC, MC::FN_H>(ares + kb * BM * 64, enter(s), hacc);
     // hidden chunk j: GELU into the H tile (its previous contents were consumed before this
     // stage's barrier)
-    static_for<4>([&](auto i) {
-      const int r = 16 * i + l16;
+    static_for<MC::FM>([&](auto i) {
+      const int r = wm * MC::TM + 16 * i + l16;
       static_for<MC::FN_H>([&](auto jj) {
-        const int c = wv * 16 * MC::FN_H + 16 * jj + 4 * kg;
+        const int c = wn * 16 * MC::FN_H + 16 * jj + 4 * kg;
         const float* bb = sb1 + j * HC + c;
         const f32x4_t& a = hacc[i][jj];
         uint2 pk;
@@ -555,14 +565,14 @@ __global__ void __launch_bounds__(256) mlp_block_kernel(const int32_t* __restric
         hacc[i][jj] = f32x4_t{0.f, 0.f, 0.f, 0.f};
       });
     });
-    for (int kb = 0; kb < MC::NKH; ++kb, ++s) mfma_block<MC::FN_C>(hres + kb * BM * 64, enter(s), acc);
+    for (int kb = 0; kb < MC::NKH; ++kb, ++s) mfma_block<MC, MC::FN_C>(hres + kb * BM * 64, enter(s), acc);
   }
   // x2 = x1 + h W_2^T + b_2 (x1 was stored by this thread above); x^ = normalise(x2)
-  resid_rows<MC::FN_C, C>(acc, sb2, x, dst, red, mean, rstd);
-  static_for<4>([&](auto i) {
+  resid_rows<MC>(acc, sb2, x, dst, red, mean, rstd);
+  static_for<MC::FM>([&](auto i) {
     if (dst[i] >= 0)
       static_for<MC::FN_C>([&](auto j) {
-        const int n = wv * 16 * MC::FN_C + 16 * j + 4 * kg;
+        const int n = wn * 16 * MC::FN_C + 16 * j + 4 * kg;
         const f32x4_t& a = acc[i][j];
         uint2 pk;
         pk.x = pack_bf2((a[0] - mean[i]) * rstd[i], (a[1] - mean[i]) * rstd[i]);
@@ -581,8 +591,8 @@ static void mlp_launch(int m_max, const int32_t* m_dev, const bf16* o, const int
     allow_lds(mlp_block_kernel<MC>, MC::LDS_BYTES);
     attr = true;
   }
-  mlp_block_kernel<MC><<<(m_max + MC::BM - 1) / MC::BM, 256, MC::LDS_BYTES, s>>>(m_dev, o, rows, wo, bo, w1, b1, w2,
-                                                                                  b2, x, xh);
+  mlp_block_kernel<MC><<<(m_max + MC::BM - 1) / MC::BM, MLP_THREADS, MC::LDS_BYTES, s>>>(m_dev, o, rows, wo, bo, w1,
+                                                                                          b1, w2, b2, x, xh);
 }
 
 bool mlp_block_supported(int C, int R) { return R == 4 * C && (C == 64 || C == 128 || C == 256); }
