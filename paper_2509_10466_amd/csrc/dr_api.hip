@@ -564,9 +564,12 @@ dr_status dr::dr_reserve_work(dr_ctx* c, Work& w, const Geo& g, bool stream_mode
     ALLOC(h, N * R * 4);
     ALLOC(k16, kvlen * 2);
     ALLOC(v16, kvlen * 2);
-    // padded key rows of K and V must read as zero
+    const size_t vtlen = nw * n.cfg.heads * (size_t)n.dh * attn_clip_vt_stride(n.Spad);
+    ALLOC(vt16, vtlen * 2);
+    // padded key rows of K and V (columns of V^T) must read as zero
     HIP_OK(c, hipMemset(w.k16, 0, kvlen * 2));
     HIP_OK(c, hipMemset(w.v16, 0, kvlen * 2));
+    HIP_OK(c, hipMemset(w.vt16, 0, vtlen * 2));
   }
 #undef ALLOC
   HIP_OK(c, hipDeviceSynchronize());
@@ -661,8 +664,8 @@ static dr_status run_blocks(dr_ctx* c, const Geo& g, dr_precision prec, hipStrea
     } else {
       // x^ (normalised rows) feeds Q/K/V; the projection leaves x1^ of the query rows in u16
       // for the MLP; the second MLP linear refreshes x^ of the query rows
-      LAUNCH(ST_QKV, launch_qkv_bf16(g, C, n.cfg.heads, n.Spad, w.xh, w.flag, w.wcount, b.wqkvf16, b.bqkvf, w.q16, w.k16, w.v16, s));
-      LAUNCH(ST_ATTN, launch_attn_bf16(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.v16, w.idx, w.woff, w.o16, nullptr, s));
+      LAUNCH(ST_QKV, launch_qkv_bf16(g, C, n.cfg.heads, n.Spad, attn_clip_vt_stride(n.Spad), w.xh, w.flag, w.wcount, b.wqkvf16, b.bqkvf, w.q16, w.k16, w.vt16, s));
+      LAUNCH(ST_ATTN, launch_attn_clip(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.vt16, w.idx, w.woff, w.o16, s));
       if (mlp_block_supported(C, R)) {
         LAUNCH(ST_MLP, launch_mlp_block_bf16(N, w.nq, C, w.o16, w.idx, b.wo16, b.bo, b.w1f16, b.b1f, b.w216, b.b2, w.x, w.xh, s));
       } else {
@@ -801,7 +804,8 @@ extern "C" dr_status dr_inspect(dr_ctx* c, const char* name, void* dst, size_t n
   const size_t kvlen = w.cap_windows * c->net.cfg.heads * (size_t)c->net.Spad * c->net.dh;
   struct Buf { const char* n; const void* p; size_t bytes; } bufs[] = {
       {"x", w.x, N * C * 4},       {"xh", w.xh, N * C * 2},     {"u16", w.u16, N * C * 2}, {"q16", w.q16, N * C * 2},
-      {"k16", w.k16, kvlen * 2},   {"v16", w.v16, kvlen * 2}, {"o16", w.o16, N * C * 2},
+      {"k16", w.k16, kvlen * 2},   {"v16", w.v16, kvlen * 2},
+      {"vt16", w.vt16, w.cap_windows * c->net.cfg.heads * (size_t)c->net.dh * attn_clip_vt_stride(c->net.Spad) * 2}, {"o16", w.o16, N * C * 2},
       {"h16", w.h16, N * R * 2},   {"u", w.u, N * C * 4},     {"kv", w.kv, N * 2 * C * 4},
       {"q", w.q, N * C * 4},       {"o", w.o, N * C * 4},     {"h", w.h, N * R * 4},
       {"flag", w.flag, N},         {"idx", w.idx, N * 4},     {"nq", w.nq, 4}};

@@ -96,6 +96,7 @@ struct Work {
   // BF16 path scratch (u16: normalised rows after the projection, compact)
   bf16 *u16 = nullptr, *q16 = nullptr, *k16 = nullptr, *v16 = nullptr, *o16 = nullptr,
        *h16 = nullptr;
+  bf16* vt16 = nullptr;  // V^T [win][head][dh][vt stride] (BF16 clip mode)
   float* amax = nullptr;  // FP8 activation amax slots [blocks][4]
   // stream mode: contiguous staging of the batch's frames, masks and outputs
   float* fst = nullptr;
@@ -253,9 +254,12 @@ void launch_embed_bf16(const Geo& g, int C, const float* frames, const uint8_t* 
                        const float* b, float* x, bf16* xh, hipStream_t s);
 void launch_decode_bf16(const Geo& g, int C, const bf16* xh, const int32_t* idx, const int32_t* nq,
                         const bf16* wd16, const float* bd, const uint8_t* masks, float* out, hipStream_t s);
-void launch_qkv_bf16(const Geo& g, int C, int heads, int Spad, const bf16* xh, const uint8_t* flag,
-                     const int32_t* wcount, const bf16* w, const float* bias, bf16* q, bf16* k, bf16* v,
+void launch_qkv_bf16(const Geo& g, int C, int heads, int Spad, int spv, const bf16* xh, const uint8_t* flag,
+                     const int32_t* wcount, const bf16* w, const float* bias, bf16* q, bf16* k, bf16* vt,
                      hipStream_t s);
+int attn_clip_vt_stride(int spad);
+void launch_attn_clip(const Geo& g, int C, int heads, int Spad, const bf16* q, const bf16* k, const bf16* vt,
+                      const int32_t* idx, const int32_t* woff, bf16* o, hipStream_t s);
 void launch_qkv_stream(const Geo& g, int C, int heads, const bf16* xh, const uint8_t* flag, const bf16* w,
                        const float* bias, bf16* q, const StreamTable& tab, hipStream_t s);
 void launch_fc1_bf16(int m_max, const int32_t* m_dev, int C, int R, const bf16* u2, const bf16* w,

@@ -274,6 +274,172 @@ void launch_attn_stream(const StreamTable& tab, const Geo& g, int C, int heads, 
 #undef DR_ATTN_CASE
 }
 
+// ------------------------------------------------------------------------------------------
+// Window attention, clip mode (BF16 path): one block of 8 wavefronts per (window, head)
+// runs every query of the window, so K and V of a (window, head) reach LDS exactly once.
+// K [Spad][dh] arrives by direct global->LDS loads with its 16-byte chunks XOR-swizzled by
+// row (chunk c of row r at c ^ (r mod dh/8)), V^T [dh][SPV] is stored transposed by the
+// Q/K/V epilogue with an odd number of 16-byte chunks per row (SPV), so its 16 fragment
+// rows fall on distinct banks, and is copied as one contiguous block.  Each wavefront
+// takes query tiles of 16: S^T = K Q^T, row softmax in FP32 registers, O^T = V^T P^T.
+// ------------------------------------------------------------------------------------------
+constexpr int ATT_THREADS = 512;
+
+__host__ __device__ constexpr int attn_vt_stride(int spad) { return (spad / 8) % 2 ? spad : spad + 8; }
+
+// Copies `bytes` (a multiple of 16) from global to LDS, 1 KB per wavefront load; the
+// K tile is swizzled on the way (dh/8 chunks per row), the V^T tile copied as is.
+template <int CH, bool SWZ>
+__device__ __forceinline__ void attn_dma(const bf16* __restrict__ src, bf16* dst, int bytes) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int chunks = bytes / 16;
+  for (int c0 = wv * 64; c0 < chunks; c0 += ATT_THREADS) {
+    const int c = c0 + lane;
+    if (c < chunks) {
+      int sc = c;
+      if (SWZ) {
+        const int row = c / CH, pc = c % CH;
+        sc = row * CH + (pc ^ (row & (CH - 1)));
+      }
+      __builtin_amdgcn_global_load_lds(src + (size_t)sc * 8, (__attribute__((address_space(3))) void*)(dst + c0 * 8),
+                                       16, 0, 0);
+    }
+  }
+}
+
+template <int DH, int NT>
+__global__ void __launch_bounds__(ATT_THREADS) attn_clip_kernel(Geo g, int C, int heads, const bf16* __restrict__ q,
+                                                                const bf16* __restrict__ kmat,
+                                                                const bf16* __restrict__ vtmat,
+                                                                const int32_t* __restrict__ idx,
+                                                                const int32_t* __restrict__ woff, bf16* __restrict__ o) {
+  constexpr int SP = NT * 16, CH = DH / 8, SPV = attn_vt_stride(SP);
+  extern __shared__ __align__(16) bf16 att_lds[];
+  bf16* Ks = att_lds;            // [SP][DH], swizzled chunks
+  bf16* Vt = att_lds + SP * DH;  // [DH][SPV]
+  const int w = blockIdx.x / heads, h = blockIdx.x - w * heads;
+  const int q0 = woff[w], nqw = woff[w + 1] - q0;
+  if (nqw == 0) return;
+  attn_dma<CH, true>(kmat + ((size_t)w * heads + h) * SP * DH, Ks, SP * DH * 2);
+  attn_dma<CH, false>(vtmat + ((size_t)w * heads + h) * DH * SPV, Vt, DH * SPV * 2);
+  asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int l16 = lane & 15, kg = lane >> 4;
+  const float sl2 = 1.4426950408889634f / sqrtf((float)DH);  // log2(e) / sqrt(dh)
+  const int S = g.S;
+  for (int qt = wv; qt * 16 < nqw; qt += ATT_THREADS / 64) {
+    // K and V^T fragments are re-read from LDS per query tile: hoisting them out of the loop
+    // would hold the whole window in registers
+    asm volatile("" ::: "memory");
+    const int qi = qt * 16 + l16;
+    const bool valid = qi < nqw;
+    const int r = q0 + (valid ? qi : 0);
+    const int n = idx[r];
+    bf16x8_t qf[DH / 32];
+#pragma unroll
+    for (int kk = 0; kk < DH / 32; ++kk) {
+      const uint4 v = valid ? *reinterpret_cast<const uint4*>(q + (size_t)n * C + h * DH + kk * 32 + kg * 8)
+                            : make_uint4(0, 0, 0, 0);
+      qf[kk] = bitcast<bf16x8_t>(v);
+    }
+    float sc[NT][4];
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+      f32x4_t a = {0.f, 0.f, 0.f, 0.f};
+      const int row = tt * 16 + l16;
+#pragma unroll
+      for (int kk = 0; kk < DH / 32; ++kk) {
+        const int pc = (kk * 4 + kg) ^ (row & (CH - 1));
+        const bf16x8_t kf = *reinterpret_cast<const bf16x8_t*>(Ks + row * DH + pc * 8);
+        a = mfma16_x2(kf, qf[kk], a);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int key = tt * 16 + kg * 4 + i;
+        sc[tt][i] = key < S ? a[i] * sl2 : -INFINITY;
+      }
+    }
+    float mx = -INFINITY;
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) mx = fmaxf(mx, sc[tt][i]);
+    mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+    float sum = 0.f;
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float p = exp2f(sc[tt][i] - mx);
+        sc[tt][i] = p;
+        sum += p;
+      }
+    sum += __shfl_xor(sum, 16, 64);
+    sum += __shfl_xor(sum, 32, 64);
+    const float inv = 1.0f / sum;
+#pragma unroll
+    for (int dt = 0; dt < DH / 16; ++dt) {
+      f32x4_t a = {0.f, 0.f, 0.f, 0.f};
+      const bf16* vrow = Vt + (dt * 16 + l16) * SPV;
+#pragma unroll
+      for (int tt = 0; tt + 1 < NT; tt += 2) {
+        const uint2 v0 = *reinterpret_cast<const uint2*>(vrow + tt * 16 + kg * 4);
+        const uint2 v1 = *reinterpret_cast<const uint2*>(vrow + tt * 16 + 16 + kg * 4);
+        uint4 pv;
+        pv.x = pack_bf2(sc[tt][0], sc[tt][1]);
+        pv.y = pack_bf2(sc[tt][2], sc[tt][3]);
+        pv.z = pack_bf2(sc[tt + 1][0], sc[tt + 1][1]);
+        pv.w = pack_bf2(sc[tt + 1][2], sc[tt + 1][3]);
+        a = mfma16_x2(bitcast<bf16x8_t>(make_uint4(v0.x, v0.y, v1.x, v1.y)), bitcast<bf16x8_t>(pv), a);
+      }
+      if (NT & 1) {
+        constexpr int tt = NT - 1;
+        const uint2 v0 = *reinterpret_cast<const uint2*>(vrow + tt * 16 + kg * 4);
+        uint2 pv;
+        pv.x = pack_bf2(sc[tt][0], sc[tt][1]);
+        pv.y = pack_bf2(sc[tt][2], sc[tt][3]);
+        a = mfma16k16(bitcast<bf16x4_t>(v0), bitcast<bf16x4_t>(pv), a);
+      }
+      if (valid) {
+        uint2 pk;
+        pk.x = pack_bf2(a[0] * inv, a[1] * inv);
+        pk.y = pack_bf2(a[2] * inv, a[3] * inv);
+        *reinterpret_cast<uint2*>(o + (size_t)r * C + h * DH + dt * 16 + kg * 4) = pk;
+      }
+    }
+  }
+}
+
+int attn_clip_vt_stride(int spad) { return attn_vt_stride(spad); }
+
+void launch_attn_clip(const Geo& g, int C, int heads, int Spad, const bf16* q, const bf16* k, const bf16* vt,
+                      const int32_t* idx, const int32_t* woff, bf16* o, hipStream_t s) {
+  const int dh = C / heads;
+  const int nt = Spad / 16;
+  const size_t lds = (size_t)Spad * dh * 2 + (size_t)dh * attn_vt_stride(Spad) * 2;
+#define DR_ATTN_CLIP(DH_, NT_)                                                                          \
+  if (dh == DH_ && nt == NT_) {                                                                         \
+    static bool attr = false;                                                                           \
+    if (!attr) {                                                                                        \
+      if (lds > 65536)                                                                                  \
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(attn_clip_kernel<DH_, NT_>),            \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
+      attr = true;                                                                                      \
+    }                                                                                                   \
+    attn_clip_kernel<DH_, NT_><<<g.nwin * heads, ATT_THREADS, lds, s>>>(g, C, heads, q, k, vt, idx, woff, o); \
+    return;                                                                                             \
+  }
+  DR_ATTN_CLIP(32, 4)
+  DR_ATTN_CLIP(64, 4)
+  DR_ATTN_CLIP(64, 15)
+  DR_ATTN_CLIP(64, 19)
+  DR_ATTN_CLIP(32, 15)
+  DR_ATTN_CLIP(32, 19)
+#undef DR_ATTN_CLIP
+}
+
 bool attn_bf16_supported(int dh, int spad) {
   const int nt = spad / 16;
   return (dh == 32 || dh == 64) && (nt == 4 || nt == 15 || nt == 19);

@@ -41,26 +41,38 @@ __device__ __forceinline__ void for_fragments(int M, int m0, int n0, f32x4_t (&a
 // ------------------------------------------------------------------------------------------
 // Q/K/V
 // ------------------------------------------------------------------------------------------
-// Columns [0, C) -> Q rows [N][C]; [C, 2C) -> K and [2C, 3C) -> V, both [win][head][Spad][dh].
+// Columns [0, C) -> Q rows [N][C]; [C, 2C) -> K [win][head][Spad][dh]; [2C, 3C) -> V
+// transposed, V^T [win][head][dh][spv] (keys contiguous, the layout the attention kernel
+// stages as is).
 struct QkvOut {
   const float* bias;
-  bf16 *q, *k, *v;
-  int C, dh, heads, Spad, S;
+  bf16 *q, *k, *vt;
+  int C, dh, heads, Spad, S, spv;
   __device__ __forceinline__ void operator()(int m, int n, const f32x4_t& a) const {
     const float4 b4 = *reinterpret_cast<const float4*>(bias + n);
-    uint2 pk;
-    pk.x = pack_bf2(a[0] + b4.x, a[1] + b4.y);
-    pk.y = pack_bf2(a[2] + b4.z, a[3] + b4.w);
-    bf16* dst;
-    if (n < C) {
-      dst = q + (size_t)m * C + n;
+    const float y0 = a[0] + b4.x, y1 = a[1] + b4.y, y2 = a[2] + b4.z, y3 = a[3] + b4.w;
+    if (n < 2 * C) {
+      bf16* dst;
+      if (n < C) {
+        dst = q + (size_t)m * C + n;
+      } else {
+        const int c = n - C, hh = c / dh, d = c - hh * dh;
+        const int w = m / S, s = m - w * S;
+        dst = k + (((size_t)w * heads + hh) * Spad + s) * dh + d;
+      }
+      uint2 pk;
+      pk.x = pack_bf2(y0, y1);
+      pk.y = pack_bf2(y2, y3);
+      *reinterpret_cast<uint2*>(dst) = pk;
     } else {
-      const int part = n < 2 * C ? 1 : 2;
-      const int c = n - part * C, hh = c / dh, d = c - hh * dh;
+      const int c = n - 2 * C, hh = c / dh, d = c - hh * dh;
       const int w = m / S, s = m - w * S;
-      dst = (part == 1 ? k : v) + (((size_t)w * heads + hh) * Spad + s) * dh + d;
+      bf16* dst = vt + (((size_t)w * heads + hh) * dh + d) * spv + s;
+      dst[0] = f2bf(y0);
+      dst[spv] = f2bf(y1);
+      dst[2 * spv] = f2bf(y2);
+      dst[3 * spv] = f2bf(y3);
     }
-    *reinterpret_cast<uint2*>(dst) = pk;
   }
 };
 
@@ -130,11 +142,11 @@ static void qkv_launch(int M, int C, int S, const bf16* xh, const uint8_t* flag,
   qkv_kernel<TL, Out><<<grid, 256, TL::LDS_BYTES, s>>>(M, C, S, xh, flag, wcount, w, out);
 }
 
-void launch_qkv_bf16(const Geo& g, int C, int heads, int Spad, const bf16* xh, const uint8_t* flag,
-                     const int32_t* wcount, const bf16* w, const float* bias, bf16* q, bf16* k, bf16* v,
+void launch_qkv_bf16(const Geo& g, int C, int heads, int Spad, int spv, const bf16* xh, const uint8_t* flag,
+                     const int32_t* wcount, const bf16* w, const float* bias, bf16* q, bf16* k, bf16* vt,
                      hipStream_t s) {
   if (g.N <= 0) return;
-  const QkvOut out{bias, q, k, v, C, C / heads, heads, Spad, g.S};
+  const QkvOut out{bias, q, k, vt, C, C / heads, heads, Spad, g.S, spv};
   if (C % 128 == 0)
     qkv_launch<GemmTile<64, 128, 2, 2, 3>>(g.N, C, g.S, xh, flag, wcount, w, out, s);
   else
