@@ -356,28 +356,31 @@ extern "C" dr_status dr_load_weights(dr_ctx* c, const void* blob, size_t nbytes)
     H.v[1] = put16({s[8]}, {CC});
     H.v[2] = put16({s[12]}, {RC});
     H.v[3] = put16({s[14]}, {RC});
-    // LayerNorm affine parts folded into the next linear: appends W diag(g) to wf and
-    // b + W beta to bf for W [outs][in] (double accumulation for the bias)
+    // LayerNorm affine parts folded into the next linear: appends sc * W diag(g) to wf and
+    // sc * (b + W beta) to bf for W [outs][in] (double precision, rounded once)
     auto fold = [](const float* wsrc, const float* bias, int outs, int in, const float* g, const float* beta,
-                   std::vector<float>& wf, std::vector<float>& bf) {
+                   double sc, std::vector<float>& wf, std::vector<float>& bf) {
       for (int o = 0; o < outs; ++o) {
         double acc = bias[o];
         for (int i = 0; i < in; ++i) {
-          wf.push_back(wsrc[(size_t)o * in + i] * g[i]);
+          wf.push_back((float)(sc * wsrc[(size_t)o * in + i] * g[i]));
           acc += (double)wsrc[(size_t)o * in + i] * beta[i];
         }
-        bf.push_back((float)acc);
+        bf.push_back((float)(sc * acc));
       }
     };
     std::vector<float> wf, bf;
-    fold(s[2], s[3], C, C, s[0], s[1], wf, bf);  // Q
-    fold(s[4], s[5], C, C, s[0], s[1], wf, bf);  // K
-    fold(s[6], s[7], C, C, s[0], s[1], wf, bf);  // V
+    // Q also carries the softmax scale in base 2, log2(e) / sqrt(dh): the attention kernels
+    // of the BF16 path exponentiate the scores with exp2 directly
+    const double qscale = 1.4426950408889634 / std::sqrt((double)n.dh);
+    fold(s[2], s[3], C, C, s[0], s[1], qscale, wf, bf);  // Q
+    fold(s[4], s[5], C, C, s[0], s[1], 1.0, wf, bf);     // K
+    fold(s[6], s[7], C, C, s[0], s[1], 1.0, wf, bf);     // V
     H.v[4] = put16({wf.data()}, {wf.size()});
     O.v[24] = put(bf.data(), bf.size());
     wf.clear();
     bf.clear();
-    fold(s[12], s[13], R, C, s[10], s[11], wf, bf);  // first MLP linear
+    fold(s[12], s[13], R, C, s[10], s[11], 1.0, wf, bf);  // first MLP linear
     H.v[5] = put16({wf.data()}, {wf.size()});
     O.v[25] = put(bf.data(), bf.size());
   }

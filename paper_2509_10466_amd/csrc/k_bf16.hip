@@ -79,7 +79,7 @@ __device__ __forceinline__ void attn_stage(bf16* Ks, bf16* Vs, const bf16* __res
 
 // Queries of one (window, head, 64-query tile) against the S keys staged in LDS (rows >= S of
 // K and columns >= S of V^T must be finite; their scores are masked to -inf).
-template <int DH, int NT>
+template <int DH, int NT, bool PRESCALED>
 __device__ __forceinline__ void attn_compute(const bf16* Ks, const bf16* Vs, int S, int C, int h,
                                              const bf16* __restrict__ q, const int32_t* __restrict__ idx,
                                              int q0, int nqw, int qbase, bf16* __restrict__ o,
@@ -103,7 +103,8 @@ __device__ __forceinline__ void attn_compute(const bf16* Ks, const bf16* Vs, int
     qf[kk] = bitcast<bf16x8_t>(v);
   }
 
-  const float sl2 = 1.4426950408889634f / sqrtf((float)DH);  // log2(e) / sqrt(dh)
+  // scores in base 2: Q of the BF16 path already carries log2(e) / sqrt(dh)
+  const float sl2 = PRESCALED ? 1.0f : 1.4426950408889634f / sqrtf((float)DH);
   float sc[NT][4];
 #pragma unroll
   for (int tt = 0; tt < NT; ++tt) {
@@ -196,7 +197,7 @@ __global__ void __launch_bounds__(256) attn_bf16_kernel(Geo g, int C, int heads,
   attn_stage<DH, NT>(Ks, Vs, kmat + ((size_t)w * heads + h) * AT::SP * DH, vmat + ((size_t)w * heads + h) * AT::SP * DH,
                      0, AT::SP);
   __syncthreads();
-  attn_compute<DH, NT>(Ks, Vs, g.S, C, h, q, idx, q0, nqw, qbase, o, amax_o);
+  attn_compute<DH, NT, false>(Ks, Vs, g.S, C, h, q, idx, q0, nqw, qbase, o, amax_o);
 }
 
 // Stream mode: the keys of window (request r, window wl) are the window's rows in the
@@ -231,7 +232,7 @@ __global__ void __launch_bounds__(256) attn_stream_kernel(StreamTable tab, int C
     Vs[d * AT::VST + row] = 0;
   }
   __syncthreads();
-  attn_compute<DH, NT>(Ks, Vs, S, C, h, q, idx, q0, nqw, qbase, o, nullptr);
+  attn_compute<DH, NT, true>(Ks, Vs, S, C, h, q, idx, q0, nqw, qbase, o, nullptr);
 }
 
 void launch_attn_bf16(const Geo& g, int C, int heads, int Spad, const bf16* q, const bf16* k,
@@ -326,7 +327,6 @@ __global__ void __launch_bounds__(ATT_THREADS) attn_clip_kernel(Geo g, int C, in
 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int l16 = lane & 15, kg = lane >> 4;
-  const float sl2 = 1.4426950408889634f / sqrtf((float)DH);  // log2(e) / sqrt(dh)
   const int S = g.S;
   for (int qt = wv; qt * 16 < nqw; qt += ATT_THREADS / 64) {
     // K and V^T fragments are re-read from LDS per query tile: hoisting them out of the loop
@@ -354,11 +354,10 @@ __global__ void __launch_bounds__(ATT_THREADS) attn_clip_kernel(Geo g, int C, in
         const bf16x8_t kf = *reinterpret_cast<const bf16x8_t*>(Ks + row * DH + pc * 8);
         a = mfma16_x2(kf, qf[kk], a);
       }
+      // scores are already in base 2 (Q carries log2(e) / sqrt(dh)); only the last key
+      // tile can hold padding keys (S > 16 (NT - 1))
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int key = tt * 16 + kg * 4 + i;
-        sc[tt][i] = key < S ? a[i] * sl2 : -INFINITY;
-      }
+      for (int i = 0; i < 4; ++i) sc[tt][i] = (tt < NT - 1 || tt * 16 + kg * 4 + i < S) ? a[i] : -INFINITY;
     }
     float mx = -INFINITY;
 #pragma unroll
