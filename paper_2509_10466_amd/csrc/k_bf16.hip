@@ -28,6 +28,17 @@ __device__ __forceinline__ f32x4_t mfma16k16(const bf16x4_t& a, const bf16x4_t& 
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+// Double-rate k = 32 product; groups of these are fenced (see above).
+__device__ __forceinline__ f32x4_t mfma32(const bf16x8_t& a, const bf16x8_t& b, const f32x4_t& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ void mfma_fence_begin() { __builtin_amdgcn_sched_barrier(0); }
+__device__ __forceinline__ void mfma_fence_end() {
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("s_nop 7" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
+}
+
 template <typename T, typename S>
 __device__ __forceinline__ T bitcast(const S& s) {
   static_assert(sizeof(T) == sizeof(S), "size");
@@ -321,13 +332,28 @@ __global__ void __launch_bounds__(ATT_THREADS) attn_clip_kernel(Geo g, int C, in
   const int w = blockIdx.x / heads, h = blockIdx.x - w * heads;
   const int q0 = woff[w], nqw = woff[w + 1] - q0;
   if (nqw == 0) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int l16 = lane & 15, kg = lane >> 4;
+  const int S = g.S;
+  // Q^T operand of query tile qt: lane holds q[idx[q0 + 16 qt + l16]][h*DH + 32 kk + 8 kg ..]
+  auto load_q = [&](int qt, bf16x8_t (&qf)[DH / 32]) {
+    const int qi = qt * 16 + l16;
+    const bool ok = qi < nqw;
+    const int n = idx[q0 + (ok ? qi : 0)];
+#pragma unroll
+    for (int kk = 0; kk < DH / 32; ++kk) {
+      const uint4 v = ok ? *reinterpret_cast<const uint4*>(q + (size_t)n * C + h * DH + kk * 32 + kg * 8)
+                         : make_uint4(0, 0, 0, 0);
+      qf[kk] = bitcast<bf16x8_t>(v);
+    }
+  };
+  // the first query tile's Q is in flight together with the K / V^T copies
+  bf16x8_t qnext[DH / 32];
+  if (wv * 16 < nqw) load_q(wv, qnext);
   attn_dma<CH, true>(kmat + ((size_t)w * heads + h) * SP * DH, Ks, SP * DH * 2);
   attn_dma<CH, false>(vtmat + ((size_t)w * heads + h) * DH * SPV, Vt, DH * SPV * 2);
   asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
 
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int l16 = lane & 15, kg = lane >> 4;
-  const int S = g.S;
   for (int qt = wv; qt * 16 < nqw; qt += ATT_THREADS / 64) {
     // K and V^T fragments are re-read from LDS per query tile: hoisting them out of the loop
     // would hold the whole window in registers
@@ -335,29 +361,50 @@ __global__ void __launch_bounds__(ATT_THREADS) attn_clip_kernel(Geo g, int C, in
     const int qi = qt * 16 + l16;
     const bool valid = qi < nqw;
     const int r = q0 + (valid ? qi : 0);
-    const int n = idx[r];
     bf16x8_t qf[DH / 32];
 #pragma unroll
-    for (int kk = 0; kk < DH / 32; ++kk) {
-      const uint4 v = valid ? *reinterpret_cast<const uint4*>(q + (size_t)n * C + h * DH + kk * 32 + kg * 8)
-                            : make_uint4(0, 0, 0, 0);
-      qf[kk] = bitcast<bf16x8_t>(v);
-    }
+    for (int kk = 0; kk < DH / 32; ++kk) qf[kk] = qnext[kk];
+    if ((qt + ATT_THREADS / 64) * 16 < nqw) load_q(qt + ATT_THREADS / 64, qnext);  // next tile, overlapped
+    // S^T = K Q^T: key tiles in groups of TG, each tile's k slices chained, the chains of a
+    // group interleaved; a group's K fragments are read while the previous group multiplies
+    constexpr int KS = DH / 32;  // 32-wide k slices
+    constexpr int TG = 5;
     float sc[NT][4];
+    bf16x8_t kf[2][TG][KS];
+    auto read_k = [&](int g0, bf16x8_t (&dst)[TG][KS]) {
 #pragma unroll
-    for (int tt = 0; tt < NT; ++tt) {
-      f32x4_t a = {0.f, 0.f, 0.f, 0.f};
-      const int row = tt * 16 + l16;
+      for (int u = 0; u < TG; ++u) {
+        const int tt = g0 + u;
+        if (tt < NT) {
+          const int row = tt * 16 + l16;
 #pragma unroll
-      for (int kk = 0; kk < DH / 32; ++kk) {
-        const int pc = (kk * 4 + kg) ^ (row & (CH - 1));
-        const bf16x8_t kf = *reinterpret_cast<const bf16x8_t*>(Ks + row * DH + pc * 8);
-        a = mfma16_x2(kf, qf[kk], a);
+          for (int kk = 0; kk < KS; ++kk)
+            dst[u][kk] = *reinterpret_cast<const bf16x8_t*>(Ks + row * DH + (((kk * 4 + kg) ^ (row & (CH - 1))) * 8));
+        }
       }
-      // scores are already in base 2 (Q carries log2(e) / sqrt(dh)); only the last key
-      // tile can hold padding keys (S > 16 (NT - 1))
+    };
+    read_k(0, kf[0]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) sc[tt][i] = (tt < NT - 1 || tt * 16 + kg * 4 + i < S) ? a[i] : -INFINITY;
+    for (int g0 = 0; g0 < NT; g0 += TG) {
+      const int cur = (g0 / TG) & 1;
+      if (g0 + TG < NT) read_k(g0 + TG, kf[cur ^ 1]);
+      f32x4_t a[TG];
+      mfma_fence_begin();
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk)
+#pragma unroll
+        for (int u = 0; u < TG; ++u)
+          if (g0 + u < NT) a[u] = mfma32(kf[cur][u][kk], qf[kk], kk ? a[u] : f32x4_t{0.f, 0.f, 0.f, 0.f});
+      mfma_fence_end();
+      // scores are already in base 2 (Q carries log2(e) / sqrt(dh)); only the last key tile
+      // can hold padding keys (S > 16 (NT - 1))
+#pragma unroll
+      for (int u = 0; u < TG; ++u) {
+        const int tt = g0 + u;
+        if (tt < NT)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) sc[tt][i] = (tt < NT - 1 || tt * 16 + kg * 4 + i < S) ? a[u][i] : -INFINITY;
+      }
     }
     float mx = -INFINITY;
 #pragma unroll
@@ -371,40 +418,64 @@ __global__ void __launch_bounds__(ATT_THREADS) attn_clip_kernel(Geo g, int C, in
     for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const float p = exp2f(sc[tt][i] - mx);
+        const float p = __builtin_amdgcn_exp2f(sc[tt][i] - mx);  // argument <= 0
         sc[tt][i] = p;
         sum += p;
       }
     sum += __shfl_xor(sum, 16, 64);
     sum += __shfl_xor(sum, 32, 64);
     const float inv = 1.0f / sum;
+
+    // O^T = V^T P^T: per pair of key tiles one MFMA for each 16-row block of dh (independent
+    // accumulators), P^T straight from the score registers (key order 4kg..+3 of each tile,
+    // matched by the V^T reads); V^T fragments of the next pair are read ahead
+    constexpr int DT = DH / 16, NP = NT / 2;
+    f32x4_t acc[DT];
 #pragma unroll
-    for (int dt = 0; dt < DH / 16; ++dt) {
-      f32x4_t a = {0.f, 0.f, 0.f, 0.f};
-      const bf16* vrow = Vt + (dt * 16 + l16) * SPV;
+    for (int dt = 0; dt < DT; ++dt) acc[dt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    bf16x8_t vf[2][DT];
+    auto read_v = [&](int p, bf16x8_t (&dst)[DT]) {
 #pragma unroll
-      for (int tt = 0; tt + 1 < NT; tt += 2) {
-        const uint2 v0 = *reinterpret_cast<const uint2*>(vrow + tt * 16 + kg * 4);
-        const uint2 v1 = *reinterpret_cast<const uint2*>(vrow + tt * 16 + 16 + kg * 4);
-        uint4 pv;
-        pv.x = pack_bf2(sc[tt][0], sc[tt][1]);
-        pv.y = pack_bf2(sc[tt][2], sc[tt][3]);
-        pv.z = pack_bf2(sc[tt + 1][0], sc[tt + 1][1]);
-        pv.w = pack_bf2(sc[tt + 1][2], sc[tt + 1][3]);
-        a = mfma16_x2(bitcast<bf16x8_t>(make_uint4(v0.x, v0.y, v1.x, v1.y)), bitcast<bf16x8_t>(pv), a);
+      for (int dt = 0; dt < DT; ++dt) {
+        const bf16* vrow = Vt + (dt * 16 + l16) * SPV + 32 * p + kg * 4;
+        const uint2 v0 = *reinterpret_cast<const uint2*>(vrow);
+        const uint2 v1 = *reinterpret_cast<const uint2*>(vrow + 16);
+        dst[dt] = bitcast<bf16x8_t>(make_uint4(v0.x, v0.y, v1.x, v1.y));
       }
-      if (NT & 1) {
-        constexpr int tt = NT - 1;
-        const uint2 v0 = *reinterpret_cast<const uint2*>(vrow + tt * 16 + kg * 4);
-        uint2 pv;
-        pv.x = pack_bf2(sc[tt][0], sc[tt][1]);
-        pv.y = pack_bf2(sc[tt][2], sc[tt][3]);
-        a = mfma16k16(bitcast<bf16x4_t>(v0), bitcast<bf16x4_t>(pv), a);
+    };
+    if (NP > 0) read_v(0, vf[0]);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const int cur = p & 1;
+      if (p + 1 < NP) read_v(p + 1, vf[cur ^ 1]);
+      uint4 pv;
+      pv.x = pack_bf2(sc[2 * p][0], sc[2 * p][1]);
+      pv.y = pack_bf2(sc[2 * p][2], sc[2 * p][3]);
+      pv.z = pack_bf2(sc[2 * p + 1][0], sc[2 * p + 1][1]);
+      pv.w = pack_bf2(sc[2 * p + 1][2], sc[2 * p + 1][3]);
+      const bf16x8_t pb = bitcast<bf16x8_t>(pv);
+      mfma_fence_begin();
+#pragma unroll
+      for (int dt = 0; dt < DT; ++dt) acc[dt] = mfma32(vf[cur][dt], pb, acc[dt]);
+      mfma_fence_end();
+    }
+    if (NT & 1) {  // last key tile alone: single-rate k = 16 (operands read at issue)
+      constexpr int tt = NT - 1;
+      uint2 pv;
+      pv.x = pack_bf2(sc[tt][0], sc[tt][1]);
+      pv.y = pack_bf2(sc[tt][2], sc[tt][3]);
+#pragma unroll
+      for (int dt = 0; dt < DT; ++dt) {
+        const uint2 v0 = *reinterpret_cast<const uint2*>(Vt + (dt * 16 + l16) * SPV + tt * 16 + kg * 4);
+        acc[dt] = mfma16k16(bitcast<bf16x4_t>(v0), bitcast<bf16x4_t>(pv), acc[dt]);
       }
-      if (valid) {
+    }
+    if (valid) {
+#pragma unroll
+      for (int dt = 0; dt < DT; ++dt) {
         uint2 pk;
-        pk.x = pack_bf2(a[0] * inv, a[1] * inv);
-        pk.y = pack_bf2(a[2] * inv, a[3] * inv);
+        pk.x = pack_bf2(acc[dt][0] * inv, acc[dt][1] * inv);
+        pk.y = pack_bf2(acc[dt][2] * inv, acc[dt][3] * inv);
         *reinterpret_cast<uint2*>(o + (size_t)r * C + h * DH + dt * 16 + kg * 4) = pk;
       }
     }
