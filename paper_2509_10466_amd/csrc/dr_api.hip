@@ -547,6 +547,7 @@ dr_status dr::dr_reserve_work(dr_ctx* c, Work& w, const Geo& g, bool stream_mode
   ALLOC(woff, (nw + 1) * 4);
   ALLOC(idx, N * 4);
   ALLOC(nq, 256);
+  ALLOC(worder, nw * 4);
   ALLOC(x, N * C * 4);
   ALLOC(q16, N * C * 2);
   ALLOC(o16, N * C * 2);
@@ -616,6 +617,7 @@ static dr_status run_tokens(dr_ctx* c, const Geo& g, const uint8_t* masks, int a
   Work& w = c->work;
   LAUNCH(ST_TOKENS, launch_token_flags(g, masks, all, w.flag, w.wcount, s));
   LAUNCH(ST_TOKENS, launch_token_gather(g, w.flag, w.wcount, w.idx, w.woff, w.nq, s));
+  LAUNCH(ST_TOKENS, launch_window_order(g, w.wcount, w.worder, s));
   return DR_OK;
 }
 
@@ -668,7 +670,7 @@ static dr_status run_blocks(dr_ctx* c, const Geo& g, dr_precision prec, hipStrea
       // x^ (normalised rows) feeds Q/K/V; the projection leaves x1^ of the query rows in u16
       // for the MLP; the second MLP linear refreshes x^ of the query rows
       LAUNCH(ST_QKV, launch_qkv_bf16(g, C, n.cfg.heads, n.Spad, attn_clip_vt_stride(n.Spad), w.xh, w.flag, w.wcount, b.wqkvf16, b.bqkvf, w.q16, w.k16, w.vt16, s));
-      LAUNCH(ST_ATTN, launch_attn_clip(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.vt16, w.idx, w.woff, w.o16, s));
+      LAUNCH(ST_ATTN, launch_attn_clip(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.vt16, w.idx, w.woff, w.worder, w.o16, s));
       if (mlp_block_supported(C, R)) {
         LAUNCH(ST_MLP, launch_mlp_block_bf16(N, w.nq, C, w.o16, w.idx, b.wo16, b.bo, b.w1f16, b.b1f, b.w216, b.b2, w.x, w.xh, s));
       } else {
@@ -701,7 +703,7 @@ extern "C" dr_status dr_inpaint(dr_ctx* c, const float* frames, const uint8_t* m
   const Net& n = c->net;
   if (prec != DR_FP32 && !attn_bf16_supported(n.dh, n.Spad))
     return fail(c, DR_ESHAPE, "BF16 attention has no kernel for %d-token windows", n.S);
-  if (prec == DR_BF16 && (!resid_ln_supported(n.C) || n.cfg.patch != 4))
+  if (prec == DR_BF16 && (!resid_ln_supported(n.C) || n.cfg.patch != 4 || !window_order_supported(g.S)))
     return fail(c, DR_ESHAPE, "the BF16 path needs dim 64, 128, 256 or 384 and patch 4");
   if (prec == DR_FP8 && !fp8_supported(n.C, n.R))
     return fail(c, DR_ESHAPE, "the FP8 path needs dim and hidden width multiples of 128");

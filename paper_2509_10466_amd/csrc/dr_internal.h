@@ -87,6 +87,7 @@ struct Work {
   int32_t* woff = nullptr;
   int32_t* idx = nullptr;
   int32_t* nq = nullptr;
+  int32_t* worder = nullptr;  // windows by decreasing query count
   // residual stream, FP32, window-major rows
   float* x = nullptr;
   // FP32 path scratch
@@ -259,7 +260,9 @@ void launch_qkv_bf16(const Geo& g, int C, int heads, int Spad, int spv, const bf
                      hipStream_t s);
 int attn_clip_vt_stride(int spad);
 void launch_attn_clip(const Geo& g, int C, int heads, int Spad, const bf16* q, const bf16* k, const bf16* vt,
-                      const int32_t* idx, const int32_t* woff, bf16* o, hipStream_t s);
+                      const int32_t* idx, const int32_t* woff, const int32_t* worder, bf16* o, hipStream_t s);
+bool window_order_supported(int S);
+void launch_window_order(const Geo& g, const int32_t* wcount, int32_t* order, hipStream_t s);
 void launch_qkv_stream(const Geo& g, int C, int heads, const bf16* xh, const uint8_t* flag, const bf16* w,
                        const float* bias, bf16* q, const StreamTable& tab, hipStream_t s);
 void launch_fc1_bf16(int m_max, const int32_t* m_dev, int C, int R, const bf16* u2, const bf16* w,

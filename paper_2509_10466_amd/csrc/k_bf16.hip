@@ -324,12 +324,16 @@ __global__ void __launch_bounds__(ATT_THREADS) attn_clip_kernel(Geo g, int C, in
                                                                 const bf16* __restrict__ kmat,
                                                                 const bf16* __restrict__ vtmat,
                                                                 const int32_t* __restrict__ idx,
-                                                                const int32_t* __restrict__ woff, bf16* __restrict__ o) {
+                                                                const int32_t* __restrict__ woff,
+                                                                const int32_t* __restrict__ worder,
+                                                                bf16* __restrict__ o) {
   constexpr int SP = NT * 16, CH = DH / 8, SPV = attn_vt_stride(SP);
   extern __shared__ __align__(16) bf16 att_lds[];
   bf16* Ks = att_lds;            // [SP][DH], swizzled chunks
   bf16* Vt = att_lds + SP * DH;  // [DH][SPV]
-  const int w = blockIdx.x / heads, h = blockIdx.x - w * heads;
+  // (window, head) work in order of decreasing query count
+  const int rank = blockIdx.x / heads, h = blockIdx.x - rank * heads;
+  const int w = worder[rank];
   const int q0 = woff[w], nqw = woff[w + 1] - q0;
   if (nqw == 0) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -485,7 +489,7 @@ __global__ void __launch_bounds__(ATT_THREADS) attn_clip_kernel(Geo g, int C, in
 int attn_clip_vt_stride(int spad) { return attn_vt_stride(spad); }
 
 void launch_attn_clip(const Geo& g, int C, int heads, int Spad, const bf16* q, const bf16* k, const bf16* vt,
-                      const int32_t* idx, const int32_t* woff, bf16* o, hipStream_t s) {
+                      const int32_t* idx, const int32_t* woff, const int32_t* worder, bf16* o, hipStream_t s) {
   const int dh = C / heads;
   const int nt = Spad / 16;
   const size_t lds = (size_t)Spad * dh * 2 + (size_t)dh * attn_vt_stride(Spad) * 2;
@@ -498,7 +502,7 @@ void launch_attn_clip(const Geo& g, int C, int heads, int Spad, const bf16* q, c
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
       attr = true;                                                                                      \
     }                                                                                                   \
-    attn_clip_kernel<DH_, NT_><<<g.nwin * heads, ATT_THREADS, lds, s>>>(g, C, heads, q, k, vt, idx, woff, o); \
+    attn_clip_kernel<DH_, NT_><<<g.nwin * heads, ATT_THREADS, lds, s>>>(g, C, heads, q, k, vt, idx, woff, worder, o); \
     return;                                                                                             \
   }
   DR_ATTN_CLIP(32, 4)

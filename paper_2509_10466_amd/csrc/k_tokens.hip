@@ -96,6 +96,37 @@ __global__ void __launch_bounds__(256) token_gather_kernel(Geo g, const uint8_t*
   }
 }
 
+// Windows listed by decreasing query count (a counting sort over counts 0..S, one block):
+// the attention kernel takes its (window, head) work in this order, so the longest windows
+// start first and the short ones fill in behind them.  Windows of equal count may come in
+// any order; that only changes scheduling, never a result.
+constexpr int ORDER_MAX_S = 2048;
+
+__global__ void __launch_bounds__(1024) window_order_kernel(int nwin, int S, const int32_t* __restrict__ wcount,
+                                                            int32_t* __restrict__ order) {
+  __shared__ int hist[ORDER_MAX_S + 1];
+  __shared__ int start[ORDER_MAX_S + 1];
+  for (int c = threadIdx.x; c <= S; c += blockDim.x) hist[c] = 0;
+  __syncthreads();
+  for (int w = threadIdx.x; w < nwin; w += blockDim.x) atomicAdd(&hist[wcount[w]], 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int c = S; c >= 0; --c) {
+      start[c] = run;
+      run += hist[c];
+    }
+  }
+  __syncthreads();
+  for (int w = threadIdx.x; w < nwin; w += blockDim.x) order[atomicAdd(&start[wcount[w]], 1)] = w;
+}
+
+bool window_order_supported(int S) { return S <= ORDER_MAX_S; }
+
+void launch_window_order(const Geo& g, const int32_t* wcount, int32_t* order, hipStream_t s) {
+  window_order_kernel<<<1, 1024, 0, s>>>(g.nwin, g.S, wcount, order);
+}
+
 void launch_token_flags(const Geo& g, const uint8_t* masks, int all, uint8_t* flag,
                         int32_t* wcount, hipStream_t s) {
   token_flags_kernel<<<g.nwin, 256, 0, s>>>(g, masks, all, flag, wcount);
