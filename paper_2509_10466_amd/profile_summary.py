@@ -1,0 +1,147 @@
+"""Text summaries of rocprofv3 result databases (SQLite ``*_results.db``).
+
+    python -m paper_2509_10466_amd.profile_summary kernels RESULTS_DB --command "CMD"
+    python -m paper_2509_10466_amd.profile_summary traffic --fetch FETCH_DB --write WRITE_DB \\
+        --kernel SUBSTRING --command-fetch "CMD" --command-write "CMD"
+
+``kernels`` tabulates a --kernel-trace run: calls, average / min / max duration and share of
+the traced GPU time per kernel.  ``traffic`` turns two --pmc runs (FETCH_SIZE, then
+WRITE_SIZE; KiB per dispatch) into HBM bytes per launch of one kernel, each counter scaled by
+what it reads for the plain 256 MiB device copy that ``bench.py --calib-copy`` performs
+(torch's copy of a 64 Mi-element float32 tensor), and records a hash of the library
+sources so that a later change of any kernel invalidates the figure.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import os
+import re
+import sqlite3
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+COPY_BYTES = 64 * 1024 * 1024 * 4  # bench.py --calib-copy: 64 Mi float32 elements
+
+
+def source_hash() -> str:
+    """sha256 over the library's HIP sources and headers (sorted by name)."""
+    h = hashlib.sha256()
+    csrc = os.path.join(HERE, "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def short(name: str) -> str:
+    return re.sub(r"\(.*", "", name).replace("void ", "")
+
+
+def kernels(db: str, command: str) -> str:
+    c = sqlite3.connect(db)
+    rows = list(c.execute("select name, count(*), avg(end-start), min(end-start), max(end-start), "
+                          "sum(end-start) from kernels group by name order by sum(end-start) desc"))
+    tot = sum(r[5] for r in rows) or 1
+    out = [f"command: {command}", "durations in microseconds (kernel trace, GPU timestamps)",
+           f"{'kernel':72s} {'calls':>6s} {'avg':>9s} {'min':>9s} {'max':>9s} {'total_ms':>9s} {'pct':>6s}"]
+    for name, cnt, avg, mn, mx, s in rows:
+        out.append(f"{short(name)[:72]:72s} {cnt:6d} {avg / 1e3:9.2f} {mn / 1e3:9.2f} {mx / 1e3:9.2f} "
+                   f"{s / 1e6:9.3f} {100 * s / tot:6.2f}")
+    return "\n".join(out)
+
+
+def _counter(db: str, counter: str):
+    """kernel name -> list of per-dispatch counter values (KiB for the *_SIZE counters)."""
+    c = sqlite3.connect(db)
+    per = defaultdict(float)
+    names = {}
+    for name, ctr, val, did in c.execute("select kernel_name, counter_name, value, dispatch_id from counters_collection"):
+        if ctr != counter:
+            continue
+        per[did] += val
+        names[did] = name
+    out = defaultdict(list)
+    for did, v in per.items():
+        out[names[did]].append(v)
+    return out
+
+
+def traffic(fetch_db, write_db, kernel, cmd_f, cmd_w) -> str:
+    fetch = _counter(fetch_db, "FETCH_SIZE")
+    write = _counter(write_db, "WRITE_SIZE")
+
+    def pick(table, sub):
+        hits = {k: v for k, v in table.items() if sub in k}
+        if not hits:
+            sys.exit(f"no kernel matching {sub!r}")
+        return hits
+
+    copy_f = [v for k, vs in fetch.items() if "copyBuffer" in k or "copy_kernel" in k for v in vs]
+    copy_w = [v for k, vs in write.items() if "copyBuffer" in k or "copy_kernel" in k for v in vs]
+    big_f = max(copy_f) if copy_f else None
+    big_w = max(copy_w) if copy_w else None
+    kf = pick(fetch, kernel)
+    kw = pick(write, kernel)
+    name = max(kf, key=lambda k: len(kf[k]))
+    f_avg = sum(kf[name]) / len(kf[name])
+    w_avg = sum(kw.get(name, [0.0])) / max(len(kw.get(name, [1])), 1)
+    ref_kib = COPY_BYTES / 1024
+    sf = ref_kib / big_f if big_f else 1.0
+    sw = ref_kib / big_w if big_w else 1.0
+    t = (f_avg * sf + w_avg * sw) * 1024
+    lines = [
+        f"command (FETCH_SIZE): {cmd_f}",
+        f"command (WRITE_SIZE): {cmd_w}",
+        f"kernel: {short(name)}",
+        f"dispatches: {len(kf[name])}",
+        f"FETCH_SIZE KiB per dispatch: {f_avg:.1f}",
+        f"WRITE_SIZE KiB per dispatch: {w_avg:.1f}",
+        f"copy calibration ({COPY_BYTES // (1 << 20)} MiB device copy): FETCH_SIZE {big_f} KiB, WRITE_SIZE {big_w} KiB "
+        f"-> scale {sf:.4f} (fetch), {sw:.4f} (write)",
+        f"traffic_bytes_per_launch: {t:.0f}",
+        f"source_sha256: {source_hash()}",
+    ]
+    return "\n".join(lines)
+
+
+def read_traffic(path: str):
+    """(kernel, bytes per launch) from a ``traffic`` summary if it was taken from the current
+    sources, else None."""
+    try:
+        with open(path) as f:
+            txt = f.read()
+    except OSError:
+        return None
+    kv = dict(line.split(": ", 1) for line in txt.splitlines() if ": " in line)
+    if kv.get("source_sha256") != source_hash():
+        return None
+    try:
+        return kv["kernel"], float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    k = sub.add_parser("kernels")
+    k.add_argument("db")
+    k.add_argument("--command", required=True)
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--command-fetch", required=True)
+    t.add_argument("--command-write", required=True)
+    a = ap.parse_args()
+    if a.cmd == "kernels":
+        print(kernels(a.db, a.command))
+    else:
+        print(traffic(a.fetch, a.write, a.kernel, a.command_fetch, a.command_write))
+
+
+if __name__ == "__main__":
+    main()
