@@ -84,7 +84,10 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("kernels using scratch memory: " + ", ".join(
             f"{k} ({v['scratchsize']} B/lane)" for k, v in sorted(spilled.items())))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *[r[0] for r in results]]
+    # every symbol must resolve at link time: a missing definition is a build error, not a
+    # failure at load time
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,--no-undefined", "-o", tmp,
+           *[r[0] for r in results]]
     p = subprocess.run(cmd, capture_output=True, text=True)
     if p.returncode != 0:
         raise RuntimeError(f"link failed:\n{p.stdout}\n{p.stderr}")

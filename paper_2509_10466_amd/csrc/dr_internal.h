@@ -116,7 +116,9 @@ struct StreamTable {
   int head[STREAM_MAXB];    // slot receiving the new frame
   int npast[STREAM_MAXB];   // cached past frames (<= ring - 1)
   int T[STREAM_MAXB];       // frames in the request's ring (memory slots + 1)
-  long long slot_stride;    // elements between slots
+  long long slot_stride;    // elements between slots of K
+  long long vslot_stride;   // elements between slots of V^T
+  int sfp;                  // key slots per frame in V^T rows ([win_f][head][dh][sfp] per slot)
 };
 
 // Entry r of a per-request table held in kernel arguments, read through selects: a runtime
@@ -279,9 +281,10 @@ void launch_resid_ln_bf16(int m_max, const int32_t* m_dev, int C, int K, const b
 // stream mode
 void launch_gather_frames(const FramePtrs& p, size_t npix, float* fst, uint8_t* mst, hipStream_t s);
 void launch_scatter_frames(const FramePtrs& p, size_t npix, const float* ost, hipStream_t s);
-void launch_attn_stream(const StreamTable& tab, const Geo& g, int C, int heads, int Spad,
-                        const bf16* q, const int32_t* idx, const int32_t* woff, bf16* o,
-                        hipStream_t s);
+int ring_vt_frame_stride(int sf);
+bool attn_ring_supported(int dh, int sf, int nf);
+void launch_attn_ring(const StreamTable& tab, const Geo& g, int C, int heads, int nf, const bf16* q, const int32_t* idx,
+                      const int32_t* woff, const int32_t* worder, bf16* o, hipStream_t s);
 
 // host helpers shared by the API translation units
 dr_status dr_fail(dr_ctx* c, dr_status st, const char* fmt, ...);

@@ -45,13 +45,20 @@ using namespace dr;
     dr_prof_end(c, stage, s, ea_, eb_);                                                                   \
   } while (0)
 
-namespace dr {
-bool attn_bf16_supported(int dh, int spad);
+// Ring bytes per slot and block: K [win_f][head][S_f][dh] and V^T [win_f][head][dh][sfp]
+// (sfp = S_f rounded up to whole 16-key tiles), bf16.
+static void ring_elems(const dr_ctx* c, int H, int W, size_t& k_elems, size_t& v_elems) {
+  const dr_netcfg& k = c->net.cfg;
+  const size_t tok = (size_t)(H / c->net.P) * (W / c->net.P);
+  const int sf = k.win_h * k.win_w;
+  k_elems = tok * c->net.C;
+  v_elems = tok / sf * c->net.C * ring_vt_frame_stride(sf);
 }
 
 static size_t stream_bytes(const dr_ctx* c, int H, int W, int slots) {
-  const size_t tok = (size_t)(H / c->net.P) * (W / c->net.P);
-  return (size_t)2 * (slots + 1) * c->net.cfg.blocks * tok * c->net.C * 2;
+  size_t ke, ve;
+  ring_elems(c, H, W, ke, ve);
+  return (size_t)(slots + 1) * c->net.cfg.blocks * (ke + ve) * 2;
 }
 
 static dr_status check_frame_shape(dr_ctx* c, int H, int W) {
@@ -90,10 +97,20 @@ extern "C" dr_status dr_stream_open_slots(dr_ctx* c, int H, int W, int slots, in
   s.W = W;
   s.slots = slots;
   s.bytes = bytes;
-  if (hipMalloc(&s.kc, bytes / 2) != hipSuccess) return dr_fail(c, DR_ENOMEM, "stream cache allocation failed");
-  if (hipMalloc(&s.vc, bytes / 2) != hipSuccess) {
+  size_t ke, ve;
+  ring_elems(c, H, W, ke, ve);
+  const size_t kbytes = (size_t)(slots + 1) * c->net.cfg.blocks * ke * 2;
+  const size_t vbytes = (size_t)(slots + 1) * c->net.cfg.blocks * ve * 2;
+  if (hipMalloc(&s.kc, kbytes) != hipSuccess) return dr_fail(c, DR_ENOMEM, "stream cache allocation failed");
+  if (hipMalloc(&s.vc, vbytes) != hipSuccess) {
     (void)hipFree(s.kc);
     return dr_fail(c, DR_ENOMEM, "stream cache allocation failed");
+  }
+  // the padding key slots of V^T are never written and must read as zero
+  if (hipMemset(s.vc, 0, vbytes) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    (void)hipFree(s.kc);
+    (void)hipFree(s.vc);
+    return dr_fail(c, DR_EHIP, "stream cache initialisation failed");
   }
   const int id = c->next_sid++;
   c->streams[id] = s;
@@ -128,7 +145,8 @@ static dr_status stream_step_locked(dr_ctx* c, Work& w, int n, const int32_t* si
   if (n < 1 || n > STREAM_MAXB) return dr_fail(c, DR_EINVAL, "batch of %d requests (1..%d)", n, STREAM_MAXB);
   if (!c->have_weights) return dr_fail(c, DR_EINVAL, "no weights loaded");
   const Net& net = c->net;
-  if (!attn_bf16_supported(net.dh, net.Spad)) return dr_fail(c, DR_ESHAPE, "no attention kernel for this window");
+  if (!attn_ring_supported(net.dh, net.cfg.win_h * net.cfg.win_w, net.cfg.win_t))
+    return dr_fail(c, DR_ESHAPE, "no stream attention kernel for this window");
   if (!resid_ln_supported(net.C) || net.cfg.patch != 4)
     return dr_fail(c, DR_ESHAPE, "stream mode needs dim 64, 128, 256 or 384 and patch 4");
   std::vector<StreamSt*> st(n);
@@ -156,24 +174,28 @@ static dr_status stream_step_locked(dr_ctx* c, Work& w, int n, const int32_t* si
   }
   fp.n = n;
   const int C = net.C, R = net.R, N = g.N, L = net.cfg.blocks;
-  const size_t blk_elems = (size_t)(g.Ht * g.Wt) * C;  // [win_f][head][S_f][dh] of one frame
+  size_t blk_elems, vblk_elems;  // K and V^T elements of one frame and block
+  ring_elems(c, H, Wd, blk_elems, vblk_elems);
   LAUNCH(ST_COPY, launch_gather_frames(fp, npix, w.fst, w.mst, s));
   LAUNCH(ST_TOKENS, launch_token_flags(g, w.mst, qs == DR_QUERY_ALL, w.flag, w.wcount, s));
   LAUNCH(ST_TOKENS, launch_token_gather(g, w.flag, w.wcount, w.idx, w.woff, w.nq, s));
+  LAUNCH(ST_TOKENS, launch_window_order(g, w.wcount, w.worder, s));
   LAUNCH(ST_EMBED, launch_embed_bf16(g, C, w.fst, w.mst, net.embed_wT16, net.embed_b, w.x, w.xh, s));
   for (int l = 0; l < L; ++l) {
     const BlockW& b = net.blk[l];
     StreamTable tab{};
     for (int r = 0; r < n; ++r) {
       tab.k[r] = st[r]->kc + (size_t)l * blk_elems;
-      tab.v[r] = st[r]->vc + (size_t)l * blk_elems;
+      tab.v[r] = st[r]->vc + (size_t)l * vblk_elems;
       tab.head[r] = st[r]->head;
       tab.npast[r] = st[r]->npast;
       tab.T[r] = st[r]->slots + 1;
     }
     tab.slot_stride = (long long)L * blk_elems;
+    tab.vslot_stride = (long long)L * vblk_elems;
+    tab.sfp = ring_vt_frame_stride(g.S);
     LAUNCH(ST_QKV, launch_qkv_stream(g, C, net.cfg.heads, w.xh, w.flag, b.wqkvf16, b.bqkvf, w.q16, tab, s));
-    LAUNCH(ST_ATTN, launch_attn_stream(tab, g, C, net.cfg.heads, net.Spad, w.q16, w.idx, w.woff, w.o16, s));
+    LAUNCH(ST_ATTN, launch_attn_ring(tab, g, C, net.cfg.heads, net.cfg.win_t, w.q16, w.idx, w.woff, w.worder, w.o16, s));
     if (mlp_block_supported(C, R)) {
       LAUNCH(ST_MLP, launch_mlp_block_bf16(N, w.nq, C, w.o16, w.idx, b.wo16, b.bo, b.w1f16, b.b1f, b.w216, b.b2, w.x, w.xh, s));
     } else {

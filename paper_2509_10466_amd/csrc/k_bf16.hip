@@ -211,80 +211,6 @@ __global__ void __launch_bounds__(256) attn_bf16_kernel(Geo g, int C, int heads,
   attn_compute<DH, NT, false>(Ks, Vs, g.S, C, h, q, idx, q0, nqw, qbase, o, amax_o);
 }
 
-// Stream mode: the keys of window (request r, window wl) are the window's rows in the
-// request's cached frames (oldest first) followed by the new frame, each frame block being
-// S_f = wh*ww rows of a ring slot [win_f][head][S_f][dh].
-template <int DH, int NT>
-__global__ void __launch_bounds__(256) attn_stream_kernel(StreamTable tab, int C, int heads, int Sf, int nwin_f,
-                                                          const bf16* __restrict__ q, const int32_t* __restrict__ idx,
-                                                          const int32_t* __restrict__ woff, bf16* __restrict__ o) {
-  using AT = AttnTile<DH, NT>;
-  __shared__ bf16 Ks[AT::SP * AT::KST];
-  __shared__ bf16 Vs[DH * AT::VST];
-  const int w = blockIdx.x / heads, h = blockIdx.x - w * heads;
-  const int q0 = woff[w], nqw = woff[w + 1] - q0;
-  const int qbase = blockIdx.y * 64;
-  if (qbase >= nqw) return;
-  const int r = w / nwin_f, wl = w - r * nwin_f;
-  const int np = pick(tab.npast, r), hd = pick(tab.head, r), nT = pick(tab.T, r);
-  const bf16* kr = pick(tab.k, r);
-  const bf16* vr = pick(tab.v, r);
-  const size_t off = ((size_t)wl * heads + h) * Sf * DH;
-  for (int j = 0; j <= np; ++j) {
-    const int slot = (hd - np + j + nT) % nT;
-    attn_stage<DH, NT>(Ks, Vs, kr + (size_t)slot * tab.slot_stride + off, vr + (size_t)slot * tab.slot_stride + off,
-                       j * Sf, Sf);
-  }
-  const int S = (np + 1) * Sf;
-  // zero the pad keys (rows of K, columns of V^T) so that P = 0 meets finite values
-  for (int e = threadIdx.x; e < (AT::SP - S) * DH; e += 256) {
-    const int row = S + e / DH, d = e % DH;
-    Ks[row * AT::KST + d] = 0;
-    Vs[d * AT::VST + row] = 0;
-  }
-  __syncthreads();
-  attn_compute<DH, NT, true>(Ks, Vs, S, C, h, q, idx, q0, nqw, qbase, o, nullptr);
-}
-
-void launch_attn_bf16(const Geo& g, int C, int heads, int Spad, const bf16* q, const bf16* k,
-                      const bf16* vt, const int32_t* idx, const int32_t* woff, bf16* o, float* amax_o,
-                      hipStream_t s) {
-  const int dh = C / heads;
-  dim3 grid(g.nwin * heads, (g.S + 63) / 64);
-  const int nt = Spad / 16;
-#define DR_ATTN_CASE(DH_, NT_)                                                          \
-  if (dh == DH_ && nt == NT_) {                                                         \
-    attn_bf16_kernel<DH_, NT_><<<grid, 256, 0, s>>>(g, C, heads, q, k, vt, idx, woff, o, amax_o); \
-    return;                                                                             \
-  }
-  DR_ATTN_CASE(32, 4)
-  DR_ATTN_CASE(64, 4)
-  DR_ATTN_CASE(64, 15)
-  DR_ATTN_CASE(64, 19)
-  DR_ATTN_CASE(32, 15)
-  DR_ATTN_CASE(32, 19)
-#undef DR_ATTN_CASE
-}
-
-void launch_attn_stream(const StreamTable& tab, const Geo& g, int C, int heads, int Spad, const bf16* q,
-                        const int32_t* idx, const int32_t* woff, bf16* o, hipStream_t s) {
-  const int dh = C / heads;
-  dim3 grid(g.nwin * heads, (g.S + 63) / 64);
-  const int nt = Spad / 16;
-  const int nwin_f = g.nwh * g.nww;
-#define DR_ATTN_CASE(DH_, NT_)                                                                      \
-  if (dh == DH_ && nt == NT_) {                                                                     \
-    attn_stream_kernel<DH_, NT_><<<grid, 256, 0, s>>>(tab, C, heads, g.S, nwin_f, q, idx, woff, o); \
-    return;                                                                                         \
-  }
-  DR_ATTN_CASE(32, 4)
-  DR_ATTN_CASE(64, 4)
-  DR_ATTN_CASE(64, 15)
-  DR_ATTN_CASE(64, 19)
-  DR_ATTN_CASE(32, 15)
-  DR_ATTN_CASE(32, 19)
-#undef DR_ATTN_CASE
-}
 
 // ------------------------------------------------------------------------------------------
 // Window attention, clip mode (BF16 path): one block of 8 wavefronts per (window, head)
@@ -319,45 +245,60 @@ __device__ __forceinline__ void attn_dma(const bf16* __restrict__ src, bf16* dst
   }
 }
 
-template <int DH, int NT>
-__global__ void __launch_bounds__(ATT_THREADS) attn_clip_kernel(Geo g, int C, int heads, const bf16* __restrict__ q,
-                                                                const bf16* __restrict__ kmat,
-                                                                const bf16* __restrict__ vtmat,
-                                                                const int32_t* __restrict__ idx,
-                                                                const int32_t* __restrict__ woff,
-                                                                const int32_t* __restrict__ worder,
-                                                                bf16* __restrict__ o) {
-  constexpr int SP = NT * 16, CH = DH / 8, SPV = attn_vt_stride(SP);
-  extern __shared__ __align__(16) bf16 att_lds[];
-  bf16* Ks = att_lds;            // [SP][DH], swizzled chunks
-  bf16* Vt = att_lds + SP * DH;  // [DH][SPV]
-  // (window, head) work in order of decreasing query count
-  const int rank = blockIdx.x / heads, h = blockIdx.x - rank * heads;
-  const int w = worder[rank];
-  const int q0 = woff[w], nqw = woff[w + 1] - q0;
-  if (nqw == 0) return;
+// Q^T operand of query tile qt: lane holds q[idx[q0 + 16 qt + l16]][h*DH + 32 kk + 8 kg ..]
+template <int DH>
+__device__ __forceinline__ void attn_load_q(const bf16* __restrict__ q, const int32_t* __restrict__ idx, int q0,
+                                            int nqw, int C, int h, int qt, bf16x8_t (&qf)[DH / 32]) {
+  const int lane = threadIdx.x & 63, l16 = lane & 15, kg = lane >> 4;
+  const int qi = qt * 16 + l16;
+  const bool ok = qi < nqw;
+  const int n = idx[q0 + (ok ? qi : 0)];
+#pragma unroll
+  for (int kk = 0; kk < DH / 32; ++kk) {
+    const uint4 v = ok ? *reinterpret_cast<const uint4*>(q + (size_t)n * C + h * DH + kk * 32 + kg * 8)
+                       : make_uint4(0, 0, 0, 0);
+    qf[kk] = bitcast<bf16x8_t>(v);
+  }
+}
+
+// Clip mode: keys 0 .. S-1 of the window; only the last tile can hold padding keys
+// (S > 16 (NT - 1)).  V^T rows of stride SPV.
+template <int NT, int SPV>
+struct ClipKeys {
+  int S;
+  __device__ __forceinline__ bool valid(int tt, int j) const { return tt < NT - 1 || tt * 16 + j < S; }
+  __device__ __forceinline__ const bf16* vt(const bf16* Vt, int d, int tt, int off) const {
+    return Vt + d * SPV + tt * 16 + off;
+  }
+};
+
+// Stream mode: NF frame blocks of SFP keys (the frame's SF window tokens, then padding);
+// frame f exists when f <= np (np cached frames, then the new one).  V^T is frame-major,
+// [NF][DH][VST].  A 16-key tile never straddles frames (SFP is a multiple of 16).
+template <int DH, int SF, int SFP, int VST>
+struct RingKeys {
+  int np;
+  __device__ __forceinline__ bool valid(int tt, int j) const {
+    const int f = tt * 16 / SFP, within = tt * 16 - f * SFP + j;
+    return f <= np && within < SF;
+  }
+  __device__ __forceinline__ const bf16* vt(const bf16* Vt, int d, int tt, int off) const {
+    const int f = tt * 16 / SFP;
+    return Vt + (f * DH + d) * VST + (tt * 16 - f * SFP) + off;
+  }
+};
+
+// Every query tile of one (window, head): K (rows = keys, swizzled) and V^T staged in LDS.
+// `keys` decides which keys exist (valid(tt, j): key 16 tt + j) and where V^T row d of the
+// 4 keys from 16 tt + off sits (vt).  qnext holds the first tile's Q operand, loaded by the
+// caller before staging.
+template <int DH, int NT, class Keys>
+__device__ __forceinline__ void attn_query_tiles(const bf16* Ks, const bf16* Vt, const Keys& keys, int C, int h,
+                                                 const bf16* __restrict__ q, const int32_t* __restrict__ idx,
+                                                 int q0, int nqw, bf16* __restrict__ o, bf16x8_t (&qnext)[DH / 32]) {
+  constexpr int CH = DH / 8;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int l16 = lane & 15, kg = lane >> 4;
-  const int S = g.S;
-  // Q^T operand of query tile qt: lane holds q[idx[q0 + 16 qt + l16]][h*DH + 32 kk + 8 kg ..]
-  auto load_q = [&](int qt, bf16x8_t (&qf)[DH / 32]) {
-    const int qi = qt * 16 + l16;
-    const bool ok = qi < nqw;
-    const int n = idx[q0 + (ok ? qi : 0)];
-#pragma unroll
-    for (int kk = 0; kk < DH / 32; ++kk) {
-      const uint4 v = ok ? *reinterpret_cast<const uint4*>(q + (size_t)n * C + h * DH + kk * 32 + kg * 8)
-                         : make_uint4(0, 0, 0, 0);
-      qf[kk] = bitcast<bf16x8_t>(v);
-    }
-  };
-  // the first query tile's Q is in flight together with the K / V^T copies
-  bf16x8_t qnext[DH / 32];
-  if (wv * 16 < nqw) load_q(wv, qnext);
-  attn_dma<CH, true>(kmat + ((size_t)w * heads + h) * SP * DH, Ks, SP * DH * 2);
-  attn_dma<CH, false>(vtmat + ((size_t)w * heads + h) * DH * SPV, Vt, DH * SPV * 2);
-  asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
-
   for (int qt = wv; qt * 16 < nqw; qt += ATT_THREADS / 64) {
     // K and V^T fragments are re-read from LDS per query tile: hoisting them out of the loop
     // would hold the whole window in registers
@@ -368,7 +309,7 @@ __global__ void __launch_bounds__(ATT_THREADS) attn_clip_kernel(Geo g, int C, in
     bf16x8_t qf[DH / 32];
 #pragma unroll
     for (int kk = 0; kk < DH / 32; ++kk) qf[kk] = qnext[kk];
-    if ((qt + ATT_THREADS / 64) * 16 < nqw) load_q(qt + ATT_THREADS / 64, qnext);  // next tile, overlapped
+    if ((qt + ATT_THREADS / 64) * 16 < nqw) attn_load_q<DH>(q, idx, q0, nqw, C, h, qt + ATT_THREADS / 64, qnext);
     // S^T = K Q^T: key tiles in groups of TG, each tile's k slices chained, the chains of a
     // group interleaved; a group's K fragments are read while the previous group multiplies
     constexpr int KS = DH / 32;  // 32-wide k slices
@@ -400,14 +341,14 @@ __global__ void __launch_bounds__(ATT_THREADS) attn_clip_kernel(Geo g, int C, in
         for (int u = 0; u < TG; ++u)
           if (g0 + u < NT) a[u] = mfma32(kf[cur][u][kk], qf[kk], kk ? a[u] : f32x4_t{0.f, 0.f, 0.f, 0.f});
       mfma_fence_end();
-      // scores are already in base 2 (Q carries log2(e) / sqrt(dh)); only the last key tile
-      // can hold padding keys (S > 16 (NT - 1))
+      // scores are already in base 2 (Q carries log2(e) / sqrt(dh)); padding keys and keys of
+      // frames that do not exist yet score -inf
 #pragma unroll
       for (int u = 0; u < TG; ++u) {
         const int tt = g0 + u;
         if (tt < NT)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) sc[tt][i] = (tt < NT - 1 || tt * 16 + kg * 4 + i < S) ? a[u][i] : -INFINITY;
+          for (int i = 0; i < 4; ++i) sc[tt][i] = keys.valid(tt, kg * 4 + i) ? a[u][i] : -INFINITY;
       }
     }
     float mx = -INFINITY;
@@ -441,9 +382,8 @@ __global__ void __launch_bounds__(ATT_THREADS) attn_clip_kernel(Geo g, int C, in
     auto read_v = [&](int p, bf16x8_t (&dst)[DT]) {
 #pragma unroll
       for (int dt = 0; dt < DT; ++dt) {
-        const bf16* vrow = Vt + (dt * 16 + l16) * SPV + 32 * p + kg * 4;
-        const uint2 v0 = *reinterpret_cast<const uint2*>(vrow);
-        const uint2 v1 = *reinterpret_cast<const uint2*>(vrow + 16);
+        const uint2 v0 = *reinterpret_cast<const uint2*>(keys.vt(Vt, dt * 16 + l16, 2 * p, kg * 4));
+        const uint2 v1 = *reinterpret_cast<const uint2*>(keys.vt(Vt, dt * 16 + l16, 2 * p + 1, kg * 4));
         dst[dt] = bitcast<bf16x8_t>(make_uint4(v0.x, v0.y, v1.x, v1.y));
       }
     };
@@ -470,7 +410,7 @@ __global__ void __launch_bounds__(ATT_THREADS) attn_clip_kernel(Geo g, int C, in
       pv.y = pack_bf2(sc[tt][2], sc[tt][3]);
 #pragma unroll
       for (int dt = 0; dt < DT; ++dt) {
-        const uint2 v0 = *reinterpret_cast<const uint2*>(Vt + (dt * 16 + l16) * SPV + tt * 16 + kg * 4);
+        const uint2 v0 = *reinterpret_cast<const uint2*>(keys.vt(Vt, dt * 16 + l16, tt, kg * 4));
         acc[dt] = mfma16k16(bitcast<bf16x4_t>(v0), bitcast<bf16x4_t>(pv), acc[dt]);
       }
     }
@@ -484,6 +424,116 @@ __global__ void __launch_bounds__(ATT_THREADS) attn_clip_kernel(Geo g, int C, in
       }
     }
   }
+}
+
+template <int DH, int NT>
+__global__ void __launch_bounds__(ATT_THREADS) attn_clip_kernel(Geo g, int C, int heads, const bf16* __restrict__ q,
+                                                                const bf16* __restrict__ kmat,
+                                                                const bf16* __restrict__ vtmat,
+                                                                const int32_t* __restrict__ idx,
+                                                                const int32_t* __restrict__ woff,
+                                                                const int32_t* __restrict__ worder,
+                                                                bf16* __restrict__ o) {
+  constexpr int SP = NT * 16, CH = DH / 8, SPV = attn_vt_stride(SP);
+  extern __shared__ __align__(16) bf16 att_lds[];
+  bf16* Ks = att_lds;            // [SP][DH], swizzled chunks
+  bf16* Vt = att_lds + SP * DH;  // [DH][SPV]
+  // (window, head) work in order of decreasing query count
+  const int rank = blockIdx.x / heads, h = blockIdx.x - rank * heads;
+  const int w = worder[rank];
+  const int q0 = woff[w], nqw = woff[w + 1] - q0;
+  if (nqw == 0) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  bf16x8_t qnext[DH / 32];
+  if (wv * 16 < nqw) attn_load_q<DH>(q, idx, q0, nqw, C, h, wv, qnext);
+  attn_dma<CH, true>(kmat + ((size_t)w * heads + h) * SP * DH, Ks, SP * DH * 2);
+  attn_dma<CH, false>(vtmat + ((size_t)w * heads + h) * DH * SPV, Vt, DH * SPV * 2);
+  asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+  attn_query_tiles<DH, NT>(Ks, Vt, ClipKeys<NT, SPV>{g.S}, C, h, q, idx, q0, nqw, o, qnext);
+}
+
+// Stream mode: the keys of window (request r, window wl) are that window's tokens in the
+// request's cached frames (oldest first) and in the new frame.  Each frame is a block of SFP
+// key slots (its SF tokens, then padding); K of a frame is a contiguous [SF][dh] run of its
+// ring slot and arrives by direct loads, V^T of a frame ([dh][SFP] in the ring) is copied
+// into a frame-major LDS layout with rows padded to VST; frames that do not exist yet get
+// zero V^T (their keys score -inf).
+template <int SF>
+struct RingShape {
+  static constexpr int SFP = (SF + 15) / 16 * 16;  // key slots per frame (whole 16-key tiles)
+  static constexpr int VST = SFP + 8;               // LDS row stride of V^T: odd 16-byte chunks
+};
+
+template <int DH, int SF, int NF>
+__global__ void __launch_bounds__(ATT_THREADS) attn_ring_kernel(StreamTable tab, int C, int heads, int nwin_f,
+                                                                const bf16* __restrict__ q,
+                                                                const int32_t* __restrict__ idx,
+                                                                const int32_t* __restrict__ woff,
+                                                                const int32_t* __restrict__ worder,
+                                                                bf16* __restrict__ o) {
+  constexpr int SFP = RingShape<SF>::SFP, VST = RingShape<SF>::VST, NT = NF * SFP / 16, CH = DH / 8;
+  extern __shared__ __align__(16) bf16 att_lds[];
+  bf16* Ks = att_lds;                 // [NT*16][DH], swizzled chunks, key = frame * SFP + token
+  bf16* Vt = att_lds + NT * 16 * DH;  // [NF][DH][VST]
+  const int rank = blockIdx.x / heads, h = blockIdx.x - rank * heads;
+  const int w = worder[rank];
+  const int q0 = woff[w], nqw = woff[w + 1] - q0;
+  if (nqw == 0) return;
+  const int r = w / nwin_f, wl = w - r * nwin_f;
+  const int np = pick(tab.npast, r), hd = pick(tab.head, r), nT = pick(tab.T, r);
+  const bf16* kr = pick(tab.k, r);
+  const bf16* vr = pick(tab.v, r);
+  const int t = threadIdx.x, wv = t >> 6;
+  bf16x8_t qnext[DH / 32];
+  if (wv * 16 < nqw) attn_load_q<DH>(q, idx, q0, nqw, C, h, wv, qnext);
+  for (int f = 0; f <= np; ++f) {
+    const int slot = (hd - np + f + nT) % nT;
+    attn_dma<CH, true>(kr + (size_t)slot * tab.slot_stride + ((size_t)wl * heads + h) * SF * DH, Ks + f * SFP * DH,
+                       SF * DH * 2);
+    const bf16* vsrc = vr + (size_t)slot * tab.vslot_stride + ((size_t)wl * heads + h) * DH * SFP;
+    for (int c = t; c < DH * SFP / 8; c += ATT_THREADS) {
+      const int d = c / (SFP / 8), ch = c - d * (SFP / 8);
+      *reinterpret_cast<uint4*>(Vt + (f * DH + d) * VST + ch * 8) = *reinterpret_cast<const uint4*>(vsrc + d * SFP + ch * 8);
+    }
+  }
+  for (int e = t; e < (NF - 1 - np) * DH * VST / 8; e += ATT_THREADS)
+    *reinterpret_cast<uint4*>(Vt + (np + 1) * DH * VST + e * 8) = make_uint4(0, 0, 0, 0);
+  asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  attn_query_tiles<DH, NT>(Ks, Vt, RingKeys<DH, SF, SFP, VST>{np}, C, h, q, idx, q0, nqw, o, qnext);
+}
+
+int ring_vt_frame_stride(int sf) { return (sf + 15) / 16 * 16; }
+
+bool attn_ring_supported(int dh, int sf, int nf) {
+  return (dh == 32 || dh == 64) && ((sf == 45 && nf == 5) || (sf == 60 && nf == 5) || (sf == 64 && nf == 1));
+}
+
+void launch_attn_ring(const StreamTable& tab, const Geo& g, int C, int heads, int nf, const bf16* q, const int32_t* idx,
+                      const int32_t* woff, const int32_t* worder, bf16* o, hipStream_t s) {
+  const int dh = C / heads, sf = g.S;
+  const int nwin_f = g.nwh * g.nww;
+#define DR_ATTN_RING(DH_, SF_, NF_)                                                                           \
+  if (dh == DH_ && sf == SF_ && nf == NF_) {                                                                  \
+    constexpr int SFP = RingShape<SF_>::SFP, VST = RingShape<SF_>::VST;                                       \
+    const size_t lds = (size_t)NF_ * SFP * DH_ * 2 + (size_t)NF_ * DH_ * VST * 2;                             \
+    static bool attr = false;                                                                                 \
+    if (!attr) {                                                                                              \
+      if (lds > 65536)                                                                                        \
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(attn_ring_kernel<DH_, SF_, NF_>),             \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                      \
+      attr = true;                                                                                            \
+    }                                                                                                         \
+    attn_ring_kernel<DH_, SF_, NF_><<<g.nwin * heads, ATT_THREADS, lds, s>>>(tab, C, heads, nwin_f, q, idx, woff, \
+                                                                             worder, o);                      \
+    return;                                                                                                   \
+  }
+  DR_ATTN_RING(64, 45, 5)
+  DR_ATTN_RING(64, 60, 5)
+  DR_ATTN_RING(32, 45, 5)
+  DR_ATTN_RING(32, 60, 5)
+  DR_ATTN_RING(32, 64, 1)
+  DR_ATTN_RING(64, 64, 1)
+#undef DR_ATTN_RING
 }
 
 int attn_clip_vt_stride(int spad) { return attn_vt_stride(spad); }
@@ -512,6 +562,26 @@ void launch_attn_clip(const Geo& g, int C, int heads, int Spad, const bf16* q, c
   DR_ATTN_CLIP(32, 15)
   DR_ATTN_CLIP(32, 19)
 #undef DR_ATTN_CLIP
+}
+
+void launch_attn_bf16(const Geo& g, int C, int heads, int Spad, const bf16* q, const bf16* k,
+                      const bf16* vt, const int32_t* idx, const int32_t* woff, bf16* o, float* amax_o,
+                      hipStream_t s) {
+  const int dh = C / heads;
+  dim3 grid(g.nwin * heads, (g.S + 63) / 64);
+  const int nt = Spad / 16;
+#define DR_ATTN_CASE(DH_, NT_)                                                          \
+  if (dh == DH_ && nt == NT_) {                                                         \
+    attn_bf16_kernel<DH_, NT_><<<grid, 256, 0, s>>>(g, C, heads, q, k, vt, idx, woff, o, amax_o); \
+    return;                                                                             \
+  }
+  DR_ATTN_CASE(32, 4)
+  DR_ATTN_CASE(64, 4)
+  DR_ATTN_CASE(64, 15)
+  DR_ATTN_CASE(64, 19)
+  DR_ATTN_CASE(32, 15)
+  DR_ATTN_CASE(32, 19)
+#undef DR_ATTN_CASE
 }
 
 bool attn_bf16_supported(int dh, int spad) {

@@ -76,8 +76,8 @@ struct QkvOut {
   }
 };
 
-// Stream mode: Q rows into the batch buffer; K and V of every token into the current ring
-// slot of its request's cache ([win_f][head][S_f][dh] per block and slot).
+// Stream mode: Q rows into the batch buffer; K [win_f][head][S_f][dh] and V^T
+// [win_f][head][dh][sfp] of every token into the current ring slot of its request's cache.
 struct StreamQkvOut {
   const float* bias;
   bf16* q;
@@ -96,8 +96,17 @@ struct StreamQkvOut {
       const int c = n - part * C, hh = c / dh, d = c - hh * dh;
       const int w = m / Sf, s = m - w * Sf;
       const int r = w / nwin_f, wl = w - r * nwin_f;
-      dst = (part == 1 ? pick(tab.k, r) : pick(tab.v, r)) + (size_t)pick(tab.head, r) * tab.slot_stride +
-            (((size_t)wl * heads + hh) * Sf + s) * dh + d;
+      if (part == 1) {
+        dst = pick(tab.k, r) + (size_t)pick(tab.head, r) * tab.slot_stride + (((size_t)wl * heads + hh) * Sf + s) * dh + d;
+      } else {  // V^T [win_f][head][dh][sfp] of the slot
+        bf16* vt = pick(tab.v, r) + (size_t)pick(tab.head, r) * tab.vslot_stride +
+                   (((size_t)wl * heads + hh) * dh + d) * tab.sfp + s;
+        vt[0] = f2bf(a[0] + b4.x);
+        vt[tab.sfp] = f2bf(a[1] + b4.y);
+        vt[2 * tab.sfp] = f2bf(a[2] + b4.z);
+        vt[3 * tab.sfp] = f2bf(a[3] + b4.w);
+        return;
+      }
     }
     *reinterpret_cast<uint2*>(dst) = pk;
   }
