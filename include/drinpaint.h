@@ -96,11 +96,12 @@ dr_status dr_load_weights(dr_ctx* ctx, const void* blob, size_t nbytes);
 dr_status dr_reserve(dr_ctx* ctx, int B, int T, int H, int W, dr_precision prec);
 
 /* Inpaint B clips of T frames.
- *   frames: device f32 [B,T,H,W,3] (NHWC, values nominally in [0,1]).
- *   masks:  device u8  [B,T,H,W], nonzero = private pixel to be filled.
+ *   frames: device f32 [B,T,H,W,3] (NHWC, values nominally in [0,1]), 16-byte aligned.
+ *   masks:  device u8  [B,T,H,W], nonzero = private pixel to be filled, 4-byte aligned.
  *   out:    device f32 [B,T,H,W,3].  out == frames (in place) is allowed; any other overlap
  *           of out with frames or masks is DR_EINVAL.
- * Pixels whose mask is 0 are copied from `frames` bit for bit.  DR_ESHAPE unless
+ * Pixels whose mask is 0 are copied from `frames` bit for bit.  DR_EINVAL for misaligned
+ * frames or masks.  DR_ESHAPE unless
  * T == win_t, H % (p*win_h) == 0 and W % (p*win_w) == 0.  DR_EINVAL without weights. */
 dr_status dr_inpaint(dr_ctx* ctx, const float* frames, const uint8_t* masks, float* out,
                      int B, int T, int H, int W, dr_precision prec, dr_query_set qs,

@@ -384,11 +384,16 @@ extern "C" dr_status dr_load_weights(dr_ctx* c, const void* blob, size_t nbytes)
     H.v[5] = put16({wf.data()}, {wf.size()});
     O.v[25] = put(bf.data(), bf.size());
   }
-  // embedding weight [C][64] (k = (ky*P + kx)*3 + c, zero-padded) and the decoder with the
-  // final LayerNorm folded in: Wd'[k][c] = gf[c] Wd[c][k], bd'[k] = bd[k % 3] + sum_c bf[c] Wd[c][k]
+  // embedding weight [C][64] in the k slot order of the MFMA embedding's patch operand (slot
+  // 32 s + 8 g + e holds patch value k = 12 g + 8 s + e for e < 8 - 4 s, zero otherwise; patch
+  // value k = (ky*P + kx)*3 + c) and the decoder with the final LayerNorm folded in:
+  // Wd'[k][c] = gf[c] Wd[c][k], bd'[k] = bd[k % 3] + sum_c bf[c] Wd[c][k]
   std::vector<float> ew64((size_t)C * 64, 0.f), dwf((size_t)48 * C), dbf(48);
   for (int o = 0; o < C; ++o)
-    for (int k = 0; k < 48; ++k) ew64[(size_t)o * 64 + k] = ewT[(size_t)k * C + o];
+    for (int sl = 0; sl < 2; ++sl)
+      for (int gq = 0; gq < 4; ++gq)
+        for (int e = 0; e < (sl ? 4 : 8); ++e)
+          ew64[(size_t)o * 64 + 32 * sl + 8 * gq + e] = ewT[(size_t)(12 * gq + 8 * sl + e) * C + o];
   {
     const float* gf = src[count - 4];
     const float* btf = src[count - 3];
@@ -711,6 +716,8 @@ extern "C" dr_status dr_inpaint(dr_ctx* c, const float* frames, const uint8_t* m
   if (out != frames && ranges_overlap(out, npix * 12, frames, npix * 12))
     return fail(c, DR_EINVAL, "out partially overlaps frames");
   if (ranges_overlap(out, npix * 12, masks, npix)) return fail(c, DR_EINVAL, "out overlaps masks");
+  if (((uintptr_t)frames & 15) || ((uintptr_t)masks & 3))
+    return fail(c, DR_EINVAL, "frames must be 16-byte and masks 4-byte aligned");
   HIP_OK(c, hipSetDevice(c->device));
   st = reserve_geo(c, g);
   if (st != DR_OK) return st;

@@ -71,7 +71,7 @@ struct Net {
   const float *lnfg, *lnfb;
   const float* dec_w;        // [C][48], column k = (ky*p + kx)*3 + ch
   const float* dec_b;        // [3]
-  const bf16* embed_wT16;    // bf16 [C][64]: embedding weight, k = (ky*p + kx)*3 + c, zero-padded
+  const bf16* embed_wT16;    // bf16 [C][64]: embedding weight, k slots permuted for the MFMA embedding
   const bf16* dec_wf16;      // bf16 [48][C]: decoder weight with the final LayerNorm gain folded in
   const float* dec_bf;       // f32 [48]: decoder bias + final LayerNorm shift through the decoder
 };

@@ -174,28 +174,12 @@ void launch_decode(const Geo& g, int C, const float* x, const int32_t* idx, cons
 // every channel of its tokens and the row statistics need no block-level exchange.
 // ------------------------------------------------------------------------------------------
 
-// 8 consecutive cut-out patch values k0 .. k0+7 (k = (ky*4 + kx)*3 + c, zero for k >= 48) of
-// token (b, t, i, j), as bf16.
-__device__ __forceinline__ bf16x8_t patch_chunk(const Geo& g, const float* __restrict__ frames,
-                                                const uint8_t* __restrict__ masks, int b, int t, int i, int j,
-                                                int k0, bool ok) {
-  bf16x8_t v;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const int k = k0 + e;
-    float f = 0.f;
-    if (ok && k < 48) {
-      const int ky = k / 12, kx = (k % 12) / 3, ch = k % 3;
-      const size_t px = (((size_t)b * g.T + t) * g.H + 4 * i + ky) * g.W + 4 * j + kx;
-      f = masks[px] ? 0.f : frames[px * 3 + ch];
-    }
-    v[e] = __builtin_bit_cast(__bf16, f2bf(f));
-  }
-  return v;
-}
-
-// x = patch W_e^T + b_e (FP32 residual) and x^ = normalise(x) (bf16).  wT16: [C][64] bf16,
-// the embedding weight with k padded to 64.
+// x = patch W_e^T + b_e (FP32 residual) and x^ = normalise(x) (bf16).  Lane (token l16, row
+// group kg) loads patch row ky = kg of its token: 4 pixels x 3 channels (three 16-byte loads)
+// and the row's 4 mask bytes, cut out.  The 48 patch values enter the two 32-wide k slices in
+// a permuted order -- slice 0: values 12 kg .. 12 kg + 7, slice 1: 12 kg + 8 .. 12 kg + 11 and
+// four zeros -- and wT16 [C][64] holds the embedding weight in that same order, so each
+// lane's MFMA operands come straight from its own loads.
 template <int C>
 __global__ void __launch_bounds__(256) embed_bf16_kernel(Geo g, const float* __restrict__ frames,
                                                          const uint8_t* __restrict__ masks,
@@ -206,10 +190,30 @@ __global__ void __launch_bounds__(256) embed_bf16_kernel(Geo g, const float* __r
   const int l16 = lane & 15, kg = lane >> 4;
   const int n = (blockIdx.x * 4 + wv) * 16 + l16;
   const bool ok = n < g.N;
-  int b = 0, t = 0, i = 0, j = 0;
-  if (ok) token_coords(g, n, b, t, i, j);
-  const bf16x8_t p0 = patch_chunk(g, frames, masks, b, t, i, j, 8 * kg, ok);
-  const bf16x8_t p1 = patch_chunk(g, frames, masks, b, t, i, j, 32 + 8 * kg, ok);
+  float v[12];
+#pragma unroll
+  for (int e = 0; e < 12; ++e) v[e] = 0.f;
+  if (ok) {
+    int b, t, i, j;
+    token_coords(g, n, b, t, i, j);
+    const size_t px = (((size_t)b * g.T + t) * g.H + 4 * i + kg) * g.W + 4 * j;
+    const float4* src = reinterpret_cast<const float4*>(frames + px * 3);
+    const float4 f0 = src[0], f1 = src[1], f2 = src[2];
+    const uint32_t m = *reinterpret_cast<const uint32_t*>(masks + px);
+    v[0] = f0.x; v[1] = f0.y; v[2] = f0.z; v[3] = f0.w;
+    v[4] = f1.x; v[5] = f1.y; v[6] = f1.z; v[7] = f1.w;
+    v[8] = f2.x; v[9] = f2.y; v[10] = f2.z; v[11] = f2.w;
+#pragma unroll
+    for (int kx = 0; kx < 4; ++kx)
+      if ((m >> (8 * kx)) & 0xffu) v[3 * kx] = v[3 * kx + 1] = v[3 * kx + 2] = 0.f;
+  }
+  bf16x8_t p0, p1;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) p0[e] = (__bf16)v[e];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) p1[e] = (__bf16)v[8 + e];
+#pragma unroll
+  for (int e = 4; e < 8; ++e) p1[e] = (__bf16)0.f;
   f32x4_t acc[FN];
   float sum = 0.f;
 #pragma unroll
