@@ -38,41 +38,68 @@ __device__ __forceinline__ void for_fragments(int M, int m0, int n0, f32x4_t (&a
   });
 }
 
+// Row-then-column epilogue: epi.row(m, n0) computes the destination of token m once (the
+// column tile's part of the output is uniform over the tile), epi.store(row, n, a) then adds
+// the fragment's channel offset.  Keeps per-token address arithmetic (divisions, table
+// selects) out of the per-fragment path.
+template <class TL, class Epi>
+__device__ __forceinline__ void for_rows(int M, int m0, int n0, f32x4_t (&acc)[TL::FM][TL::FN], const Epi& epi) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wm = wv / TL::WN, wn = wv % TL::WN, l16 = lane & 15, kg = lane >> 4;
+  static_for<TL::FM>([&](auto i) {
+    const int m = m0 + wm * TL::TM + 16 * i + l16;
+    if (m < M) {
+      const auto row = epi.row(m, n0);
+      static_for<TL::FN>([&](auto j) { epi.store(row, n0 + wn * TL::TN + 16 * j + 4 * kg, acc[i][j]); });
+    }
+  });
+}
+
 // ------------------------------------------------------------------------------------------
 // Q/K/V
 // ------------------------------------------------------------------------------------------
 // Columns [0, C) -> Q rows [N][C]; [C, 2C) -> K [win][head][Spad][dh]; [2C, 3C) -> V
 // transposed, V^T [win][head][dh][spv] (keys contiguous, the layout the attention kernel
-// stages as is).
+// stages as is).  A column tile lies inside one of the three parts (C % BN == 0); dh is a
+// power of two (2^dsh).  Channel c of a part sits at head c >> dsh, lane c & (dh - 1), so K's
+// offset is (c >> dsh) Spad dh + (c & (dh - 1)) and V^T's row is c itself.
+struct QkvRow {
+  bf16* base;  // token's Q row / K row of head 0 / V^T column of head 0, lane 0
+  int part;    // 0 Q, 1 K, 2 V
+};
+
+__device__ __forceinline__ void qkv_store(const QkvRow& r, int c, int C, int dsh, int kstride, int vstride,
+                                          const float4& b4, const f32x4_t& a) {
+  const float y0 = a[0] + b4.x, y1 = a[1] + b4.y, y2 = a[2] + b4.z, y3 = a[3] + b4.w;
+  if (r.part == 2) {
+    bf16* dst = r.base + (size_t)c * vstride;
+    dst[0] = f2bf(y0);
+    dst[vstride] = f2bf(y1);
+    dst[2 * vstride] = f2bf(y2);
+    dst[3 * vstride] = f2bf(y3);
+    return;
+  }
+  const int off = r.part == 0 ? c : (c >> dsh) * kstride + (c & ((1 << dsh) - 1));
+  uint2 pk;
+  pk.x = pack_bf2(y0, y1);
+  pk.y = pack_bf2(y2, y3);
+  *reinterpret_cast<uint2*>(r.base + off) = pk;
+}
+
 struct QkvOut {
   const float* bias;
   bf16 *q, *k, *vt;
-  int C, dh, heads, Spad, S, spv;
-  __device__ __forceinline__ void operator()(int m, int n, const f32x4_t& a) const {
+  int C, dsh, heads, Spad, S, spv;
+  __device__ __forceinline__ QkvRow row(int m, int n0) const {
+    const int part = n0 >= 2 * C ? 2 : n0 >= C ? 1 : 0;
+    if (part == 0) return {q + (size_t)m * C, 0};
+    const int w = m / S, s = m - w * S;
+    if (part == 1) return {k + (((size_t)w * heads * Spad + s) << dsh), 1};
+    return {vt + (((size_t)w * heads) << dsh) * spv + s, 2};
+  }
+  __device__ __forceinline__ void store(const QkvRow& r, int n, const f32x4_t& a) const {
     const float4 b4 = *reinterpret_cast<const float4*>(bias + n);
-    const float y0 = a[0] + b4.x, y1 = a[1] + b4.y, y2 = a[2] + b4.z, y3 = a[3] + b4.w;
-    if (n < 2 * C) {
-      bf16* dst;
-      if (n < C) {
-        dst = q + (size_t)m * C + n;
-      } else {
-        const int c = n - C, hh = c / dh, d = c - hh * dh;
-        const int w = m / S, s = m - w * S;
-        dst = k + (((size_t)w * heads + hh) * Spad + s) * dh + d;
-      }
-      uint2 pk;
-      pk.x = pack_bf2(y0, y1);
-      pk.y = pack_bf2(y2, y3);
-      *reinterpret_cast<uint2*>(dst) = pk;
-    } else {
-      const int c = n - 2 * C, hh = c / dh, d = c - hh * dh;
-      const int w = m / S, s = m - w * S;
-      bf16* dst = vt + (((size_t)w * heads + hh) * dh + d) * spv + s;
-      dst[0] = f2bf(y0);
-      dst[spv] = f2bf(y1);
-      dst[2 * spv] = f2bf(y2);
-      dst[3 * spv] = f2bf(y3);
-    }
+    qkv_store(r, n - r.part * C, C, dsh, Spad << dsh, spv, b4, a);
   }
 };
 
@@ -82,33 +109,19 @@ struct StreamQkvOut {
   const float* bias;
   bf16* q;
   StreamTable tab;
-  int C, dh, heads, Sf, nwin_f;
-  __device__ __forceinline__ void operator()(int m, int n, const f32x4_t& a) const {
+  int C, dsh, heads, Sf, nwin_f;
+  __device__ __forceinline__ QkvRow row(int m, int n0) const {
+    const int part = n0 >= 2 * C ? 2 : n0 >= C ? 1 : 0;
+    if (part == 0) return {q + (size_t)m * C, 0};
+    const int w = m / Sf, s = m - w * Sf;
+    const int r = w / nwin_f, wl = w - r * nwin_f;
+    const size_t slot = (size_t)pick(tab.head, r);
+    if (part == 1) return {pick(tab.k, r) + slot * tab.slot_stride + (((size_t)wl * heads * Sf + s) << dsh), 1};
+    return {pick(tab.v, r) + slot * tab.vslot_stride + (((size_t)wl * heads) << dsh) * tab.sfp + s, 2};
+  }
+  __device__ __forceinline__ void store(const QkvRow& r, int n, const f32x4_t& a) const {
     const float4 b4 = *reinterpret_cast<const float4*>(bias + n);
-    uint2 pk;
-    pk.x = pack_bf2(a[0] + b4.x, a[1] + b4.y);
-    pk.y = pack_bf2(a[2] + b4.z, a[3] + b4.w);
-    bf16* dst;
-    if (n < C) {
-      dst = q + (size_t)m * C + n;
-    } else {
-      const int part = n < 2 * C ? 1 : 2;
-      const int c = n - part * C, hh = c / dh, d = c - hh * dh;
-      const int w = m / Sf, s = m - w * Sf;
-      const int r = w / nwin_f, wl = w - r * nwin_f;
-      if (part == 1) {
-        dst = pick(tab.k, r) + (size_t)pick(tab.head, r) * tab.slot_stride + (((size_t)wl * heads + hh) * Sf + s) * dh + d;
-      } else {  // V^T [win_f][head][dh][sfp] of the slot
-        bf16* vt = pick(tab.v, r) + (size_t)pick(tab.head, r) * tab.vslot_stride +
-                   (((size_t)wl * heads + hh) * dh + d) * tab.sfp + s;
-        vt[0] = f2bf(a[0] + b4.x);
-        vt[tab.sfp] = f2bf(a[1] + b4.y);
-        vt[2 * tab.sfp] = f2bf(a[2] + b4.z);
-        vt[3 * tab.sfp] = f2bf(a[3] + b4.w);
-        return;
-      }
-    }
-    *reinterpret_cast<uint2*>(dst) = pk;
+    qkv_store(r, n - r.part * C, C, dsh, Sf << dsh, tab.sfp, b4, a);
   }
 };
 
@@ -136,7 +149,7 @@ __global__ void __launch_bounds__(256) qkv_kernel(int M, int C, int S, const bf1
   if (!__syncthreads_or(need)) return;
   f32x4_t acc[TL::FM][TL::FN];
   gemm_core<TL>(xh, M, m0, W, n0, C, ring, acc);
-  for_fragments<TL>(M, m0, n0, acc, out);
+  for_rows<TL>(M, m0, n0, acc, out);
 }
 
 template <class TL, class Out>
@@ -151,11 +164,18 @@ static void qkv_launch(int M, int C, int S, const bf16* xh, const uint8_t* flag,
   qkv_kernel<TL, Out><<<grid, 256, TL::LDS_BYTES, s>>>(M, C, S, xh, flag, wcount, w, out);
 }
 
+// log2 of a power of two (head widths 32 and 64 are the ones the attention kernels take)
+static int log2_pow2(int v) {
+  int k = 0;
+  while ((1 << k) < v) ++k;
+  return k;
+}
+
 void launch_qkv_bf16(const Geo& g, int C, int heads, int Spad, int spv, const bf16* xh, const uint8_t* flag,
                      const int32_t* wcount, const bf16* w, const float* bias, bf16* q, bf16* k, bf16* vt,
                      hipStream_t s) {
   if (g.N <= 0) return;
-  const QkvOut out{bias, q, k, vt, C, C / heads, heads, Spad, g.S, spv};
+  const QkvOut out{bias, q, k, vt, C, log2_pow2(C / heads), heads, Spad, g.S, spv};
   if (C % 128 == 0)
     qkv_launch<GemmTile<64, 128, 2, 2, 3>>(g.N, C, g.S, xh, flag, wcount, w, out, s);
   else
@@ -165,7 +185,7 @@ void launch_qkv_bf16(const Geo& g, int C, int heads, int Spad, int spv, const bf
 void launch_qkv_stream(const Geo& g, int C, int heads, const bf16* xh, const uint8_t* flag, const bf16* w,
                        const float* bias, bf16* q, const StreamTable& tab, hipStream_t s) {
   if (g.N <= 0) return;
-  const StreamQkvOut out{bias, q, tab, C, C / heads, heads, g.S, g.nwh * g.nww};
+  const StreamQkvOut out{bias, q, tab, C, log2_pow2(C / heads), heads, g.S, g.nwh * g.nww};
   if (C % 128 == 0)
     qkv_launch<GemmTile<64, 128, 2, 2, 3>>(g.N, C, g.S, xh, flag, nullptr, w, out, s);
   else
