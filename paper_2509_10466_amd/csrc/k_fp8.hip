@@ -351,8 +351,8 @@ struct F8GeluEpi {
   __device__ __forceinline__ void operator()(bool ok, int m, int n, const f32x4_t& a) {
     if (!ok) return;
     const float4 b4 = *reinterpret_cast<const float4*>(bias + n);
-    const float y0 = gelu_erf(a[0] * sc + b4.x), y1 = gelu_erf(a[1] * sc + b4.y);
-    const float y2 = gelu_erf(a[2] * sc + b4.z), y3 = gelu_erf(a[3] * sc + b4.w);
+    const float y0 = gelu_fast(a[0] * sc + b4.x), y1 = gelu_fast(a[1] * sc + b4.y);
+    const float y2 = gelu_fast(a[2] * sc + b4.z), y3 = gelu_fast(a[3] * sc + b4.w);
     mx = fmaxf(mx, fmaxf(fmaxf(fabsf(y0), fabsf(y1)), fmaxf(fabsf(y2), fabsf(y3))));
     uint2 pk;
     pk.x = pack_bf2(y0, y1);

@@ -202,8 +202,8 @@ struct GeluOut {
   __device__ __forceinline__ void operator()(int m, int n, const f32x4_t& a) const {
     const float4 b4 = *reinterpret_cast<const float4*>(bias + n);
     uint2 pk;
-    pk.x = pack_bf2(gelu_erf(a[0] + b4.x), gelu_erf(a[1] + b4.y));
-    pk.y = pack_bf2(gelu_erf(a[2] + b4.z), gelu_erf(a[3] + b4.w));
+    pk.x = pack_bf2(gelu_fast(a[0] + b4.x), gelu_fast(a[1] + b4.y));
+    pk.y = pack_bf2(gelu_fast(a[2] + b4.z), gelu_fast(a[3] + b4.w));
     *reinterpret_cast<uint2*>(h + (size_t)m * R + n) = pk;
   }
 };
@@ -375,13 +375,17 @@ struct MlpCfg {
   static constexpr int SLOT = SLOT_ROWS * 64;          // bf16 elements per ring slot
   static constexpr int NKC = C / 64, NKH = HC / 64;    // k blocks of C- and HC-wide operands
   static constexpr int NCH = R / HC;                   // hidden chunks
-  static constexpr int PER_CHUNK = NKC + NKH;
+  // k blocks of W1' per stage: as many HC-row blocks as a ring slot holds, so that every
+  // stage moves a full slot (fewer stages, each with the same fixed wait + barrier cost)
+  static constexpr int KB1 = (SLOT_ROWS / HC < NKC) ? SLOT_ROWS / HC : NKC;
+  static constexpr int NW1 = NKC / KB1;                // W1' stages per hidden chunk
+  static constexpr int PER_CHUNK = NW1 + NKH;
   static constexpr int NSTAGE = NKC + NCH * PER_CHUNK;
   static constexpr int FN_C = C / 64, FN_H = HC / 64;  // 16-wide fragments per wavefront
   static constexpr size_t RING = (size_t)ST * SLOT, ARES = (size_t)NKC * BM * 64, HRES = (size_t)NKH * BM * 64;
   static constexpr size_t FLOATS = 2 * (size_t)C + R + 2 * WN * BM;  // b_o, b1', b_2, row sums
   static constexpr size_t LDS_BYTES = (RING + ARES + HRES) * 2 + FLOATS * 4;
-  static_assert(C % 64 == 0 && HC % 64 == 0 && R % HC == 0 && C % 64 == 0, "shapes");
+  static_assert(C % 64 == 0 && HC % 64 == 0 && R % HC == 0 && NKC % KB1 == 0, "shapes");
   static_assert(LDS_BYTES <= 160 * 1024, "LDS");
 };
 
@@ -412,17 +416,58 @@ __device__ __forceinline__ void mfma_block(const bf16* As, const bf16* Ws, f32x4
   });
 }
 
+// As mfma_block with the A fragments already in registers (af[kk][i]: rows wm*TM + 16 i + l16,
+// k values 32 kk + 8 kg .. +7 of the 64-wide k block).
+template <class MC, int FN>
+__device__ __forceinline__ void mfma_block_ra(const bf16x8_t (&af)[2][MC::FM], const bf16* Ws,
+                                              f32x4_t (&acc)[MC::FM][FN]) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wn = wv % MC::WN;
+  const int l16 = lane & 15, kg = lane >> 4;
+  bf16x8_t wf[2][FN];
+  static_for<2>([&](auto kk) {
+    static_for<FN>([&](auto j) {
+      const int row = wn * 16 * FN + 16 * j + l16;
+      wf[kk][j] = *reinterpret_cast<const bf16x8_t*>(Ws + row * 64 + (((4 * kk + kg) ^ lds_swz(row)) * 8));
+    });
+  });
+  static_for<2>([&](auto kk) {
+    mfma_fence_begin();
+    static_for<MC::FM>([&](auto i) {
+      static_for<FN>([&](auto j) { acc[i][j] = mfma_bf16_16x16x32(wf[kk][j], af[kk][i], acc[i][j]); });
+    });
+    mfma_fence_end();
+  });
+}
+
 // Element offset of (row r, column c) in a resident [k block][64 rows][64] swizzled tile.
 __device__ __forceinline__ int res_off(int r, int c) {
   return (c >> 6) * (64 * 64) + r * 64 + ((((c & 63) >> 3) ^ lds_swz(r)) << 3) + (c & 7);
 }
 
-// Residual + row normalisation for the [64][C] accumulators: acc += bias + x[dst];
+// This thread's residual values x[dst] for the [64][C] accumulators (zero for rows past M),
+// loaded ahead of the epilogue so that their latency overlaps the last k stage.
+template <class MC>
+__device__ __forceinline__ void load_resid(const float* __restrict__ x, const int (&dst)[MC::FM],
+                                           float4 (&xo)[MC::FM][MC::FN_C]) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wn = wv % MC::WN, kg = lane >> 4;
+  static_for<MC::FM>([&](auto i) {
+    static_for<MC::FN_C>([&](auto j) {
+      const int n = wn * 16 * MC::FN_C + 16 * j + 4 * kg;
+      xo[i][j] = dst[i] >= 0 ? *reinterpret_cast<const float4*>(x + (size_t)dst[i] * MC::C + n)
+                             : make_float4(0.f, 0.f, 0.f, 0.f);
+    });
+  });
+}
+
+// Residual + row normalisation for the [64][C] accumulators: acc += bias + xo (= x[dst]);
 // x[dst] = acc; the row statistics come back through mean/rstd.  The four column
 // wavefronts of a row group exchange partial sums through red[2][WN][64].
 template <class MC>
 __device__ __forceinline__ void resid_rows(f32x4_t (&acc)[MC::FM][MC::FN_C], const float* sbias,
-                                           float* __restrict__ x, const int (&dst)[MC::FM], float (*red)[MC::WN][64],
+                                           float* __restrict__ x, const int (&dst)[MC::FM],
+                                           const float4 (&xo_in)[MC::FM][MC::FN_C], float (*red)[MC::WN][64],
                                            float (&mean)[MC::FM], float (&rstd)[MC::FM]) {
   constexpr int C = MC::C, FN = MC::FN_C;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -433,8 +478,7 @@ __device__ __forceinline__ void resid_rows(f32x4_t (&acc)[MC::FM][MC::FN_C], con
     float sum = 0.f;
     static_for<FN>([&](auto j) {
       const int n = wn * 16 * FN + 16 * j + 4 * kg;
-      float4 xo = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (dst[i] >= 0) xo = *reinterpret_cast<const float4*>(x + (size_t)dst[i] * C + n);
+      const float4 xo = xo_in[i][j];
       f32x4_t& a = acc[i][j];
       a[0] += sbias[n] + xo.x;
       a[1] += sbias[n + 1] + xo.y;
@@ -509,29 +553,33 @@ __global__ void __launch_bounds__(MLP_THREADS) mlp_block_kernel(const int32_t* _
     const int m = min(m0 + row, M - 1);
     dma16(o + (size_t)m * C + 64 * kb + ((lane & 7) ^ lds_swz(row)) * 8, ares + kb * BM * 64 + wv * 512);
   });
-  // weight stages: stage s holds rows [0, stage_rows(s)) of 64 k columns
+  // weight stages: stage s holds rows [0, stage_rows(s)) of 64 k columns; a W1' stage holds
+  // KB1 blocks of HC rows, k block b of the stage at rows [b HC, (b+1) HC)
   auto stage_rows = [](int s) {
     if (s < MC::NKC) return C;
     const int tt = (s - MC::NKC) % MC::PER_CHUNK;
-    return tt < MC::NKC ? HC : C;
+    return tt < MC::NW1 ? HC * MC::KB1 : C;
   };
   auto issue = [&](int s) {
     const bf16* base;
-    int rows_s, ld;
+    int rows_s, ld, blk_rows;  // slot rows; source row stride; rows per k block in the slot
     if (s < MC::NKC) {
       base = Wo + 64 * s;
       rows_s = C;
       ld = C;
+      blk_rows = C;
     } else {
       const int q = s - MC::NKC, j = q / MC::PER_CHUNK, tt = q - j * MC::PER_CHUNK;
-      if (tt < MC::NKC) {
-        base = W1 + (size_t)j * HC * C + 64 * tt;
-        rows_s = HC;
+      if (tt < MC::NW1) {
+        base = W1 + (size_t)j * HC * C + 64 * MC::KB1 * tt;
+        rows_s = HC * MC::KB1;
         ld = C;
+        blk_rows = HC;
       } else {
-        base = W2 + j * HC + 64 * (tt - MC::NKC);
+        base = W2 + j * HC + 64 * (tt - MC::NW1);
         rows_s = C;
         ld = R;
+        blk_rows = C;
       }
     }
     bf16* dst = ring + (s % MC::ST) * MC::SLOT;
@@ -539,7 +587,8 @@ __global__ void __launch_bounds__(MLP_THREADS) mlp_block_kernel(const int32_t* _
       const int g8 = wv + NW * c;
       if (g8 * 8 < rows_s) {  // uniform per wavefront
         const int row = g8 * 8 + (lane >> 3);
-        dma16(base + (size_t)row * ld + ((lane & 7) ^ lds_swz(row)) * 8, dst + g8 * 512);
+        const int b = row / blk_rows, rr = row - b * blk_rows;  // blk_rows is a multiple of 8
+        dma16(base + (size_t)rr * ld + 64 * b + ((lane & 7) ^ lds_swz(row)) * 8, dst + g8 * 512);
       }
     });
   };
@@ -566,16 +615,22 @@ __global__ void __launch_bounds__(MLP_THREADS) mlp_block_kernel(const int32_t* _
     else if (stage_rows(s + 1) == C)
       vm_wait_barrier<C / (8 * NW)>();
     else
-      vm_wait_barrier<HC / (8 * NW)>();
+      vm_wait_barrier<HC * MC::KB1 / (8 * NW)>();
     drained = false;
     if (s + 2 < MC::NSTAGE) issue(s + 2);
     return ring + (s % MC::ST) * MC::SLOT;
   };
   int s = 0;
-  for (int kb = 0; kb < MC::NKC; ++kb, ++s) mfma_block<MC, MC::FN_C>(ares + kb * BM * 64, enter(s), acc);
+  float4 xo[MC::FM][MC::FN_C];
+  static_for<MC::NKC>([&](auto kb) {
+    const bf16* ws = enter(s);
+    if (kb == MC::NKC - 1) load_resid<MC>(x, dst, xo);  // youngest loads: no stage waits for them
+    mfma_block<MC, MC::FN_C>(ares + kb * BM * 64, ws, acc);
+    ++s;
+  });
   // x1 = x + o W_o^T + b_o; u2 = normalise(x1) into the resident tile (every wavefront has
   // finished reading o there: resid_rows passes two block barriers)
-  resid_rows<MC>(acc, sbo, x, dst, red, mean, rstd);
+  resid_rows<MC>(acc, sbo, x, dst, xo, red, mean, rstd);
   static_for<MC::FM>([&](auto i) {
     const int r = wm * MC::TM + 16 * i + l16;
     static_for<MC::FN_C>([&](auto j) {
@@ -589,8 +644,24 @@ __global__ void __launch_bounds__(MLP_THREADS) mlp_block_kernel(const int32_t* _
     });
   });
   drained = true;  // x was read and written
+  // this wavefront's u2 fragments stay in registers for every hidden chunk
+  lds_barrier();
+  bf16x8_t ua[MC::NKC][2][MC::FM];
+  static_for<MC::NKC>([&](auto kb) {
+    static_for<2>([&](auto kk) {
+      static_for<MC::FM>([&](auto i) {
+        const int row = wm * MC::TM + 16 * i + l16;
+        ua[kb][kk][i] = *reinterpret_cast<const bf16x8_t*>(ares + kb * BM * 64 + row * 64 +
+                                                           (((4 * kk + kg) ^ lds_swz(row)) * 8));
+      });
+    });
+  });
   for (int j = 0; j < MC::NCH; ++j) {
-    for (int kb = 0; kb < MC::NKC; ++kb, ++s) mfma_block<MC, MC::FN_H>(ares + kb * BM * 64, enter(s), hacc);
+    static_for<MC::NW1>([&](auto tt) {
+      const bf16* ws = enter(s);
+      static_for<MC::KB1>([&](auto b) { mfma_block_ra<MC, MC::FN_H>(ua[tt * MC::KB1 + b], ws + b * HC * 64, hacc); });
+      ++s;
+    });
     // hidden chunk j: GELU into the H tile (its previous contents were consumed before this
     // stage's barrier)
     static_for<MC::FM>([&](auto i) {
@@ -600,16 +671,21 @@ __global__ void __launch_bounds__(MLP_THREADS) mlp_block_kernel(const int32_t* _
         const float* bb = sb1 + j * HC + c;
         const f32x4_t& a = hacc[i][jj];
         uint2 pk;
-        pk.x = pack_bf2(gelu_erf(a[0] + bb[0]), gelu_erf(a[1] + bb[1]));
-        pk.y = pack_bf2(gelu_erf(a[2] + bb[2]), gelu_erf(a[3] + bb[3]));
+        pk.x = pack_bf2(gelu_fast(a[0] + bb[0]), gelu_fast(a[1] + bb[1]));
+        pk.y = pack_bf2(gelu_fast(a[2] + bb[2]), gelu_fast(a[3] + bb[3]));
         *reinterpret_cast<uint2*>(hres + res_off(r, c)) = pk;
         hacc[i][jj] = f32x4_t{0.f, 0.f, 0.f, 0.f};
       });
     });
-    for (int kb = 0; kb < MC::NKH; ++kb, ++s) mfma_block<MC, MC::FN_C>(hres + kb * BM * 64, enter(s), acc);
+    static_for<MC::NKH>([&](auto kb) {
+      const bf16* ws = enter(s);
+      mfma_block<MC, MC::FN_C>(hres + kb * BM * 64, ws, acc);
+      ++s;
+    });
   }
-  // x2 = x1 + h W_2^T + b_2 (x1 was stored by this thread above); x^ = normalise(x2)
-  resid_rows<MC>(acc, sb2, x, dst, red, mean, rstd);
+  // x2 = x1 + h W_2^T + b_2 (x1 was stored by this thread above, an L2 hit); x^ = normalise(x2)
+  load_resid<MC>(x, dst, xo);
+  resid_rows<MC>(acc, sb2, x, dst, xo, red, mean, rstd);
   static_for<MC::FM>([&](auto i) {
     if (dst[i] >= 0)
       static_for<MC::FN_C>([&](auto j) {
