@@ -572,12 +572,10 @@ dr_status dr::dr_reserve_work(dr_ctx* c, Work& w, const Geo& g, bool stream_mode
     ALLOC(o, N * C * 4);
     ALLOC(h, N * R * 4);
     ALLOC(k16, kvlen * 2);
-    ALLOC(v16, kvlen * 2);
     const size_t vtlen = nw * n.cfg.heads * (size_t)n.dh * attn_clip_vt_stride(n.Spad);
     ALLOC(vt16, vtlen * 2);
     // padded key rows of K and V (columns of V^T) must read as zero
     HIP_OK(c, hipMemset(w.k16, 0, kvlen * 2));
-    HIP_OK(c, hipMemset(w.v16, 0, kvlen * 2));
     HIP_OK(c, hipMemset(w.vt16, 0, vtlen * 2));
   }
 #undef ALLOC
@@ -665,8 +663,8 @@ static dr_status run_blocks(dr_ctx* c, const Geo& g, dr_precision prec, hipStrea
     } else if (prec == DR_FP8) {
       float* am = w.amax + 4 * l;  // [0] LN1 out, [1] O, [2] LN2 out, [3] h
       LAUNCH(ST_LN1, launch_ln_amax(w.x, nullptr, nullptr, N, w.wcount, g.S, C, b.ln1g, b.ln1b, am + 0, s));
-      LAUNCH(ST_QKV, launch_ln_qkv_fp8(g, C, n.cfg.heads, n.Spad, w.x, w.flag, w.wcount, b.ln1g, b.ln1b, b.wqkv8, b.wscale8, b.bqkv, am + 0, w.q16, w.k16, w.v16, s));
-      LAUNCH(ST_ATTN, launch_attn_bf16(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.v16, w.idx, w.woff, w.o16, am + 1, s));
+      LAUNCH(ST_QKV, launch_ln_qkv_fp8(g, C, n.cfg.heads, n.Spad, w.x, w.flag, w.wcount, b.ln1g, b.ln1b, b.wqkv8, b.wscale8, b.bqkv, am + 0, (float)(1.4426950408889634 / std::sqrt((double)n.dh)), attn_clip_vt_stride(n.Spad), w.q16, w.k16, w.vt16, s));
+      LAUNCH(ST_ATTN, launch_attn_clip(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.vt16, w.idx, w.woff, w.worder, w.o16, am + 1, s));
       LAUNCH(ST_PROJ, launch_gemm_fp8_resid(w.o16, w.nq, N, C, b.wo8, b.so8, am + 1, b.bo, C, w.x, w.idx, s));
       LAUNCH(ST_LN2, launch_ln_amax(w.x, w.idx, w.nq, N, nullptr, g.S, C, b.ln2g, b.ln2b, am + 2, s));
       LAUNCH(ST_FC1, launch_ln_fc1_fp8(N, C, R, w.x, w.idx, w.nq, b.ln2g, b.ln2b, b.w18, b.s18, b.b1, am + 2, w.h16, am + 3, s));
@@ -675,7 +673,7 @@ static dr_status run_blocks(dr_ctx* c, const Geo& g, dr_precision prec, hipStrea
       // x^ (normalised rows) feeds Q/K/V; the projection leaves x1^ of the query rows in u16
       // for the MLP; the second MLP linear refreshes x^ of the query rows
       LAUNCH(ST_QKV, launch_qkv_bf16(g, C, n.cfg.heads, n.Spad, attn_clip_vt_stride(n.Spad), w.xh, w.flag, w.wcount, b.wqkvf16, b.bqkvf, w.q16, w.k16, w.vt16, s));
-      LAUNCH(ST_ATTN, launch_attn_clip(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.vt16, w.idx, w.woff, w.worder, w.o16, s));
+      LAUNCH(ST_ATTN, launch_attn_clip(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.vt16, w.idx, w.woff, w.worder, w.o16, nullptr, s));
       if (mlp_block_supported(C, R)) {
         LAUNCH(ST_MLP, launch_mlp_block_bf16(N, w.nq, C, w.o16, w.idx, b.wo16, b.bo, b.w1f16, b.b1f, b.w216, b.b2, w.x, w.xh, s));
       } else {
@@ -816,7 +814,7 @@ extern "C" dr_status dr_inspect(dr_ctx* c, const char* name, void* dst, size_t n
   const size_t kvlen = w.cap_windows * c->net.cfg.heads * (size_t)c->net.Spad * c->net.dh;
   struct Buf { const char* n; const void* p; size_t bytes; } bufs[] = {
       {"x", w.x, N * C * 4},       {"xh", w.xh, N * C * 2},     {"u16", w.u16, N * C * 2}, {"q16", w.q16, N * C * 2},
-      {"k16", w.k16, kvlen * 2},   {"v16", w.v16, kvlen * 2},
+      {"k16", w.k16, kvlen * 2},
       {"vt16", w.vt16, w.cap_windows * c->net.cfg.heads * (size_t)c->net.dh * attn_clip_vt_stride(c->net.Spad) * 2}, {"o16", w.o16, N * C * 2},
       {"h16", w.h16, N * R * 2},   {"u", w.u, N * C * 4},     {"kv", w.kv, N * 2 * C * 4},
       {"q", w.q, N * C * 4},       {"o", w.o, N * C * 4},     {"h", w.h, N * R * 4},

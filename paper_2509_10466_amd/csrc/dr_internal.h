@@ -95,7 +95,7 @@ struct Work {
   // BF16 path: normalised residual rows x^ (window-major, all tokens)
   bf16* xh = nullptr;
   // BF16 path scratch (u16: normalised rows after the projection, compact)
-  bf16 *u16 = nullptr, *q16 = nullptr, *k16 = nullptr, *v16 = nullptr, *o16 = nullptr,
+  bf16 *u16 = nullptr, *q16 = nullptr, *k16 = nullptr, *o16 = nullptr,
        *h16 = nullptr;
   bf16* vt16 = nullptr;  // V^T [win][head][dh][vt stride] (BF16 clip mode)
   float* amax = nullptr;  // FP8 activation amax slots [blocks][4]
@@ -228,10 +228,6 @@ void launch_attn_f32(const Geo& g, int C, int heads, const float* q, const float
 // BF16 path
 // LN1 fused into the Q/K/V projection: q [N, C]; k, v [win][head][Spad][dh].
 // LN2 fused into the first MLP linear + GELU over the gathered rows x[idx[r]]: h [Nq, R].
-// amax_o (nullable): max |O| of the call is max-reduced into *amax_o (FP8 path)
-void launch_attn_bf16(const Geo& g, int C, int heads, int Spad, const bf16* q, const bf16* k,
-                      const bf16* v, const int32_t* idx, const int32_t* woff, bf16* o,
-                      float* amax_o, hipStream_t s);
 
 // FP8 path (OCP e4m3 operands, per-tensor scales s = amax/448, FP32 accumulation)
 bool fp8_supported(int C, int R);
@@ -243,7 +239,8 @@ void launch_ln_amax(const float* x, const int32_t* rows, const int32_t* nrows_de
 void launch_ln_qkv_fp8(const Geo& g, int C, int heads, int Spad, const float* x,
                        const uint8_t* flag, const int32_t* wcount, const float* lng,
                        const float* lnb, const uint8_t* w, const float* wscale, const float* bias,
-                       const float* amax_u, bf16* q, bf16* k, bf16* v, hipStream_t s);
+                       const float* amax_u, float qscale, int spv, bf16* q, bf16* k, bf16* vt,
+                       hipStream_t s);
 void launch_ln_fc1_fp8(int m_max, int C, int R, const float* x, const int32_t* idx,
                        const int32_t* nq, const float* lng, const float* lnb, const uint8_t* w,
                        float s_w, const float* bias, const float* amax_u, bf16* h, float* amax_h,
@@ -261,8 +258,10 @@ void launch_qkv_bf16(const Geo& g, int C, int heads, int Spad, int spv, const bf
                      const int32_t* wcount, const bf16* w, const float* bias, bf16* q, bf16* k, bf16* vt,
                      hipStream_t s);
 int attn_clip_vt_stride(int spad);
+// amax_o (nullable): max |O| of the call is max-reduced into *amax_o (FP8 path)
 void launch_attn_clip(const Geo& g, int C, int heads, int Spad, const bf16* q, const bf16* k, const bf16* vt,
-                      const int32_t* idx, const int32_t* woff, const int32_t* worder, bf16* o, hipStream_t s);
+                      const int32_t* idx, const int32_t* woff, const int32_t* worder, bf16* o, float* amax_o,
+                      hipStream_t s);
 bool window_order_supported(int S);
 void launch_window_order(const Geo& g, const int32_t* wcount, int32_t* order, hipStream_t s);
 void launch_qkv_stream(const Geo& g, int C, int heads, const bf16* xh, const uint8_t* flag, const bf16* w,

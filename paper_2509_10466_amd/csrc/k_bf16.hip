@@ -17,13 +17,6 @@
 
 namespace dr {
 
-// k = 32 product from two single-rate 16x16x16 MFMAs (k slots 0-3, then 4-7).
-__device__ __forceinline__ f32x4_t mfma16_x2(const bf16x8_t& a, const bf16x8_t& b, const f32x4_t& c) {
-  const bf16x4_t a0 = {a[0], a[1], a[2], a[3]}, a1 = {a[4], a[5], a[6], a[7]};
-  const bf16x4_t b0 = {b[0], b[1], b[2], b[3]}, b1 = {b[4], b[5], b[6], b[7]};
-  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0, c, 0, 0, 0), 0, 0, 0);
-}
-
 __device__ __forceinline__ f32x4_t mfma16k16(const bf16x4_t& a, const bf16x4_t& b, const f32x4_t& c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
@@ -48,172 +41,7 @@ __device__ __forceinline__ T bitcast(const S& s) {
 }
 
 // ------------------------------------------------------------------------------------------
-// Window attention on MFMA.  Block = 4 waves = 64 queries of one (window, head); K and V of
-// the window/head ([Spad][dh] each in global memory) are staged in LDS once, V transposed to
-// V^T [dh][keys] on the way in.  Each wave: 16 queries.
-//   S^T tile (16 keys x 16 queries) = K_tile (16 x dh) . Q^T  -> lane l holds the scores of
-//   query l%16 for keys 16t + 4*(l/16) + i.  Softmax statistics stay FP32: max/sum over
-//   registers, then across the 4 lane groups with two xor shuffles.
-//   O^T (16 dh x 16 queries) = V^T (dh x keys) . P^T, with P taken from the score registers
-//   (the k slots of both operands use the same key permutation).
-// ------------------------------------------------------------------------------------------
-template <int DH, int NT>
-struct AttnTile {
-  static constexpr int SP = NT * 16;   // padded window length
-  static constexpr int KST = DH + 8;   // LDS row stride of K (bf16)
-  static constexpr int VST = SP + 4;   // LDS row stride of V^T: rows spread over distinct bank
-                                       // pairs, 8-byte aligned
-};
-
-// Stage `nrows` keys/values (rows of [.][DH] in global memory) into LDS rows row0.. of K and
-// columns row0.. of V^T.
-template <int DH, int NT>
-__device__ __forceinline__ void attn_stage(bf16* Ks, bf16* Vs, const bf16* __restrict__ kg_,
-                                           const bf16* __restrict__ vg_, int row0, int nrows) {
-  using AT = AttnTile<DH, NT>;
-  const int t = threadIdx.x;
-  for (int c = t; c < nrows * DH / 8; c += 256) {
-    const int row = c / (DH / 8), col = (c % (DH / 8)) * 8;
-    *reinterpret_cast<uint4*>(&Ks[(row0 + row) * AT::KST + col]) = *reinterpret_cast<const uint4*>(kg_ + row * DH + col);
-  }
-  for (int c = t; c < nrows * DH / 8; c += 256) {
-    const int key = c / (DH / 8), d0 = (c % (DH / 8)) * 8;
-    const uint4 v = *reinterpret_cast<const uint4*>(vg_ + key * DH + d0);
-    const uint32_t wds[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      Vs[(d0 + 2 * e) * AT::VST + row0 + key] = (bf16)(wds[e] & 0xffffu);
-      Vs[(d0 + 2 * e + 1) * AT::VST + row0 + key] = (bf16)(wds[e] >> 16);
-    }
-  }
-}
-
-// Queries of one (window, head, 64-query tile) against the S keys staged in LDS (rows >= S of
-// K and columns >= S of V^T must be finite; their scores are masked to -inf).
-template <int DH, int NT, bool PRESCALED>
-__device__ __forceinline__ void attn_compute(const bf16* Ks, const bf16* Vs, int S, int C, int h,
-                                             const bf16* __restrict__ q, const int32_t* __restrict__ idx,
-                                             int q0, int nqw, int qbase, bf16* __restrict__ o,
-                                             float* __restrict__ amax_o) {
-  constexpr int KST = AttnTile<DH, NT>::KST;
-  constexpr int VST = AttnTile<DH, NT>::VST;
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int l16 = lane & 15, kg = lane >> 4;
-  const int qi = qbase + wv * 16 + l16;  // this lane's query (column of S^T)
-  if (qbase + wv * 16 >= nqw) return;    // whole wave idle (no block barrier follows)
-  const bool valid = qi < nqw;
-  const int r = q0 + (valid ? qi : 0);
-  const int n = idx[r];
-
-  // Q^T operand: lane holds q[n][kk*32 + 8*kg .. +7]
-  bf16x8_t qf[DH / 32];
-#pragma unroll
-  for (int kk = 0; kk < DH / 32; ++kk) {
-    uint4 v = valid ? *reinterpret_cast<const uint4*>(q + (size_t)n * C + h * DH + kk * 32 + kg * 8)
-                    : make_uint4(0, 0, 0, 0);
-    qf[kk] = bitcast<bf16x8_t>(v);
-  }
-
-  // scores in base 2: Q of the BF16 path already carries log2(e) / sqrt(dh)
-  const float sl2 = PRESCALED ? 1.0f : 1.4426950408889634f / sqrtf((float)DH);
-  float sc[NT][4];
-#pragma unroll
-  for (int tt = 0; tt < NT; ++tt) {
-    f32x4_t a = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kk = 0; kk < DH / 32; ++kk) {
-      const bf16x8_t kf = *reinterpret_cast<const bf16x8_t*>(&Ks[(tt * 16 + l16) * KST + kk * 32 + kg * 8]);
-      a = mfma16_x2(kf, qf[kk], a);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int key = tt * 16 + kg * 4 + i;
-      sc[tt][i] = key < S ? a[i] * sl2 : -INFINITY;
-    }
-  }
-  float mx = -INFINITY;
-#pragma unroll
-  for (int tt = 0; tt < NT; ++tt)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) mx = fmaxf(mx, sc[tt][i]);
-  mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
-  mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
-  float sum = 0.f;
-#pragma unroll
-  for (int tt = 0; tt < NT; ++tt)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const float p = exp2f(sc[tt][i] - mx);
-      sc[tt][i] = p;
-      sum += p;
-    }
-  sum += __shfl_xor(sum, 16, 64);
-  sum += __shfl_xor(sum, 32, 64);
-  const float inv = 1.0f / sum;
-  float omax = 0.f;
-
-#pragma unroll
-  for (int dt = 0; dt < DH / 16; ++dt) {
-    f32x4_t a = {0.f, 0.f, 0.f, 0.f};
-    const bf16* vrow = &Vs[(dt * 16 + l16) * VST];
-#pragma unroll
-    for (int tt = 0; tt + 1 < NT; tt += 2) {
-      const uint2 v0 = *reinterpret_cast<const uint2*>(vrow + tt * 16 + kg * 4);
-      const uint2 v1 = *reinterpret_cast<const uint2*>(vrow + tt * 16 + 16 + kg * 4);
-      uint4 pv;
-      pv.x = pack_bf2(sc[tt][0], sc[tt][1]);
-      pv.y = pack_bf2(sc[tt][2], sc[tt][3]);
-      pv.z = pack_bf2(sc[tt + 1][0], sc[tt + 1][1]);
-      pv.w = pack_bf2(sc[tt + 1][2], sc[tt + 1][3]);
-      const uint4 vv = make_uint4(v0.x, v0.y, v1.x, v1.y);
-      a = mfma16_x2(bitcast<bf16x8_t>(vv), bitcast<bf16x8_t>(pv), a);
-    }
-    if (NT & 1) {
-      constexpr int tt = NT - 1;
-      const uint2 v0 = *reinterpret_cast<const uint2*>(vrow + tt * 16 + kg * 4);
-      uint2 pv;
-      pv.x = pack_bf2(sc[tt][0], sc[tt][1]);
-      pv.y = pack_bf2(sc[tt][2], sc[tt][3]);
-      a = mfma16k16(bitcast<bf16x4_t>(v0), bitcast<bf16x4_t>(pv), a);
-    }
-    if (valid) {
-      uint2 pk;
-      pk.x = pack_bf2(a[0] * inv, a[1] * inv);
-      pk.y = pack_bf2(a[2] * inv, a[3] * inv);
-      *reinterpret_cast<uint2*>(o + (size_t)r * C + h * DH + dt * 16 + kg * 4) = pk;
-      omax = fmaxf(omax, fmaxf(fmaxf(fabsf(a[0]), fabsf(a[1])), fmaxf(fabsf(a[2]), fabsf(a[3]))) * inv);
-    }
-  }
-  if (amax_o) {
-    // max |O| of this wave into the per-call slot (non-negative floats order like their bits)
-    const float wmx = wave_max(omax);
-    if (lane == 0 && wmx > 0.f) atomicMax(reinterpret_cast<unsigned int*>(amax_o), __float_as_uint(wmx));
-  }
-}
-
-template <int DH, int NT>
-__global__ void __launch_bounds__(256) attn_bf16_kernel(Geo g, int C, int heads, const bf16* __restrict__ q,
-                                                        const bf16* __restrict__ kmat, const bf16* __restrict__ vmat,
-                                                        const int32_t* __restrict__ idx,
-                                                        const int32_t* __restrict__ woff, bf16* __restrict__ o,
-                                                        float* __restrict__ amax_o) {
-  using AT = AttnTile<DH, NT>;
-  __shared__ bf16 Ks[AT::SP * AT::KST];
-  __shared__ bf16 Vs[DH * AT::VST];
-  const int w = blockIdx.x / heads, h = blockIdx.x - w * heads;
-  const int q0 = woff[w], nqw = woff[w + 1] - q0;
-  const int qbase = blockIdx.y * 64;
-  if (qbase >= nqw) return;
-  // K and V of (w, h) hold SP rows, the pad rows zero in memory
-  attn_stage<DH, NT>(Ks, Vs, kmat + ((size_t)w * heads + h) * AT::SP * DH, vmat + ((size_t)w * heads + h) * AT::SP * DH,
-                     0, AT::SP);
-  __syncthreads();
-  attn_compute<DH, NT, false>(Ks, Vs, g.S, C, h, q, idx, q0, nqw, qbase, o, amax_o);
-}
-
-
-// ------------------------------------------------------------------------------------------
-// Window attention, clip mode (BF16 path): one block of 8 wavefronts per (window, head)
+// Window attention, clip mode (BF16 and FP8 paths): one block of 8 wavefronts per (window, head)
 // runs every query of the window, so K and V of a (window, head) reach LDS exactly once.
 // K [Spad][dh] arrives by direct global->LDS loads with its 16-byte chunks XOR-swizzled by
 // row (chunk c of row r at c ^ (r mod dh/8)), V^T [dh][SPV] is stored transposed by the
@@ -293,12 +121,14 @@ struct RingKeys {
 // 4 keys from 16 tt + off sits (vt).  qnext holds the first tile's Q operand, loaded by the
 // caller before staging.
 template <int DH, int NT, class Keys>
-__device__ __forceinline__ void attn_query_tiles(const bf16* Ks, const bf16* Vt, const Keys& keys, int C, int h,
+__device__ __forceinline__ float attn_query_tiles(const bf16* Ks, const bf16* Vt, const Keys& keys, int C, int h,
                                                  const bf16* __restrict__ q, const int32_t* __restrict__ idx,
-                                                 int q0, int nqw, bf16* __restrict__ o, bf16x8_t (&qnext)[DH / 32]) {
+                                                 int q0, int nqw, bf16* __restrict__ o, bf16x8_t (&qnext)[DH / 32],
+                                                 bool want_amax) {
   constexpr int CH = DH / 8;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int l16 = lane & 15, kg = lane >> 4;
+  float omax = 0.f;
   for (int qt = wv; qt * 16 < nqw; qt += ATT_THREADS / 64) {
     // K and V^T fragments are re-read from LDS per query tile: hoisting them out of the loop
     // would hold the whole window in registers
@@ -421,9 +251,14 @@ __device__ __forceinline__ void attn_query_tiles(const bf16* Ks, const bf16* Vt,
         pk.x = pack_bf2(acc[dt][0] * inv, acc[dt][1] * inv);
         pk.y = pack_bf2(acc[dt][2] * inv, acc[dt][3] * inv);
         *reinterpret_cast<uint2*>(o + (size_t)r * C + h * DH + dt * 16 + kg * 4) = pk;
+        if (want_amax)
+          omax = fmaxf(omax, fmaxf(fmaxf(fabsf(acc[dt][0]), fabsf(acc[dt][1])),
+                                   fmaxf(fabsf(acc[dt][2]), fabsf(acc[dt][3]))) * inv);
       }
     }
   }
+  // max |O| of this wavefront's rows (the loop bound is uniform per wavefront)
+  return want_amax ? wave_max(omax) : 0.f;
 }
 
 template <int DH, int NT>
@@ -433,7 +268,7 @@ __global__ void __launch_bounds__(ATT_THREADS) attn_clip_kernel(Geo g, int C, in
                                                                 const int32_t* __restrict__ idx,
                                                                 const int32_t* __restrict__ woff,
                                                                 const int32_t* __restrict__ worder,
-                                                                bf16* __restrict__ o) {
+                                                                bf16* __restrict__ o, float* __restrict__ amax_o) {
   constexpr int SP = NT * 16, CH = DH / 8, SPV = attn_vt_stride(SP);
   extern __shared__ __align__(16) bf16 att_lds[];
   bf16* Ks = att_lds;            // [SP][DH], swizzled chunks
@@ -449,7 +284,22 @@ __global__ void __launch_bounds__(ATT_THREADS) attn_clip_kernel(Geo g, int C, in
   attn_dma<CH, true>(kmat + ((size_t)w * heads + h) * SP * DH, Ks, SP * DH * 2);
   attn_dma<CH, false>(vtmat + ((size_t)w * heads + h) * DH * SPV, Vt, DH * SPV * 2);
   asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
-  attn_query_tiles<DH, NT>(Ks, Vt, ClipKeys<NT, SPV>{g.S}, C, h, q, idx, q0, nqw, o, qnext);
+  const float wmx = attn_query_tiles<DH, NT>(Ks, Vt, ClipKeys<NT, SPV>{g.S}, C, h, q, idx, q0, nqw, o, qnext,
+                                            amax_o != nullptr);
+  if (amax_o) {
+    // max |O| of the block into the per-call slot that scales O for an FP8 projection: one
+    // atomic per block, skipped when the slot already holds more (non-negative floats order
+    // like their bits)
+    __shared__ float wred[ATT_THREADS / 64];
+    if ((threadIdx.x & 63) == 0) wred[wv] = wmx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float m = 0.f;
+      for (int i = 0; i < ATT_THREADS / 64; ++i) m = fmaxf(m, wred[i]);
+      if (m > 0.f && m > *reinterpret_cast<volatile float*>(amax_o))
+        atomicMax(reinterpret_cast<unsigned int*>(amax_o), __float_as_uint(m));
+    }
+  }
 }
 
 // Stream mode: the keys of window (request r, window wl) are that window's tokens in the
@@ -499,7 +349,7 @@ __global__ void __launch_bounds__(ATT_THREADS) attn_ring_kernel(StreamTable tab,
   for (int e = t; e < (NF - 1 - np) * DH * VST / 8; e += ATT_THREADS)
     *reinterpret_cast<uint4*>(Vt + (np + 1) * DH * VST + e * 8) = make_uint4(0, 0, 0, 0);
   asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-  attn_query_tiles<DH, NT>(Ks, Vt, RingKeys<DH, SF, SFP, VST>{np}, C, h, q, idx, q0, nqw, o, qnext);
+  attn_query_tiles<DH, NT>(Ks, Vt, RingKeys<DH, SF, SFP, VST>{np}, C, h, q, idx, q0, nqw, o, qnext, false);
 }
 
 int ring_vt_frame_stride(int sf) { return (sf + 15) / 16 * 16; }
@@ -539,7 +389,8 @@ void launch_attn_ring(const StreamTable& tab, const Geo& g, int C, int heads, in
 int attn_clip_vt_stride(int spad) { return attn_vt_stride(spad); }
 
 void launch_attn_clip(const Geo& g, int C, int heads, int Spad, const bf16* q, const bf16* k, const bf16* vt,
-                      const int32_t* idx, const int32_t* woff, const int32_t* worder, bf16* o, hipStream_t s) {
+                      const int32_t* idx, const int32_t* woff, const int32_t* worder, bf16* o, float* amax_o,
+                      hipStream_t s) {
   const int dh = C / heads;
   const int nt = Spad / 16;
   const size_t lds = (size_t)Spad * dh * 2 + (size_t)dh * attn_vt_stride(Spad) * 2;
@@ -552,7 +403,8 @@ void launch_attn_clip(const Geo& g, int C, int heads, int Spad, const bf16* q, c
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
       attr = true;                                                                                      \
     }                                                                                                   \
-    attn_clip_kernel<DH_, NT_><<<g.nwin * heads, ATT_THREADS, lds, s>>>(g, C, heads, q, k, vt, idx, woff, worder, o); \
+    attn_clip_kernel<DH_, NT_><<<g.nwin * heads, ATT_THREADS, lds, s>>>(g, C, heads, q, k, vt, idx, woff, worder, o, \
+                                                                        amax_o);                                \
     return;                                                                                             \
   }
   DR_ATTN_CLIP(32, 4)
@@ -562,26 +414,6 @@ void launch_attn_clip(const Geo& g, int C, int heads, int Spad, const bf16* q, c
   DR_ATTN_CLIP(32, 15)
   DR_ATTN_CLIP(32, 19)
 #undef DR_ATTN_CLIP
-}
-
-void launch_attn_bf16(const Geo& g, int C, int heads, int Spad, const bf16* q, const bf16* k,
-                      const bf16* vt, const int32_t* idx, const int32_t* woff, bf16* o, float* amax_o,
-                      hipStream_t s) {
-  const int dh = C / heads;
-  dim3 grid(g.nwin * heads, (g.S + 63) / 64);
-  const int nt = Spad / 16;
-#define DR_ATTN_CASE(DH_, NT_)                                                          \
-  if (dh == DH_ && nt == NT_) {                                                         \
-    attn_bf16_kernel<DH_, NT_><<<grid, 256, 0, s>>>(g, C, heads, q, k, vt, idx, woff, o, amax_o); \
-    return;                                                                             \
-  }
-  DR_ATTN_CASE(32, 4)
-  DR_ATTN_CASE(64, 4)
-  DR_ATTN_CASE(64, 15)
-  DR_ATTN_CASE(64, 19)
-  DR_ATTN_CASE(32, 15)
-  DR_ATTN_CASE(32, 19)
-#undef DR_ATTN_CASE
 }
 
 bool attn_bf16_supported(int dh, int spad) {

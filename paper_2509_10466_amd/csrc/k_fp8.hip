@@ -45,8 +45,11 @@ __device__ __forceinline__ float scale_of(const float* amax_slot) {
 }
 
 __device__ __forceinline__ void atomic_amax(float* slot, float v) {
-  // non-negative floats order like their bit patterns
-  atomicMax(reinterpret_cast<unsigned int*>(slot), __float_as_uint(v));
+  // non-negative floats order like their bit patterns.  Read first: once the slot holds the
+  // call's maximum, later blocks skip the atomic (many blocks contend for one address; a
+  // stale read only costs an atomic that changes nothing)
+  if (v > *reinterpret_cast<volatile float*>(slot))
+    atomicMax(reinterpret_cast<unsigned int*>(slot), __float_as_uint(v));
 }
 
 __device__ __forceinline__ float wave_max_abs(float v) { return wave_max(fabsf(v)); }
@@ -114,8 +117,15 @@ __global__ void __launch_bounds__(256) ln_amax_kernel(const float* __restrict__ 
       mx = fmaxf(mx, fabsf((v[e] - mean) * rstd * g[c] + b[c]));
     }
   }
+  // one atomic per block
+  __shared__ float wred[4];
   mx = wave_max(mx);
-  if (lane == 0 && mx > 0.f) atomic_amax(slot, mx);
+  if (lane == 0) wred[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    mx = fmaxf(fmaxf(wred[0], wred[1]), fmaxf(wred[2], wred[3]));
+    if (mx > 0.f) atomic_amax(slot, mx);
+  }
 }
 
 void launch_ln_amax(const float* x, const int32_t* rows, const int32_t* nrows_dev, int nrows_max,
@@ -286,29 +296,42 @@ __device__ __forceinline__ void f8_panel_gemm(const float* __restrict__ x, const
   epi.finish();
 }
 
+// Q rows [N][C] multiplied by qscale (log2(e)/sqrt(dh): the attention kernel takes Q scaled
+// for base-2 exponentials), K [win][head][Spad][dh], V transposed [win][head][dh][spv] -- the
+// layouts of the BF16 path, so both precisions share one attention kernel.
 struct F8QkvEpi {
   const float* bias;
   const float* wscale;  // per block: [0] s_q, [1] s_k, [2] s_v
-  float sa;
-  bf16 *q, *k, *v;
-  int C, dh, heads, Spad, S;
+  float sa, qscale;
+  bf16 *q, *k, *vt;
+  int C, dh, heads, Spad, S, spv;
   __device__ __forceinline__ void operator()(bool ok, int m, int n, const f32x4_t& a) const {
     if (!ok) return;
     const int part = n < C ? 0 : (n < 2 * C ? 1 : 2);
     const float sc = sa * wscale[part];
     const float4 b4 = *reinterpret_cast<const float4*>(bias + n);
-    uint2 pk;
-    pk.x = pack_bf2(a[0] * sc + b4.x, a[1] * sc + b4.y);
-    pk.y = pack_bf2(a[2] * sc + b4.z, a[3] * sc + b4.w);
-    bf16* dst;
+    float y0 = a[0] * sc + b4.x, y1 = a[1] * sc + b4.y, y2 = a[2] * sc + b4.z, y3 = a[3] * sc + b4.w;
     if (part == 0) {
-      dst = q + (size_t)m * C + n;
-    } else {
-      const int c = n - part * C, hh = c / dh, d = c - hh * dh;
-      const int w = m / S, s = m - w * S;
-      dst = (part == 1 ? k : v) + (((size_t)w * heads + hh) * Spad + s) * dh + d;
+      uint2 pk;
+      pk.x = pack_bf2(y0 * qscale, y1 * qscale);
+      pk.y = pack_bf2(y2 * qscale, y3 * qscale);
+      *reinterpret_cast<uint2*>(q + (size_t)m * C + n) = pk;
+      return;
     }
-    *reinterpret_cast<uint2*>(dst) = pk;
+    const int c = n - part * C, hh = c / dh, d = c - hh * dh;
+    const int w = m / S, s = m - w * S;
+    if (part == 1) {
+      uint2 pk;
+      pk.x = pack_bf2(y0, y1);
+      pk.y = pack_bf2(y2, y3);
+      *reinterpret_cast<uint2*>(k + (((size_t)w * heads + hh) * Spad + s) * dh + d) = pk;
+    } else {
+      bf16* dst = vt + (((size_t)w * heads + hh) * dh + d) * spv + s;
+      dst[0] = f2bf(y0);
+      dst[spv] = f2bf(y1);
+      dst[2 * spv] = f2bf(y2);
+      dst[3 * spv] = f2bf(y3);
+    }
   }
   __device__ __forceinline__ void finish() const {}
 };
@@ -323,8 +346,8 @@ __global__ void __launch_bounds__(F8_THREADS) ln_qkv_fp8_kernel(Geo g, int C, in
                                                                 const uint8_t* __restrict__ W,
                                                                 const float* __restrict__ wscale,
                                                                 const float* __restrict__ bias,
-                                                                const float* __restrict__ amax_u,
-                                                                bf16* q, bf16* k, bf16* v) {
+                                                                const float* __restrict__ amax_u, float qscale,
+                                                                int spv, bf16* q, bf16* k, bf16* vt) {
   extern __shared__ __align__(16) uint8_t smem_f8[];
   const int M = g.N;
   const int n0 = blockIdx.x * BN, m0 = blockIdx.y * F8_PANEL_M;
@@ -336,7 +359,7 @@ __global__ void __launch_bounds__(F8_THREADS) ln_qkv_fp8_kernel(Geo g, int C, in
   }
   if (!__syncthreads_or(need)) return;
   const float sa = scale_of(amax_u);
-  F8QkvEpi epi{bias, wscale, sa, q, k, v, C, C / heads, heads, Spad, g.S};
+  F8QkvEpi epi{bias, wscale, sa, qscale, q, k, vt, C, C / heads, heads, Spad, g.S, spv};
   f8_panel_gemm<BN>(x, nullptr, M, m0, C, lng, lnb, 1.0f / sa, W, n0, smem_f8, epi);
 }
 
@@ -395,26 +418,26 @@ static void f8_allow(Kern k, size_t smem, size_t& granted) {
 template <int BN>
 static void qkv_fp8_launch(const Geo& g, int C, int heads, int Spad, const float* x, const uint8_t* flag,
                            const int32_t* wcount, const float* lng, const float* lnb, const uint8_t* w,
-                           const float* wscale, const float* bias, const float* amax_u, bf16* q, bf16* k,
-                           bf16* v, hipStream_t s) {
+                           const float* wscale, const float* bias, const float* amax_u, float qscale, int spv,
+                           bf16* q, bf16* k, bf16* vt, hipStream_t s) {
   static size_t granted = 0;
   const size_t smem = f8_panel_smem<BN>(C);
   f8_allow(ln_qkv_fp8_kernel<BN>, smem, granted);
   dim3 grid(3 * C / BN, (g.N + F8_PANEL_M - 1) / F8_PANEL_M);
   ln_qkv_fp8_kernel<BN><<<grid, F8_THREADS, smem, s>>>(g, C, heads, Spad, x, flag, wcount, lng, lnb, w, wscale,
-                                                        bias, amax_u, q, k, v);
+                                                        bias, amax_u, qscale, spv, q, k, vt);
 }
 
 void launch_ln_qkv_fp8(const Geo& g, int C, int heads, int Spad, const float* x, const uint8_t* flag,
                        const int32_t* wcount, const float* lng, const float* lnb, const uint8_t* w,
-                       const float* wscale, const float* bias, const float* amax_u, bf16* q, bf16* k, bf16* v,
-                       hipStream_t s) {
+                       const float* wscale, const float* bias, const float* amax_u, float qscale, int spv, bf16* q,
+                       bf16* k, bf16* vt, hipStream_t s) {
   if (C % 256 == 0)
-    qkv_fp8_launch<256>(g, C, heads, Spad, x, flag, wcount, lng, lnb, w, wscale, bias, amax_u, q, k, v, s);
+    qkv_fp8_launch<256>(g, C, heads, Spad, x, flag, wcount, lng, lnb, w, wscale, bias, amax_u, qscale, spv, q, k, vt, s);
   else if (C % 128 == 0)
-    qkv_fp8_launch<128>(g, C, heads, Spad, x, flag, wcount, lng, lnb, w, wscale, bias, amax_u, q, k, v, s);
+    qkv_fp8_launch<128>(g, C, heads, Spad, x, flag, wcount, lng, lnb, w, wscale, bias, amax_u, qscale, spv, q, k, vt, s);
   else
-    qkv_fp8_launch<64>(g, C, heads, Spad, x, flag, wcount, lng, lnb, w, wscale, bias, amax_u, q, k, v, s);
+    qkv_fp8_launch<64>(g, C, heads, Spad, x, flag, wcount, lng, lnb, w, wscale, bias, amax_u, qscale, spv, q, k, vt, s);
 }
 
 template <int BN>
