@@ -225,26 +225,23 @@ void launch_gemm_f32(const float* A, const int32_t* arows, const int32_t* m_dev,
 void launch_attn_f32(const Geo& g, int C, int heads, const float* q, const float* kv,
                      const int32_t* woff, float* o, hipStream_t s);
 
-// BF16 path
-// LN1 fused into the Q/K/V projection: q [N, C]; k, v [win][head][Spad][dh].
-// LN2 fused into the first MLP linear + GELU over the gathered rows x[idx[r]]: h [Nq, R].
-
 // FP8 path (OCP e4m3 operands, per-tensor scales s = amax/448, FP32 accumulation)
 bool fp8_supported(int C, int R);
 void launch_quantize_fp8(const float* in, uint8_t* out, size_t n, float inv_scale, hipStream_t s);
 void launch_zero_f32(float* p, int n, hipStream_t s);
-void launch_ln_amax(const float* x, const int32_t* rows, const int32_t* nrows_dev, int nrows_max,
-                    const int32_t* wcount, int S, int C, const float* g, const float* b, float* slot,
-                    hipStream_t s);
-void launch_ln_qkv_fp8(const Geo& g, int C, int heads, int Spad, const float* x,
-                       const uint8_t* flag, const int32_t* wcount, const float* lng,
-                       const float* lnb, const uint8_t* w, const float* wscale, const float* bias,
-                       const float* amax_u, float qscale, int spv, bf16* q, bf16* k, bf16* vt,
-                       hipStream_t s);
-void launch_ln_fc1_fp8(int m_max, int C, int R, const float* x, const int32_t* idx,
-                       const int32_t* nq, const float* lng, const float* lnb, const uint8_t* w,
-                       float s_w, const float* bias, const float* amax_u, bf16* h, float* amax_h,
-                       hipStream_t s);
+// LayerNorm of rows (affine) into bf16 rows plus the call's amax: rows given -> compact output
+// rows r < *nrows_dev from x[rows[r]]; else rows r < nrows_max of windows with queries.
+void launch_ln_rows_amax(const float* x, const int32_t* rows, const int32_t* nrows_dev, int nrows_max,
+                         const int32_t* wcount, int S, int C, const float* g, const float* b, bf16* out,
+                         float* slot, hipStream_t s);
+// Q/K/V from the LayerNorm rows u [N][C]: q [N][C] (times qscale), k [win][head][Spad][dh],
+// vt [win][head][dh][spv]
+void launch_qkv_fp8(const Geo& g, int C, int heads, int Spad, int spv, const bf16* u, const uint8_t* flag,
+                    const int32_t* wcount, const uint8_t* w, const float* wscale, const float* bias,
+                    const float* amax_u, float qscale, bf16* q, bf16* k, bf16* vt, hipStream_t s);
+// first MLP linear + GELU over compact rows u [*m_dev][C] -> h [.][R], amax of h
+void launch_fc1_fp8(int m_max, const int32_t* m_dev, int C, int R, const bf16* u, const uint8_t* w, float s_w,
+                    const float* bias, const float* amax_u, bf16* h, float* amax_h, hipStream_t s);
 void launch_gemm_fp8_resid(const bf16* A, const int32_t* m_dev, int m_max, int K,
                            const uint8_t* W, float s_w, const float* amax_a, const float* bias,
                            int Nout, float* x, const int32_t* res_rows, hipStream_t s);

@@ -25,14 +25,24 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 64 * 1024 * 1024 * 4  # bench.py --calib-copy: 64 Mi float32 elements
 
 
-def source_hash() -> str:
-    """sha256 over the library's HIP sources and headers (sorted by name)."""
-    h = hashlib.sha256()
+# Sources each profiled kernel is compiled from (its translation unit and the headers it
+# includes); a traffic figure stays valid while these files are unchanged.
+KERNEL_SOURCES = {
+    "mlp_block_kernel": ["k_gemm.hip", "gemm_core.h", "dr_device.h", "dr_internal.h"],
+    "qkv_kernel": ["k_gemm.hip", "gemm_core.h", "dr_device.h", "dr_internal.h"],
+    "attn_clip_kernel": ["k_bf16.hip", "dr_device.h", "dr_internal.h"],
+}
+
+
+def source_hash(files=None) -> str:
+    """sha256 over the named library sources (default: every HIP source and header), sorted."""
     csrc = os.path.join(HERE, "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    if files is None:
+        files = [n for n in os.listdir(csrc) if n.endswith((".hip", ".h"))]
+    h = hashlib.sha256()
+    for name in sorted(files):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 
@@ -79,6 +89,7 @@ def traffic(fetch_db, write_db, kernel, cmd_f, cmd_w) -> str:
             sys.exit(f"no kernel matching {sub!r}")
         return hits
 
+    srcs = KERNEL_SOURCES.get(kernel)
     copy_f = [v for k, vs in fetch.items() if "copyBuffer" in k or "copy_kernel" in k for v in vs]
     copy_w = [v for k, vs in write.items() if "copyBuffer" in k or "copy_kernel" in k for v in vs]
     big_f = max(copy_f) if copy_f else None
@@ -102,7 +113,8 @@ def traffic(fetch_db, write_db, kernel, cmd_f, cmd_w) -> str:
         f"copy calibration ({COPY_BYTES // (1 << 20)} MiB device copy): FETCH_SIZE {big_f} KiB, WRITE_SIZE {big_w} KiB "
         f"-> scale {sf:.4f} (fetch), {sw:.4f} (write)",
         f"traffic_bytes_per_launch: {t:.0f}",
-        f"source_sha256: {source_hash()}",
+        f"sources: {' '.join(srcs) if srcs else 'all'}",
+        f"source_sha256: {source_hash(srcs)}",
     ]
     return "\n".join(lines)
 
@@ -116,7 +128,8 @@ def read_traffic(path: str):
     except OSError:
         return None
     kv = dict(line.split(": ", 1) for line in txt.splitlines() if ": " in line)
-    if kv.get("source_sha256") != source_hash():
+    srcs = kv.get("sources", "all")
+    if kv.get("source_sha256") != source_hash(None if srcs == "all" else srcs.split()):
         return None
     try:
         return kv["kernel"], float(kv["traffic_bytes_per_launch"])
