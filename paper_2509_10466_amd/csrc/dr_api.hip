@@ -725,7 +725,7 @@ extern "C" dr_status dr_inpaint(dr_ctx* c, const float* frames, const uint8_t* m
   st = run_tokens(c, g, masks, qs == DR_QUERY_ALL, s);
   if (st != DR_OK) return st;
   if (prec == DR_BF16)
-    LAUNCH(ST_EMBED, launch_embed_bf16(g, C, frames, masks, n.embed_wT16, n.embed_b, w.x, w.xh, s));
+    LAUNCH(ST_EMBED, launch_embed_bf16(g, C, frames, masks, w.flag, w.wcount, n.embed_wT16, n.embed_b, w.x, w.xh, s));
   else
     LAUNCH(ST_EMBED, launch_embed(g, C, frames, masks, n.embed_wT, n.embed_b, w.x, s));
   if (prec == DR_FP8) LAUNCH(ST_LN1, launch_zero_f32(w.amax, 4 * n.cfg.blocks, s));

@@ -247,8 +247,9 @@ void launch_gemm_fp8_resid(const bf16* A, const int32_t* m_dev, int m_max, int K
                            int Nout, float* x, const int32_t* res_rows, hipStream_t s);
 
 // weight preparation
-void launch_embed_bf16(const Geo& g, int C, const float* frames, const uint8_t* masks, const bf16* wT16,
-                       const float* b, float* x, bf16* xh, hipStream_t s);
+// x (f32) of flagged tokens, x^ (bf16) of tokens in windows with queries (wcount null: all)
+void launch_embed_bf16(const Geo& g, int C, const float* frames, const uint8_t* masks, const uint8_t* flag,
+                       const int32_t* wcount, const bf16* wT16, const float* b, float* x, bf16* xh, hipStream_t s);
 void launch_decode_bf16(const Geo& g, int C, const bf16* xh, const int32_t* idx, const int32_t* nq,
                         const bf16* wd16, const float* bd, const uint8_t* masks, float* out, hipStream_t s);
 void launch_qkv_bf16(const Geo& g, int C, int heads, int Spad, int spv, const bf16* xh, const uint8_t* flag,

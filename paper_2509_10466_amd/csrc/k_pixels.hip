@@ -180,20 +180,26 @@ void launch_decode(const Geo& g, int C, const float* x, const int32_t* idx, cons
 // a permuted order -- slice 0: values 12 kg .. 12 kg + 7, slice 1: 12 kg + 8 .. 12 kg + 11 and
 // four zeros -- and wT16 [C][64] holds the embedding weight in that same order, so each
 // lane's MFMA operands come straight from its own loads.
+// Only what later steps read is stored: x^ of tokens in windows with queries (of every token
+// when wcount is null: stream mode keeps K/V of all tokens), x of flagged tokens.
 template <int C>
 __global__ void __launch_bounds__(256) embed_bf16_kernel(Geo g, const float* __restrict__ frames,
                                                          const uint8_t* __restrict__ masks,
+                                                         const uint8_t* __restrict__ flag,
+                                                         const int32_t* __restrict__ wcount,
                                                          const bf16* __restrict__ wT16, const float* __restrict__ bias,
                                                          float* __restrict__ x, bf16* __restrict__ xh) {
   constexpr int FN = C / 16;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int l16 = lane & 15, kg = lane >> 4;
   const int n = (blockIdx.x * 4 + wv) * 16 + l16;
-  const bool ok = n < g.N;
+  const bool need_h = n < g.N && (wcount == nullptr || wcount[n / g.S] > 0);
+  if (!__any(need_h)) return;  // wave-uniform: no barrier in this kernel
+  const bool need_x = need_h && flag[n] != 0;
   float v[12];
 #pragma unroll
   for (int e = 0; e < 12; ++e) v[e] = 0.f;
-  if (ok) {
+  if (need_h) {
     int b, t, i, j;
     token_coords(g, n, b, t, i, j);
     const size_t px = (((size_t)b * g.T + t) * g.H + 4 * i + kg) * g.W + 4 * j;
@@ -247,12 +253,12 @@ __global__ void __launch_bounds__(256) embed_bf16_kernel(Geo g, const float* __r
   sq += __shfl_xor(sq, 16, 64);
   sq += __shfl_xor(sq, 32, 64);
   const float rstd = rsqrtf(sq * (1.0f / C) + 1e-5f);
-  if (!ok) return;
+  if (!need_h) return;
 #pragma unroll
   for (int f = 0; f < FN; ++f) {
     const int c = 16 * f + 4 * kg;
     const f32x4_t& a = acc[f];
-    *reinterpret_cast<float4*>(x + (size_t)n * C + c) = make_float4(a[0], a[1], a[2], a[3]);
+    if (need_x) *reinterpret_cast<float4*>(x + (size_t)n * C + c) = make_float4(a[0], a[1], a[2], a[3]);
     uint2 pk;
     pk.x = pack_bf2((a[0] - mean) * rstd, (a[1] - mean) * rstd);
     pk.y = pack_bf2((a[2] - mean) * rstd, (a[3] - mean) * rstd);
@@ -260,15 +266,15 @@ __global__ void __launch_bounds__(256) embed_bf16_kernel(Geo g, const float* __r
   }
 }
 
-void launch_embed_bf16(const Geo& g, int C, const float* frames, const uint8_t* masks, const bf16* wT16,
-                       const float* b, float* x, bf16* xh, hipStream_t s) {
+void launch_embed_bf16(const Geo& g, int C, const float* frames, const uint8_t* masks, const uint8_t* flag,
+                       const int32_t* wcount, const bf16* wT16, const float* b, float* x, bf16* xh, hipStream_t s) {
   const int blocks = (g.N + 63) / 64;
   if (blocks == 0) return;
   switch (C) {
-    case 64: embed_bf16_kernel<64><<<blocks, 256, 0, s>>>(g, frames, masks, wT16, b, x, xh); break;
-    case 128: embed_bf16_kernel<128><<<blocks, 256, 0, s>>>(g, frames, masks, wT16, b, x, xh); break;
-    case 256: embed_bf16_kernel<256><<<blocks, 256, 0, s>>>(g, frames, masks, wT16, b, x, xh); break;
-    case 384: embed_bf16_kernel<384><<<blocks, 256, 0, s>>>(g, frames, masks, wT16, b, x, xh); break;
+    case 64: embed_bf16_kernel<64><<<blocks, 256, 0, s>>>(g, frames, masks, flag, wcount, wT16, b, x, xh); break;
+    case 128: embed_bf16_kernel<128><<<blocks, 256, 0, s>>>(g, frames, masks, flag, wcount, wT16, b, x, xh); break;
+    case 256: embed_bf16_kernel<256><<<blocks, 256, 0, s>>>(g, frames, masks, flag, wcount, wT16, b, x, xh); break;
+    case 384: embed_bf16_kernel<384><<<blocks, 256, 0, s>>>(g, frames, masks, flag, wcount, wT16, b, x, xh); break;
     default: break;  // rejected by the caller (resid_ln_supported)
   }
 }
