@@ -553,6 +553,8 @@ dr_status dr::dr_reserve_work(dr_ctx* c, Work& w, const Geo& g, bool stream_mode
   ALLOC(idx, N * 4);
   ALLOC(nq, 256);
   ALLOC(worder, nw * 4);
+  ALLOC(tiles, 2 * ((N + ROW_TILE - 1) / ROW_TILE) * 4);
+  ALLOC(ntiles, 256);
   ALLOC(x, N * C * 4);
   ALLOC(q16, N * C * 2);
   ALLOC(o16, N * C * 2);
@@ -620,7 +622,7 @@ static dr_status run_tokens(dr_ctx* c, const Geo& g, const uint8_t* masks, int a
   Work& w = c->work;
   LAUNCH(ST_TOKENS, launch_token_flags(g, masks, all, w.flag, w.wcount, s));
   LAUNCH(ST_TOKENS, launch_token_gather(g, w.flag, w.wcount, w.idx, w.woff, w.nq, s));
-  LAUNCH(ST_TOKENS, launch_window_order(g, w.wcount, w.worder, s));
+  LAUNCH(ST_TOKENS, launch_window_order(g, w.wcount, w.flag, w.worder, w.tiles, w.ntiles, s));
   return DR_OK;
 }
 
@@ -672,7 +674,7 @@ static dr_status run_blocks(dr_ctx* c, const Geo& g, dr_precision prec, hipStrea
     } else {
       // x^ (normalised rows) feeds Q/K/V; the projection leaves x1^ of the query rows in u16
       // for the MLP; the second MLP linear refreshes x^ of the query rows
-      LAUNCH(ST_QKV, launch_qkv_bf16(g, C, n.cfg.heads, n.Spad, attn_clip_vt_stride(n.Spad), w.xh, w.flag, w.wcount, b.wqkvf16, b.bqkvf, w.q16, w.k16, w.vt16, s));
+      LAUNCH(ST_QKV, launch_qkv_bf16(g, C, n.cfg.heads, n.Spad, attn_clip_vt_stride(n.Spad), w.xh, w.tiles, w.ntiles, b.wqkvf16, b.bqkvf, w.q16, w.k16, w.vt16, s));
       LAUNCH(ST_ATTN, launch_attn_clip(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.vt16, w.idx, w.woff, w.worder, w.o16, nullptr, s));
       if (mlp_block_supported(C, R)) {
         LAUNCH(ST_MLP, launch_mlp_block_bf16(N, w.nq, C, w.o16, w.idx, b.wo16, b.bo, b.w1f16, b.b1f, b.w216, b.b2, w.x, w.xh, s));

@@ -88,6 +88,9 @@ struct Work {
   int32_t* idx = nullptr;
   int32_t* nq = nullptr;
   int32_t* worder = nullptr;  // windows by decreasing query count
+  int32_t* tiles = nullptr;   // [2][ceil(N / ROW_TILE)]: row tiles with a flagged token, then
+                              // row tiles touching a window with queries (any order)
+  int32_t* ntiles = nullptr;  // [2]: lengths of the two lists
   // residual stream, FP32, window-major rows
   float* x = nullptr;
   // FP32 path scratch
@@ -252,8 +255,10 @@ void launch_embed_bf16(const Geo& g, int C, const float* frames, const uint8_t* 
                        const int32_t* wcount, const bf16* wT16, const float* b, float* x, bf16* xh, hipStream_t s);
 void launch_decode_bf16(const Geo& g, int C, const bf16* xh, const int32_t* idx, const int32_t* nq,
                         const bf16* wd16, const float* bd, const uint8_t* masks, float* out, hipStream_t s);
-void launch_qkv_bf16(const Geo& g, int C, int heads, int Spad, int spv, const bf16* xh, const uint8_t* flag,
-                     const int32_t* wcount, const bf16* w, const float* bias, bf16* q, bf16* k, bf16* vt,
+// clip mode: the row tiles listed by launch_window_order (Q tiles with a flagged token, K/V
+// tiles touching a window with queries)
+void launch_qkv_bf16(const Geo& g, int C, int heads, int Spad, int spv, const bf16* xh, const int32_t* tiles,
+                     const int32_t* ntiles, const bf16* w, const float* bias, bf16* q, bf16* k, bf16* vt,
                      hipStream_t s);
 int attn_clip_vt_stride(int spad);
 // amax_o (nullable): max |O| of the call is max-reduced into *amax_o (FP8 path)
@@ -261,7 +266,12 @@ void launch_attn_clip(const Geo& g, int C, int heads, int Spad, const bf16* q, c
                       const int32_t* idx, const int32_t* woff, const int32_t* worder, bf16* o, float* amax_o,
                       hipStream_t s);
 bool window_order_supported(int S);
-void launch_window_order(const Geo& g, const int32_t* wcount, int32_t* order, hipStream_t s);
+// Rows of the Q/K/V GEMM tiles listed by the token step (the GEMM's row tile height).
+constexpr int ROW_TILE = 64;
+// windows by decreasing query count, plus the two row-tile lists (tiles [2][ceil(N/ROW_TILE)],
+// counts ntiles[2])
+void launch_window_order(const Geo& g, const int32_t* wcount, const uint8_t* flag, int32_t* order, int32_t* tiles,
+                         int32_t* ntiles, hipStream_t s);
 void launch_qkv_stream(const Geo& g, int C, int heads, const bf16* xh, const uint8_t* flag, const bf16* w,
                        const float* bias, bf16* q, const StreamTable& tab, hipStream_t s);
 void launch_fc1_bf16(int m_max, const int32_t* m_dev, int C, int R, const bf16* u2, const bf16* w,

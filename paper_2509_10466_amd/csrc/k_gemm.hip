@@ -152,6 +152,43 @@ __global__ void __launch_bounds__(256) qkv_kernel(int M, int C, int S, const bf1
   for_rows<TL>(M, m0, n0, acc, out);
 }
 
+// Clip mode: blocks run only the listed row tiles (computed with the window order): the first
+// xcd_grid(mt, C/BN) blocks take Q column tiles over the tiles with a flagged token, the rest
+// K/V column tiles over the tiles touching a window with queries.  Slots past a list's length
+// exit; they come last in dispatch order.
+template <class TL, class Out>
+__global__ void __launch_bounds__(256) qkv_list_kernel(int M, int C, const bf16* __restrict__ xh,
+                                                       const int32_t* __restrict__ tiles,
+                                                       const int32_t* __restrict__ ntiles, const bf16* __restrict__ W,
+                                                       Out out) {
+  static_assert(TL::BM == ROW_TILE, "row tiles are listed in ROW_TILE units");
+  extern __shared__ __align__(16) bf16 ring[];
+  const int mt = (M + TL::BM - 1) / TL::BM;
+  const int ntq = C / TL::BN, gq = xcd_grid(mt, ntq);
+  const bool is_q = (int)blockIdx.x < gq;
+  const int b = is_q ? blockIdx.x : blockIdx.x - gq;
+  int i, ct;
+  xcd_tile(b, is_q ? ntq : 2 * ntq, i, ct);
+  if (i >= ntiles[is_q ? 0 : 1]) return;
+  const int m0 = tiles[(is_q ? 0 : mt) + i] * TL::BM, n0 = (is_q ? 0 : C) + ct * TL::BN;
+  f32x4_t acc[TL::FM][TL::FN];
+  gemm_core<TL>(xh, M, m0, W, n0, C, ring, acc);
+  for_rows<TL>(M, m0, n0, acc, out);
+}
+
+template <class TL, class Out>
+static void qkv_list_launch(int M, int C, const bf16* xh, const int32_t* tiles, const int32_t* ntiles, const bf16* w,
+                            const Out& out, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    allow_lds(qkv_list_kernel<TL, Out>, TL::LDS_BYTES);
+    attr = true;
+  }
+  const int mt = (M + TL::BM - 1) / TL::BM;
+  const int grid = xcd_grid(mt, C / TL::BN) + xcd_grid(mt, 2 * C / TL::BN);
+  qkv_list_kernel<TL, Out><<<grid, 256, TL::LDS_BYTES, s>>>(M, C, xh, tiles, ntiles, w, out);
+}
+
 template <class TL, class Out>
 static void qkv_launch(int M, int C, int S, const bf16* xh, const uint8_t* flag, const int32_t* wcount,
                        const bf16* w, const Out& out, hipStream_t s) {
@@ -171,15 +208,15 @@ static int log2_pow2(int v) {
   return k;
 }
 
-void launch_qkv_bf16(const Geo& g, int C, int heads, int Spad, int spv, const bf16* xh, const uint8_t* flag,
-                     const int32_t* wcount, const bf16* w, const float* bias, bf16* q, bf16* k, bf16* vt,
+void launch_qkv_bf16(const Geo& g, int C, int heads, int Spad, int spv, const bf16* xh, const int32_t* tiles,
+                     const int32_t* ntiles, const bf16* w, const float* bias, bf16* q, bf16* k, bf16* vt,
                      hipStream_t s) {
   if (g.N <= 0) return;
   const QkvOut out{bias, q, k, vt, C, log2_pow2(C / heads), heads, Spad, g.S, spv};
   if (C % 128 == 0)
-    qkv_launch<GemmTile<64, 128, 2, 2, 3>>(g.N, C, g.S, xh, flag, wcount, w, out, s);
+    qkv_list_launch<GemmTile<64, 128, 2, 2, 3>>(g.N, C, xh, tiles, ntiles, w, out, s);
   else
-    qkv_launch<GemmTile<64, 64, 2, 2, 3>>(g.N, C, g.S, xh, flag, wcount, w, out, s);
+    qkv_list_launch<GemmTile<64, 64, 2, 2, 3>>(g.N, C, xh, tiles, ntiles, w, out, s);
 }
 
 void launch_qkv_stream(const Geo& g, int C, int heads, const bf16* xh, const uint8_t* flag, const bf16* w,

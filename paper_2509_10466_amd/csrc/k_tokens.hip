@@ -102,12 +102,38 @@ __global__ void __launch_bounds__(256) token_gather_kernel(Geo g, const uint8_t*
 // any order; that only changes scheduling, never a result.
 constexpr int ORDER_MAX_S = 2048;
 
-__global__ void __launch_bounds__(1024) window_order_kernel(int nwin, int S, const int32_t* __restrict__ wcount,
-                                                            int32_t* __restrict__ order) {
+//
+// The same block lists the Q/K/V GEMM's row tiles of ROW_TILE tokens that have work: tiles
+// holding a flagged token (their Q rows are read) and tiles touching a window with queries
+// (their K/V rows are read), so that the GEMM launches no block for the others.
+static_assert(ROW_TILE == 64, "the flag scan reads a tile as four 16-byte words");
+
+__global__ void __launch_bounds__(1024) window_order_kernel(int nwin, int S, int N, const int32_t* __restrict__ wcount,
+                                                            const uint8_t* __restrict__ flag,
+                                                            int32_t* __restrict__ order, int32_t* __restrict__ tiles,
+                                                            int32_t* __restrict__ ntiles) {
   __shared__ int hist[ORDER_MAX_S + 1];
   __shared__ int start[ORDER_MAX_S + 1];
+  __shared__ int nlist[2];
   for (int c = threadIdx.x; c <= S; c += blockDim.x) hist[c] = 0;
+  if (threadIdx.x < 2) nlist[threadIdx.x] = 0;
   __syncthreads();
+  const int mt = (N + ROW_TILE - 1) / ROW_TILE;
+  for (int rt = threadIdx.x; rt < mt; rt += blockDim.x) {
+    const int r0 = rt * ROW_TILE, r1 = min(N, r0 + ROW_TILE);  // rows [r0, r1)
+    bool kv = false;
+    for (int w = r0 / S; w <= (r1 - 1) / S; ++w) kv |= wcount[w] > 0;
+    bool q = false;
+    if (r1 - r0 == ROW_TILE) {  // whole tile: four independent 16-byte loads (64-byte aligned)
+      const uint4* f4 = reinterpret_cast<const uint4*>(flag + r0);
+      uint4 a = f4[0], b = f4[1], c = f4[2], d = f4[3];
+      q = ((a.x | a.y | a.z | a.w) | (b.x | b.y | b.z | b.w) | (c.x | c.y | c.z | c.w) | (d.x | d.y | d.z | d.w)) != 0;
+    } else {
+      for (int r = r0; r < r1; ++r) q |= flag[r] != 0;
+    }
+    if (q) tiles[atomicAdd(&nlist[0], 1)] = rt;
+    if (kv) tiles[mt + atomicAdd(&nlist[1], 1)] = rt;
+  }
   for (int w = threadIdx.x; w < nwin; w += blockDim.x) atomicAdd(&hist[wcount[w]], 1);
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -119,12 +145,14 @@ __global__ void __launch_bounds__(1024) window_order_kernel(int nwin, int S, con
   }
   __syncthreads();
   for (int w = threadIdx.x; w < nwin; w += blockDim.x) order[atomicAdd(&start[wcount[w]], 1)] = w;
+  if (threadIdx.x < 2) ntiles[threadIdx.x] = nlist[threadIdx.x];
 }
 
 bool window_order_supported(int S) { return S <= ORDER_MAX_S; }
 
-void launch_window_order(const Geo& g, const int32_t* wcount, int32_t* order, hipStream_t s) {
-  window_order_kernel<<<1, 1024, 0, s>>>(g.nwin, g.S, wcount, order);
+void launch_window_order(const Geo& g, const int32_t* wcount, const uint8_t* flag, int32_t* order, int32_t* tiles,
+                         int32_t* ntiles, hipStream_t s) {
+  window_order_kernel<<<1, 1024, 0, s>>>(g.nwin, g.S, g.N, wcount, flag, order, tiles, ntiles);
 }
 
 void launch_token_flags(const Geo& g, const uint8_t* masks, int all, uint8_t* flag,
