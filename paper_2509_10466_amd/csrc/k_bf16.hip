@@ -143,7 +143,7 @@ __device__ __forceinline__ float attn_query_tiles(const bf16* Ks, const bf16* Vt
     // S^T = K Q^T: key tiles in groups of TG, each tile's k slices chained, the chains of a
     // group interleaved; a group's K fragments are read while the previous group multiplies
     constexpr int KS = DH / 32;  // 32-wide k slices
-    constexpr int TG = 5;
+    constexpr int TG = 3;
     float sc[NT][4];
     bf16x8_t kf[2][TG][KS];
     auto read_k = [&](int g0, bf16x8_t (&dst)[TG][KS]) {
@@ -203,12 +203,14 @@ __device__ __forceinline__ float attn_query_tiles(const bf16* Ks, const bf16* Vt
 
     // O^T = V^T P^T: per pair of key tiles one MFMA for each 16-row block of dh (independent
     // accumulators), P^T straight from the score registers (key order 4kg..+3 of each tile,
-    // matched by the V^T reads); V^T fragments of the next pair are read ahead
+    // matched by the V^T reads)
     constexpr int DT = DH / 16, NP = NT / 2;
     f32x4_t acc[DT];
 #pragma unroll
     for (int dt = 0; dt < DT; ++dt) acc[dt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-    bf16x8_t vf[2][DT];
+    bf16x8_t vf[DT];
+    // (V^T fragments are read per pair, not double-buffered: the spare registers let two
+    // blocks share a CU at 240 keys)
     auto read_v = [&](int p, bf16x8_t (&dst)[DT]) {
 #pragma unroll
       for (int dt = 0; dt < DT; ++dt) {
@@ -217,11 +219,9 @@ __device__ __forceinline__ float attn_query_tiles(const bf16* Ks, const bf16* Vt
         dst[dt] = bitcast<bf16x8_t>(make_uint4(v0.x, v0.y, v1.x, v1.y));
       }
     };
-    if (NP > 0) read_v(0, vf[0]);
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-      const int cur = p & 1;
-      if (p + 1 < NP) read_v(p + 1, vf[cur ^ 1]);
+      read_v(p, vf);
       uint4 pv;
       pv.x = pack_bf2(sc[2 * p][0], sc[2 * p][1]);
       pv.y = pack_bf2(sc[2 * p][2], sc[2 * p][3]);
@@ -230,7 +230,7 @@ __device__ __forceinline__ float attn_query_tiles(const bf16* Ks, const bf16* Vt
       const bf16x8_t pb = bitcast<bf16x8_t>(pv);
       mfma_fence_begin();
 #pragma unroll
-      for (int dt = 0; dt < DT; ++dt) acc[dt] = mfma32(vf[cur][dt], pb, acc[dt]);
+      for (int dt = 0; dt < DT; ++dt) acc[dt] = mfma32(vf[dt], pb, acc[dt]);
       mfma_fence_end();
     }
     if (NT & 1) {  // last key tile alone: single-rate k = 16 (operands read at issue)
@@ -261,8 +261,12 @@ __device__ __forceinline__ float attn_query_tiles(const bf16* Ks, const bf16* Vt
   return want_amax ? wave_max(omax) : 0.f;
 }
 
+// At up to 240 keys the kernel fits 128 VGPRs: 4 wavefronts per SIMD, two blocks per CU.
+template <int NT>
+constexpr int attn_clip_waves_per_simd() { return NT <= 15 ? 4 : 3; }
+
 template <int DH, int NT>
-__global__ void __launch_bounds__(ATT_THREADS) attn_clip_kernel(Geo g, int C, int heads, const bf16* __restrict__ q,
+__global__ void __launch_bounds__(ATT_THREADS, attn_clip_waves_per_simd<NT>()) attn_clip_kernel(Geo g, int C, int heads, const bf16* __restrict__ q,
                                                                 const bf16* __restrict__ kmat,
                                                                 const bf16* __restrict__ vtmat,
                                                                 const int32_t* __restrict__ idx,
