@@ -1,8 +1,8 @@
 // BF16 GEMM core for gfx950: C[m][n] = sum_k A[m][k] * W[n][k], FP32 accumulation on
 // v_mfma_f32_16x16x32_bf16.
 //
-// Block = 256 threads = 4 wavefronts in a WM x WN grid; block tile BM tokens x BN output
-// channels; K is consumed 64 at a time through an ST-stage ring in LDS.  Each stage holds the
+// Block = 64 WM WN threads (4 or 8 wavefronts) in a WM x WN grid; block tile BM tokens x BN
+// output channels; K is consumed 64 at a time through an ST-stage ring in LDS.  Each stage holds the
 // BM rows of A followed by the BN rows of W, 128 bytes (64 bf16) per row, and is filled by
 // direct global->LDS loads (global_load_lds_dwordx4: each lane of a wavefront moves 16 bytes,
 // lane i landing at byte 16*i of the wavefront's 1 KB destination, i.e. 8 rows per
@@ -64,15 +64,16 @@ __device__ __forceinline__ void dma16(const void* gsrc, bf16_t* lds_dst) {
 template <int BM_, int BN_, int WM_, int WN_, int ST_>
 struct GemmTile {
   static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, ST = ST_;
+  static constexpr int NW = WM * WN, THREADS = 64 * NW;  // wavefronts, threads per block
   static constexpr int TM = BM / WM, TN = BN / WN;  // wavefront tile
   static constexpr int FM = TM / 16, FN = TN / 16;  // 16 x 16 fragments per wavefront
   static constexpr int ROWS = BM + BN;              // LDS rows per stage
-  static constexpr int LOADS = ROWS / 32;           // 1 KB loads per wavefront per stage
+  static constexpr int LOADS = ROWS / (8 * NW);     // 1 KB loads per wavefront per stage
   static constexpr int STAGE = ROWS * 64;           // bf16 elements per stage
   static constexpr size_t LDS_BYTES = (size_t)ST * STAGE * 2;
-  static_assert(WM * WN == 4, "4 wavefronts");
+  static_assert(NW == 4 || NW == 8, "4 or 8 wavefronts");
   static_assert(TM % 16 == 0 && TN % 16 == 0 && BM % 16 == 0, "fragment multiples");
-  static_assert(ROWS % 32 == 0, "whole loads");
+  static_assert(ROWS % (8 * NW) == 0, "whole loads");
   static_assert(ST >= 2 && (ST - 2) * LOADS < 64, "vmcnt range");
 };
 
@@ -95,7 +96,7 @@ __device__ __forceinline__ void gemm_core(const bf16_t* __restrict__ A, int M, i
   // global source of each of this lane's loads (fixed over K; advanced by 64 per stage)
   const bf16_t* src[TL::LOADS];
   static_for<TL::LOADS>([&](auto c) {
-    const int row = (wv + 4 * c) * 8 + (lane >> 3);
+    const int row = (wv + TL::NW * c) * 8 + (lane >> 3);
     const int chunk = (lane & 7) ^ lds_swz(row);
     const bf16_t* base;
     if (row < TL::BM) {
@@ -108,7 +109,7 @@ __device__ __forceinline__ void gemm_core(const bf16_t* __restrict__ A, int M, i
   });
   auto issue = [&](int kt, int buf) {
     bf16_t* dst = lds + buf * TL::STAGE;
-    static_for<TL::LOADS>([&](auto c) { dma16(src[c] + kt * 64, dst + (wv + 4 * c) * 512); });
+    static_for<TL::LOADS>([&](auto c) { dma16(src[c] + kt * 64, dst + (wv + TL::NW * c) * 512); });
   };
   // per-lane LDS element offsets of the operand rows (chunk position applied per k slice)
   int arow[TL::FM], wrow[TL::FN];

@@ -130,7 +130,7 @@ struct StreamQkvOut {
 // values of a window without queries are never read.  Stream mode keeps K/V of every token
 // (later frames may query any window): wcount == nullptr.
 template <class TL, class Out>
-__global__ void __launch_bounds__(256) qkv_kernel(int M, int C, int S, const bf16* __restrict__ xh,
+__global__ void __launch_bounds__(TL::THREADS) qkv_kernel(int M, int C, int S, const bf16* __restrict__ xh,
                                                   const uint8_t* __restrict__ flag,
                                                   const int32_t* __restrict__ wcount,
                                                   const bf16* __restrict__ W, Out out) {
@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(256) qkv_kernel(int M, int C, int S, const bf1
 // K/V column tiles over the tiles touching a window with queries.  Slots past a list's length
 // exit; they come last in dispatch order.
 template <class TL, class Out>
-__global__ void __launch_bounds__(256) qkv_list_kernel(int M, int C, const bf16* __restrict__ xh,
+__global__ void __launch_bounds__(TL::THREADS) qkv_list_kernel(int M, int C, const bf16* __restrict__ xh,
                                                        const int32_t* __restrict__ tiles,
                                                        const int32_t* __restrict__ ntiles, const bf16* __restrict__ W,
                                                        Out out) {
@@ -186,7 +186,7 @@ static void qkv_list_launch(int M, int C, const bf16* xh, const int32_t* tiles, 
   }
   const int mt = (M + TL::BM - 1) / TL::BM;
   const int grid = xcd_grid(mt, C / TL::BN) + xcd_grid(mt, 2 * C / TL::BN);
-  qkv_list_kernel<TL, Out><<<grid, 256, TL::LDS_BYTES, s>>>(M, C, xh, tiles, ntiles, w, out);
+  qkv_list_kernel<TL, Out><<<grid, TL::THREADS, TL::LDS_BYTES, s>>>(M, C, xh, tiles, ntiles, w, out);
 }
 
 template <class TL, class Out>
@@ -198,7 +198,7 @@ static void qkv_launch(int M, int C, int S, const bf16* xh, const uint8_t* flag,
     attr = true;
   }
   const int grid = xcd_grid((M + TL::BM - 1) / TL::BM, 3 * C / TL::BN);
-  qkv_kernel<TL, Out><<<grid, 256, TL::LDS_BYTES, s>>>(M, C, S, xh, flag, wcount, w, out);
+  qkv_kernel<TL, Out><<<grid, TL::THREADS, TL::LDS_BYTES, s>>>(M, C, S, xh, flag, wcount, w, out);
 }
 
 // log2 of a power of two (head widths 32 and 64 are the ones the attention kernels take)
@@ -246,7 +246,7 @@ struct GeluOut {
 };
 
 template <class TL>
-__global__ void __launch_bounds__(256) fc1_kernel(const int32_t* __restrict__ m_dev, int C, int R,
+__global__ void __launch_bounds__(TL::THREADS) fc1_kernel(const int32_t* __restrict__ m_dev, int C, int R,
                                                   const bf16* __restrict__ u2, const bf16* __restrict__ W,
                                                   GeluOut out) {
   extern __shared__ __align__(16) bf16 ring[];
@@ -273,7 +273,7 @@ void launch_fc1_bf16(int m_max, const int32_t* m_dev, int C, int R, const bf16* 
     attr = true;
   }
   const int grid = xcd_grid((m_max + TL::BM - 1) / TL::BM, R / TL::BN);
-  fc1_kernel<TL><<<grid, 256, TL::LDS_BYTES, s>>>(m_dev, C, R, u2, w, GeluOut{bias, h, R});
+  fc1_kernel<TL><<<grid, TL::THREADS, TL::LDS_BYTES, s>>>(m_dev, C, R, u2, w, GeluOut{bias, h, R});
 }
 
 // ------------------------------------------------------------------------------------------
@@ -283,14 +283,15 @@ void launch_fc1_bf16(int m_max, const int32_t* m_dev, int C, int R, const bf16* 
 // centred sum of squares), FP32, biased variance, eps 1e-5.
 // ------------------------------------------------------------------------------------------
 template <class TL>
-__global__ void __launch_bounds__(256) resid_ln_kernel(const int32_t* __restrict__ m_dev, int K,
+__global__ void __launch_bounds__(TL::THREADS) resid_ln_kernel(const int32_t* __restrict__ m_dev, int K,
                                                        const bf16* __restrict__ A, const bf16* __restrict__ W,
                                                        const float* __restrict__ bias, float* __restrict__ x,
                                                        const int32_t* __restrict__ rows, bf16* __restrict__ xh,
                                                        const int32_t* __restrict__ hrows) {
   constexpr int C = TL::BN;
   extern __shared__ __align__(16) bf16 ring[];
-  __shared__ float red[2][4][TL::BM];
+  __shared__ float red[2][TL::WN][TL::BM];
+  static_assert(TL::WN == 4, "row sums over four column wavefronts");
   const int M = m_dev[0];
   // row tile b: consecutive row tiles run on different XCDs
   const int m0 = blockIdx.x * TL::BM;
@@ -298,12 +299,13 @@ __global__ void __launch_bounds__(256) resid_ln_kernel(const int32_t* __restrict
   f32x4_t acc[TL::FM][TL::FN];
   gemm_core<TL>(A, M, m0, W, 0, K, ring, acc);
 
-  const int lane = threadIdx.x & 63, wn = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wm = wv / TL::WN, wn = wv % TL::WN;
   const int l16 = lane & 15, kg = lane >> 4;
   int dst[TL::FM];
   float part[TL::FM];
   static_for<TL::FM>([&](auto i) {
-    const int m = m0 + 16 * i + l16;
+    const int m = m0 + wm * TL::TM + 16 * i + l16;
     const bool ok = m < M;
     dst[i] = ok ? rows[m] : -1;
     float sum = 0.f;
@@ -324,11 +326,11 @@ __global__ void __launch_bounds__(256) resid_ln_kernel(const int32_t* __restrict
     sum += __shfl_xor(sum, 32, 64);
     part[i] = sum;
   });
-  if (kg == 0) static_for<TL::FM>([&](auto i) { red[0][wn][16 * i + l16] = part[i]; });
+  if (kg == 0) static_for<TL::FM>([&](auto i) { red[0][wn][wm * TL::TM + 16 * i + l16] = part[i]; });
   __syncthreads();
   float mean[TL::FM];
   static_for<TL::FM>([&](auto i) {
-    const int r = 16 * i + l16;
+    const int r = wm * TL::TM + 16 * i + l16;
     mean[i] = ((red[0][0][r] + red[0][1][r]) + (red[0][2][r] + red[0][3][r])) * (1.0f / C);
     float sq = 0.f;
     static_for<TL::FN>([&](auto j) {
@@ -341,10 +343,10 @@ __global__ void __launch_bounds__(256) resid_ln_kernel(const int32_t* __restrict
     sq += __shfl_xor(sq, 32, 64);
     part[i] = sq;
   });
-  if (kg == 0) static_for<TL::FM>([&](auto i) { red[1][wn][16 * i + l16] = part[i]; });
+  if (kg == 0) static_for<TL::FM>([&](auto i) { red[1][wn][wm * TL::TM + 16 * i + l16] = part[i]; });
   __syncthreads();
   static_for<TL::FM>([&](auto i) {
-    const int r = 16 * i + l16;
+    const int r = wm * TL::TM + 16 * i + l16;
     const float var = ((red[1][0][r] + red[1][1][r]) + (red[1][2][r] + red[1][3][r])) * (1.0f / C);
     const float rstd = rsqrtf(var + 1e-5f);
     if (dst[i] >= 0) {
@@ -369,7 +371,7 @@ static void resid_ln_launch(int m_max, const int32_t* m_dev, int K, const bf16* 
     allow_lds(resid_ln_kernel<TL>, TL::LDS_BYTES);
     attr = true;
   }
-  resid_ln_kernel<TL><<<(m_max + TL::BM - 1) / TL::BM, 256, TL::LDS_BYTES, s>>>(m_dev, K, A, w, bias, x, rows, xh, hrows);
+  resid_ln_kernel<TL><<<(m_max + TL::BM - 1) / TL::BM, TL::THREADS, TL::LDS_BYTES, s>>>(m_dev, K, A, w, bias, x, rows, xh, hrows);
 }
 
 bool resid_ln_supported(int C) { return C == 64 || C == 128 || C == 256 || C == 384; }
@@ -382,7 +384,7 @@ void launch_resid_ln_bf16(int m_max, const int32_t* m_dev, int C, int K, const b
     case 64: resid_ln_launch<GemmTile<64, 64, 1, 4, 3>>(m_max, m_dev, K, A, w, bias, x, rows, xh, hrows, s); break;
     case 128: resid_ln_launch<GemmTile<64, 128, 1, 4, 3>>(m_max, m_dev, K, A, w, bias, x, rows, xh, hrows, s); break;
     case 256: resid_ln_launch<GemmTile<64, 256, 1, 4, 3>>(m_max, m_dev, K, A, w, bias, x, rows, xh, hrows, s); break;
-    case 384: resid_ln_launch<GemmTile<64, 384, 1, 4, 2>>(m_max, m_dev, K, A, w, bias, x, rows, xh, hrows, s); break;
+    case 384: resid_ln_launch<GemmTile<64, 384, 2, 4, 2>>(m_max, m_dev, K, A, w, bias, x, rows, xh, hrows, s); break;
     default: break;  // rejected by the caller (resid_ln_supported)
   }
 }
