@@ -92,49 +92,68 @@ void launch_zero_f32(float* p, int n, hipStream_t s) {
 // ------------------------------------------------------------------------------------------
 // LayerNorm rows: out[r] = LN(x[rows[r]]) (r < *nrows, compact output) or LN(x[r]) (r <
 // nrows_max, only rows whose window has queries when wcount is given; output at row r), in
-// bf16, and amax |out| of the call into *slot.  One wavefront per row, FP32 statistics
-// (mean, then the centred sum of squares; biased variance, eps 1e-5).
+// bf16, and amax |out| of the call into *slot.  Sixteen lanes per row, four rows per
+// wavefront; lane j of a row holds columns 4 (j + 16 e) .. +3 (16-byte loads).  FP32
+// statistics (mean, then the centred sum of squares; biased variance, eps 1e-5).
 // ------------------------------------------------------------------------------------------
-constexpr int LNR_PER_MAX = 16;  // C <= 1024
+constexpr int LNR_PER_MAX = 16;  // float4 groups per lane: C <= 1024
+
+__device__ __forceinline__ float sum16(float v) {
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 4, 64);
+  v += __shfl_xor(v, 8, 64);
+  return v;
+}
 
 __global__ void __launch_bounds__(256) ln_rows_amax_kernel(const float* __restrict__ x, const int32_t* __restrict__ rows,
                                                            const int32_t* __restrict__ nrows_dev, int nrows_max,
                                                            const int32_t* __restrict__ wcount, int S, int C,
                                                            const float* __restrict__ g, const float* __restrict__ b,
                                                            bf16* __restrict__ out, float* slot) {
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, j = lane & 15;
   const int nrows = nrows_dev ? nrows_dev[0] : nrows_max;
   const int per = C / 64;
   float mx = 0.f;
-  for (int r = blockIdx.x * 4 + (threadIdx.x >> 6); r < nrows; r += gridDim.x * 4) {
-    if (wcount && wcount[r / S] == 0) continue;
-    const float* xr = x + (size_t)(rows ? rows[r] : r) * C;
-    float v[LNR_PER_MAX];
+  // the loop bound is uniform per wavefront: 16-lane shuffles stay inside the wavefront
+  for (int r0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 4; r0 < nrows; r0 += gridDim.x * 16) {
+    const int r = r0 + (lane >> 4);
+    bool ok = r < nrows;
+    if (ok && wcount) ok = wcount[r / S] > 0;
+    const float* xr = x + (size_t)(ok ? (rows ? rows[r] : r) : 0) * C;
+    float4 v[LNR_PER_MAX];
     float s = 0.f;
 #pragma unroll
     for (int e = 0; e < LNR_PER_MAX; ++e)
       if (e < per) {
-        v[e] = xr[lane + 64 * e];
-        s += v[e];
+        v[e] = ok ? *reinterpret_cast<const float4*>(xr + 4 * (j + 16 * e)) : make_float4(0.f, 0.f, 0.f, 0.f);
+        s += (v[e].x + v[e].y) + (v[e].z + v[e].w);
       }
-    const float mean = wave_sum(s) / C;
+    const float mean = sum16(s) / C;
     float q = 0.f;
 #pragma unroll
     for (int e = 0; e < LNR_PER_MAX; ++e)
       if (e < per) {
-        const float d = v[e] - mean;
-        q += d * d;
+        const float d0 = v[e].x - mean, d1 = v[e].y - mean, d2 = v[e].z - mean, d3 = v[e].w - mean;
+        q += (d0 * d0 + d1 * d1) + (d2 * d2 + d3 * d3);
       }
-    const float rstd = rsqrtf(wave_sum(q) / C + 1e-5f);
-    bf16* orow = out + (size_t)r * C;
+    const float rstd = rsqrtf(sum16(q) / C + 1e-5f);
+    if (ok) {
+      bf16* orow = out + (size_t)r * C;
 #pragma unroll
-    for (int e = 0; e < LNR_PER_MAX; ++e)
-      if (e < per) {
-        const int c = lane + 64 * e;
-        const float y = (v[e] - mean) * rstd * g[c] + b[c];
-        orow[c] = f2bf(y);
-        mx = fmaxf(mx, fabsf(y));
-      }
+      for (int e = 0; e < LNR_PER_MAX; ++e)
+        if (e < per) {
+          const int c = 4 * (j + 16 * e);
+          const float4 g4 = *reinterpret_cast<const float4*>(g + c), b4 = *reinterpret_cast<const float4*>(b + c);
+          const float y0 = (v[e].x - mean) * rstd * g4.x + b4.x, y1 = (v[e].y - mean) * rstd * g4.y + b4.y;
+          const float y2 = (v[e].z - mean) * rstd * g4.z + b4.z, y3 = (v[e].w - mean) * rstd * g4.w + b4.w;
+          uint2 pk;
+          pk.x = pack_bf2(y0, y1);
+          pk.y = pack_bf2(y2, y3);
+          *reinterpret_cast<uint2*>(orow + c) = pk;
+          mx = fmaxf(mx, fmaxf(fmaxf(fabsf(y0), fabsf(y1)), fmaxf(fabsf(y2), fabsf(y3))));
+        }
+    }
   }
   // one atomic per block
   __shared__ float wred[4];
@@ -151,7 +170,7 @@ void launch_ln_rows_amax(const float* x, const int32_t* rows, const int32_t* nro
                          const int32_t* wcount, int S, int C, const float* g, const float* b, bf16* out, float* slot,
                          hipStream_t s) {
   if (nrows_max <= 0) return;
-  int grid = (nrows_max + 3) / 4;
+  int grid = (nrows_max + 15) / 16;
   if (grid > 4096) grid = 4096;
   ln_rows_amax_kernel<<<grid, 256, 0, s>>>(x, rows, nrows_dev, nrows_max, wcount, S, C, g, b, out, slot);
 }
