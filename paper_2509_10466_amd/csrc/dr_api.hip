@@ -665,7 +665,7 @@ static dr_status run_blocks(dr_ctx* c, const Geo& g, dr_precision prec, hipStrea
     } else if (prec == DR_FP8) {
       float* am = w.amax + 4 * l;  // [0] LN1 out, [1] O, [2] LN2 out, [3] h
       LAUNCH(ST_LN1, launch_ln_rows_amax(w.x, nullptr, nullptr, N, w.wcount, g.S, C, b.ln1g, b.ln1b, w.u16, am + 0, s));
-      LAUNCH(ST_QKV, launch_qkv_fp8(g, C, n.cfg.heads, n.Spad, attn_clip_vt_stride(n.Spad), w.u16, w.flag, w.wcount, b.wqkv8, b.wscale8, b.bqkv, am + 0, (float)(1.4426950408889634 / std::sqrt((double)n.dh)), w.q16, w.k16, w.vt16, s));
+      LAUNCH(ST_QKV, launch_qkv_fp8(g, C, n.cfg.heads, n.Spad, attn_clip_vt_stride(n.Spad), w.u16, w.tiles, w.ntiles, b.wqkv8, b.wscale8, b.bqkv, am + 0, (float)(1.4426950408889634 / std::sqrt((double)n.dh)), w.q16, w.k16, w.vt16, s));
       LAUNCH(ST_ATTN, launch_attn_clip(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.vt16, w.idx, w.woff, w.worder, w.o16, am + 1, s));
       LAUNCH(ST_PROJ, launch_gemm_fp8_resid(w.o16, w.nq, N, C, b.wo8, b.so8, am + 1, b.bo, C, w.x, w.idx, s));
       LAUNCH(ST_LN2, launch_ln_rows_amax(w.x, w.idx, w.nq, N, nullptr, g.S, C, b.ln2g, b.ln2b, w.u16, am + 2, s));

@@ -238,9 +238,9 @@ void launch_ln_rows_amax(const float* x, const int32_t* rows, const int32_t* nro
                          const int32_t* wcount, int S, int C, const float* g, const float* b, bf16* out,
                          float* slot, hipStream_t s);
 // Q/K/V from the LayerNorm rows u [N][C]: q [N][C] (times qscale), k [win][head][Spad][dh],
-// vt [win][head][dh][spv]
-void launch_qkv_fp8(const Geo& g, int C, int heads, int Spad, int spv, const bf16* u, const uint8_t* flag,
-                    const int32_t* wcount, const uint8_t* w, const float* wscale, const float* bias,
+// vt [win][head][dh][spv]; row tiles from the lists of launch_window_order
+void launch_qkv_fp8(const Geo& g, int C, int heads, int Spad, int spv, const bf16* u, const int32_t* tiles,
+                    const int32_t* ntiles, const uint8_t* w, const float* wscale, const float* bias,
                     const float* amax_u, float qscale, bf16* q, bf16* k, bf16* vt, hipStream_t s);
 // first MLP linear + GELU over compact rows u [*m_dev][C] -> h [.][R], amax of h
 void launch_fc1_fp8(int m_max, const int32_t* m_dev, int C, int R, const bf16* u, const uint8_t* w, float s_w,

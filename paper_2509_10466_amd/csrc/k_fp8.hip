@@ -179,8 +179,9 @@ void launch_ln_rows_amax(const float* x, const int32_t* rows, const int32_t* nro
 // FP8 GEMM over bf16 rows: Y[m, n] = s_a (e4m3(A/s_a) . e4m3(W)^T)[m, n], handed with s_a to
 // an epilogue (which applies s_w, the bias and the destination).  256 threads = 2 x 2 waves,
 // tile 64 x 128, 128-wide k stages, A converted bf16 -> e4m3 while it is staged into LDS.
-// Rows: M = *m_dev when given, else m_host.  A tile runs only if epi.need(m, n0) holds for
-// one of its rows.
+// Rows: M = *m_dev when given, else m_host.  Without a tile list a tile runs only if
+// epi.need(m, n0) holds for one of its rows; with one (Q/K/V), block x takes row tile
+// tiles[list * mt + x] of list epi.list(n0) (lists built with the window order, ROW_TILE rows).
 // ------------------------------------------------------------------------------------------
 constexpr int F8_BK = 128;          // fp8 elements per stage = one MFMA k step
 constexpr int F8_WST = F8_BK + 16;  // stage row stride in bytes
@@ -189,13 +190,21 @@ constexpr int G8_BM = 64, G8_BN = 128;
 template <class Epi>
 __global__ void __launch_bounds__(256) gemm_fp8_kernel(const bf16* __restrict__ A, const int32_t* __restrict__ m_dev,
                                                        int m_host, int K, const uint8_t* __restrict__ W,
-                                                       const float* __restrict__ amax_a, Epi epi) {
+                                                       const float* __restrict__ amax_a,
+                                                       const int32_t* __restrict__ tiles,
+                                                       const int32_t* __restrict__ ntiles, Epi epi) {
+  static_assert(G8_BM == ROW_TILE, "row tiles are listed in ROW_TILE units");
   __shared__ __align__(16) uint8_t As[2][G8_BM][F8_WST];
   __shared__ __align__(16) uint8_t Ws[2][G8_BN][F8_WST];
   const int M = m_dev ? m_dev[0] : m_host;
-  const int m0 = blockIdx.x * G8_BM, n0 = blockIdx.y * G8_BN;
-  if (m0 >= M) return;
-  {
+  const int n0 = blockIdx.y * G8_BN;
+  int m0 = blockIdx.x * G8_BM;
+  if (tiles) {
+    const int l = epi.list(n0);
+    if ((int)blockIdx.x >= ntiles[l]) return;
+    m0 = tiles[l * ((m_host + G8_BM - 1) / G8_BM) + blockIdx.x] * G8_BM;
+  } else {
+    if (m0 >= M) return;
     int nd = 0;
     if ((int)threadIdx.x < G8_BM && m0 + (int)threadIdx.x < M) nd = epi.need(m0 + threadIdx.x, n0);
     if (!__syncthreads_or(nd)) return;
@@ -283,10 +292,11 @@ __global__ void __launch_bounds__(256) gemm_fp8_kernel(const bf16* __restrict__ 
 
 template <class Epi>
 static void gemm_fp8_launch(const bf16* A, const int32_t* m_dev, int m_max, int K, int Nout, const uint8_t* W,
-                            const float* amax_a, const Epi& epi, hipStream_t s) {
+                            const float* amax_a, const Epi& epi, hipStream_t s, const int32_t* tiles = nullptr,
+                            const int32_t* ntiles = nullptr) {
   if (m_max <= 0) return;
   dim3 grid((m_max + G8_BM - 1) / G8_BM, Nout / G8_BN);
-  gemm_fp8_kernel<Epi><<<grid, 256, 0, s>>>(A, m_dev, m_max, K, W, amax_a, epi);
+  gemm_fp8_kernel<Epi><<<grid, 256, 0, s>>>(A, m_dev, m_max, K, W, amax_a, tiles, ntiles, epi);
 }
 
 // x[res_rows[m], n] += s_a s_w Y + bias[n]
@@ -297,6 +307,7 @@ struct F8ResidEpi {
   const int32_t* res_rows;
   int Nout;
   __device__ __forceinline__ int need(int, int) const { return 1; }
+  __device__ __forceinline__ int list(int) const { return 0; }
   __device__ __forceinline__ void operator()(int m, int n, const f32x4_t& a, float sa) const {
     const float sc = sa * s_w;
     const float4 b4 = *reinterpret_cast<const float4*>(bias + n);
@@ -319,17 +330,16 @@ void launch_gemm_fp8_resid(const bf16* A, const int32_t* m_dev, int m_max, int K
 
 // Q rows [N][C] multiplied by qscale (log2(e)/sqrt(dh): the attention kernel takes Q scaled
 // for base-2 exponentials), K [win][head][Spad][dh], V transposed [win][head][dh][spv] -- the
-// layouts of the BF16 path, so both precisions share one attention kernel.  Q tiles run for
-// rows with a query, K/V tiles for rows in windows with queries.
+// layouts of the BF16 path, so both precisions share one attention kernel.  Q tiles run over
+// the listed row tiles with a query, K/V tiles over those touching a window with queries.
 struct F8QkvEpi {
   const float* bias;
   const float* wscale;  // [0] s_q, [1] s_k, [2] s_v
-  const uint8_t* flag;
-  const int32_t* wcount;
   float qscale;
   bf16 *q, *k, *vt;
   int C, dh, heads, Spad, S, spv;
-  __device__ __forceinline__ int need(int m, int n0) const { return n0 < C ? flag[m] != 0 : wcount[m / S] > 0; }
+  __device__ __forceinline__ int need(int, int) const { return 1; }
+  __device__ __forceinline__ int list(int n0) const { return n0 < C ? 0 : 1; }
   __device__ __forceinline__ void operator()(int m, int n, const f32x4_t& a, float sa) const {
     const int part = n < C ? 0 : (n < 2 * C ? 1 : 2);
     const float sc = sa * wscale[part];
@@ -360,11 +370,11 @@ struct F8QkvEpi {
   __device__ __forceinline__ void finish() const {}
 };
 
-void launch_qkv_fp8(const Geo& g, int C, int heads, int Spad, int spv, const bf16* u, const uint8_t* flag,
-                    const int32_t* wcount, const uint8_t* w, const float* wscale, const float* bias,
+void launch_qkv_fp8(const Geo& g, int C, int heads, int Spad, int spv, const bf16* u, const int32_t* tiles,
+                    const int32_t* ntiles, const uint8_t* w, const float* wscale, const float* bias,
                     const float* amax_u, float qscale, bf16* q, bf16* k, bf16* vt, hipStream_t s) {
-  const F8QkvEpi epi{bias, wscale, flag, wcount, qscale, q, k, vt, C, C / heads, heads, Spad, g.S, spv};
-  gemm_fp8_launch(u, nullptr, g.N, C, 3 * C, w, amax_u, epi, s);
+  const F8QkvEpi epi{bias, wscale, qscale, q, k, vt, C, C / heads, heads, Spad, g.S, spv};
+  gemm_fp8_launch(u, nullptr, g.N, C, 3 * C, w, amax_u, epi, s, tiles, ntiles);
 }
 
 // h = GELU(s_a s_w Y + b1) in bf16, amax |h| of the call into *amax_h (one atomic per wave)
@@ -376,6 +386,7 @@ struct F8GeluEpi {
   int R;
   float mx;
   __device__ __forceinline__ int need(int, int) const { return 1; }
+  __device__ __forceinline__ int list(int) const { return 0; }
   __device__ __forceinline__ void operator()(int m, int n, const f32x4_t& a, float sa) {
     const float sc = sa * s_w;
     const float4 b4 = *reinterpret_cast<const float4*>(bias + n);
