@@ -127,11 +127,14 @@ dr_status dr_profile_read(dr_ctx* ctx, double* ms, int64_t* count, int nstage);
 const char* dr_stage_name(int stage);
 
 /* Inspection, for tests: copy the first `nbytes` of the named workspace buffer into device
- * memory `dst` on `stream`.  Names: "x" (f32 residual [N,C], window-major), "u16", "q16",
- * "o16" (bf16 [N,C]), "k16", "v16" (bf16 [win][head][Spad][dh]),
- * "h16" (bf16 [N,rC]), "u", "q", "o" (f32 [N,C]), "kv" (f32 [N,2C]), "h" (f32 [N,rC]),
- * "flag" (u8 [N]), "idx" (int32 [N]), "nq" (int32).  DR_EINVAL for an unknown name or a
- * size beyond the buffer. */
+ * memory `dst` on `stream`.  Names: "x" (f32 residual [N,C], window-major; BF16 path: rows
+ * of flagged tokens), "xh", "u16", "q16", "o16" (bf16 [N,C]), "k16" (bf16
+ * [win][head][Spad][dh]), "vt16" (bf16 [win][head][dh][spv]), "h16" (bf16 [N,rC]), "u", "q",
+ * "o" (f32 [N,C]), "kv" (f32 [N,2C]), "h" (f32 [N,rC]), "flag" (u8 [N]), "idx" (int32 [N]),
+ * "nq" (int32), "wcount" (int32 [win]), "worder" (int32 [win]: windows by decreasing query
+ * count), "tiles" (int32 [2][ceil(N/64)]: row tiles of 64 tokens with a flagged token, then
+ * row tiles touching a window with queries, each list in any order), "ntiles" (int32 [2]).
+ * DR_EINVAL for an unknown name or a size beyond the buffer. */
 dr_status dr_inspect(dr_ctx* ctx, const char* name, void* dst, size_t nbytes, void* stream);
 
 /* Inspection, for tests: key "blocks" = number of transformer blocks later dr_inpaint calls

@@ -820,7 +820,9 @@ extern "C" dr_status dr_inspect(dr_ctx* c, const char* name, void* dst, size_t n
       {"vt16", w.vt16, w.cap_windows * c->net.cfg.heads * (size_t)c->net.dh * attn_clip_vt_stride(c->net.Spad) * 2}, {"o16", w.o16, N * C * 2},
       {"h16", w.h16, N * R * 2},   {"u", w.u, N * C * 4},     {"kv", w.kv, N * 2 * C * 4},
       {"q", w.q, N * C * 4},       {"o", w.o, N * C * 4},     {"h", w.h, N * R * 4},
-      {"flag", w.flag, N},         {"idx", w.idx, N * 4},     {"nq", w.nq, 4}};
+      {"flag", w.flag, N},         {"idx", w.idx, N * 4},     {"nq", w.nq, 4},
+      {"wcount", w.wcount, w.cap_windows * 4},                  {"worder", w.worder, w.cap_windows * 4},
+      {"tiles", w.tiles, 2 * ((N + ROW_TILE - 1) / ROW_TILE) * 4}, {"ntiles", w.ntiles, 8}};
   for (const Buf& b : bufs) {
     if (std::strcmp(b.n, name) == 0) {
       if (!b.p) return fail(c, DR_EINVAL, "dr_inspect: no workspace yet");

@@ -222,3 +222,41 @@ def test_graph_replay_equals_direct_launches(dev, precision):
         _ = torch.ones(1000, device="cuda").sum().item()  # unrelated eager work + sync
         assert np.array_equal(run(eng, fb, mb, precision), rb), ("b", rep)
     eng.close()
+
+
+# ------------------------------------------------------------------------------------------
+# work lists of the token step: windows by decreasing query count, Q/K/V row tiles
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["tiny64", "mid", "mid_b2", "clip240"])
+@pytest.mark.parametrize("qs", ["masked", "all"])
+def test_work_lists_exact(dev, case, qs):
+    """The window order is a permutation with non-increasing query counts; the row-tile lists
+    hold exactly the 64-token tiles with a flagged token (Q) and the tiles touching a window
+    with queries (K/V).  Integer work: compared exactly (the lists' order is free)."""
+    cfg, frames, masks = case_inputs(case)
+    _say(f"[work-lists] case={case} qs={qs} shape={masks.shape}")
+    eng, _ = engine(cfg)
+    run(eng, frames, masks, "bf16", qs)
+    rf, _, rw = on.gather_lists(masks, cfg, qs)
+    N = rf.size
+    nwin = rw.size - 1
+    S = N // nwin
+    wcount = np.diff(rw)
+
+    def ints(name, n):
+        return eng.inspect(name, 4 * n).view(torch.int32).cpu().numpy()
+
+    assert np.array_equal(ints("wcount", nwin), wcount)
+    order = ints("worder", nwin)
+    assert np.array_equal(np.sort(order), np.arange(nwin))
+    assert np.all(np.diff(wcount[order]) <= 0)
+    mt = (N + 63) // 64
+    tiles = ints("tiles", 2 * mt)
+    nq_t, nkv_t = ints("ntiles", 2)
+    flags = rf != 0
+    q_ref = {t for t in range(mt) if flags[64 * t:64 * t + 64].any()}
+    kv_ref = {t for t in range(mt)
+              if any(wcount[w] > 0 for w in range(64 * t // S, (min(N, 64 * t + 64) - 1) // S + 1))}
+    assert nq_t == len(q_ref) and nkv_t == len(kv_ref)
+    assert sorted(tiles[:nq_t].tolist()) == sorted(q_ref)
+    assert sorted(tiles[mt:mt + nkv_t].tolist()) == sorted(kv_ref)
