@@ -12,6 +12,8 @@ Contents
              blocks, final LN, transposed-conv decoder, composite.
 ``grad``     the training loss and its analytic FP64 gradient (reverse mode, by hand).
 ``stream``   stream mode: one new frame per call against cached K/V of past frames.
+``prepost``  camera-resolution pre/post-processing: BGRA -> RGB, union + dilation of the
+             selected instance masks, 2x downscale, nearest 2x upscale, u8 composite.
 
 Parity status: every function is pinned by the ``-m "not gpu"`` tests (library routines,
 brute force, closed forms, invariants, finite differences).  The paper prints no worked
