@@ -175,6 +175,33 @@ dr_status dr_stream_step(dr_ctx* ctx, int n, const int32_t* sids, const float* c
                          const uint8_t* const* masks, float* const* outs, dr_precision prec,
                          dr_query_set qs, void* stream);
 
+/* ---- Camera-resolution pre/post-processing ----------------------------------------------
+ * The thesis runs its models at half the camera resolution and scales their outputs by 2
+ * (Methods, "Performance Optimisations -- Upscaling"); the server cuts the masks of the
+ * objects the user selected out of the camera frame (Methods, "Object Control").  These two
+ * calls put the steps around the network on the GPU.  Asynchronous on `stream`. */
+
+/* Camera frame -> network input at half resolution.
+ *   bgra:      device u8 [H,W,4] (B, G, R, alpha), 8-byte aligned.
+ *   inst:      device u8 [K,H,W] per-object instance masks (nonzero = object), K in 0..32
+ *              (may be NULL when K == 0); bit k of `select` selects instance k.
+ *   radius:    dilation of the union by a square (2r+1)^2 window, 0..16; pixels outside the
+ *              frame do not contribute.
+ * Outputs (device, caller-owned): mask_full u8 [H,W] (1 = private: the selected union,
+ * dilated), mask_low u8 [H/2,W/2] (1 where any pixel of the 2x2 block is private),
+ * frame_low f32 [H/2,W/2,3] (RGB mean of the 2x2 block / 255).  DR_ESHAPE unless H and W are
+ * even; DR_EINVAL for null pointers, K or radius out of range, a misaligned bgra. */
+dr_status dr_prep_frame(dr_ctx* ctx, const uint8_t* bgra, const uint8_t* inst, int K, uint32_t select,
+                        int radius, int H, int W, float* frame_low, uint8_t* mask_low, uint8_t* mask_full,
+                        void* stream);
+/* Half-resolution prediction -> camera frame: out[y][x] = mask_full[y][x] ? B, G, R of
+ * pred_low[y/2][x/2] (nearest 2x upscale) as clamp(rint(255 v), 0, 255) with alpha kept :
+ * bgra[y][x] unchanged.  bgra, out: device u8 [H,W,4], 16-byte aligned (out == bgra allowed,
+ * other overlaps DR_EINVAL); pred_low f32 [H/2,W/2,3]; mask_full u8 [H,W], 4-byte aligned.
+ * DR_ESHAPE unless H is even and W % 4 == 0. */
+dr_status dr_post_frame(dr_ctx* ctx, const uint8_t* bgra, const float* pred_low, const uint8_t* mask_full,
+                        int H, int W, uint8_t* out, void* stream);
+
 /* ---- Serving loop ---------------------------------------------------------------------
  * A persistent native thread that batches submitted requests continuously: per resolution
  * class it launches the oldest pending requests (at most one per stream, up to max_batch)

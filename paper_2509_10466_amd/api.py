@@ -89,6 +89,46 @@ class Inpainter:
         n = int(nq.item())
         return flag, idx[:n], woff
 
+    def prep_frame(self, bgra: torch.Tensor, instances: torch.Tensor | None = None, select: int = 0xFFFFFFFF,
+                   radius: int = 0, stream=None):
+        """Camera frame u8 BGRA [H,W,4] and instance masks u8 [K,H,W] -> (frame_low f32
+        [H/2,W/2,3], mask_low u8 [H/2,W/2], mask_full u8 [H,W]); bit k of ``select`` picks
+        instance k, the union is dilated by a (2 radius + 1)^2 square."""
+        if not bgra.is_cuda or bgra.dtype != torch.uint8 or bgra.dim() != 3 or bgra.shape[2] != 4 \
+                or not bgra.is_contiguous():
+            raise ValueError("bgra must be a contiguous uint8 device tensor [H,W,4]")
+        H, W, _ = bgra.shape
+        K = 0
+        if instances is not None:
+            if instances.dtype != torch.uint8 or instances.dim() != 3 or tuple(instances.shape[1:]) != (H, W) \
+                    or not instances.is_contiguous() or instances.device != bgra.device:
+                raise ValueError("instances must be a contiguous uint8 tensor [K,H,W] on the frame's device")
+            K = instances.shape[0]
+        dev = bgra.device
+        frame_low = torch.empty((H // 2, W // 2, 3), dtype=torch.float32, device=dev)
+        mask_low = torch.empty((H // 2, W // 2), dtype=torch.uint8, device=dev)
+        mask_full = torch.empty((H, W), dtype=torch.uint8, device=dev)
+        st = self.lib.dr_prep_frame(self._ctx, _ptr(bgra), _ptr(instances) if K else None, K, select & 0xFFFFFFFF,
+                                    radius, H, W, _ptr(frame_low), _ptr(mask_low), _ptr(mask_full), _stream(stream))
+        _lib.check(self.lib, self._ctx, st)
+        return frame_low, mask_low, mask_full
+
+    def post_frame(self, bgra: torch.Tensor, pred_low: torch.Tensor, mask_full: torch.Tensor,
+                   out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Composite the half-resolution prediction f32 [H/2,W/2,3] into the camera frame
+        (u8 BGRA [H,W,4]) where ``mask_full`` is set; other pixels are copied."""
+        H, W, _ = bgra.shape
+        for t, dt, shape in ((bgra, torch.uint8, (H, W, 4)), (pred_low, torch.float32, (H // 2, W // 2, 3)),
+                             (mask_full, torch.uint8, (H, W))):
+            if not t.is_cuda or t.dtype != dt or tuple(t.shape) != shape or not t.is_contiguous():
+                raise ValueError(f"expected a contiguous {dt} device tensor {shape}")
+        if out is None:
+            out = torch.empty_like(bgra)
+        st = self.lib.dr_post_frame(self._ctx, _ptr(bgra), _ptr(pred_low), _ptr(mask_full), H, W, _ptr(out),
+                                    _stream(stream))
+        _lib.check(self.lib, self._ctx, st)
+        return out
+
     def inspect(self, name: str, nbytes: int, stream=None) -> torch.Tensor:
         """Copy of the first ``nbytes`` of a named workspace buffer (uint8 device tensor)."""
         dst = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{self.device}")
