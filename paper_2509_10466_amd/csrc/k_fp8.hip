@@ -185,53 +185,71 @@ void launch_ln_rows_amax(const float* x, const int32_t* rows, const int32_t* nro
 // ------------------------------------------------------------------------------------------
 constexpr int F8_BK = 128;          // fp8 elements per stage = one MFMA k step
 constexpr int F8_WST = F8_BK + 16;  // stage row stride in bytes
-constexpr int G8_BM = 64, G8_BN = 128;
+// Tile: BM x BN outputs, WM x WN wavefronts (each TM x TN), two LDS stages of 128-wide k.
+template <int BM_, int BN_, int WM_, int WN_>
+struct F8Tile {
+  static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_;
+  static constexpr int THREADS = 64 * WM * WN;
+  static constexpr int TM = BM / WM, TN = BN / WN, FM = TM / 16, FN = TN / 16;
+  static constexpr int LA = BM * 16 / THREADS;  // 16-byte bf16 chunks of A per thread per stage
+  static constexpr int LW = BN * 8 / THREADS;   // 16-byte e4m3 chunks of W per thread per stage
+  static constexpr size_t LDS_BYTES = (size_t)2 * (BM + BN) * F8_WST;
+  static_assert(TM % 16 == 0 && TN % 16 == 0, "fragment multiples");
+  static_assert(BM * 16 % THREADS == 0 && BN * 8 % THREADS == 0, "whole chunks per thread");
+};
+using F8Small = F8Tile<64, 128, 2, 2>;  // 4 wavefronts; the Q/K/V row-tile lists use its 64 rows
+static_assert(F8Small::BM == ROW_TILE, "row tiles are listed in ROW_TILE units");
 
-template <class Epi>
-__global__ void __launch_bounds__(256) gemm_fp8_kernel(const bf16* __restrict__ A, const int32_t* __restrict__ m_dev,
-                                                       int m_host, int K, const uint8_t* __restrict__ W,
-                                                       const float* __restrict__ amax_a,
-                                                       const int32_t* __restrict__ tiles,
-                                                       const int32_t* __restrict__ ntiles, Epi epi) {
-  static_assert(G8_BM == ROW_TILE, "row tiles are listed in ROW_TILE units");
-  __shared__ __align__(16) uint8_t As[2][G8_BM][F8_WST];
-  __shared__ __align__(16) uint8_t Ws[2][G8_BN][F8_WST];
+template <class TL, class Epi>
+__global__ void __launch_bounds__(TL::THREADS) gemm_fp8_kernel(const bf16* __restrict__ A,
+                                                               const int32_t* __restrict__ m_dev, int m_host, int K,
+                                                               const uint8_t* __restrict__ W,
+                                                               const float* __restrict__ amax_a,
+                                                               const int32_t* __restrict__ tiles,
+                                                               const int32_t* __restrict__ ntiles, Epi epi) {
+  extern __shared__ __align__(16) uint8_t f8_lds[];
+  uint8_t(*As)[TL::BM][F8_WST] = reinterpret_cast<uint8_t(*)[TL::BM][F8_WST]>(f8_lds);
+  uint8_t(*Ws)[TL::BN][F8_WST] = reinterpret_cast<uint8_t(*)[TL::BN][F8_WST]>(f8_lds + 2 * TL::BM * F8_WST);
   const int M = m_dev ? m_dev[0] : m_host;
-  const int n0 = blockIdx.y * G8_BN;
-  int m0 = blockIdx.x * G8_BM;
-  if (tiles) {
+  const int n0 = blockIdx.y * TL::BN;
+  int m0 = blockIdx.x * TL::BM;
+  if (tiles) {  // (launched with F8Small only)
     const int l = epi.list(n0);
     if ((int)blockIdx.x >= ntiles[l]) return;
-    m0 = tiles[l * ((m_host + G8_BM - 1) / G8_BM) + blockIdx.x] * G8_BM;
+    m0 = tiles[l * ((m_host + TL::BM - 1) / TL::BM) + blockIdx.x] * TL::BM;
   } else {
     if (m0 >= M) return;
     int nd = 0;
-    if ((int)threadIdx.x < G8_BM && m0 + (int)threadIdx.x < M) nd = epi.need(m0 + threadIdx.x, n0);
+    if ((int)threadIdx.x < TL::BM && m0 + (int)threadIdx.x < M) nd = epi.need(m0 + threadIdx.x, n0);
     if (!__syncthreads_or(nd)) return;
   }
   const float sa = scale_of(amax_a);
   const float inv_sa = 1.0f / sa;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int wm = wv >> 1, wn = wv & 1;
+  const int wm = wv / TL::WN, wn = wv % TL::WN;
   const int l16 = lane & 15, kg = lane >> 4;
-  // A stage: 64 rows x 128 k = 1024 chunks of 8 bf16 -> 4 per thread; W stage: 128 rows x
-  // 128 B = 1024 chunks of 16 B -> 4 per thread
-  u32x4_t ra[4], rw[4];
+  // A stage: BM rows x 128 k = 16 chunks of 8 bf16 per row; W stage: BN rows x 128 B = 8
+  // chunks of 16 B per row
+  u32x4_t ra[TL::LA], rw[TL::LW];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int id = t + 256 * c;
+    for (int c = 0; c < TL::LA; ++c) {
+      const int id = t + TL::THREADS * c;
       const int row = id >> 4, col = (id & 15) * 8;
       const int m = m0 + row;
       ra[c] = m < M ? *reinterpret_cast<const u32x4_t*>(A + (size_t)m * K + k0 + col) : u32x4_t{0u, 0u, 0u, 0u};
+    }
+#pragma unroll
+    for (int c = 0; c < TL::LW; ++c) {
+      const int id = t + TL::THREADS * c;
       const int wr = id >> 3, wc = (id & 7) * 16;
       rw[c] = *reinterpret_cast<const u32x4_t*>(W + (size_t)(n0 + wr) * K + k0 + wc);
     }
   };
   auto stash = [&](int buf) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int id = t + 256 * c;
+    for (int c = 0; c < TL::LA; ++c) {
+      const int id = t + TL::THREADS * c;
       const int row = id >> 4, col = (id & 15) * 8;
       const uint32_t w4[4] = {ra[c].x, ra[c].y, ra[c].z, ra[c].w};
       uint32_t lo = 0, hi = 0;
@@ -240,15 +258,19 @@ __global__ void __launch_bounds__(256) gemm_fp8_kernel(const bf16* __restrict__ 
       hi = f32x2_to_fp8(bf2f(w4[2] & 0xffff) * inv_sa, bf2f(w4[2] >> 16) * inv_sa) |
            (f32x2_to_fp8(bf2f(w4[3] & 0xffff) * inv_sa, bf2f(w4[3] >> 16) * inv_sa) << 16);
       *reinterpret_cast<uint2*>(&As[buf][row][col]) = make_uint2(lo, hi);
+    }
+#pragma unroll
+    for (int c = 0; c < TL::LW; ++c) {
+      const int id = t + TL::THREADS * c;
       const int wr = id >> 3, wc = (id & 7) * 16;
       *reinterpret_cast<u32x4_t*>(&Ws[buf][wr][wc]) = rw[c];
     }
   };
-  f32x4_t acc[2][4];
+  f32x4_t acc[TL::FM][TL::FN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TL::FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < TL::FN; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   load(0);
   stash(0);
   __syncthreads();
@@ -256,24 +278,24 @@ __global__ void __launch_bounds__(256) gemm_fp8_kernel(const bf16* __restrict__ 
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
     if (kt + 1 < nk) load((kt + 1) * F8_BK);
-    i32x8_t af[2], wf[4];
+    i32x8_t af[TL::FM], wf[TL::FN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const uint8_t* p = &As[buf][wm * 32 + i * 16 + l16][kg * 32];
+    for (int i = 0; i < TL::FM; ++i) {
+      const uint8_t* p = &As[buf][wm * TL::TM + i * 16 + l16][kg * 32];
       const uint4 lo = *reinterpret_cast<const uint4*>(p), hi = *reinterpret_cast<const uint4*>(p + 16);
       af[i] = i32x8_t{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const uint8_t* p = &Ws[buf][wn * 64 + j * 16 + l16][kg * 32];
+    for (int j = 0; j < TL::FN; ++j) {
+      const uint8_t* p = &Ws[buf][wn * TL::TN + j * 16 + l16][kg * 32];
       const uint4 lo = *reinterpret_cast<const uint4*>(p), hi = *reinterpret_cast<const uint4*>(p + 16);
       wf[j] = i32x8_t{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
     }
     fp8_group_begin();
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TL::FM; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = mfma_fp8(wf[j], af[i], acc[i][j]);
+      for (int j = 0; j < TL::FN; ++j) acc[i][j] = mfma_fp8(wf[j], af[i], acc[i][j]);
     fp8_group_end();
     if (kt + 1 < nk) {
       stash(buf ^ 1);
@@ -281,23 +303,32 @@ __global__ void __launch_bounds__(256) gemm_fp8_kernel(const bf16* __restrict__ 
     }
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int m = m0 + wm * 32 + i * 16 + l16;
+  for (int i = 0; i < TL::FM; ++i) {
+    const int m = m0 + wm * TL::TM + i * 16 + l16;
     if (m >= M) continue;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) epi(m, n0 + wn * 64 + j * 16 + kg * 4, acc[i][j], sa);
+    for (int j = 0; j < TL::FN; ++j) epi(m, n0 + wn * TL::TN + j * 16 + kg * 4, acc[i][j], sa);
   }
   epi.finish();
 }
 
-template <class Epi>
+template <class TL, class Epi>
 static void gemm_fp8_launch(const bf16* A, const int32_t* m_dev, int m_max, int K, int Nout, const uint8_t* W,
                             const float* amax_a, const Epi& epi, hipStream_t s, const int32_t* tiles = nullptr,
                             const int32_t* ntiles = nullptr) {
   if (m_max <= 0) return;
-  dim3 grid((m_max + G8_BM - 1) / G8_BM, Nout / G8_BN);
-  gemm_fp8_kernel<Epi><<<grid, 256, 0, s>>>(A, m_dev, m_max, K, W, amax_a, tiles, ntiles, epi);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(gemm_fp8_kernel<TL, Epi>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)TL::LDS_BYTES);
+    attr = true;
+  }
+  dim3 grid((m_max + TL::BM - 1) / TL::BM, Nout / TL::BN);
+  gemm_fp8_kernel<TL, Epi><<<grid, TL::THREADS, TL::LDS_BYTES, s>>>(A, m_dev, m_max, K, W, amax_a, tiles, ntiles, epi);
 }
+
+// Row count from which the first MLP linear uses the 8-wavefront FP8 tile (as for BF16).
+constexpr int F8_BIG_M = 32768;
 
 // x[res_rows[m], n] += s_a s_w Y + bias[n]
 struct F8ResidEpi {
@@ -325,7 +356,8 @@ struct F8ResidEpi {
 void launch_gemm_fp8_resid(const bf16* A, const int32_t* m_dev, int m_max, int K, const uint8_t* W, float s_w,
                            const float* amax_a, const float* bias, int Nout, float* x, const int32_t* res_rows,
                            hipStream_t s) {
-  gemm_fp8_launch(A, m_dev, m_max, K, Nout, W, amax_a, F8ResidEpi{bias, s_w, x, res_rows, Nout}, s);
+  // (a 128 x 128 tile on 8 wavefronts measured slower here at 720p)
+  gemm_fp8_launch<F8Small>(A, m_dev, m_max, K, Nout, W, amax_a, F8ResidEpi{bias, s_w, x, res_rows, Nout}, s);
 }
 
 // Q rows [N][C] multiplied by qscale (log2(e)/sqrt(dh): the attention kernel takes Q scaled
@@ -374,7 +406,7 @@ void launch_qkv_fp8(const Geo& g, int C, int heads, int Spad, int spv, const bf1
                     const int32_t* ntiles, const uint8_t* w, const float* wscale, const float* bias,
                     const float* amax_u, float qscale, bf16* q, bf16* k, bf16* vt, hipStream_t s) {
   const F8QkvEpi epi{bias, wscale, qscale, q, k, vt, C, C / heads, heads, Spad, g.S, spv};
-  gemm_fp8_launch(u, nullptr, g.N, C, 3 * C, w, amax_u, epi, s, tiles, ntiles);
+  gemm_fp8_launch<F8Small>(u, nullptr, g.N, C, 3 * C, w, amax_u, epi, s, tiles, ntiles);
 }
 
 // h = GELU(s_a s_w Y + b1) in bf16, amax |h| of the call into *amax_h (one atomic per wave)
@@ -406,7 +438,11 @@ struct F8GeluEpi {
 
 void launch_fc1_fp8(int m_max, const int32_t* m_dev, int C, int R, const bf16* u, const uint8_t* w, float s_w,
                     const float* bias, const float* amax_u, bf16* h, float* amax_h, hipStream_t s) {
-  gemm_fp8_launch(u, m_dev, m_max, C, R, w, amax_u, F8GeluEpi{bias, s_w, h, amax_h, R, 0.f}, s);
+  const F8GeluEpi epi{bias, s_w, h, amax_h, R, 0.f};
+  if (m_max >= F8_BIG_M && R % 256 == 0)
+    gemm_fp8_launch<F8Tile<128, 256, 2, 4>>(u, m_dev, m_max, C, R, w, amax_u, epi, s);
+  else
+    gemm_fp8_launch<F8Small>(u, m_dev, m_max, C, R, w, amax_u, epi, s);
 }
 
 bool fp8_supported(int C, int R) { return C % 128 == 0 && R % 128 == 0 && C / 64 <= LNR_PER_MAX; }
