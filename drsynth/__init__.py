@@ -36,7 +36,9 @@ __all__ = [
 @dataclasses.dataclass(frozen=True)
 class NetCfg:
     """Network hyper-parameters.  ``dim`` = C, ``heads`` = h, ``blocks`` = L, ``mlp_ratio`` = r,
-    ``patch`` = p (conv kernel = stride), window = win_t x win_h x win_w tokens."""
+    ``patch`` = p (conv kernel = stride), window = win_t x win_h x win_w tokens.  ``attn``:
+    "joint" (every block attends over the whole window) or "decoupled" (even blocks attend
+    within one frame of the window, odd blocks across its frames at one token position)."""
     dim: int
     heads: int
     blocks: int
@@ -45,6 +47,7 @@ class NetCfg:
     win_h: int
     win_w: int
     win_t: int
+    attn: str = "joint"
 
     @property
     def head_dim(self) -> int:
@@ -59,6 +62,8 @@ NETS = {
     "tiny64": NetCfg(dim=64, heads=2, blocks=2, mlp_ratio=4, patch=4, win_h=8, win_w=8, win_t=1),
     "clip240": NetCfg(dim=256, heads=4, blocks=8, mlp_ratio=4, patch=4, win_h=5, win_w=9, win_t=5),
     "clip720": NetCfg(dim=384, heads=6, blocks=12, mlp_ratio=4, patch=4, win_h=6, win_w=10, win_t=5),
+    "clip240_dec": NetCfg(dim=256, heads=4, blocks=8, mlp_ratio=4, patch=4, win_h=5, win_w=9, win_t=5,
+                          attn="decoupled"),
 }
 
 # (net name, B, T, H, W) of each named workload.

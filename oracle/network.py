@@ -24,6 +24,9 @@ Readings taken where the description is silent (each is also the GPU path's defi
 * blocks: pre-LN, LayerNorm with biased variance and eps = 1e-5, affine.
 * attention: scale 1/sqrt(dh), head k owns channels [k*dh, (k+1)*dh), QKV biases, no
   dropout, no relative bias, no shifted windows; windows tile the token grid from (0, 0).
+* decoupled variant (``cfg.attn == "decoupled"``): even blocks attend within the per-frame
+  windows (win_h x win_w tokens), odd blocks across the win_t frames of a window at one
+  token position; everything else is the joint network.
 * MLP: Linear(C, rC) -> exact-erf GELU -> Linear(rC, C).
 * final LayerNorm before the decoder; decoder = ConvTranspose2d(C, 3, k=p, s=p) + sigmoid.
 * composite: a per-pixel select, out = pred where the mask is nonzero, else the input.
@@ -110,6 +113,46 @@ def from_windows(xw, cfg):
     return x.reshape(B, nT * wt, nH * wh, nW * ww, C)
 
 
+def to_frame_windows(x, cfg):
+    """[B, T, Ht, Wt, C] -> [B, T, nH, nW, wh*ww, C]: the spatial windows of one frame."""
+    B, T, Ht, Wt, C = x.shape
+    wh, ww = cfg.win_h, cfg.win_w
+    x = x.reshape(B, T, Ht // wh, wh, Wt // ww, ww, C).transpose(0, 1, 2, 4, 3, 5, 6)
+    return x.reshape(B, T, Ht // wh, Wt // ww, wh * ww, C)
+
+
+def from_frame_windows(xw, cfg):
+    """Inverse of ``to_frame_windows``."""
+    B, T, nH, nW, _, C = xw.shape
+    wh, ww = cfg.win_h, cfg.win_w
+    x = xw.reshape(B, T, nH, nW, wh, ww, C).transpose(0, 1, 2, 4, 3, 5, 6)
+    return x.reshape(B, T, nH * wh, nW * ww, C)
+
+
+def to_time_windows(x, cfg):
+    """[B, T, Ht, Wt, C] -> [B, T/wt, Ht, Wt, wt, C]: one token position across the win_t
+    frames of a window."""
+    B, T, Ht, Wt, C = x.shape
+    wt = cfg.win_t
+    return x.reshape(B, T // wt, wt, Ht, Wt, C).transpose(0, 1, 3, 4, 2, 5)
+
+
+def from_time_windows(xw, cfg):
+    """Inverse of ``to_time_windows``."""
+    B, nT, Ht, Wt, wt, C = xw.shape
+    return xw.transpose(0, 1, 4, 2, 3, 5).reshape(B, nT * wt, Ht, Wt, C)
+
+
+def block_attention_kind(l, cfg):
+    """"joint" for every block of a joint-attention network; for a decoupled one (DSTT-style,
+    Background, "Decoupled Spatial-Temporal Transformer") block l attends "spatial"-ly
+    (within one frame of its window) when l is even and "temporal"-ly (across the window's
+    frames at one token position) when l is odd."""
+    if getattr(cfg, "attn", "joint") == "joint":
+        return "joint"
+    return "spatial" if l % 2 == 0 else "temporal"
+
+
 def softmax(s):
     """Row softmax over the last axis (the row max is subtracted first; this changes no
     value in exact arithmetic)."""
@@ -156,9 +199,11 @@ def block(x, upd, W, l, cfg, trace=None):
     q = linear(u, _w(W, p + "wq"), _w(W, p + "bq"))
     k = linear(u, _w(W, p + "wk"), _w(W, p + "bk"))
     v = linear(u, _w(W, p + "wv"), _w(W, p + "bv"))
-    o_w, probs = multi_head_attention(to_windows(q, cfg), to_windows(k, cfg),
-                                      to_windows(v, cfg), cfg.heads)
-    o = from_windows(o_w, cfg)
+    kind = block_attention_kind(l, cfg)
+    to, back = {"joint": (to_windows, from_windows), "spatial": (to_frame_windows, from_frame_windows),
+                "temporal": (to_time_windows, from_time_windows)}[kind]
+    o_w, probs = multi_head_attention(to(q, cfg), to(k, cfg), to(v, cfg), cfg.heads)
+    o = back(o_w, cfg)
     x1 = x + linear(o, _w(W, p + "wo"), _w(W, p + "bo"))
     h = linear(layer_norm(x1, _w(W, p + "ln2.g"), _w(W, p + "ln2.b")), _w(W, p + "w1"),
                _w(W, p + "b1"))
