@@ -175,6 +175,15 @@ dr_status dr_stream_step(dr_ctx* ctx, int n, const int32_t* sids, const float* c
                          const uint8_t* const* masks, float* const* outs, dr_precision prec,
                          dr_query_set qs, void* stream);
 
+/* Attention pattern of the network (a context setting; the weights are the same):
+ * 0 (default) every block attends over its whole window; 1 decoupled, in the manner of the
+ * DSTT network the thesis builds on (Background, "Decoupled Spatial-Temporal Transformer"):
+ * even blocks attend within one frame of the window, odd blocks across the window's frames
+ * at one token position.  Pattern 1 runs on the BF16 and FP8 paths of dr_inpaint (FP32,
+ * stream mode and training return DR_EINVAL) with at most 8 frames per window.  Waits for the
+ * device when the pattern changes. */
+dr_status dr_set_attention_pattern(dr_ctx* ctx, int pattern);
+
 /* ---- Camera-resolution pre/post-processing ----------------------------------------------
  * The thesis runs its models at half the camera resolution and scales their outputs by 2
  * (Methods, "Performance Optimisations -- Upscaling"); the server cuts the masks of the

@@ -39,7 +39,15 @@ class Inpainter:
         blob = wblob.pack(cfg, weights)
         buf = ct.create_string_buffer(blob, len(blob))
         _lib.check(self.lib, self._ctx, self.lib.dr_load_weights(self._ctx, buf, len(blob)))
+        if getattr(cfg, "attn", "joint") == "decoupled":
+            self.set_attention("decoupled")
         self.stages = _lib.stage_names(self.lib)
+
+    def set_attention(self, pattern: str):
+        """"joint" (every block over its whole window) or "decoupled" (even blocks within a
+        frame of the window, odd blocks across its frames at one position)."""
+        code = {"joint": 0, "decoupled": 1}[pattern]
+        _lib.check(self.lib, self._ctx, self.lib.dr_set_attention_pattern(self._ctx, code))
 
     # ------------------------------------------------------------------------------------
     def _check_inputs(self, frames, masks):

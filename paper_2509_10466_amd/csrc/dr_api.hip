@@ -146,6 +146,9 @@ void dr::dr_free_work(Work& w) {
   w = Work();
 }
 
+// attention mode of block l (see launch_attn_clip)
+static int attn_mode(const dr_ctx* c, int l) { return c->attn_pattern == 0 ? 0 : (l % 2 == 0 ? 1 : 2); }
+
 static void invalidate_graphs(dr_ctx* c) {
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   c->graphs.clear();
@@ -666,7 +669,7 @@ static dr_status run_blocks(dr_ctx* c, const Geo& g, dr_precision prec, hipStrea
       float* am = w.amax + 4 * l;  // [0] LN1 out, [1] O, [2] LN2 out, [3] h
       LAUNCH(ST_LN1, launch_ln_rows_amax(w.x, nullptr, nullptr, N, w.wcount, g.S, C, b.ln1g, b.ln1b, w.u16, am + 0, s));
       LAUNCH(ST_QKV, launch_qkv_fp8(g, C, n.cfg.heads, n.Spad, attn_clip_vt_stride(n.Spad), w.u16, w.tiles, w.ntiles, b.wqkv8, b.wscale8, b.bqkv, am + 0, (float)(1.4426950408889634 / std::sqrt((double)n.dh)), w.q16, w.k16, w.vt16, s));
-      LAUNCH(ST_ATTN, launch_attn_clip(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.vt16, w.idx, w.woff, w.worder, w.o16, am + 1, s));
+      LAUNCH(ST_ATTN, launch_attn_clip(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.vt16, w.idx, w.woff, w.worder, w.o16, am + 1, attn_mode(c, l), s));
       LAUNCH(ST_PROJ, launch_gemm_fp8_resid(w.o16, w.nq, N, C, b.wo8, b.so8, am + 1, b.bo, C, w.x, w.idx, s));
       LAUNCH(ST_LN2, launch_ln_rows_amax(w.x, w.idx, w.nq, N, nullptr, g.S, C, b.ln2g, b.ln2b, w.u16, am + 2, s));
       LAUNCH(ST_FC1, launch_fc1_fp8(N, w.nq, C, R, w.u16, b.w18, b.s18, b.b1, am + 2, w.h16, am + 3, s));
@@ -675,7 +678,7 @@ static dr_status run_blocks(dr_ctx* c, const Geo& g, dr_precision prec, hipStrea
       // x^ (normalised rows) feeds Q/K/V; the projection leaves x1^ of the query rows in u16
       // for the MLP; the second MLP linear refreshes x^ of the query rows
       LAUNCH(ST_QKV, launch_qkv_bf16(g, C, n.cfg.heads, n.Spad, attn_clip_vt_stride(n.Spad), w.xh, w.tiles, w.ntiles, b.wqkvf16, b.bqkvf, w.q16, w.k16, w.vt16, s));
-      LAUNCH(ST_ATTN, launch_attn_clip(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.vt16, w.idx, w.woff, w.worder, w.o16, nullptr, s));
+      LAUNCH(ST_ATTN, launch_attn_clip(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.vt16, w.idx, w.woff, w.worder, w.o16, nullptr, attn_mode(c, l), s));
       if (mlp_block_supported(C, R)) {
         LAUNCH(ST_MLP, launch_mlp_block_bf16(N, w.nq, C, w.o16, w.idx, b.wo16, b.bo, b.w1f16, b.b1f, b.w216, b.b2, w.x, w.xh, s));
       } else {
@@ -712,6 +715,8 @@ extern "C" dr_status dr_inpaint(dr_ctx* c, const float* frames, const uint8_t* m
     return fail(c, DR_ESHAPE, "the BF16 path needs dim 64, 128, 256 or 384 and patch 4");
   if (prec == DR_FP8 && !fp8_supported(n.C, n.R))
     return fail(c, DR_ESHAPE, "the FP8 path needs dim and hidden width multiples of 128");
+  if (prec == DR_FP32 && c->attn_pattern != 0)
+    return fail(c, DR_EINVAL, "decoupled attention runs on the BF16 and FP8 paths");
   const size_t npix = (size_t)B * T * H * W;
   if (out != frames && ranges_overlap(out, npix * 12, frames, npix * 12))
     return fail(c, DR_EINVAL, "out partially overlaps frames");
@@ -832,6 +837,19 @@ extern "C" dr_status dr_inspect(dr_ctx* c, const char* name, void* dst, size_t n
     }
   }
   return fail(c, DR_EINVAL, "dr_inspect: unknown buffer '%s'", name);
+}
+
+extern "C" dr_status dr_set_attention_pattern(dr_ctx* c, int pattern) {
+  if (!c) return DR_EINVAL;
+  if (pattern != 0 && pattern != 1) return fail(c, DR_EINVAL, "attention pattern %d (0 joint, 1 decoupled)", pattern);
+  if (pattern == 1 && c->net.cfg.win_t > 8) return fail(c, DR_EINVAL, "decoupled attention takes at most 8 frames per window");
+  if (c->attn_pattern != pattern) {
+    HIP_OK(c, hipSetDevice(c->device));
+    HIP_OK(c, hipDeviceSynchronize());
+    invalidate_graphs(c);  // captured block sequences hold the previous attention kernels
+    c->attn_pattern = pattern;
+  }
+  return DR_OK;
 }
 
 extern "C" dr_status dr_debug_set(dr_ctx* c, const char* key, int64_t value) {

@@ -165,6 +165,7 @@ struct dr_ctx {
   // profiling
   bool prof = false;
   int debug_blocks = -1;  // inspection: run only this many blocks (-1 = all)
+  int attn_pattern = 0;   // 0 joint window attention; 1 decoupled (even blocks spatial, odd temporal)
   struct Rec { int stage; hipEvent_t a, b; };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> event_pool;
@@ -261,10 +262,12 @@ void launch_qkv_bf16(const Geo& g, int C, int heads, int Spad, int spv, const bf
                      const int32_t* ntiles, const bf16* w, const float* bias, bf16* q, bf16* k, bf16* vt,
                      hipStream_t s);
 int attn_clip_vt_stride(int spad);
-// amax_o (nullable): max |O| of the call is max-reduced into *amax_o (FP8 path)
+// amax_o (nullable): max |O| of the call is max-reduced into *amax_o (FP8 path).  mode: 0 joint
+// window attention, 1 spatial (keys of the query's frame), 2 temporal (keys at the query's
+// position in every frame) -- the blocks of a decoupled network.
 void launch_attn_clip(const Geo& g, int C, int heads, int Spad, const bf16* q, const bf16* k, const bf16* vt,
                       const int32_t* idx, const int32_t* woff, const int32_t* worder, bf16* o, float* amax_o,
-                      hipStream_t s);
+                      int mode, hipStream_t s);
 bool window_order_supported(int S);
 // Rows of the Q/K/V GEMM tiles listed by the token step (the GEMM's row tile height).
 constexpr int ROW_TILE = 64;

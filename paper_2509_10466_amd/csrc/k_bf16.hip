@@ -120,11 +120,20 @@ struct RingKeys {
 // `keys` decides which keys exist (valid(tt, j): key 16 tt + j) and where V^T row d of the
 // 4 keys from 16 tt + off sits (vt).  qnext holds the first tile's Q operand, loaded by the
 // caller before staging.
-template <int DH, int NT, class Keys>
+// MODE selects the keys a query sees inside its window (tokens ordered (frame, row, column),
+// A = tokens per frame, wt frames, wbase = the window's first token): 0 all of them, 1 those of
+// the query's own frame (spatial attention of a decoupled network), 2 those at the query's
+// own position in every frame (temporal attention).  Masked keys score -inf, like padding;
+// the query's own key is always visible.
+struct KeyMask {
+  int A, wt, wbase;
+};
+
+template <int DH, int NT, class Keys, int MODE = 0>
 __device__ __forceinline__ float attn_query_tiles(const bf16* Ks, const bf16* Vt, const Keys& keys, int C, int h,
                                                  const bf16* __restrict__ q, const int32_t* __restrict__ idx,
                                                  int q0, int nqw, bf16* __restrict__ o, bf16x8_t (&qnext)[DH / 32],
-                                                 bool want_amax) {
+                                                 bool want_amax, KeyMask km = KeyMask{0, 0, 0}) {
   constexpr int CH = DH / 8;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int l16 = lane & 15, kg = lane >> 4;
@@ -136,6 +145,42 @@ __device__ __forceinline__ float attn_query_tiles(const bf16* Ks, const bf16* Vt
     const int qi = qt * 16 + l16;
     const bool valid = qi < nqw;
     const int r = q0 + (valid ? qi : 0);
+    // MODE 1 / 2: bit p of vis = key slot p of this lane (key 16 (p / 4) + 4 kg + p % 4) is
+    // visible to its query; built once per query tile, three registers at most
+    constexpr int MW = (4 * NT + 31) / 32;
+    uint32_t vis[MW];
+    if (MODE != 0) {
+      const int sq = idx[r] - km.wbase;
+      if (MODE == 1) {
+        // the query's frame [klo, klo + A) maps to a contiguous run of slots (key order is
+        // monotone in p): slots below key x number 4 floor(y / 16) + min(y mod 16, 4),
+        // y = x - 4 kg
+        const int klo = (sq / km.A) * km.A;
+        auto below = [&](int x) {
+          const int y = x - kg * 4;
+          return y <= 0 ? 0 : min(4 * NT, (y >> 4) * 4 + min(y & 15, 4));
+        };
+        const int plo = below(klo), phi = below(klo + km.A);
+#pragma unroll
+        for (int j = 0; j < MW; ++j) {
+          const int lo = min(max(plo - 32 * j, 0), 32), hi = min(max(phi - 32 * j, 0), 32);
+          vis[j] = (uint32_t)(((1ull << hi) - 1ull) & ~((1ull << lo) - 1ull));
+        }
+      } else {
+        const int kpos = sq % km.A;
+#pragma unroll
+        for (int j = 0; j < MW; ++j) vis[j] = 0u;
+#pragma unroll
+        for (int f = 0; f < 8; ++f) {
+          const int sk = kpos + f * km.A;
+          if (f < km.wt && ((sk >> 2) & 3) == kg) {
+            const int p = (sk >> 4) * 4 + (sk & 3);
+#pragma unroll
+            for (int j = 0; j < MW; ++j) vis[j] |= (p >> 5) == j ? 1u << (p & 31) : 0u;
+          }
+        }
+      }
+    }
     bf16x8_t qf[DH / 32];
 #pragma unroll
     for (int kk = 0; kk < DH / 32; ++kk) qf[kk] = qnext[kk];
@@ -178,7 +223,11 @@ __device__ __forceinline__ float attn_query_tiles(const bf16* Ks, const bf16* Vt
         const int tt = g0 + u;
         if (tt < NT)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) sc[tt][i] = keys.valid(tt, kg * 4 + i) ? a[u][i] : -INFINITY;
+          for (int i = 0; i < 4; ++i) {
+            // (a visible key of MODE 1 / 2 always exists: it lies inside the window)
+            const bool ok = MODE == 0 ? keys.valid(tt, kg * 4 + i) : ((vis[tt >> 3] >> ((tt & 7) * 4 + i)) & 1u);
+            sc[tt][i] = ok ? a[u][i] : -INFINITY;
+          }
       }
     }
     float mx = -INFINITY;
@@ -261,12 +310,13 @@ __device__ __forceinline__ float attn_query_tiles(const bf16* Ks, const bf16* Vt
   return want_amax ? wave_max(omax) : 0.f;
 }
 
-// At up to 240 keys the kernel fits 128 VGPRs: 4 wavefronts per SIMD, two blocks per CU.
-template <int NT>
-constexpr int attn_clip_waves_per_simd() { return NT <= 15 ? 4 : 3; }
+// At up to 240 keys the kernel fits 128 VGPRs: 4 wavefronts per SIMD, two blocks per CU.  The
+// key masks of the decoupled patterns take a few more registers at 240 keys and dh = 64.
+template <int NT, int MODE>
+constexpr int attn_clip_waves_per_simd() { return NT <= 4 || (NT <= 15 && MODE == 0) ? 4 : 3; }
 
-template <int DH, int NT>
-__global__ void __launch_bounds__(ATT_THREADS, attn_clip_waves_per_simd<NT>()) attn_clip_kernel(Geo g, int C, int heads, const bf16* __restrict__ q,
+template <int DH, int NT, int MODE>
+__global__ void __launch_bounds__(ATT_THREADS, (attn_clip_waves_per_simd<NT, MODE>())) attn_clip_kernel(Geo g, int C, int heads, const bf16* __restrict__ q,
                                                                 const bf16* __restrict__ kmat,
                                                                 const bf16* __restrict__ vtmat,
                                                                 const int32_t* __restrict__ idx,
@@ -288,8 +338,9 @@ __global__ void __launch_bounds__(ATT_THREADS, attn_clip_waves_per_simd<NT>()) a
   attn_dma<CH, true>(kmat + ((size_t)w * heads + h) * SP * DH, Ks, SP * DH * 2);
   attn_dma<CH, false>(vtmat + ((size_t)w * heads + h) * DH * SPV, Vt, DH * SPV * 2);
   asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
-  const float wmx = attn_query_tiles<DH, NT>(Ks, Vt, ClipKeys<NT, SPV>{g.S}, C, h, q, idx, q0, nqw, o, qnext,
-                                            amax_o != nullptr);
+  const float wmx = attn_query_tiles<DH, NT, ClipKeys<NT, SPV>, MODE>(
+      Ks, Vt, ClipKeys<NT, SPV>{g.S}, C, h, q, idx, q0, nqw, o, qnext, amax_o != nullptr,
+      KeyMask{g.wh * g.ww, g.wt, w * g.S});
   if (amax_o) {
     // max |O| of the block into the per-call slot that scales O for an FP8 projection: one
     // atomic per block, skipped when the slot already holds more (non-negative floats order
@@ -394,29 +445,31 @@ int attn_clip_vt_stride(int spad) { return attn_vt_stride(spad); }
 
 void launch_attn_clip(const Geo& g, int C, int heads, int Spad, const bf16* q, const bf16* k, const bf16* vt,
                       const int32_t* idx, const int32_t* woff, const int32_t* worder, bf16* o, float* amax_o,
-                      hipStream_t s) {
+                      int mode, hipStream_t s) {
   const int dh = C / heads;
   const int nt = Spad / 16;
   const size_t lds = (size_t)Spad * dh * 2 + (size_t)dh * attn_vt_stride(Spad) * 2;
-#define DR_ATTN_CLIP(DH_, NT_)                                                                          \
-  if (dh == DH_ && nt == NT_) {                                                                         \
+#define DR_ATTN_CLIP(DH_, NT_, MODE_)                                                                   \
+  if (dh == DH_ && nt == NT_ && mode == MODE_) {                                                        \
     static bool attr = false;                                                                           \
     if (!attr) {                                                                                        \
       if (lds > 65536)                                                                                  \
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(attn_clip_kernel<DH_, NT_>),            \
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(attn_clip_kernel<DH_, NT_, MODE_>),     \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
       attr = true;                                                                                      \
     }                                                                                                   \
-    attn_clip_kernel<DH_, NT_><<<g.nwin * heads, ATT_THREADS, lds, s>>>(g, C, heads, q, k, vt, idx, woff, worder, o, \
-                                                                        amax_o);                                \
+    attn_clip_kernel<DH_, NT_, MODE_><<<g.nwin * heads, ATT_THREADS, lds, s>>>(g, C, heads, q, k, vt, idx, woff, \
+                                                                               worder, o, amax_o);      \
     return;                                                                                             \
   }
-  DR_ATTN_CLIP(32, 4)
-  DR_ATTN_CLIP(64, 4)
-  DR_ATTN_CLIP(64, 15)
-  DR_ATTN_CLIP(64, 19)
-  DR_ATTN_CLIP(32, 15)
-  DR_ATTN_CLIP(32, 19)
+#define DR_ATTN_CLIP_MODES(DH_, NT_) DR_ATTN_CLIP(DH_, NT_, 0) DR_ATTN_CLIP(DH_, NT_, 1) DR_ATTN_CLIP(DH_, NT_, 2)
+  DR_ATTN_CLIP_MODES(32, 4)
+  DR_ATTN_CLIP_MODES(64, 4)
+  DR_ATTN_CLIP_MODES(64, 15)
+  DR_ATTN_CLIP_MODES(64, 19)
+  DR_ATTN_CLIP_MODES(32, 15)
+  DR_ATTN_CLIP_MODES(32, 19)
+#undef DR_ATTN_CLIP_MODES
 #undef DR_ATTN_CLIP
 }
 
