@@ -38,7 +38,10 @@ class NetCfg:
     """Network hyper-parameters.  ``dim`` = C, ``heads`` = h, ``blocks`` = L, ``mlp_ratio`` = r,
     ``patch`` = p (conv kernel = stride), window = win_t x win_h x win_w tokens.  ``attn``:
     "joint" (every block attends over the whole window) or "decoupled" (even blocks attend
-    within one frame of the window, odd blocks across its frames at one token position)."""
+    within one frame of the window, odd blocks across its frames at one token position).
+    ``overlap``: the patch embedding and the decoder use kernel 2p at stride p with p/2
+    padding (neighbouring patches overlap, and the decoder sums the overlaps) instead of
+    kernel p."""
     dim: int
     heads: int
     blocks: int
@@ -48,6 +51,12 @@ class NetCfg:
     win_w: int
     win_t: int
     attn: str = "joint"
+    overlap: bool = False
+
+    @property
+    def kernel(self) -> int:
+        """Kernel size of the patch embedding and the decoder."""
+        return 2 * self.patch if self.overlap else self.patch
 
     @property
     def head_dim(self) -> int:
@@ -64,6 +73,8 @@ NETS = {
     "clip720": NetCfg(dim=384, heads=6, blocks=12, mlp_ratio=4, patch=4, win_h=6, win_w=10, win_t=5),
     "clip240_dec": NetCfg(dim=256, heads=4, blocks=8, mlp_ratio=4, patch=4, win_h=5, win_w=9, win_t=5,
                           attn="decoupled"),
+    "clip240_ovl": NetCfg(dim=256, heads=4, blocks=8, mlp_ratio=4, patch=4, win_h=5, win_w=9, win_t=5,
+                          overlap=True),
 }
 
 # (net name, B, T, H, W) of each named workload.
@@ -82,9 +93,9 @@ SHAPES = {
 def weight_order(cfg: NetCfg):
     """(name, shape) of every parameter in draw order.
 
-    Linear weights are [out, in]; the patch-embed conv is OIHW [C, 3, p, p]; the
-    transposed-conv decoder is IOHW [C, 3, p, p]."""
-    C, p, R = cfg.dim, cfg.patch, cfg.mlp_ratio * cfg.dim
+    Linear weights are [out, in]; the patch-embed conv is OIHW [C, 3, k, k]; the
+    transposed-conv decoder is IOHW [C, 3, k, k] (k = cfg.kernel)."""
+    C, p, R = cfg.dim, cfg.kernel, cfg.mlp_ratio * cfg.dim
     out = [("embed.w", (C, 3, p, p)), ("embed.b", (C,))]
     for l in range(cfg.blocks):
         b = f"blk{l}."

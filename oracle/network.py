@@ -30,6 +30,14 @@ Readings taken where the description is silent (each is also the GPU path's defi
 * MLP: Linear(C, rC) -> exact-erf GELU -> Linear(rC, C).
 * final LayerNorm before the decoder; decoder = ConvTranspose2d(C, 3, k=p, s=p) + sigmoid.
 * composite: a per-pixel select, out = pred where the mask is nonzero, else the input.
+* overlapping variant (``cfg.overlap``; the thesis's DSTT base embeds overlapping patches and
+  rebuilds the frame with a fold that sums the overlaps, which the thesis replaced by a
+  reduction convolution plus a crop for TensorRT; Methods, "Performance Optimisations --
+  Modified Vec2Patch"): embedding Conv2d(3, C, k = 2p, s = p, padding p/2) with zero
+  padding; decoder = each token's 2p x 2p x 3 patch of logits, folded (overlaps summed)
+  onto the padded frame, cropped by p/2 on every side, plus the bias, then the sigmoid.  A
+  token is a query when any pixel of its 2p x 2p footprint inside the frame is private, so
+  every token that a private pixel's logit sums over is updated.
 """
 from __future__ import annotations
 
@@ -64,6 +72,53 @@ def token_flags(masks, p):
     frame t is private (OR rule)."""
     B, T, H, W = masks.shape
     return (masks != 0).reshape(B, T, H // p, p, W // p, p).any(axis=(3, 5))
+
+
+def token_flags_overlap(masks, p):
+    """flag[b, t, i, j] is True iff any pixel of rows p*i - p/2 .. p*i + 3p/2 - 1, columns
+    likewise, that lies inside the frame is private (the footprint of a kernel-2p token)."""
+    m = masks != 0
+    B, T, H, W = m.shape
+    h = p // 2
+    mp = np.zeros((B, T, H + 2 * h, W + 2 * h), dtype=bool)
+    mp[:, :, h:h + H, h:h + W] = m
+    Ht, Wt = H // p, W // p
+    out = np.zeros((B, T, Ht, Wt), dtype=bool)
+    for ky in range(2 * p):
+        for kx in range(2 * p):
+            out |= mp[:, :, ky:ky + p * Ht:p, kx:kx + p * Wt:p]
+    return out
+
+
+def patch_embed_overlap(xc, w, b, p):
+    """Conv2d(3 -> C, kernel 2p, stride p, padding p/2, zero padding) on each frame, w OIHW
+    [C, 3, 2p, 2p]: x[.., i, j, o] = b[o] + sum w[o, c, ky, kx] * xpad[p*i + ky, p*j + kx, c]."""
+    B, T, H, W, _ = xc.shape
+    h = p // 2
+    xp = np.zeros((B, T, H + 2 * h, W + 2 * h, 3))
+    xp[:, :, h:h + H, h:h + W] = xc
+    w = np.asarray(w, F64)
+    Ht, Wt = H // p, W // p
+    x = np.zeros((B, T, Ht, Wt, w.shape[0])) + np.asarray(b, F64)
+    for ky in range(2 * p):
+        for kx in range(2 * p):
+            x += xp[:, :, ky:ky + p * Ht:p, kx:kx + p * Wt:p, :] @ w[:, :, ky, kx].T
+    return x
+
+
+def decode_logits_fold(z, wd, bd, p):
+    """Vec2Patch by fold: token (i, j) projects z to a 2p x 2p x 3 patch
+    patch[ky, kx, ch] = sum_c z[c] wd[c, ch, ky, kx] (wd IOHW [C, 3, 2p, 2p]); the patches are
+    added onto the padded frame at (p*i, p*j) (overlaps summed), the p/2 border is cropped and
+    the bias added.  Equals ConvTranspose2d(C, 3, 2p, stride p, padding p/2)."""
+    B, T, Ht, Wt, _ = z.shape
+    k, h = 2 * p, p // 2
+    patches = np.einsum("btijc,cdyx->btijyxd", z, np.asarray(wd, F64))
+    canvas = np.zeros((B, T, p * Ht + 2 * h, p * Wt + 2 * h, 3))
+    for i in range(Ht):
+        for j in range(Wt):
+            canvas[:, :, p * i:p * i + k, p * j:p * j + k] += patches[:, :, i, j]
+    return canvas[:, :, h:h + p * Ht, h:h + p * Wt] + np.asarray(bd, F64)
 
 
 def patch_embed(xc, w, b, p):
@@ -232,16 +287,17 @@ def forward_detail(frames, masks, W, cfg, query_set="masked", keep_blocks=False)
     per-block tensors under "blocks" when ``keep_blocks``)."""
     check_shape(frames, masks, cfg)
     p = cfg.patch
+    ovl = getattr(cfg, "overlap", False)
     xc = cut_out(frames, masks)
-    flags = token_flags(masks, p)
+    flags = token_flags_overlap(masks, p) if ovl else token_flags(masks, p)
     upd = flags if query_set == "masked" else np.ones_like(flags)
-    x0 = patch_embed(xc, W["embed.w"], W["embed.b"], p)
+    x0 = (patch_embed_overlap if ovl else patch_embed)(xc, W["embed.w"], W["embed.b"], p)
     x = x0
     trace = [] if keep_blocks else None
     for l in range(cfg.blocks):
         x = block(x, upd, W, l, cfg, trace)
     z = layer_norm(x, _w(W, "lnf.g"), _w(W, "lnf.b"))
-    pred = sigmoid(decode_logits(z, W["dec.w"], W["dec.b"], p))
+    pred = sigmoid((decode_logits_fold if ovl else decode_logits)(z, W["dec.w"], W["dec.b"], p))
     out = composite(frames, masks, pred)
     return dict(xc=xc, flags=flags, upd=upd, x0=x0, x=x, z=z, pred=pred, out=out,
                 blocks=trace)
@@ -259,7 +315,8 @@ def forward(frames, masks, W, cfg, query_set="masked"):
 def window_major_flags(masks, cfg):
     """Token flags listed in window-major order: windows in (b, a, u, v) order, tokens inside
     a window in (dt, di, dj) order.  Returns uint8 [num_windows * S]."""
-    f = token_flags(masks, cfg.patch)[..., None].astype(np.uint8)
+    tf = token_flags_overlap if getattr(cfg, "overlap", False) else token_flags
+    f = tf(masks, cfg.patch)[..., None].astype(np.uint8)
     fw = to_windows(f, cfg)
     return fw.reshape(-1).copy()
 

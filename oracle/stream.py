@@ -55,6 +55,8 @@ def _unwindows2d(a, cfg):
 def step(state: StreamState, frame, mask, W, cfg, query_set="masked"):
     """Inpaint one new frame [H, W, 3] with mask [H, W]; updates ``state``.
     Returns (out [H, W, 3] FP64, pred [H, W, 3])."""
+    if getattr(cfg, "overlap", False):
+        raise NotImplementedError("the overlapping embedding/decoder runs in clip mode only")
     p = cfg.patch
     H, Wd, _ = frame.shape
     if H % (p * cfg.win_h) or Wd % (p * cfg.win_w):
