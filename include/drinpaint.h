@@ -88,6 +88,13 @@ dr_status dr_create(dr_ctx** out, int device, const dr_netcfg* cfg);
  * embed.b [C]; per block l: blk{l}.ln1.g, .ln1.b, .wq, .bq, .wk, .bk, .wv, .bv, .wo, .bo,
  * .ln2.g, .ln2.b, .w1 [rC,C], .b1, .w2 [C,rC], .b2 (linear weights [out,in]); lnf.g, lnf.b,
  * dec.w [C,3,p,p] (IOHW), dec.b [3].  Derived BF16 copies are built on the device.
+ * Kernels of size 2p in embed.w and dec.w ([C,3,2p,2p], p = 4) select the overlapping
+ * variant, after the thesis's Vec2Patch change (Methods, "Performance Optimisations --
+ * Modified Vec2Patch"): a Conv2d(3, C, 2p, stride p, padding p/2) embedding, and a decoder
+ * whose overlapping 2p x 2p patches are summed (the fold), computed as a per-pixel reduction
+ * over the covering tokens with the padding cropped.  Its queries are the tokens whose
+ * 2p x 2p footprint holds a private pixel.  It runs in clip mode on the BF16 path
+ * (dr_inpaint with another precision, stream mode and training return DR_EINVAL).
  * DR_EINVAL on a malformed blob or a config mismatch. */
 dr_status dr_load_weights(dr_ctx* ctx, const void* blob, size_t nbytes);
 

@@ -215,10 +215,19 @@ extern "C" dr_status dr_load_weights(dr_ctx* c, const void* blob, size_t nbytes)
     return fail(c, DR_EINVAL, "weight blob: network config differs from the context's");
   const Net& n = c->net;
   const int C = n.C, R = n.R, L = n.cfg.blocks, P = n.P;
+  // kernel size of the embedding and the decoder: P (non-overlapping) or 2P (overlapping,
+  // stride P, padding P/2), read from the first tensor's shape
+  int K = P;
+  if (nbytes >= head + sizeof(BlobRec)) {
+    BlobRec r0;
+    std::memcpy(&r0, b + head, sizeof r0);
+    if (r0.ndim == 4 && r0.shape[2] == (uint32_t)(2 * P) && r0.shape[3] == (uint32_t)(2 * P)) K = 2 * P;
+  }
+  if (K != P && P != 4) return fail(c, DR_EINVAL, "weight blob: the overlapping embedding needs patch 4");
   // expected tensors in order
   struct Want { std::string name; std::vector<uint32_t> shape; };
   std::vector<Want> want;
-  want.push_back({"embed.w", {(uint32_t)C, 3, (uint32_t)P, (uint32_t)P}});
+  want.push_back({"embed.w", {(uint32_t)C, 3, (uint32_t)K, (uint32_t)K}});
   want.push_back({"embed.b", {(uint32_t)C}});
   for (int l = 0; l < L; ++l) {
     const std::string p = "blk" + std::to_string(l) + ".";
@@ -242,7 +251,7 @@ extern "C" dr_status dr_load_weights(dr_ctx* c, const void* blob, size_t nbytes)
   }
   want.push_back({"lnf.g", {(uint32_t)C}});
   want.push_back({"lnf.b", {(uint32_t)C}});
-  want.push_back({"dec.w", {(uint32_t)C, 3, (uint32_t)P, (uint32_t)P}});
+  want.push_back({"dec.w", {(uint32_t)C, 3, (uint32_t)K, (uint32_t)K}});
   want.push_back({"dec.b", {3}});
   if (count != want.size())
     return fail(c, DR_EINVAL, "weight blob: %u tensors, expected %zu", count, want.size());
@@ -286,17 +295,48 @@ extern "C" dr_status dr_load_weights(dr_ctx* c, const void* blob, size_t nbytes)
   // embed weight transposed to [48][C], row (ky*4+kx)*3+c
   std::vector<float> ewT((size_t)48 * C), dw((size_t)C * 48);
   const float* ew = src[0];
-  for (int o = 0; o < C; ++o)
-    for (int ch = 0; ch < 3; ++ch)
-      for (int ky = 0; ky < P; ++ky)
-        for (int kx = 0; kx < P; ++kx)
-          ewT[(size_t)((ky * P + kx) * 3 + ch) * C + o] = ew[((o * 3 + ch) * P + ky) * P + kx];
   const float* dws = src[count - 2];
-  for (int ci = 0; ci < C; ++ci)
-    for (int ch = 0; ch < 3; ++ch)
-      for (int ky = 0; ky < P; ++ky)
-        for (int kx = 0; kx < P; ++kx)
-          dw[(size_t)ci * 48 + (ky * P + kx) * 3 + ch] = dws[((ci * 3 + ch) * P + ky) * P + kx];
+  if (K == P) {
+    for (int o = 0; o < C; ++o)
+      for (int ch = 0; ch < 3; ++ch)
+        for (int ky = 0; ky < P; ++ky)
+          for (int kx = 0; kx < P; ++kx)
+            ewT[(size_t)((ky * P + kx) * 3 + ch) * C + o] = ew[((o * 3 + ch) * P + ky) * P + kx];
+    for (int ci = 0; ci < C; ++ci)
+      for (int ch = 0; ch < 3; ++ch)
+        for (int ky = 0; ky < P; ++ky)
+          for (int kx = 0; kx < P; ++kx)
+            dw[(size_t)ci * 48 + (ky * P + kx) * 3 + ch] = dws[((ci * 3 + ch) * P + ky) * P + kx];
+  }
+  // overlapping variant: embedding weight [C][192] in the slot order of the overlapping MFMA
+  // embedding (slot 32 s + 8 g + e holds footprint row ky = g + 4 (s / 3), value m = 8 (s % 3)
+  // + e = 3 kx + c), decoder [192][C] (k = (ky*8 + kx)*3 + ch) with the final LayerNorm gain
+  // folded in, its shift through the decoder per token, and the decoder bias per pixel
+  std::vector<float> eo, dwo, dbo;
+  if (K != P) {
+    eo.assign((size_t)C * 192, 0.f);
+    for (int o = 0; o < C; ++o)
+      for (int sl = 0; sl < 6; ++sl)
+        for (int gq = 0; gq < 4; ++gq)
+          for (int e = 0; e < 8; ++e) {
+            const int ky = gq + 4 * (sl / 3), m = 8 * (sl % 3) + e, kx = m / 3, ch = m % 3;
+            eo[(size_t)o * 192 + 32 * sl + 8 * gq + e] = ew[((o * 3 + ch) * K + ky) * K + kx];
+          }
+    dwo.assign((size_t)192 * C, 0.f);
+    dbo.assign(192, 0.f);
+    const float* gf = src[count - 4];
+    const float* btf = src[count - 3];
+    for (int k = 0; k < 192; ++k) {
+      const int ky = (k / 3) / 8, kx = (k / 3) % 8, ch = k % 3;
+      double acc = 0.0;
+      for (int ci = 0; ci < C; ++ci) {
+        const float wv = dws[((ci * 3 + ch) * K + ky) * K + kx];
+        dwo[(size_t)k * C + ci] = gf[ci] * wv;
+        acc += (double)btf[ci] * wv;
+      }
+      dbo[k] = (float)acc;
+    }
+  }
   struct Off { size_t v[32]; };
   const size_t o_ewT = put(ewT.data(), ewT.size());
   const size_t o_eb = put(src[1], C);
@@ -417,6 +457,12 @@ extern "C" dr_status dr_load_weights(dr_ctx* c, const void* blob, size_t nbytes)
   const size_t o_lnfb = put(src[count - 3], C);
   const size_t o_dw = put(dw.data(), dw.size());
   const size_t o_db = put(src[count - 1], 3);
+  size_t o16_eo = 0, o16_dwo = 0, o_dbo = 0;
+  if (K != P) {
+    o16_eo = put16({eo.data()}, {eo.size()});
+    o16_dwo = put16({dwo.data()}, {dwo.size()});
+    o_dbo = put(dbo.data(), dbo.size());
+  }
 
   HIP_OK(c, hipSetDevice(c->device));
   HIP_OK(c, hipDeviceSynchronize());
@@ -465,6 +511,11 @@ extern "C" dr_status dr_load_weights(dr_ctx* c, const void* blob, size_t nbytes)
   nn.lnfb = F + o_lnfb;
   nn.dec_w = F + o_dw;
   nn.dec_b = F + o_db;
+  nn.K = K;
+  nn.embed_ovl16 = K != P ? B16 + o16_eo : nullptr;
+  nn.dec_ovl16 = K != P ? B16 + o16_dwo : nullptr;
+  nn.dec_ovl_bf = K != P ? F + o_dbo : nullptr;
+  nn.dec_ovl_b = K != P ? F + o_db : nullptr;
 
   // FP8 e4m3 copies of the GEMM weights, one scale per tensor (amax / 448)
   if (fp8_supported(C, R)) {
@@ -534,7 +585,10 @@ static dr_status make_geo(dr_ctx* c, int B, int T, int H, int W, Geo& g) {
 }
 
 dr_status dr::dr_reserve_work(dr_ctx* c, Work& w, const Geo& g, bool stream_mode) {
-  if ((size_t)g.N <= w.cap_tokens && (size_t)g.nwin <= w.cap_windows && w.stream_mode == stream_mode) return DR_OK;
+  const bool need_contrib = !stream_mode && c->net.K != c->net.P;
+  if ((size_t)g.N <= w.cap_tokens && (size_t)g.nwin <= w.cap_windows && w.stream_mode == stream_mode &&
+      (!need_contrib || w.contrib))
+    return DR_OK;
   HIP_OK(c, hipSetDevice(c->device));
   HIP_OK(c, hipDeviceSynchronize());
   dr_free_work(w);
@@ -579,6 +633,7 @@ dr_status dr::dr_reserve_work(dr_ctx* c, Work& w, const Geo& g, bool stream_mode
     ALLOC(k16, kvlen * 2);
     const size_t vtlen = nw * n.cfg.heads * (size_t)n.dh * attn_clip_vt_stride(n.Spad);
     ALLOC(vt16, vtlen * 2);
+    if (need_contrib) ALLOC(contrib, N * 192 * 4);
     // padded key rows of K and V (columns of V^T) must read as zero
     HIP_OK(c, hipMemset(w.k16, 0, kvlen * 2));
     HIP_OK(c, hipMemset(w.vt16, 0, vtlen * 2));
@@ -593,7 +648,7 @@ dr_status dr::dr_reserve_work(dr_ctx* c, Work& w, const Geo& g, bool stream_mode
 
 static dr_status reserve_geo(dr_ctx* c, const Geo& g) {
   const bool grows = !((size_t)g.N <= c->work.cap_tokens && (size_t)g.nwin <= c->work.cap_windows &&
-                       !c->work.stream_mode);
+                       !c->work.stream_mode && (c->net.K == c->net.P || c->work.contrib));
   if (grows) invalidate_graphs(c);
   return dr_reserve_work(c, c->work, g, false);
 }
@@ -623,7 +678,7 @@ extern "C" dr_status dr_reserve(dr_ctx* c, int B, int T, int H, int W, dr_precis
 
 static dr_status run_tokens(dr_ctx* c, const Geo& g, const uint8_t* masks, int all, hipStream_t s) {
   Work& w = c->work;
-  LAUNCH(ST_TOKENS, launch_token_flags(g, masks, all, w.flag, w.wcount, s));
+  LAUNCH(ST_TOKENS, launch_token_flags(g, masks, all, w.flag, w.wcount, s, c->net.K != c->net.P));
   LAUNCH(ST_TOKENS, launch_token_gather(g, w.flag, w.wcount, w.idx, w.woff, w.nq, s));
   LAUNCH(ST_TOKENS, launch_window_order(g, w.wcount, w.flag, w.worder, w.tiles, w.ntiles, s));
   return DR_OK;
@@ -642,7 +697,7 @@ extern "C" dr_status dr_gather_tokens(dr_ctx* c, const uint8_t* masks, int B, in
   st = reserve_geo(c, g);
   if (st != DR_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  LAUNCH(ST_TOKENS, launch_token_flags(g, masks, qs == DR_QUERY_ALL, flag, c->work.wcount, s));
+  LAUNCH(ST_TOKENS, launch_token_flags(g, masks, qs == DR_QUERY_ALL, flag, c->work.wcount, s, c->net.K != c->net.P));
   LAUNCH(ST_TOKENS, launch_token_gather(g, flag, c->work.wcount, idx, woff, nq, s));
   return DR_OK;
 }
@@ -717,6 +772,8 @@ extern "C" dr_status dr_inpaint(dr_ctx* c, const float* frames, const uint8_t* m
     return fail(c, DR_ESHAPE, "the FP8 path needs dim and hidden width multiples of 128");
   if (prec == DR_FP32 && c->attn_pattern != 0)
     return fail(c, DR_EINVAL, "decoupled attention runs on the BF16 and FP8 paths");
+  const bool ovl = n.K != n.P;
+  if (ovl && prec != DR_BF16) return fail(c, DR_EINVAL, "the overlapping embedding and decoder run on the BF16 path");
   const size_t npix = (size_t)B * T * H * W;
   if (out != frames && ranges_overlap(out, npix * 12, frames, npix * 12))
     return fail(c, DR_EINVAL, "out partially overlaps frames");
@@ -731,7 +788,9 @@ extern "C" dr_status dr_inpaint(dr_ctx* c, const float* frames, const uint8_t* m
   const int C = n.C, R = n.R, N = g.N;
   st = run_tokens(c, g, masks, qs == DR_QUERY_ALL, s);
   if (st != DR_OK) return st;
-  if (prec == DR_BF16)
+  if (ovl)
+    LAUNCH(ST_EMBED, launch_embed_ovl_bf16(g, C, frames, masks, w.flag, w.wcount, n.embed_ovl16, n.embed_b, w.x, w.xh, s));
+  else if (prec == DR_BF16)
     LAUNCH(ST_EMBED, launch_embed_bf16(g, C, frames, masks, w.flag, w.wcount, n.embed_wT16, n.embed_b, w.x, w.xh, s));
   else
     LAUNCH(ST_EMBED, launch_embed(g, C, frames, masks, n.embed_wT, n.embed_b, w.x, s));
@@ -770,7 +829,10 @@ extern "C" dr_status dr_inpaint(dr_ctx* c, const float* frames, const uint8_t* m
     br = run_blocks(c, g, prec, s);
   }
   if (br != DR_OK) return br;
-  if (prec == DR_BF16)
+  if (ovl) {
+    LAUNCH(ST_DECODE, launch_decode_ovl_bf16(g, C, w.xh, w.idx, w.nq, n.dec_ovl16, n.dec_ovl_bf, w.contrib, s));
+    LAUNCH(ST_DECODE, launch_fold_ovl(g, w.contrib, n.dec_ovl_b, masks, out, s));
+  } else if (prec == DR_BF16)
     LAUNCH(ST_DECODE, launch_decode_bf16(g, C, w.xh, w.idx, w.nq, n.dec_wf16, n.dec_bf, masks, out, s));
   else
     LAUNCH(ST_DECODE, launch_decode(g, C, w.x, w.idx, w.nq, n.lnfg, n.lnfb, n.dec_w, n.dec_b, masks, out, s));

@@ -74,6 +74,12 @@ struct Net {
   const bf16* embed_wT16;    // bf16 [C][64]: embedding weight, k slots permuted for the MFMA embedding
   const bf16* dec_wf16;      // bf16 [48][C]: decoder weight with the final LayerNorm gain folded in
   const float* dec_bf;       // f32 [48]: decoder bias + final LayerNorm shift through the decoder
+  // overlapping embedding and decoder (K = 2P; K = P otherwise and these are null)
+  int K = 4;
+  const bf16* embed_ovl16 = nullptr;  // bf16 [C][192], slot order of the overlapping embedding
+  const bf16* dec_ovl16 = nullptr;    // bf16 [192][C]: decoder with the final LayerNorm gain folded in
+  const float* dec_ovl_bf = nullptr;  // f32 [192]: final LayerNorm shift through the decoder (per token)
+  const float* dec_ovl_b = nullptr;   // f32 [3]: decoder bias (once per pixel)
 };
 
 struct Work {
@@ -102,6 +108,7 @@ struct Work {
        *h16 = nullptr;
   bf16* vt16 = nullptr;  // V^T [win][head][dh][vt stride] (BF16 clip mode)
   float* amax = nullptr;  // FP8 activation amax slots [blocks][4]
+  float* contrib = nullptr;  // overlapping decoder: per-token logit patches [N][192]
   // stream mode: contiguous staging of the batch's frames, masks and outputs
   float* fst = nullptr;
   uint8_t* mst = nullptr;
@@ -200,8 +207,10 @@ struct Geo {
 };
 
 // step 1 -- token flags and gather lists
+// halo 1: a token is flagged when its 8 x 8 footprint (overlapping embedding) holds a
+// private pixel
 void launch_token_flags(const Geo& g, const uint8_t* masks, int all, uint8_t* flag,
-                        int32_t* wcount, hipStream_t s);
+                        int32_t* wcount, hipStream_t s, int halo = 0);
 void launch_token_gather(const Geo& g, const uint8_t* flag, const int32_t* wcount,
                          int32_t* idx, int32_t* woff, int32_t* nq, hipStream_t s);
 // step 2 -- cut-out + patch embedding, x [N, C] f32 window-major
@@ -256,6 +265,17 @@ void launch_embed_bf16(const Geo& g, int C, const float* frames, const uint8_t* 
                        const int32_t* wcount, const bf16* wT16, const float* b, float* x, bf16* xh, hipStream_t s);
 void launch_decode_bf16(const Geo& g, int C, const bf16* xh, const int32_t* idx, const int32_t* nq,
                         const bf16* wd16, const float* bd, const uint8_t* masks, float* out, hipStream_t s);
+// overlapping variant (kernel 8, stride 4, padding 2): the embedding with wT16 [C][192] in
+// the slot order of embed_ovl_bf16_kernel; the decoder as per-token logit patches
+// contrib [N][192] of the flagged tokens (k = (ky*8 + kx)*3 + ch, wd16 [192][C] with the final
+// LayerNorm folded in) and a per-pixel sum over the covering tokens + bias + sigmoid
+void launch_embed_ovl_bf16(const Geo& g, int C, const float* frames, const uint8_t* masks, const uint8_t* flag,
+                           const int32_t* wcount, const bf16* wT16, const float* b, float* x, bf16* xh,
+                           hipStream_t s);
+void launch_decode_ovl_bf16(const Geo& g, int C, const bf16* xh, const int32_t* idx, const int32_t* nq,
+                            const bf16* wd16, const float* bd, float* contrib, hipStream_t s);
+void launch_fold_ovl(const Geo& g, const float* contrib, const float* db, const uint8_t* masks, float* out,
+                     hipStream_t s);
 // clip mode: the row tiles listed by launch_window_order (Q tiles with a flagged token, K/V
 // tiles touching a window with queries)
 void launch_qkv_bf16(const Geo& g, int C, int heads, int Spad, int spv, const bf16* xh, const int32_t* tiles,

@@ -145,6 +145,7 @@ static dr_status stream_step_locked(dr_ctx* c, Work& w, int n, const int32_t* si
   if (n < 1 || n > STREAM_MAXB) return dr_fail(c, DR_EINVAL, "batch of %d requests (1..%d)", n, STREAM_MAXB);
   if (!c->have_weights) return dr_fail(c, DR_EINVAL, "no weights loaded");
   if (c->attn_pattern != 0) return dr_fail(c, DR_EINVAL, "stream mode runs the joint-attention network");
+  if (c->net.K != c->net.P) return dr_fail(c, DR_EINVAL, "stream mode runs the non-overlapping embedding");
   const Net& net = c->net;
   if (!attn_ring_supported(net.dh, net.cfg.win_h * net.cfg.win_w, net.cfg.win_t))
     return dr_fail(c, DR_ESHAPE, "no stream attention kernel for this window");

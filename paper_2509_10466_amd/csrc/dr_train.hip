@@ -226,6 +226,7 @@ extern "C" dr_status dr_train_forward(dr_ctx* c, const float* frames, const uint
   if (!c || !frames || !masks || !pred) return dr_fail(c, DR_EINVAL, "dr_train_forward: null argument");
   if (!c->have_weights) return dr_fail(c, DR_EINVAL, "no weights loaded");
   if (c->attn_pattern != 0) return dr_fail(c, DR_EINVAL, "training runs the joint-attention network");
+  if (c->net.K != c->net.P) return dr_fail(c, DR_EINVAL, "training runs the non-overlapping embedding");
   Geo g;
   dr_status st = dr_make_geo(c, B, T, H, W, c->net.cfg.win_t, g);
   if (st != DR_OK) return st;

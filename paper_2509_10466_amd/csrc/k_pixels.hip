@@ -343,6 +343,256 @@ void launch_decode_bf16(const Geo& g, int C, const bf16* xh, const int32_t* idx,
 }
 
 // ------------------------------------------------------------------------------------------
+// Overlapping variant: embedding Conv2d(3, C, 8, stride 4, padding 2) and the decoder as the
+// matching transposed convolution, whose overlapping patches are summed (the fold) -- done
+// here as a reduction: each token's 8 x 8 x 3 logit patch, then each private pixel sums the
+// patches of the (at most 2 x 2) tokens whose footprint covers it.
+// ------------------------------------------------------------------------------------------
+
+// Window-major index of token (b, t, i, j) (inverse of token_coords).
+__device__ __forceinline__ int token_index(const Geo& g, int b, int t, int i, int j) {
+  const int nT = g.T / g.wt;
+  const int a = t / g.wt, dt = t - a * g.wt;
+  const int u = i / g.wh, di = i - u * g.wh;
+  const int v = j / g.ww, dj = j - v * g.ww;
+  const int w = ((b * nT + a) * g.nwh + u) * g.nww + v;
+  return w * g.S + (dt * g.wh + di) * g.ww + dj;
+}
+
+// Lane (token l16, group kg) loads rows ky = kg and kg + 4 of its token's footprint (pixel
+// rows 4i - 2 + ky, columns 4j - 2 .. 4j + 5; zero outside the frame and where the mask is
+// set): 24 values per row, m = 3 kx + c.  32-wide k slice s takes values m = 8 (s % 3) .. + 7
+// of row kg + 4 (s / 3) in the lane's 8 slots, and wT16 [C][192] holds the weight in the
+// same slot order.  Columns come in pixel pairs (x0 and W are even), each pair wholly inside
+// or outside the frame: three 8-byte loads and one 2-byte mask load per pair.
+template <int C>
+__global__ void __launch_bounds__(256) embed_ovl_bf16_kernel(Geo g, const float* __restrict__ frames,
+                                                             const uint8_t* __restrict__ masks,
+                                                             const uint8_t* __restrict__ flag,
+                                                             const int32_t* __restrict__ wcount,
+                                                             const bf16* __restrict__ wT16,
+                                                             const float* __restrict__ bias, float* __restrict__ x,
+                                                             bf16* __restrict__ xh) {
+  constexpr int FN = C / 16, KS = 6;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int l16 = lane & 15, kg = lane >> 4;
+  const int n = (blockIdx.x * 4 + wv) * 16 + l16;
+  const bool need_h = n < g.N && (wcount == nullptr || wcount[n / g.S] > 0);
+  if (!__any(need_h)) return;  // wave-uniform: no barrier in this kernel
+  const bool need_x = need_h && flag[n] != 0;
+  bf16x8_t pk[KS];
+  int b = 0, t = 0, i = 0, j = 0;
+  if (need_h) token_coords(g, n, b, t, i, j);
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    float v[24];
+#pragma unroll
+    for (int e = 0; e < 24; ++e) v[e] = 0.f;
+    const int y = 4 * i - 2 + kg + 4 * r;
+    if (need_h && y >= 0 && y < g.H) {
+      const size_t rowpx = (((size_t)b * g.T + t) * g.H + y) * g.W;
+      const int x0 = 4 * j - 2;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int xx = x0 + 2 * q;
+        if (xx >= 0 && xx < g.W) {
+          const float2* src = reinterpret_cast<const float2*>(frames + (rowpx + xx) * 3);
+          const float2 f0 = src[0], f1 = src[1], f2 = src[2];
+          const uint32_t m = *reinterpret_cast<const uint16_t*>(masks + rowpx + xx);
+          const bool m0 = (m & 0xffu) != 0, m1 = (m >> 8) != 0;
+          v[6 * q + 0] = m0 ? 0.f : f0.x;
+          v[6 * q + 1] = m0 ? 0.f : f0.y;
+          v[6 * q + 2] = m0 ? 0.f : f1.x;
+          v[6 * q + 3] = m1 ? 0.f : f1.y;
+          v[6 * q + 4] = m1 ? 0.f : f2.x;
+          v[6 * q + 5] = m1 ? 0.f : f2.y;
+        }
+      }
+    }
+#pragma unroll
+    for (int part = 0; part < 3; ++part)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) pk[3 * r + part][e] = (__bf16)v[8 * part + e];
+  }
+  f32x4_t acc[FN];
+  float sum = 0.f;
+#pragma unroll
+  for (int f = 0; f < FN; ++f) {
+    const bf16* wr = wT16 + (size_t)(16 * f + l16) * (32 * KS) + 8 * kg;
+    bf16x8_t w[KS];
+#pragma unroll
+    for (int sl = 0; sl < KS; ++sl) w[sl] = *reinterpret_cast<const bf16x8_t*>(wr + 32 * sl);
+    f32x4_t a = {0.f, 0.f, 0.f, 0.f};
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int sl = 0; sl < KS; ++sl) a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[sl], pk[sl], a, 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("s_nop 7" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+    const float4 b4 = *reinterpret_cast<const float4*>(bias + 16 * f + 4 * kg);
+    a[0] += b4.x; a[1] += b4.y; a[2] += b4.z; a[3] += b4.w;
+    acc[f] = a;
+    sum += (a[0] + a[1]) + (a[2] + a[3]);
+  }
+  sum += __shfl_xor(sum, 16, 64);
+  sum += __shfl_xor(sum, 32, 64);
+  const float mean = sum * (1.0f / C);
+  float sq = 0.f;
+#pragma unroll
+  for (int f = 0; f < FN; ++f)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float d = acc[f][e] - mean;
+      sq += d * d;
+    }
+  sq += __shfl_xor(sq, 16, 64);
+  sq += __shfl_xor(sq, 32, 64);
+  const float rstd = rsqrtf(sq * (1.0f / C) + 1e-5f);
+  if (!need_h) return;
+#pragma unroll
+  for (int f = 0; f < FN; ++f) {
+    const int c = 16 * f + 4 * kg;
+    const f32x4_t& a = acc[f];
+    if (need_x) *reinterpret_cast<float4*>(x + (size_t)n * C + c) = make_float4(a[0], a[1], a[2], a[3]);
+    uint2 pw;
+    pw.x = pack_bf2((a[0] - mean) * rstd, (a[1] - mean) * rstd);
+    pw.y = pack_bf2((a[2] - mean) * rstd, (a[3] - mean) * rstd);
+    *reinterpret_cast<uint2*>(xh + (size_t)n * C + c) = pw;
+  }
+}
+
+void launch_embed_ovl_bf16(const Geo& g, int C, const float* frames, const uint8_t* masks, const uint8_t* flag,
+                           const int32_t* wcount, const bf16* wT16, const float* b, float* x, bf16* xh,
+                           hipStream_t s) {
+  const int blocks = (g.N + 63) / 64;
+  if (blocks == 0) return;
+  switch (C) {
+    case 64: embed_ovl_bf16_kernel<64><<<blocks, 256, 0, s>>>(g, frames, masks, flag, wcount, wT16, b, x, xh); break;
+    case 128: embed_ovl_bf16_kernel<128><<<blocks, 256, 0, s>>>(g, frames, masks, flag, wcount, wT16, b, x, xh); break;
+    case 256: embed_ovl_bf16_kernel<256><<<blocks, 256, 0, s>>>(g, frames, masks, flag, wcount, wT16, b, x, xh); break;
+    case 384: embed_ovl_bf16_kernel<384><<<blocks, 256, 0, s>>>(g, frames, masks, flag, wcount, wT16, b, x, xh); break;
+    default: break;  // rejected by the caller
+  }
+}
+
+// Logit patch of each flagged token: contrib[n][k] = bd'[k] + sum_c x^[n][c] Wd'[k][c],
+// k = (ky*8 + kx)*3 + ch; twelve 16-wide output fragments per 16 tokens.
+template <int C>
+__global__ void __launch_bounds__(256) decode_ovl_bf16_kernel(Geo g, const bf16* __restrict__ xh,
+                                                              const int32_t* __restrict__ idx,
+                                                              const int32_t* __restrict__ nq,
+                                                              const bf16* __restrict__ wd16,
+                                                              const float* __restrict__ bd,
+                                                              float* __restrict__ contrib) {
+  constexpr int NF = 12;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int l16 = lane & 15, kg = lane >> 4;
+  const int total = nq[0];
+  for (int r0 = (blockIdx.x * 4 + wv) * 16; r0 < total; r0 += gridDim.x * 64) {
+    const int r = r0 + l16;
+    const bool ok = r < total;
+    const int n = ok ? idx[r] : 0;
+    f32x4_t acc[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[f] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int kk = 0; kk < C / 32; ++kk) {
+      const bf16x8_t z = ok ? *reinterpret_cast<const bf16x8_t*>(xh + (size_t)n * C + kk * 32 + 8 * kg)
+                            : bf16x8_t{};
+      bf16x8_t w[NF];
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+        w[f] = *reinterpret_cast<const bf16x8_t*>(wd16 + (size_t)(16 * f + l16) * C + kk * 32 + 8 * kg);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) acc[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[f], z, acc[f], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      asm volatile("s_nop 7" ::: "memory");
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (!ok) continue;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const int k = 16 * f + 4 * kg;
+      const float4 b4 = *reinterpret_cast<const float4*>(bd + k);
+      *reinterpret_cast<float4*>(contrib + (size_t)n * 192 + k) =
+          make_float4(acc[f][0] + b4.x, acc[f][1] + b4.y, acc[f][2] + b4.z, acc[f][3] + b4.w);
+    }
+  }
+}
+
+void launch_decode_ovl_bf16(const Geo& g, int C, const bf16* xh, const int32_t* idx, const int32_t* nq,
+                            const bf16* wd16, const float* bd, float* contrib, hipStream_t s) {
+  int grid = (g.N + 63) / 64;
+  if (grid > DEC_GRID) grid = DEC_GRID;
+  if (grid == 0) return;
+  switch (C) {
+    case 64: decode_ovl_bf16_kernel<64><<<grid, 256, 0, s>>>(g, xh, idx, nq, wd16, bd, contrib); break;
+    case 128: decode_ovl_bf16_kernel<128><<<grid, 256, 0, s>>>(g, xh, idx, nq, wd16, bd, contrib); break;
+    case 256: decode_ovl_bf16_kernel<256><<<grid, 256, 0, s>>>(g, xh, idx, nq, wd16, bd, contrib); break;
+    case 384: decode_ovl_bf16_kernel<384><<<grid, 256, 0, s>>>(g, xh, idx, nq, wd16, bd, contrib); break;
+    default: break;
+  }
+}
+
+// Each private pixel (y, x): the covering tokens are rows i1 = (y + 2) / 4 (kernel row
+// y + 2 - 4 i1 in 0..3) and i1 - 1 (kernel row + 4), likewise for columns, those inside the
+// token grid (the crop); the pixel sums their logit patches at its kernel offset, adds the
+// bias and applies the sigmoid.  Every covering token is flagged by the footprint rule, so
+// its patch has been written.  Four pixels per thread (W % 4 == 0).
+__global__ void __launch_bounds__(256) fold_ovl_kernel(Geo g, const float* __restrict__ contrib,
+                                                       const float* __restrict__ db,
+                                                       const uint8_t* __restrict__ masks, float* __restrict__ out) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t npix = (size_t)g.B * g.T * g.H * g.W;
+  if (q * 4 >= npix) return;
+  const size_t p0 = q * 4;
+  const uint32_t m4 = *reinterpret_cast<const uint32_t*>(masks + p0);
+  if (m4 == 0) return;
+  const size_t plane = (size_t)g.H * g.W;
+  const int bt = (int)(p0 / plane);
+  const int b = bt / g.T, t = bt - b * g.T;
+  const size_t in_plane = p0 - (size_t)bt * plane;
+  const int y = (int)(in_plane / g.W), x0 = (int)(in_plane - (size_t)y * g.W);
+  const int i1 = (y + 2) >> 2;
+  const float b0 = db[0], b1 = db[1], b2 = db[2];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    if (!((m4 >> (8 * e)) & 0xffu)) continue;
+    const int x = x0 + e;
+    const int j1 = (x + 2) >> 2;
+    float a0 = b0, a1 = b1, a2 = b2;
+#pragma unroll
+    for (int di = 0; di < 2; ++di) {
+      const int i = i1 - di;
+      if (i < 0 || i >= g.Ht) continue;
+      const int ky = y + 2 - 4 * i;
+#pragma unroll
+      for (int dj = 0; dj < 2; ++dj) {
+        const int j = j1 - dj;
+        if (j < 0 || j >= g.Wt) continue;
+        const int kx = x + 2 - 4 * j;
+        const float* cp = contrib + (size_t)token_index(g, b, t, i, j) * 192 + (ky * 8 + kx) * 3;
+        a0 += cp[0];
+        a1 += cp[1];
+        a2 += cp[2];
+      }
+    }
+    float* o = out + (p0 + e) * 3;
+    o[0] = 1.0f / (1.0f + expf(-a0));
+    o[1] = 1.0f / (1.0f + expf(-a1));
+    o[2] = 1.0f / (1.0f + expf(-a2));
+  }
+}
+
+void launch_fold_ovl(const Geo& g, const float* contrib, const float* db, const uint8_t* masks, float* out,
+                     hipStream_t s) {
+  const size_t quads = (size_t)g.B * g.T * g.H * g.W / 4;
+  if (quads == 0) return;
+  fold_ovl_kernel<<<(unsigned)((quads + 255) / 256), 256, 0, s>>>(g, contrib, db, masks, out);
+}
+
+// ------------------------------------------------------------------------------------------
 // out = frames wherever the mask is 0 (4 pixels per thread, vector loads and stores).
 // ------------------------------------------------------------------------------------------
 __global__ void copy_unmasked_kernel(size_t nquad, const float4* __restrict__ frames,

@@ -27,9 +27,31 @@ __device__ __forceinline__ size_t token_pixel(const Geo& g, int n) {
   return (((size_t)b * g.T + t) * g.H + (size_t)g.P * i) * g.W + (size_t)g.P * j;
 }
 
-// One workgroup per window: flag its S tokens and count them.
+// Halo rule of the overlapping embedding and decoder (kernel 8, stride 4, padding 2): the
+// token's footprint is rows 4i - 2 .. 4i + 5 and columns 4j - 2 .. 4j + 5, clipped to the
+// frame.  Per row: the upper two mask bytes of the word left of the patch, the patch's word
+// and the lower two bytes of the word right of it (each read only when inside the frame).
+__device__ __forceinline__ int footprint_any(const Geo& g, const uint8_t* __restrict__ masks, size_t px) {
+  const size_t plane = (size_t)g.H * g.W;
+  const size_t in_plane = px % plane;
+  const int y = (int)(in_plane / g.W), x = (int)(in_plane - (size_t)y * g.W);
+  const size_t base = px - in_plane;
+  uint32_t any = 0;
+  for (int dy = -2; dy < 6; ++dy) {
+    const int yy = y + dy;
+    if (yy < 0 || yy >= g.H) continue;
+    const uint8_t* row = masks + base + (size_t)yy * g.W;
+    any |= *reinterpret_cast<const uint32_t*>(row + x);
+    if (x > 0) any |= *reinterpret_cast<const uint32_t*>(row + x - 4) >> 16;
+    if (x + 4 < g.W) any |= *reinterpret_cast<const uint32_t*>(row + x + 4) & 0xffffu;
+  }
+  return any != 0;
+}
+
+// One workgroup per window: flag its S tokens and count them.  halo: 0 = the token's own
+// 4 x 4 patch, 1 = the 8 x 8 footprint of the overlapping embedding and decoder.
 __global__ void __launch_bounds__(256) token_flags_kernel(Geo g, const uint8_t* __restrict__ masks,
-                                                          int all, uint8_t* __restrict__ flag,
+                                                          int all, int halo, uint8_t* __restrict__ flag,
                                                           int32_t* __restrict__ wcount) {
   __shared__ int cnt;
   const int w = blockIdx.x;
@@ -39,7 +61,9 @@ __global__ void __launch_bounds__(256) token_flags_kernel(Geo g, const uint8_t* 
   for (int s = threadIdx.x; s < g.S; s += blockDim.x) {
     const int n = w * g.S + s;
     int f = 1;
-    if (!all) {
+    if (!all && halo) {
+      f = footprint_any(g, masks, token_pixel(g, n));
+    } else if (!all) {
       const size_t px = token_pixel(g, n);
       uint32_t any = 0;
       // p == 4 and W % 4 == 0: each patch row is one aligned 32-bit word of mask bytes.
@@ -156,8 +180,8 @@ void launch_window_order(const Geo& g, const int32_t* wcount, const uint8_t* fla
 }
 
 void launch_token_flags(const Geo& g, const uint8_t* masks, int all, uint8_t* flag,
-                        int32_t* wcount, hipStream_t s) {
-  token_flags_kernel<<<g.nwin, 256, 0, s>>>(g, masks, all, flag, wcount);
+                        int32_t* wcount, hipStream_t s, int halo) {
+  token_flags_kernel<<<g.nwin, 256, 0, s>>>(g, masks, all, halo, flag, wcount);
 }
 
 void launch_token_gather(const Geo& g, const uint8_t* flag, const int32_t* wcount, int32_t* idx,
