@@ -159,3 +159,48 @@ def test_gather_lists_use_the_overlap_rule():
     ref = on.to_windows(on.token_flags_overlap(m, 4)[..., None].astype(np.uint8), CFG).reshape(-1)
     assert np.array_equal(flag, ref)
     assert woff[-1] == idx.size == int(ref.sum())
+
+
+# ------------------------------------------------------------------------------------------
+# the pins above have teeth: plausible mistakes planted in the oracle are caught
+# ------------------------------------------------------------------------------------------
+_orig_fold = on.decode_logits_fold
+_orig_embed = on.patch_embed_overlap
+_orig_flags = on.token_flags_overlap
+
+
+def _fold_crop_shifted(z, wd, bd, p):
+    y = _orig_fold(z, wd, bd, p) - np.asarray(bd)
+    y = np.roll(y, 1, axis=2)  # crop taken one row too early
+    return y + np.asarray(bd)
+
+
+def _fold_kernel_transposed(z, wd, bd, p):
+    return _orig_fold(z, np.asarray(wd).transpose(0, 1, 3, 2), bd, p)
+
+
+def _embed_pad_one_side(xc, w, b, p):
+    pad = np.zeros_like(xc)
+    pad[:, :, :-2] = xc[:, :, 2:]  # the frame shifted up by the padding
+    return _orig_embed(pad, w, b, p)
+
+
+def _flags_no_halo(masks, p):
+    return on.token_flags(masks, p)
+
+
+_OVL_MUTATIONS = {
+    "fold crop shifted": ("decode_logits_fold", _fold_crop_shifted, test_fold_matches_conv_transpose2d),
+    "fold kernel transposed": ("decode_logits_fold", _fold_kernel_transposed,
+                               test_fold_equals_reduction_over_covering_tokens),
+    "embedding padding on one side": ("patch_embed_overlap", _embed_pad_one_side, test_embed_matches_conv2d),
+    "flags without the footprint halo": ("token_flags_overlap", _flags_no_halo, test_overlap_flags_brute_force_and_cover),
+}
+
+
+@pytest.mark.parametrize("name", sorted(_OVL_MUTATIONS))
+def test_planted_overlap_mistake_is_caught(name, monkeypatch):
+    attr, fn, pin = _OVL_MUTATIONS[name]
+    monkeypatch.setattr(on, attr, fn)
+    with pytest.raises(AssertionError):
+        pin()
