@@ -122,18 +122,18 @@ struct RingKeys {
 // caller before staging.
 // MODE selects the keys a query sees inside its window (tokens ordered (frame, row, column),
 // A = tokens per frame, wt frames, wbase = the window's first token): 0 all of them, 1 those of
-// the query's own frame (spatial attention of a decoupled network), 2 those at the query's
-// own position in every frame (temporal attention).  Masked keys score -inf, like padding;
-// the query's own key is always visible.
+// the query's own frame (spatial attention of a decoupled network).  Masked keys score -inf,
+// like padding; the query's own key is always visible.  (Temporal attention, the query's own
+// position in every frame, has its own kernel: attn_temporal_kernel.)
 struct KeyMask {
-  int A, wt, wbase;
+  int A, wbase;
 };
 
 template <int DH, int NT, class Keys, int MODE = 0>
 __device__ __forceinline__ float attn_query_tiles(const bf16* Ks, const bf16* Vt, const Keys& keys, int C, int h,
                                                  const bf16* __restrict__ q, const int32_t* __restrict__ idx,
                                                  int q0, int nqw, bf16* __restrict__ o, bf16x8_t (&qnext)[DH / 32],
-                                                 bool want_amax, KeyMask km = KeyMask{0, 0, 0}) {
+                                                 bool want_amax, KeyMask km = KeyMask{0, 0}) {
   constexpr int CH = DH / 8;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int l16 = lane & 15, kg = lane >> 4;
@@ -145,13 +145,17 @@ __device__ __forceinline__ float attn_query_tiles(const bf16* Ks, const bf16* Vt
     const int qi = qt * 16 + l16;
     const bool valid = qi < nqw;
     const int r = q0 + (valid ? qi : 0);
-    // MODE 1 / 2: bit p of vis = key slot p of this lane (key 16 (p / 4) + 4 kg + p % 4) is
+    // MODE 1: bit p of vis = key slot p of this lane (key 16 (p / 4) + 4 kg + p % 4) is
     // visible to its query; built once per query tile, three registers at most
+    static_assert(MODE == 0 || MODE == 1, "key mask mode");
     constexpr int MW = (4 * NT + 31) / 32;
     uint32_t vis[MW];
+    // key tiles tlo .. thi hold every key the tile's queries see (wave-uniform); MODE 1 skips
+    // the products, exponentials and V^T reads of the others
+    int tlo = 0, thi = NT - 1;
     if (MODE != 0) {
       const int sq = idx[r] - km.wbase;
-      if (MODE == 1) {
+      {
         // the query's frame [klo, klo + A) maps to a contiguous run of slots (key order is
         // monotone in p): slots below key x number 4 floor(y / 16) + min(y mod 16, 4),
         // y = x - 4 kg
@@ -161,23 +165,18 @@ __device__ __forceinline__ float attn_query_tiles(const bf16* Ks, const bf16* Vt
           return y <= 0 ? 0 : min(4 * NT, (y >> 4) * 4 + min(y & 15, 4));
         };
         const int plo = below(klo), phi = below(klo + km.A);
+        int lo = klo, hi = klo + km.A - 1;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+          lo = min(lo, __shfl_xor(lo, off, 64));
+          hi = max(hi, __shfl_xor(hi, off, 64));
+        }
+        tlo = __builtin_amdgcn_readfirstlane(lo) >> 4;
+        thi = __builtin_amdgcn_readfirstlane(hi) >> 4;
 #pragma unroll
         for (int j = 0; j < MW; ++j) {
           const int lo = min(max(plo - 32 * j, 0), 32), hi = min(max(phi - 32 * j, 0), 32);
           vis[j] = (uint32_t)(((1ull << hi) - 1ull) & ~((1ull << lo) - 1ull));
-        }
-      } else {
-        const int kpos = sq % km.A;
-#pragma unroll
-        for (int j = 0; j < MW; ++j) vis[j] = 0u;
-#pragma unroll
-        for (int f = 0; f < 8; ++f) {
-          const int sk = kpos + f * km.A;
-          if (f < km.wt && ((sk >> 2) & 3) == kg) {
-            const int p = (sk >> 4) * 4 + (sk & 3);
-#pragma unroll
-            for (int j = 0; j < MW; ++j) vis[j] |= (p >> 5) == j ? 1u << (p & 31) : 0u;
-          }
         }
       }
     }
@@ -203,11 +202,20 @@ __device__ __forceinline__ float attn_query_tiles(const bf16* Ks, const bf16* Vt
         }
       }
     };
+    auto group_live = [&](int g0) { return MODE == 0 || (g0 <= thi && g0 + TG - 1 >= tlo); };
     read_k(0, kf[0]);
 #pragma unroll
     for (int g0 = 0; g0 < NT; g0 += TG) {
       const int cur = (g0 / TG) & 1;
       if (g0 + TG < NT) read_k(g0 + TG, kf[cur ^ 1]);
+      if (!group_live(g0)) {
+#pragma unroll
+        for (int u = 0; u < TG; ++u)
+          if (g0 + u < NT)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sc[g0 + u][i] = -INFINITY;
+        continue;
+      }
       f32x4_t a[TG];
       mfma_fence_begin();
 #pragma unroll
@@ -224,7 +232,7 @@ __device__ __forceinline__ float attn_query_tiles(const bf16* Ks, const bf16* Vt
         if (tt < NT)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            // (a visible key of MODE 1 / 2 always exists: it lies inside the window)
+            // (a visible key of MODE 1 always exists: it lies inside the window)
             const bool ok = MODE == 0 ? keys.valid(tt, kg * 4 + i) : ((vis[tt >> 3] >> ((tt & 7) * 4 + i)) & 1u);
             sc[tt][i] = ok ? a[u][i] : -INFINITY;
           }
@@ -239,13 +247,19 @@ __device__ __forceinline__ float attn_query_tiles(const bf16* Ks, const bf16* Vt
     mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
     float sum = 0.f;
 #pragma unroll
-    for (int tt = 0; tt < NT; ++tt)
+    for (int tt = 0; tt < NT; ++tt) {
+      if (MODE != 0 && (tt < tlo || tt > thi)) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sc[tt][i] = 0.f;
+        continue;
+      }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const float p = __builtin_amdgcn_exp2f(sc[tt][i] - mx);  // argument <= 0
         sc[tt][i] = p;
         sum += p;
       }
+    }
     sum += __shfl_xor(sum, 16, 64);
     sum += __shfl_xor(sum, 32, 64);
     const float inv = 1.0f / sum;
@@ -270,6 +284,7 @@ __device__ __forceinline__ float attn_query_tiles(const bf16* Ks, const bf16* Vt
     };
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
+      if (MODE != 0 && (2 * p + 1 < tlo || 2 * p > thi)) continue;  // P = 0 on both tiles
       read_v(p, vf);
       uint4 pv;
       pv.x = pack_bf2(sc[2 * p][0], sc[2 * p][1]);
@@ -282,7 +297,7 @@ __device__ __forceinline__ float attn_query_tiles(const bf16* Ks, const bf16* Vt
       for (int dt = 0; dt < DT; ++dt) acc[dt] = mfma32(vf[dt], pb, acc[dt]);
       mfma_fence_end();
     }
-    if (NT & 1) {  // last key tile alone: single-rate k = 16 (operands read at issue)
+    if ((NT & 1) && (MODE == 0 || NT - 1 <= thi)) {  // last key tile alone: single-rate k = 16
       constexpr int tt = NT - 1;
       uint2 pv;
       pv.x = pack_bf2(sc[tt][0], sc[tt][1]);
@@ -340,12 +355,120 @@ __global__ void __launch_bounds__(ATT_THREADS, (attn_clip_waves_per_simd<NT, MOD
   asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
   const float wmx = attn_query_tiles<DH, NT, ClipKeys<NT, SPV>, MODE>(
       Ks, Vt, ClipKeys<NT, SPV>{g.S}, C, h, q, idx, q0, nqw, o, qnext, amax_o != nullptr,
-      KeyMask{g.wh * g.ww, g.wt, w * g.S});
+      KeyMask{g.wh * g.ww, w * g.S});
   if (amax_o) {
     // max |O| of the block into the per-call slot that scales O for an FP8 projection: one
     // atomic per block, skipped when the slot already holds more (non-negative floats order
     // like their bits)
     __shared__ float wred[ATT_THREADS / 64];
+    if ((threadIdx.x & 63) == 0) wred[wv] = wmx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float m = 0.f;
+      for (int i = 0; i < ATT_THREADS / 64; ++i) m = fmaxf(m, wred[i]);
+      if (m > 0.f && m > *reinterpret_cast<volatile float*>(amax_o))
+        atomicMax(reinterpret_cast<unsigned int*>(amax_o), __float_as_uint(m));
+    }
+  }
+}
+
+// Temporal blocks of a decoupled network: a query sees only the wt keys at its own token
+// position in the frames of its window (keys s mod A + f A), so there are no key tiles to
+// multiply.  One block per (window, head), as in attn_clip_kernel: V^T of the window is
+// staged in LDS, and four lanes per query each take DH/4 channels -- of Q and of the key rows
+// (16-byte loads from global memory, all issued before the first product), combining their
+// partial scores with two shuffles, and of O, read from the V^T columns.  Scores are in
+// base 2 (Q carries log2(e) / sqrt(dh)).
+template <int DH>
+__global__ void __launch_bounds__(ATT_THREADS) attn_temporal_kernel(Geo g, int C, int heads, int Spad,
+                                                                    const bf16* __restrict__ q,
+                                                                    const bf16* __restrict__ kmat,
+                                                                    const bf16* __restrict__ vtmat,
+                                                                    const int32_t* __restrict__ idx,
+                                                                    const int32_t* __restrict__ woff,
+                                                                    const int32_t* __restrict__ worder,
+                                                                    bf16* __restrict__ o, float* __restrict__ amax_o) {
+  constexpr int DPL = DH / 4, NV = DPL / 8;  // channels per lane, 16-byte vectors per lane
+  const int spv = attn_vt_stride(Spad);
+  const int rank = blockIdx.x / heads, h = blockIdx.x - rank * heads;
+  const int w = worder[rank];
+  const int q0 = woff[w], nqw = woff[w + 1] - q0;
+  if (nqw == 0) return;
+  extern __shared__ __align__(16) bf16 att_lds[];
+  bf16* Vt = att_lds;  // [DH][spv]
+  attn_dma<DH / 8, false>(vtmat + ((size_t)w * heads + h) * DH * spv, Vt, DH * spv * 2);
+  asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");  // every thread, once
+  const int A = g.wh * g.ww, part = threadIdx.x & 3;
+  const bf16* kb = kmat + ((size_t)w * heads + h) * Spad * DH + part * DPL;
+  float omax = 0.f;
+  for (int qi = threadIdx.x >> 2; qi < nqw; qi += ATT_THREADS / 4) {  // uniform per 4 lanes
+    const int r = q0 + qi;
+    const int n = idx[r];
+    const int kpos = (n - w * g.S) % A;
+    u16x8_t qu[NV], ku[8][NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      qu[v] = *reinterpret_cast<const u16x8_t*>(q + (size_t)n * C + h * DH + part * DPL + 8 * v);
+#pragma unroll
+    for (int f = 0; f < 8; ++f)
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        ku[f][v] = f < g.wt ? *reinterpret_cast<const u16x8_t*>(kb + (size_t)(kpos + f * A) * DH + 8 * v)
+                            : u16x8_t{};
+    float sc[8];
+    float mx = -INFINITY;
+#pragma unroll
+    for (int f = 0; f < 8; ++f) {
+      float d = -INFINITY;
+      if (f < g.wt) {
+        float acc = 0.f;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) acc = fmaf(bf2f(qu[v][e]), bf2f(ku[f][v][e]), acc);
+        acc += __shfl_xor(acc, 1, 64);
+        acc += __shfl_xor(acc, 2, 64);
+        d = acc;
+      }
+      sc[f] = d;
+      mx = fmaxf(mx, d);
+    }
+    float sum = 0.f;
+#pragma unroll
+    for (int f = 0; f < 8; ++f) {
+      const float p = f < g.wt ? __builtin_amdgcn_exp2f(sc[f] - mx) : 0.f;
+      sc[f] = p;
+      sum += p;
+    }
+    const float inv = 1.0f / sum;
+    float ov[DPL];
+#pragma unroll
+    for (int e = 0; e < DPL; ++e) ov[e] = 0.f;
+#pragma unroll
+    for (int f = 0; f < 8; ++f) {
+      if (f < g.wt) {
+        const bf16* vc = Vt + (size_t)(part * DPL) * spv + kpos + f * A;
+#pragma unroll
+        for (int e = 0; e < DPL; ++e) ov[e] = fmaf(sc[f], bf2f(vc[(size_t)e * spv]), ov[e]);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      uint4 pk;
+      pk.x = pack_bf2(ov[8 * v + 0] * inv, ov[8 * v + 1] * inv);
+      pk.y = pack_bf2(ov[8 * v + 2] * inv, ov[8 * v + 3] * inv);
+      pk.z = pack_bf2(ov[8 * v + 4] * inv, ov[8 * v + 5] * inv);
+      pk.w = pack_bf2(ov[8 * v + 6] * inv, ov[8 * v + 7] * inv);
+      *reinterpret_cast<uint4*>(o + (size_t)r * C + h * DH + part * DPL + 8 * v) = pk;
+    }
+    if (amax_o)
+#pragma unroll
+      for (int e = 0; e < DPL; ++e) omax = fmaxf(omax, fabsf(ov[e]) * inv);
+  }
+  if (amax_o) {
+    const float wmx = wave_max(omax);
+    __shared__ float wred[ATT_THREADS / 64];
+    const int wv = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) wred[wv] = wmx;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -448,6 +571,16 @@ void launch_attn_clip(const Geo& g, int C, int heads, int Spad, const bf16* q, c
                       int mode, hipStream_t s) {
   const int dh = C / heads;
   const int nt = Spad / 16;
+  if (mode == 2) {  // temporal blocks of a decoupled network
+    const size_t vlds = (size_t)dh * attn_vt_stride(Spad) * 2;  // V^T of one (window, head)
+    if (dh == 64)
+      attn_temporal_kernel<64><<<g.nwin * heads, ATT_THREADS, vlds, s>>>(g, C, heads, Spad, q, k, vt, idx, woff,
+                                                                         worder, o, amax_o);
+    else if (dh == 32)
+      attn_temporal_kernel<32><<<g.nwin * heads, ATT_THREADS, vlds, s>>>(g, C, heads, Spad, q, k, vt, idx, woff,
+                                                                         worder, o, amax_o);
+    return;
+  }
   const size_t lds = (size_t)Spad * dh * 2 + (size_t)dh * attn_vt_stride(Spad) * 2;
 #define DR_ATTN_CLIP(DH_, NT_, MODE_)                                                                   \
   if (dh == DH_ && nt == NT_ && mode == MODE_) {                                                        \
@@ -462,7 +595,7 @@ void launch_attn_clip(const Geo& g, int C, int heads, int Spad, const bf16* q, c
                                                                                worder, o, amax_o);      \
     return;                                                                                             \
   }
-#define DR_ATTN_CLIP_MODES(DH_, NT_) DR_ATTN_CLIP(DH_, NT_, 0) DR_ATTN_CLIP(DH_, NT_, 1) DR_ATTN_CLIP(DH_, NT_, 2)
+#define DR_ATTN_CLIP_MODES(DH_, NT_) DR_ATTN_CLIP(DH_, NT_, 0) DR_ATTN_CLIP(DH_, NT_, 1)
   DR_ATTN_CLIP_MODES(32, 4)
   DR_ATTN_CLIP_MODES(64, 4)
   DR_ATTN_CLIP_MODES(64, 15)
