@@ -238,10 +238,17 @@ dr_status dr_server_stats(dr_server* srv, int64_t* batches, int64_t* requests, i
 /* Finish all queued work, stop the thread and free the executors. */
 void dr_server_destroy(dr_server* srv);
 
-/* ---- Training (FP32) --------------------------------------------------------------------
+/* ---- Training ----------------------------------------------------------------------------
  * Parameters are addressed as one flat f32 vector in the blob order of dr_load_weights
  * (embed.w OIHW, embed.b, per block ln1.g ... b2, lnf.g, lnf.b, dec.w IOHW, dec.b). */
 size_t dr_param_count(dr_ctx* ctx);
+/* Precision of the training passes (the reverse pass of the thesis's L1-trained network,
+ * Methods, "Model Training"): DR_FP32 (default) or DR_BF16, mixed precision -- the weight
+ * products of the forward (Q/K/V, projection, MLP) and of the reverse pass (input and weight
+ * gradients) take operands rounded to bf16 and accumulate in FP32; weights, activations,
+ * LayerNorm, attention, the loss and every gradient stay FP32.  Applies from the next
+ * dr_train_forward (its dr_train_backward uses the same precision).  DR_EINVAL otherwise. */
+dr_status dr_train_set_precision(dr_ctx* ctx, dr_precision prec);
 /* Forward of B clips (as dr_inpaint, masked queries) keeping the activations the reverse
  * pass needs (per block: block input, LN1 output, K/V, Q, attention output and row max/sum,
  * post-projection rows, LN2 output, MLP pre-activation) in the context.  pred: device f32

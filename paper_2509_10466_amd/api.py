@@ -186,6 +186,12 @@ class Inpainter:
         buf = ct.create_string_buffer(blob, len(blob))
         _lib.check(self.lib, self._ctx, self.lib.dr_load_weights(self._ctx, buf, len(blob)))
 
+    def train_precision(self, precision: str):
+        """"fp32" (default) or "bf16": bf16 operands with FP32 accumulation for the weight
+        products of the training forward and reverse passes (FP32 master weights and
+        gradients); takes effect at the next train_forward."""
+        _lib.check(self.lib, self._ctx, self.lib.dr_train_set_precision(self._ctx, _lib.PRECISION[precision]))
+
     def train_forward(self, frames: torch.Tensor, masks: torch.Tensor, stream=None) -> torch.Tensor:
         """Decoder prediction at every pixel [B,T,H,W,3] (before the composite), keeping the
         activations for train_backward."""

@@ -173,6 +173,7 @@ struct dr_ctx {
   bool prof = false;
   int debug_blocks = -1;  // inspection: run only this many blocks (-1 = all)
   int attn_pattern = 0;   // 0 joint window attention; 1 decoupled (even blocks spatial, odd temporal)
+  int train_bf16 = 0;     // training products with bf16 operands (FP32 accumulation, master weights)
   struct Rec { int stage; hipEvent_t a, b; };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> event_pool;

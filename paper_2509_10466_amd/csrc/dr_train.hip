@@ -1,6 +1,8 @@
 // Training entry points: a forward that keeps the activations the reverse pass needs, the
 // hand-written reverse pass, the L1 training loss, and in-place weight updates from a flat
-// device parameter vector.  All FP32.
+// device parameter vector.  FP32 throughout, or (dr_train_set_precision) with the weight
+// products of both passes taking bf16 operands and accumulating in FP32, against FP32
+// master weights, activations and gradients.
 //
 // The loss follows the thesis's region-weighted per-pixel L1 (Methods, "Model Training --
 // Loss"), taken on the prediction before the composite.  Attention probabilities are not
@@ -33,6 +35,11 @@ void launch_sum_parts(const float* part, int nparts, int width, float* out, int 
 int tn_chunks(int M_max);
 void launch_tn_partial(const float* A, const int32_t* arow, int lda, const float* B, const int32_t* brow, int ldb,
                        const int32_t* M_dev, int M_max, int I, int J, float* part, hipStream_t s);
+void launch_tn_bf16ops(const float* A, const int32_t* arow, int lda, const float* B, const int32_t* brow, int ldb,
+                       const int32_t* M_dev, int M_max, int I, int J, float* part, hipStream_t s);
+void launch_gemm_bf16ops(const float* A, const int32_t* arows, const int32_t* m_dev, int m_max, int K,
+                         const float* W, const float* bias, int Nout, int epi, float* out,
+                         const int32_t* res_rows, hipStream_t s);
 void launch_colsum_partial(const float* B, int ldb, const int32_t* M_dev, int M_max, int J, float* part, hipStream_t s);
 void launch_patches(const Geo& g, const float* frames, const uint8_t* masks, float* P, hipStream_t s);
 void launch_decoder_full(const Geo& g, int C, const float* z, const float* dw, const float* db, float* pred, hipStream_t s);
@@ -76,6 +83,7 @@ struct dr_train {
         *dz = nullptr, *part = nullptr, *lnpart = nullptr, *zeros = nullptr, *tmp = nullptr;
   float *lpart = nullptr, *lacc = nullptr;
   bool have_fwd = false;
+  bool bf16 = false;  // precision of the products of the last forward (and of its reverse pass)
 };
 
 static void train_free(dr_train* t) {
@@ -83,6 +91,13 @@ static void train_free(dr_train* t) {
   t->allocs.clear();
   t->blk.clear();
   t->cap = 0;
+}
+
+// products of both passes: FP32 operands, or bf16 operands with FP32 accumulation
+static void train_gemm(const dr_train* t, const float* A, const int32_t* arows, const int32_t* m_dev, int m_max,
+                       int K, const float* W, const float* bias, int Nout, int epi, float* out,
+                       const int32_t* res_rows, hipStream_t s) {
+  (t->bf16 ? launch_gemm_bf16ops : launch_gemm_f32)(A, arows, m_dev, m_max, K, W, bias, Nout, epi, out, res_rows, s);
 }
 
 static dr_train* train_of(dr_ctx* c) {
@@ -234,6 +249,7 @@ extern "C" dr_status dr_train_forward(dr_ctx* c, const float* frames, const uint
   dr_train* t = train_of(c);
   st = train_reserve(c, t, g);
   if (st != DR_OK) return st;
+  t->bf16 = c->train_bf16 != 0;
   hipStream_t s = (hipStream_t)stream;
   const Net& n = c->net;
   const int C = n.C, R = n.R, N = g.N, heads = n.cfg.heads;
@@ -247,15 +263,15 @@ extern "C" dr_status dr_train_forward(dr_ctx* c, const float* frames, const uint
     TrainBlock& tb = t->blk[l];
     HIP_OK(c, hipMemcpyAsync(tb.x_in, t->x, (size_t)N * C * 4, hipMemcpyDeviceToDevice, s));
     launch_ln_f32(t->x, nullptr, nullptr, N, C, b.ln1g, b.ln1b, tb.u, s);
-    launch_gemm_f32(tb.u, nullptr, nullptr, N, C, b.wkv, b.bkv, 2 * C, EPI_STORE, tb.kv, nullptr, s);
-    launch_gemm_f32(tb.u, t->idx, t->nq, N, C, b.wq, b.bq, C, EPI_STORE, tb.q, nullptr, s);
+    train_gemm(t, tb.u, nullptr, nullptr, N, C, b.wkv, b.bkv, 2 * C, EPI_STORE, tb.kv, nullptr, s);
+    train_gemm(t, tb.u, t->idx, t->nq, N, C, b.wq, b.bq, C, EPI_STORE, tb.q, nullptr, s);
     launch_attn_f32_save(g, C, heads, tb.q, tb.kv, t->woff, tb.o, tb.stats, s);
-    launch_gemm_f32(tb.o, nullptr, t->nq, N, C, b.wo, b.bo, C, EPI_RESID, t->x, t->idx, s);
+    train_gemm(t, tb.o, nullptr, t->nq, N, C, b.wo, b.bo, C, EPI_RESID, t->x, t->idx, s);
     launch_gather_rows(t->x, t->idx, t->nq, N, C, tb.x1, s);
     launch_ln_f32(tb.x1, nullptr, t->nq, N, C, b.ln2g, b.ln2b, tb.n2, s);
-    launch_gemm_f32(tb.n2, nullptr, t->nq, N, C, b.w1, b.b1, R, EPI_STORE, tb.hpre, nullptr, s);
+    train_gemm(t, tb.n2, nullptr, t->nq, N, C, b.w1, b.b1, R, EPI_STORE, tb.hpre, nullptr, s);
     launch_gelu_fwd(tb.hpre, t->nq, N, R, t->a, s);
-    launch_gemm_f32(t->a, nullptr, t->nq, N, R, b.w2, b.b2, C, EPI_RESID, t->x, t->idx, s);
+    train_gemm(t, t->a, nullptr, t->nq, N, R, b.w2, b.b2, C, EPI_RESID, t->x, t->idx, s);
     KCHECK("block");
   }
   HIP_OK(c, hipMemcpyAsync(t->xf, t->x, (size_t)N * C * 4, hipMemcpyDeviceToDevice, s));
@@ -270,7 +286,7 @@ extern "C" dr_status dr_train_forward(dr_ctx* c, const float* frames, const uint
 // grads[off .. off + I*J) = sum over chunks of TN partials
 static void tn_grad(dr_train* t, const float* A, const int32_t* arow, int lda, const float* Bm, const int32_t* brow,
                     int ldb, const int32_t* M_dev, int M_max, int I, int J, float* out, hipStream_t s) {
-  launch_tn_partial(A, arow, lda, Bm, brow, ldb, M_dev, M_max, I, J, t->part, s);
+  (t->bf16 ? launch_tn_bf16ops : launch_tn_partial)(A, arow, lda, Bm, brow, ldb, M_dev, M_max, I, J, t->part, s);
   launch_sum_parts(t->part, tn_chunks(M_max), I * J, out, 0, s);
 }
 
@@ -318,7 +334,7 @@ extern "C" dr_status dr_train_backward(dr_ctx* c, const float* dpred, float* gra
   permute48_kernel<<<(C * 48 + 255) / 256, 256, 0, s>>>(t->tmp, C, G + po.dw);
   colsum_grad(t, t->dyt, 48, nullptr, N, 48, t->tmp, s);
   fold48_kernel<<<1, 64, 0, s>>>(t->tmp, G + po.db);
-  launch_gemm_f32(t->dyt, nullptr, nullptr, N, 48, n.dec_w, t->zeros, C, EPI_STORE, t->dz, nullptr, s);
+  train_gemm(t, t->dyt, nullptr, nullptr, N, 48, n.dec_w, t->zeros, C, EPI_STORE, t->dz, nullptr, s);
   // final LayerNorm
   launch_ln_bwd(t->xf, nullptr, nullptr, N, C, n.lnfg, t->dz, t->dx, 0, 0, t->lnpart, s);
   launch_sum_parts(t->lnpart, ln_bwd_blocks(N), 2 * C, G + po.lnfg, 0, s);  // lnf.g then lnf.b
@@ -332,18 +348,18 @@ extern "C" dr_status dr_train_backward(dr_ctx* c, const float* dpred, float* gra
     launch_gelu_fwd(tb.hpre, t->nq, N, R, t->a, s);
     tn_grad(t, t->dx2, nullptr, C, t->a, nullptr, R, t->nq, N, C, R, G + pb.w2, s);
     colsum_grad(t, t->dx2, C, t->nq, N, C, G + pb.b2, s);
-    launch_gemm_f32(t->dx2, nullptr, t->nq, N, C, b.w2T, t->zeros, R, EPI_STORE, t->da, nullptr, s);
+    train_gemm(t, t->dx2, nullptr, t->nq, N, C, b.w2T, t->zeros, R, EPI_STORE, t->da, nullptr, s);
     launch_gelu_bwd(tb.hpre, t->da, t->nq, N, R, t->dh, s);
     tn_grad(t, t->dh, nullptr, R, tb.n2, nullptr, C, t->nq, N, R, C, G + pb.w1, s);
     colsum_grad(t, t->dh, R, t->nq, N, R, G + pb.b1, s);
-    launch_gemm_f32(t->dh, nullptr, t->nq, N, R, b.w1T, t->zeros, C, EPI_STORE, t->dn2, nullptr, s);
+    train_gemm(t, t->dh, nullptr, t->nq, N, R, b.w1T, t->zeros, C, EPI_STORE, t->dn2, nullptr, s);
     HIP_OK(c, hipMemcpyAsync(t->dx1, t->dx2, (size_t)N * C * 4, hipMemcpyDeviceToDevice, s));
     launch_ln_bwd(tb.x1, nullptr, t->nq, N, C, b.ln2g, t->dn2, t->dx1, 1, 1, t->lnpart, s);
     launch_sum_parts(t->lnpart, ln_bwd_blocks(N), 2 * C, G + pb.ln2g, 0, s);  // ln2.g then ln2.b
     // x1 = x + Wo O + bo
     tn_grad(t, t->dx1, nullptr, C, tb.o, nullptr, C, t->nq, N, C, C, G + pb.wo, s);
     colsum_grad(t, t->dx1, C, t->nq, N, C, G + pb.bo, s);
-    launch_gemm_f32(t->dx1, nullptr, t->nq, N, C, b.woT, t->zeros, C, EPI_STORE, t->dout, nullptr, s);
+    train_gemm(t, t->dx1, nullptr, t->nq, N, C, b.woT, t->zeros, C, EPI_STORE, t->dout, nullptr, s);
     launch_scatter_rows(t->dx1, t->idx, t->nq, N, C, t->dx, s);
     KCHECK("mlp/proj backward");
     // attention
@@ -357,8 +373,8 @@ extern "C" dr_status dr_train_backward(dr_ctx* c, const float* dpred, float* gra
     tn_grad(t, t->dkv + C, nullptr, 2 * C, tb.u, nullptr, C, nullptr, N, C, C, G + pb.wv, s);
     colsum_grad(t, t->dkv, 2 * C, nullptr, N, C, G + pb.bk, s);
     colsum_grad(t, t->dkv + C, 2 * C, nullptr, N, C, G + pb.bv, s);
-    launch_gemm_f32(t->dkv, nullptr, nullptr, N, 2 * C, b.wkvT, t->zeros, C, EPI_STORE, t->du, nullptr, s);
-    launch_gemm_f32(t->dq, nullptr, t->nq, N, C, b.wqT, t->zeros, C, EPI_RESID, t->du, t->idx, s);
+    train_gemm(t, t->dkv, nullptr, nullptr, N, 2 * C, b.wkvT, t->zeros, C, EPI_STORE, t->du, nullptr, s);
+    train_gemm(t, t->dq, nullptr, t->nq, N, C, b.wqT, t->zeros, C, EPI_RESID, t->du, t->idx, s);
     // LN1
     launch_ln_bwd(tb.x_in, nullptr, nullptr, N, C, b.ln1g, t->du, t->dx, 1, 0, t->lnpart, s);
     launch_sum_parts(t->lnpart, ln_bwd_blocks(N), 2 * C, G + pb.ln1g, 0, s);  // ln1.g then ln1.b
@@ -385,5 +401,12 @@ extern "C" dr_status dr_l1_loss(dr_ctx* c, const float* pred, const float* gt, c
   }
   launch_l1_loss(pred, gt, masks, npix, w_in, w_out, t->lpart, t->lacc, loss, dpred, (hipStream_t)stream);
   KCHECK("l1 loss");
+  return DR_OK;
+}
+
+extern "C" dr_status dr_train_set_precision(dr_ctx* c, dr_precision prec) {
+  if (!c) return DR_EINVAL;
+  if (prec != DR_FP32 && prec != DR_BF16) return dr_fail(c, DR_EINVAL, "training precision must be FP32 or BF16");
+  c->train_bf16 = prec == DR_BF16;
   return DR_OK;
 }

@@ -320,8 +320,17 @@ __global__ void sum_parts_kernel(const float* __restrict__ part, int nparts, int
                                  int accumulate) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= width) return;
-  float acc = 0.f;
-  for (int b = 0; b < nparts; ++b) acc += part[(size_t)b * width + c];
+  // four interleaved partial sums (loads in flight together), combined in a fixed order
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+  int b = 0;
+  for (; b + 3 < nparts; b += 4) {
+    a0 += part[(size_t)b * width + c];
+    a1 += part[(size_t)(b + 1) * width + c];
+    a2 += part[(size_t)(b + 2) * width + c];
+    a3 += part[(size_t)(b + 3) * width + c];
+  }
+  for (; b < nparts; ++b) a0 += part[(size_t)b * width + c];
+  const float acc = (a0 + a1) + (a2 + a3);
   out[c] = accumulate ? out[c] + acc : acc;
 }
 
@@ -393,6 +402,208 @@ __global__ void __launch_bounds__(256) tn_partial_kernel(const float* __restrict
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// BF16-operand products for mixed-precision training: FP32 master weights, activations and
+// gradients; every operand is rounded to bf16 (round to nearest even) as it is loaded, and
+// the products accumulate in FP32 on MFMA 16x16x32.  A 64 x 64 output tile per block of four
+// wavefronts, each wavefront 2 x 2 fragments of 16 x 16.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ void tr_mfma_fence() {
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("s_nop 7" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// 8 consecutive FP32 values (32-byte aligned) as bf16, or zeros
+__device__ __forceinline__ bf16x8_t tr_load8(const float* p, bool ok) {
+  bf16x8_t r;
+  if (ok) {
+    const float4 a = *reinterpret_cast<const float4*>(p), b = *reinterpret_cast<const float4*>(p + 4);
+    r[0] = (__bf16)a.x; r[1] = (__bf16)a.y; r[2] = (__bf16)a.z; r[3] = (__bf16)a.w;
+    r[4] = (__bf16)b.x; r[5] = (__bf16)b.y; r[6] = (__bf16)b.z; r[7] = (__bf16)b.w;
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) r[e] = (__bf16)0.f;
+  }
+  return r;
+}
+
+// Y[m, n] = sum_k A[arow(m), k] W[n, k] + bias[n] with the epilogues of the FP32 GEMM
+// (store, exact GELU, or add into out[res_rows(m)]); K % 8 == 0, a k chunk past K reads zeros.
+__global__ void __launch_bounds__(256) gemm_bf16ops_kernel(const float* __restrict__ A, const int32_t* __restrict__ arows,
+                                                           const int32_t* __restrict__ m_dev, int m_max, int K,
+                                                           const float* __restrict__ W, const float* __restrict__ bias,
+                                                           int Nout, int epi, float* __restrict__ out,
+                                                           const int32_t* __restrict__ res_rows) {
+  const int M = m_dev ? m_dev[0] : m_max;
+  const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
+  if (m0 >= M) return;  // uniform per block; no barrier in this kernel
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int l16 = lane & 15, kg = lane >> 4;
+  const int wm = wv >> 1, wn = wv & 1;
+  const float* arow[2];
+  bool aok[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int m = m0 + 32 * wm + 16 * i + l16;
+    aok[i] = m < M;
+    arow[i] = A + (size_t)(aok[i] ? (arows ? arows[m] : m) : 0) * K;
+  }
+  const float* wrow[2];
+  bool wok[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int n = n0 + 32 * wn + 16 * j + l16;
+    wok[j] = n < Nout;
+    wrow[j] = W + (size_t)(wok[j] ? n : 0) * K;
+  }
+  f32x4_t acc[2][2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int i = 0; i < 2; ++i) acc[j][i] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    const int k = k0 + 8 * kg;
+    const bool kok = k < K;
+    bf16x8_t a[2], w[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) a[i] = tr_load8(arow[i] + k, aok[i] && kok);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) w[j] = tr_load8(wrow[j] + k, wok[j] && kok);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[j], a[i], acc[j][i], 0, 0, 0);
+    tr_mfma_fence();
+  }
+  // lane holds Y[m = .. + l16][n = .. + 4 kg + e]
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int m = m0 + 32 * wm + 16 * i + l16;
+    if (m >= M) continue;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int n = n0 + 32 * wn + 16 * j + 4 * kg + e;
+        if (n >= Nout) continue;
+        const float y = acc[j][i][e] + bias[n];
+        if (epi == EPI_STORE) {
+          out[(size_t)m * Nout + n] = y;
+        } else if (epi == EPI_GELU) {
+          out[(size_t)m * Nout + n] = gelu_erf(y);
+        } else {
+          const int dst = res_rows ? res_rows[m] : m;
+          out[(size_t)dst * Nout + n] += y;
+        }
+      }
+    }
+  }
+}
+
+void launch_gemm_bf16ops(const float* A, const int32_t* arows, const int32_t* m_dev, int m_max, int K,
+                         const float* W, const float* bias, int Nout, int epi, float* out,
+                         const int32_t* res_rows, hipStream_t s) {
+  if (m_max <= 0) return;
+  dim3 grid((m_max + 63) / 64, (Nout + 63) / 64);
+  gemm_bf16ops_kernel<<<grid, 256, 0, s>>>(A, arows, m_dev, m_max, K, W, bias, Nout, epi, out, res_rows);
+}
+
+// TN partials with bf16 operands: part[chunk][i][j] = sum over the chunk's rows m of
+// A[arow(m)][i] B[brow(m)][j] (the same partial layout as tn_partial_kernel).  A 64 x 64
+// output tile per block of four wavefronts (32 x 32 each).  Per step of 32 rows, the block
+// loads the rows' 64 columns of A and of B with 16-byte loads, rounds them to bf16 and stores
+// them transposed in LDS ([column][row], rows padded to 40), so that each lane's operand --
+// 8 consecutive rows of one column -- is one 16-byte LDS read.
+constexpr int TN_T = 64, TN_LD = 40;
+__global__ void __launch_bounds__(256) tn_bf16ops_kernel(const float* __restrict__ A, const int32_t* __restrict__ arow,
+                                                         int lda, const float* __restrict__ B,
+                                                         const int32_t* __restrict__ brow, int ldb,
+                                                         const int32_t* __restrict__ M_dev, int M_max, int I, int J,
+                                                         float* __restrict__ part) {
+  __shared__ __align__(16) __bf16 As[TN_T][TN_LD];
+  __shared__ __align__(16) __bf16 Bs[TN_T][TN_LD];
+  const int M = M_dev ? M_dev[0] : M_max;
+  const int i0 = blockIdx.x * TN_T, j0 = blockIdx.y * TN_T, chunk = blockIdx.z;
+  const int m_begin = chunk * RED_CHUNK;
+  const int m_end = min(M, m_begin + RED_CHUNK);
+  const int t = threadIdx.x;
+  const int lane = t & 63, wv = t >> 6;
+  const int l16 = lane & 15, kg = lane >> 4;
+  const int wi = wv >> 1, wj = wv & 1;
+  const int lr = t >> 3, lc = (t & 7) * 8;  // loader: row of the step, first of 8 columns
+  f32x4_t acc[2][2];
+#pragma unroll
+  for (int fj = 0; fj < 2; ++fj)
+#pragma unroll
+    for (int fi = 0; fi < 2; ++fi) acc[fj][fi] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  for (int m0 = m_begin; m0 < m_end; m0 += 32) {
+    const int m = m0 + lr;
+    float va[8], vb[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) va[e] = vb[e] = 0.f;
+    if (m < m_end) {
+      const float* pa = A + (arow ? (size_t)arow[m] : (size_t)m) * lda + i0 + lc;
+      const float* pb = B + (brow ? (size_t)brow[m] : (size_t)m) * ldb + j0 + lc;
+      if (i0 + lc + 8 <= I && ((reinterpret_cast<uintptr_t>(pa) & 15) == 0)) {
+        const float4 a0 = *reinterpret_cast<const float4*>(pa), a1 = *reinterpret_cast<const float4*>(pa + 4);
+        va[0] = a0.x; va[1] = a0.y; va[2] = a0.z; va[3] = a0.w; va[4] = a1.x; va[5] = a1.y; va[6] = a1.z; va[7] = a1.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) va[e] = i0 + lc + e < I ? pa[e] : 0.f;
+      }
+      if (j0 + lc + 8 <= J && ((reinterpret_cast<uintptr_t>(pb) & 15) == 0)) {
+        const float4 b0 = *reinterpret_cast<const float4*>(pb), b1 = *reinterpret_cast<const float4*>(pb + 4);
+        vb[0] = b0.x; vb[1] = b0.y; vb[2] = b0.z; vb[3] = b0.w; vb[4] = b1.x; vb[5] = b1.y; vb[6] = b1.z; vb[7] = b1.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) vb[e] = j0 + lc + e < J ? pb[e] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      As[lc + e][lr] = (__bf16)va[e];
+      Bs[lc + e][lr] = (__bf16)vb[e];
+    }
+    __syncthreads();
+    bf16x8_t x[2], y[2];
+#pragma unroll
+    for (int fi = 0; fi < 2; ++fi) x[fi] = *reinterpret_cast<const bf16x8_t*>(&As[32 * wi + 16 * fi + l16][8 * kg]);
+#pragma unroll
+    for (int fj = 0; fj < 2; ++fj) y[fj] = *reinterpret_cast<const bf16x8_t*>(&Bs[32 * wj + 16 * fj + l16][8 * kg]);
+    __syncthreads();
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int fj = 0; fj < 2; ++fj)
+#pragma unroll
+      for (int fi = 0; fi < 2; ++fi) acc[fj][fi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(y[fj], x[fi], acc[fj][fi], 0, 0, 0);
+    tr_mfma_fence();
+  }
+  // lane holds D[j = .. + 4 kg + e][i = .. + l16]
+  float* P = part + (size_t)chunk * I * J;
+#pragma unroll
+  for (int fi = 0; fi < 2; ++fi) {
+    const int i = i0 + 32 * wi + 16 * fi + l16;
+    if (i >= I) continue;
+#pragma unroll
+    for (int fj = 0; fj < 2; ++fj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int j = j0 + 32 * wj + 16 * fj + 4 * kg + e;
+        if (j < J) P[(size_t)i * J + j] = acc[fj][fi][e];
+      }
+  }
+}
+
+void launch_tn_bf16ops(const float* A, const int32_t* arow, int lda, const float* B, const int32_t* brow, int ldb,
+                       const int32_t* M_dev, int M_max, int I, int J, float* part, hipStream_t s) {
+  const int chunks = (M_max + RED_CHUNK - 1) / RED_CHUNK;
+  if (chunks <= 0) return;
+  dim3 grid((I + TN_T - 1) / TN_T, (J + TN_T - 1) / TN_T, chunks);
+  tn_bf16ops_kernel<<<grid, 256, 0, s>>>(A, arow, lda, B, brow, ldb, M_dev, M_max, I, J, part);
+}
+
 int tn_chunks(int M_max) { return (M_max + RED_CHUNK - 1) / RED_CHUNK; }
 
 void launch_tn_partial(const float* A, const int32_t* arow, int lda, const float* B, const int32_t* brow, int ldb,
@@ -403,23 +614,42 @@ void launch_tn_partial(const float* A, const int32_t* arow, int lda, const float
   tn_partial_kernel<<<grid, 256, 0, s>>>(A, arow, lda, B, brow, ldb, M_dev, M_max, I, J, part);
 }
 
-__global__ void colsum_partial_kernel(const float* __restrict__ B, int ldb, const int32_t* __restrict__ M_dev,
-                                      int M_max, int J, float* __restrict__ part) {
+// One block per (64 columns, chunk): 16 row groups of 64 lanes, each lane summing every 16th
+// row of its column with 8 independent partial sums (loads in flight together), then a fixed
+// order reduction of the groups in LDS (deterministic).
+__global__ void __launch_bounds__(1024) colsum_partial_kernel(const float* __restrict__ B, int ldb,
+                                                              const int32_t* __restrict__ M_dev, int M_max, int J,
+                                                              float* __restrict__ part) {
+  __shared__ float red[16][64];
   const int M = M_dev ? M_dev[0] : M_max;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int col = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + col;
   const int chunk = blockIdx.y;
-  if (j >= J) return;
-  const int m_end = min(M, (chunk + 1) * RED_CHUNK);
-  float acc = 0.f;
-  for (int m = chunk * RED_CHUNK; m < m_end; ++m) acc += B[(size_t)m * ldb + j];
-  part[(size_t)chunk * J + j] = acc;
+  const int m_begin = chunk * RED_CHUNK, m_end = min(M, m_begin + RED_CHUNK);
+  float acc[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) acc[u] = 0.f;
+  if (j < J) {
+    int m = m_begin + grp;
+    for (; m + 7 * 16 < m_end; m += 8 * 16)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] += B[(size_t)(m + 16 * u) * ldb + j];
+    for (; m < m_end; m += 16) acc[0] += B[(size_t)m * ldb + j];
+  }
+  red[grp][col] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  __syncthreads();
+  if (grp == 0 && j < J) {
+    float t = 0.f;
+    for (int g = 0; g < 16; ++g) t += red[g][col];
+    part[(size_t)chunk * J + j] = t;
+  }
 }
 
 void launch_colsum_partial(const float* B, int ldb, const int32_t* M_dev, int M_max, int J, float* part,
                            hipStream_t s) {
   const int chunks = tn_chunks(M_max);
   if (chunks <= 0) return;
-  colsum_partial_kernel<<<dim3((J + 255) / 256, chunks), 256, 0, s>>>(B, ldb, M_dev, M_max, J, part);
+  colsum_partial_kernel<<<dim3((J + 63) / 64, chunks), 1024, 0, s>>>(B, ldb, M_dev, M_max, J, part);
 }
 
 // ------------------------------------------------------------------------------------------

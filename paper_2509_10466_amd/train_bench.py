@@ -1,7 +1,9 @@
 """Training-step timing: forward with saved activations, weighted L1 loss, hand-written
-backward (FP32), on 4 clips of 5 x 240 x 432 (seeds 0..3, ground truth = the uncut frames).
+backward, on 4 clips of 5 x 240 x 432 (seeds 0..3, ground truth = the uncut frames), in
+FP32 or mixed precision (bf16 operands of the weight products, FP32 accumulation and master
+weights and gradients).
 
-    python -m paper_2509_10466_amd.train_bench [--steps 5]
+    python -m paper_2509_10466_amd.train_bench [--steps 5] [--precision fp32|bf16]
 
 Prints one JSON line with the per-step time split (forward, loss, backward) from HIP events
 on the launch stream, and the parameter-gradient norm as a sanity figure.
@@ -24,6 +26,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--clips", type=int, default=4)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
     args = ap.parse_args()
 
     import torch
@@ -32,6 +35,7 @@ def main():
 
     cfg = drsynth.NETS["clip240"]
     eng = Inpainter(cfg, drsynth.make_weights(cfg, 0))
+    eng.train_precision(args.precision)
     fs, ms = [], []
     for seed in range(args.clips):
         f, m, _ = drsynth.make_clip(seed, 5, 240, 432)
@@ -59,7 +63,7 @@ def main():
         t_b.append(e[2].elapsed_time(e[3]))
         gnorm = float(grads.norm())
     tot = np.array(t_f) + np.array(t_l) + np.array(t_b)
-    print(json.dumps({"workload": f"{args.clips} clips x 5 x 240 x 432, clip240 net, FP32 forward + backward",
+    print(json.dumps({"workload": f"{args.clips} clips x 5 x 240 x 432, clip240 net, {args.precision} forward + backward",
                       "ms_per_step": round(float(tot.mean()), 3), "forward_ms": round(float(np.mean(t_f)), 3),
                       "loss_ms": round(float(np.mean(t_l)), 3), "backward_ms": round(float(np.mean(t_b)), 3),
                       "frames_per_s": round(args.clips * 5 * 1000.0 / float(tot.mean()), 2),

@@ -106,3 +106,58 @@ def test_autograd_function_and_sgd_step(dev):
     _say(f"loss {float(loss):.6f} -> {float(loss2):.6f} after one normalised step")
     assert float(loss2) < float(loss)
     eng.close()
+
+
+# ------------------------------------------------------------------------------------------
+# mixed precision: bf16 operands, FP32 accumulation, FP32 master weights and gradients
+# ------------------------------------------------------------------------------------------
+# Every weight product rounds both operands to bf16 (unit roundoff u = 2^-9); a gradient entry
+# of a 2-block network passes through about ten such products in the forward and reverse
+# passes, so its relative error is bounded by roughly 10 * 2u = 4e-2 (first order), and the
+# rounding errors of different products are independent, so the normwise error sits well
+# inside that.  The forward prediction is held to the BF16 inference bound.
+BF16_GRAD_TOL = 4e-2
+
+
+@pytest.mark.parametrize("case", ["tiny64", "mid"])
+def test_bf16_backward_matches_oracle_gradient(dev, case):
+    from paper_2509_10466_amd import Inpainter
+    cfg, frames, masks = case_inputs(case)
+    W = drsynth.make_weights(cfg, 0)
+    eng = Inpainter(cfg, W)
+    _, _, pred32 = _gpu_grad(eng, frames, masks)
+    eng.train_precision("bf16")
+    L, g, pred = _gpu_grad(eng, frames, masks)
+    Lr, Gr = og.loss_and_grad(frames, masks, W, cfg)
+    gr = _flat(cfg, Gr)
+    assert np.abs(pred - pred32).max() <= 2e-2
+    assert abs(L - Lr) <= 1e-2 * abs(Lr)
+    rel = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    cos = float(g @ gr / (np.linalg.norm(g) * np.linalg.norm(gr)))
+    _say(f"[bf16 grad] {case}: loss gpu {L:.7f} oracle {Lr:.7f}; normwise relative error {rel:.3e}, cosine {cos:.6f}")
+    assert rel <= BF16_GRAD_TOL
+    eng.train_precision("fp32")
+    _, g32, _ = _gpu_grad(eng, frames, masks)
+    assert np.linalg.norm(g32 - gr) / np.linalg.norm(gr) <= 1e-3  # switching back restores FP32
+    eng.close()
+
+
+def test_bf16_backward_is_deterministic(dev):
+    from paper_2509_10466_amd import Inpainter
+    cfg, frames, masks = case_inputs("mid_b2")
+    eng = Inpainter(cfg, drsynth.make_weights(cfg, 0))
+    eng.train_precision("bf16")
+    _, g1, _ = _gpu_grad(eng, frames, masks)
+    _, g2, _ = _gpu_grad(eng, frames, masks)
+    assert np.array_equal(g1, g2)
+    eng.close()
+
+
+def test_train_precision_rejects_fp8(dev):
+    from paper_2509_10466_amd import Inpainter
+    from paper_2509_10466_amd._lib import DrError
+    cfg, _, _ = case_inputs("tiny64")
+    eng = Inpainter(cfg, drsynth.make_weights(cfg, 0))
+    with pytest.raises(DrError, match="DR_EINVAL"):
+        eng.train_precision("fp8")
+    eng.close()
