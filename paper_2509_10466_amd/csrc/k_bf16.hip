@@ -50,6 +50,11 @@ __device__ __forceinline__ T bitcast(const S& s) {
 // takes query tiles of 16: S^T = K Q^T, row softmax in FP32 registers, O^T = V^T P^T.
 // ------------------------------------------------------------------------------------------
 constexpr int ATT_THREADS = 512;
+// Blocks per (window, head) of the clip attention kernel.  Two (each staging the window and
+// taking every other group of 8 query tiles) measured slower at 240 keys: 128 against
+// 114 us of attention per clip, the second staging of the busiest windows costing more
+// than their second pass over query tiles.
+constexpr int ATT_SPLIT = 1;
 
 __host__ __device__ constexpr int attn_vt_stride(int spad) { return (spad / 8) % 2 ? spad : spad + 8; }
 
@@ -129,16 +134,17 @@ struct KeyMask {
   int A, wbase;
 };
 
-template <int DH, int NT, class Keys, int MODE = 0>
+template <int DH, int NT, class Keys, int MODE = 0, int QSTEP = ATT_THREADS / 64>
 __device__ __forceinline__ float attn_query_tiles(const bf16* Ks, const bf16* Vt, const Keys& keys, int C, int h,
                                                  const bf16* __restrict__ q, const int32_t* __restrict__ idx,
                                                  int q0, int nqw, bf16* __restrict__ o, bf16x8_t (&qnext)[DH / 32],
-                                                 bool want_amax, KeyMask km = KeyMask{0, 0}) {
+                                                 bool want_amax, KeyMask km = KeyMask{0, 0}, int qt_base = 0) {
   constexpr int CH = DH / 8;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int l16 = lane & 15, kg = lane >> 4;
   float omax = 0.f;
-  for (int qt = wv; qt * 16 < nqw; qt += ATT_THREADS / 64) {
+  // query tiles qt_base + wv, then every QSTEP-th (the caller loaded the first one's Q)
+  for (int qt = qt_base + wv; qt * 16 < nqw; qt += QSTEP) {
     // K and V^T fragments are re-read from LDS per query tile: hoisting them out of the loop
     // would hold the whole window in registers
     asm volatile("" ::: "memory");
@@ -183,7 +189,8 @@ __device__ __forceinline__ float attn_query_tiles(const bf16* Ks, const bf16* Vt
     bf16x8_t qf[DH / 32];
 #pragma unroll
     for (int kk = 0; kk < DH / 32; ++kk) qf[kk] = qnext[kk];
-    if ((qt + ATT_THREADS / 64) * 16 < nqw) attn_load_q<DH>(q, idx, q0, nqw, C, h, qt + ATT_THREADS / 64, qnext);
+    // (nqw <= 16 NT: with QSTEP >= NT no wavefront has a second tile)
+    if (QSTEP < NT && (qt + QSTEP) * 16 < nqw) attn_load_q<DH>(q, idx, q0, nqw, C, h, qt + QSTEP, qnext);
     // S^T = K Q^T: key tiles in groups of TG, each tile's k slices chained, the chains of a
     // group interleaved; a group's K fragments are read while the previous group multiplies
     constexpr int KS = DH / 32;  // 32-wide k slices
@@ -342,20 +349,24 @@ __global__ void __launch_bounds__(ATT_THREADS, (attn_clip_waves_per_simd<NT, MOD
   extern __shared__ __align__(16) bf16 att_lds[];
   bf16* Ks = att_lds;            // [SP][DH], swizzled chunks
   bf16* Vt = att_lds + SP * DH;  // [DH][SPV]
-  // (window, head) work in order of decreasing query count
-  const int rank = blockIdx.x / heads, h = blockIdx.x - rank * heads;
+  // (window, head) work in order of decreasing query count; ATT_SPLIT blocks per (window,
+  // head), block `part` taking query tiles 8 part + wv, then every 8 ATT_SPLIT-th, so a
+  // window with more than 8 query tiles spreads over several CUs
+  const int part = blockIdx.x % ATT_SPLIT, wh_ = blockIdx.x / ATT_SPLIT;
+  const int rank = wh_ / heads, h = wh_ - rank * heads;
   const int w = worder[rank];
   const int q0 = woff[w], nqw = woff[w + 1] - q0;
-  if (nqw == 0) return;
+  constexpr int QW = ATT_THREADS / 64;  // query tiles per pass of the block
+  if (QW * part * 16 >= nqw) return;    // uniform per block
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   bf16x8_t qnext[DH / 32];
-  if (wv * 16 < nqw) attn_load_q<DH>(q, idx, q0, nqw, C, h, wv, qnext);
+  if ((QW * part + wv) * 16 < nqw) attn_load_q<DH>(q, idx, q0, nqw, C, h, QW * part + wv, qnext);
   attn_dma<CH, true>(kmat + ((size_t)w * heads + h) * SP * DH, Ks, SP * DH * 2);
   attn_dma<CH, false>(vtmat + ((size_t)w * heads + h) * DH * SPV, Vt, DH * SPV * 2);
   asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
-  const float wmx = attn_query_tiles<DH, NT, ClipKeys<NT, SPV>, MODE>(
+  const float wmx = attn_query_tiles<DH, NT, ClipKeys<NT, SPV>, MODE, QW * ATT_SPLIT>(
       Ks, Vt, ClipKeys<NT, SPV>{g.S}, C, h, q, idx, q0, nqw, o, qnext, amax_o != nullptr,
-      KeyMask{g.wh * g.ww, w * g.S});
+      KeyMask{g.wh * g.ww, w * g.S}, QW * part);
   if (amax_o) {
     // max |O| of the block into the per-call slot that scales O for an FP8 projection: one
     // atomic per block, skipped when the slot already holds more (non-negative floats order
@@ -591,7 +602,7 @@ void launch_attn_clip(const Geo& g, int C, int heads, int Spad, const bf16* q, c
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
       attr = true;                                                                                      \
     }                                                                                                   \
-    attn_clip_kernel<DH_, NT_, MODE_><<<g.nwin * heads, ATT_THREADS, lds, s>>>(g, C, heads, q, k, vt, idx, woff, \
+    attn_clip_kernel<DH_, NT_, MODE_><<<g.nwin * heads * ATT_SPLIT, ATT_THREADS, lds, s>>>(g, C, heads, q, k, vt, idx, woff, \
                                                                                worder, o, amax_o);      \
     return;                                                                                             \
   }
