@@ -167,3 +167,15 @@ def test_reloading_plain_weights_switches_back(dev):
     assert np.array_equal(run(eng, frames, masks), plain)
     assert not np.array_equal(first, plain)
     eng.close()
+
+
+@pytest.mark.parametrize("qs", ["masked", "all"])
+def test_overlap_with_decoupled_attention(dev, qs):
+    """The two variants together: kernel-8 embedding and fold decoder around decoupled blocks."""
+    cfg, frames, masks = case_inputs("mid")
+    cfg = dataclasses.replace(cfg, overlap=True, attn="decoupled")
+    _say(f"[ovl+dec] qs={qs}")
+    eng, W = engine(cfg)
+    out = run(eng, frames, masks, "bf16", qs)
+    mx, n = compare(out, on.forward(frames, masks, W, cfg, qs), frames, masks, TOL["bf16"])
+    _say(f"    max abs err {mx:.3e} over {n} in-mask values")
