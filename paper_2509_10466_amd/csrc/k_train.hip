@@ -430,46 +430,46 @@ __device__ __forceinline__ bf16x8_t tr_load8(const float* p, bool ok) {
 
 // Y[m, n] = sum_k A[arow(m), k] W[n, k] + bias[n] with the epilogues of the FP32 GEMM
 // (store, exact GELU, or add into out[res_rows(m)]); K % 8 == 0, a k chunk past K reads zeros.
+// Per 32-wide k step the block loads the 64 rows of A and of W once (two 16-byte loads per
+// thread each), rounds them to bf16 into LDS (rows padded to 40), and each wavefront reads
+// its operand fragments from there.
+constexpr int GB_LD = 40;
 __global__ void __launch_bounds__(256) gemm_bf16ops_kernel(const float* __restrict__ A, const int32_t* __restrict__ arows,
                                                            const int32_t* __restrict__ m_dev, int m_max, int K,
                                                            const float* __restrict__ W, const float* __restrict__ bias,
                                                            int Nout, int epi, float* __restrict__ out,
                                                            const int32_t* __restrict__ res_rows) {
+  __shared__ __align__(16) __bf16 As[64][GB_LD];
+  __shared__ __align__(16) __bf16 Ws[64][GB_LD];
   const int M = m_dev ? m_dev[0] : m_max;
   const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
-  if (m0 >= M) return;  // uniform per block; no barrier in this kernel
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (m0 >= M) return;  // uniform per block
+  const int t = threadIdx.x;
+  const int lane = t & 63, wv = t >> 6;
   const int l16 = lane & 15, kg = lane >> 4;
   const int wm = wv >> 1, wn = wv & 1;
-  const float* arow[2];
-  bool aok[2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int m = m0 + 32 * wm + 16 * i + l16;
-    aok[i] = m < M;
-    arow[i] = A + (size_t)(aok[i] ? (arows ? arows[m] : m) : 0) * K;
-  }
-  const float* wrow[2];
-  bool wok[2];
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int n = n0 + 32 * wn + 16 * j + l16;
-    wok[j] = n < Nout;
-    wrow[j] = W + (size_t)(wok[j] ? n : 0) * K;
-  }
+  // loader: row lr of the tile, k columns lk .. lk + 7 of the step
+  const int lr = t >> 2, lk = (t & 3) * 8;
+  const int am = m0 + lr, wnr = n0 + lr;
+  const bool aok = am < M, wok = wnr < Nout;
+  const float* arow = A + (size_t)(aok ? (arows ? arows[am] : am) : 0) * K;
+  const float* wrow = W + (size_t)(wok ? wnr : 0) * K;
   f32x4_t acc[2][2];
 #pragma unroll
   for (int j = 0; j < 2; ++j)
 #pragma unroll
     for (int i = 0; i < 2; ++i) acc[j][i] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < K; k0 += 32) {
-    const int k = k0 + 8 * kg;
-    const bool kok = k < K;
+    const int k = k0 + lk;
+    *reinterpret_cast<bf16x8_t*>(&As[lr][lk]) = tr_load8(arow + k, aok && k < K);
+    *reinterpret_cast<bf16x8_t*>(&Ws[lr][lk]) = tr_load8(wrow + k, wok && k < K);
+    __syncthreads();
     bf16x8_t a[2], w[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) a[i] = tr_load8(arow[i] + k, aok[i] && kok);
+    for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8_t*>(&As[32 * wm + 16 * i + l16][8 * kg]);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) w[j] = tr_load8(wrow[j] + k, wok[j] && kok);
+    for (int j = 0; j < 2; ++j) w[j] = *reinterpret_cast<const bf16x8_t*>(&Ws[32 * wn + 16 * j + l16][8 * kg]);
+    __syncthreads();
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int j = 0; j < 2; ++j)
