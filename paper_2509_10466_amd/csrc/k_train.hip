@@ -88,7 +88,7 @@ __global__ void __launch_bounds__(256) attn_f32_save_kernel(Geo g, int C, int he
                                                             const float* __restrict__ kv,
                                                             const int32_t* __restrict__ woff, float* __restrict__ o,
                                                             float2* __restrict__ stats) {
-  __shared__ float qs[4][64];
+  __shared__ __align__(16) float qs[4][64];
   __shared__ float ps[4][320];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int w = blockIdx.x / heads, h = blockIdx.x - w * heads;
@@ -105,7 +105,16 @@ __global__ void __launch_bounds__(256) attn_f32_save_kernel(Geo g, int C, int he
   for (int s = lane; s < g.S; s += 64) {
     const float* kr = kbase + (size_t)s * 2 * C;
     float d = 0.f;
-    for (int e = 0; e < dh; ++e) d = fmaf(qs[wv][e], kr[e], d);
+    // the lane's key row in 16-byte pieces (dh % 4 == 0; rows and head offsets are 16-byte
+    // aligned), summed in channel order
+    for (int e = 0; e < dh; e += 4) {
+      const float4 k4 = *reinterpret_cast<const float4*>(kr + e);
+      const float4 q4 = *reinterpret_cast<const float4*>(&qs[wv][e]);
+      d = fmaf(q4.x, k4.x, d);
+      d = fmaf(q4.y, k4.y, d);
+      d = fmaf(q4.z, k4.z, d);
+      d = fmaf(q4.w, k4.w, d);
+    }
     d *= scale;
     ps[wv][s] = d;
     mx = fmaxf(mx, d);
@@ -121,8 +130,14 @@ __global__ void __launch_bounds__(256) attn_f32_save_kernel(Geo g, int C, int he
   __builtin_amdgcn_wave_barrier();
   if (lane < dh) {
     const float* vbase = kbase + C + lane;
-    float acc = 0.f;
-    for (int s = 0; s < g.S; ++s) acc = fmaf(ps[wv][s], vbase[(size_t)s * 2 * C], acc);
+    // eight interleaved partial sums keep eight loads in flight; fixed combination order
+    float a8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int s = 0;
+    for (; s + 7 < g.S; s += 8)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a8[u] = fmaf(ps[wv][s + u], vbase[(size_t)(s + u) * 2 * C], a8[u]);
+    for (; s < g.S; ++s) a8[0] = fmaf(ps[wv][s], vbase[(size_t)s * 2 * C], a8[0]);
+    const float acc = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
     o[(size_t)r * C + h * dh + lane] = acc / sum;
   }
   if (lane == 0) stats[(size_t)r * heads + h] = make_float2(mx, sum);
@@ -145,8 +160,8 @@ __global__ void __launch_bounds__(256) attn_bwd_q_kernel(Geo g, int C, int heads
                                                          const float2* __restrict__ stats,
                                                          const int32_t* __restrict__ woff, float* __restrict__ dq,
                                                          float* __restrict__ P, float* __restrict__ dS) {
-  __shared__ float qs[4][64];
-  __shared__ float dos[4][64];
+  __shared__ __align__(16) float qs[4][64];
+  __shared__ __align__(16) float dos[4][64];
   __shared__ float ds_[4][320];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int w = blockIdx.x / heads, h = blockIdx.x - w * heads;
@@ -170,9 +185,19 @@ __global__ void __launch_bounds__(256) attn_bwd_q_kernel(Geo g, int C, int heads
     const float* kr = kbase + (size_t)s * 2 * C;
     const float* vr = kr + C;
     float d = 0.f, dp = 0.f;
-    for (int e = 0; e < dh; ++e) {
-      d = fmaf(qs[wv][e], kr[e], d);
-      dp = fmaf(dos[wv][e], vr[e], dp);
+    for (int e = 0; e < dh; e += 4) {  // 16-byte pieces of the key and value rows, channel order
+      const float4 k4 = *reinterpret_cast<const float4*>(kr + e);
+      const float4 v4 = *reinterpret_cast<const float4*>(vr + e);
+      const float4 q4 = *reinterpret_cast<const float4*>(&qs[wv][e]);
+      const float4 o4 = *reinterpret_cast<const float4*>(&dos[wv][e]);
+      d = fmaf(q4.x, k4.x, d);
+      d = fmaf(q4.y, k4.y, d);
+      d = fmaf(q4.z, k4.z, d);
+      d = fmaf(q4.w, k4.w, d);
+      dp = fmaf(o4.x, v4.x, dp);
+      dp = fmaf(o4.y, v4.y, dp);
+      dp = fmaf(o4.z, v4.z, dp);
+      dp = fmaf(o4.w, v4.w, dp);
     }
     const float p = expf(d * scale - st.x) / st.y;
     prow[s] = p;
@@ -188,8 +213,14 @@ __global__ void __launch_bounds__(256) attn_bwd_q_kernel(Geo g, int C, int heads
   }
   __builtin_amdgcn_wave_barrier();
   if (lane < dh) {
-    float acc = 0.f;
-    for (int s = 0; s < g.S; ++s) acc = fmaf(ds_[wv][s], kbase[(size_t)s * 2 * C + lane], acc);
+    // eight interleaved partial sums keep eight loads in flight; fixed combination order
+    float a8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int s = 0;
+    for (; s + 7 < g.S; s += 8)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a8[u] = fmaf(ds_[wv][s + u], kbase[(size_t)(s + u) * 2 * C + lane], a8[u]);
+    for (; s < g.S; ++s) a8[0] = fmaf(ds_[wv][s], kbase[(size_t)s * 2 * C + lane], a8[0]);
+    const float acc = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
     dq[(size_t)r * C + h * dh + lane] = acc * scale;
   }
 }
@@ -216,13 +247,24 @@ __global__ void __launch_bounds__(256) attn_bwd_kv_kernel(Geo g, int C, int head
   const float scale = rsqrtf((float)dh);
   for (int e = blockIdx.y * blockDim.x + threadIdx.x; e < g.S * dh; e += gridDim.y * blockDim.x) {
     const int s = e / dh, d = e - s * dh;
-    float ak = 0.f, av = 0.f;
-    for (int j = 0; j < nqw; ++j) {
+    // four interleaved partial sums per output (loads of four queries in flight), fixed order
+    float ak4[4] = {0.f, 0.f, 0.f, 0.f}, av4[4] = {0.f, 0.f, 0.f, 0.f};
+    int j = 0;
+    for (; j + 3 < nqw; j += 4)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const size_t r = (size_t)(q0 + j + u);
+        const size_t pi = (r * heads + h) * g.S + s;
+        ak4[u] = fmaf(dS[pi], q[r * C + h * dh + d], ak4[u]);
+        av4[u] = fmaf(P[pi], dout[r * C + h * dh + d], av4[u]);
+      }
+    for (; j < nqw; ++j) {
       const size_t r = (size_t)(q0 + j);
       const size_t pi = (r * heads + h) * g.S + s;
-      ak = fmaf(dS[pi], q[r * C + h * dh + d], ak);
-      av = fmaf(P[pi], dout[r * C + h * dh + d], av);
+      ak4[0] = fmaf(dS[pi], q[r * C + h * dh + d], ak4[0]);
+      av4[0] = fmaf(P[pi], dout[r * C + h * dh + d], av4[0]);
     }
+    const float ak = (ak4[0] + ak4[1]) + (ak4[2] + ak4[3]), av = (av4[0] + av4[1]) + (av4[2] + av4[3]);
     float* row = dkv + ((size_t)w * g.S + s) * 2 * C + h * dh + d;
     row[0] = ak * scale;
     row[C] = av;
