@@ -140,3 +140,22 @@ def test_decoupled_rejects_fp32_stream_and_training(dev):
     from paper_2509_10466_amd import _lib
     with pytest.raises(DrError, match="DR_EINVAL"):
         _lib.check(eng.lib, eng._ctx, eng.lib.dr_set_attention_pattern(eng._ctx, 2))
+
+
+def _clip720_net_small(seed=3):
+    """The 384-dim, 12-block clip720 network (6 x 10 x 5-token windows: 300 keys, padded to
+    304) on a 5 x 48 x 80 clip of 2 x 2 windows, small enough for the whole-clip oracle."""
+    f, m, _ = drsynth.make_clip(seed, 5, 48, 80, cov_range=(0.2, 0.4))
+    return drsynth.NETS["clip720"], f, m
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+@pytest.mark.parametrize("qs", ["masked", "all"])
+def test_decoupled_clip720_network(dev, precision, qs):
+    cfg, frames, masks = _clip720_net_small()
+    cfg = dec(cfg)
+    _say(f"[decoupled clip720 net] prec={precision} qs={qs}")
+    eng, W = engine(cfg)
+    out = run(eng, frames, masks, precision, qs)
+    mx, n = compare(out, on.forward(frames, masks, W, cfg, qs), frames, masks, TOL[precision])
+    _say(f"    max abs err {mx:.3e} over {n} in-mask values")

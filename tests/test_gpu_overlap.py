@@ -179,3 +179,16 @@ def test_overlap_with_decoupled_attention(dev, qs):
     out = run(eng, frames, masks, "bf16", qs)
     mx, n = compare(out, on.forward(frames, masks, W, cfg, qs), frames, masks, TOL["bf16"])
     _say(f"    max abs err {mx:.3e} over {n} in-mask values")
+
+
+@pytest.mark.parametrize("qs", ["masked", "all"])
+def test_overlap_clip720_network(dev, qs):
+    """The 384-dim, 12-block clip720 network with the kernel-8 embedding and fold decoder on
+    a 5 x 48 x 80 clip (2 x 2 windows of 6 x 10 tokens), whole clip against the oracle."""
+    f, m, _ = drsynth.make_clip(4, 5, 48, 80, cov_range=(0.2, 0.4))
+    cfg = ovl(drsynth.NETS["clip720"])
+    _say(f"[ovl clip720 net] qs={qs}")
+    eng, W = engine(cfg)
+    out = run(eng, f, m, "bf16", qs)
+    mx, n = compare(out, on.forward(f, m, W, cfg, qs), f, m, TOL["bf16"])
+    _say(f"    max abs err {mx:.3e} over {n} in-mask values")
