@@ -182,6 +182,8 @@ void launch_decode(const Geo& g, int C, const float* x, const int32_t* idx, cons
 // lane's MFMA operands come straight from its own loads.
 // Only what later steps read is stored: x^ of tokens in windows with queries (of every token
 // when wcount is null: stream mode keeps K/V of all tokens), x of flagged tokens.
+constexpr int EMB_WLD = 72;  // LDS row stride (bf16) of the staged embedding weight
+
 template <int C>
 __global__ void __launch_bounds__(256) embed_bf16_kernel(Geo g, const float* __restrict__ frames,
                                                          const uint8_t* __restrict__ masks,
@@ -194,7 +196,17 @@ __global__ void __launch_bounds__(256) embed_bf16_kernel(Geo g, const float* __r
   const int l16 = lane & 15, kg = lane >> 4;
   const int n = (blockIdx.x * 4 + wv) * 16 + l16;
   const bool need_h = n < g.N && (wcount == nullptr || wcount[n / g.S] > 0);
-  if (!__any(need_h)) return;  // wave-uniform: no barrier in this kernel
+  // the weight [C][64] staged once per block in LDS (rows padded to EMB_WLD) for the four
+  // wavefronts, instead of each reading it from L2
+  if (!__syncthreads_or(need_h)) return;  // uniform per block
+  extern __shared__ __align__(16) bf16 emb_w[];
+  for (int c = threadIdx.x; c < C * 8; c += blockDim.x) {
+    const int row = c >> 3, part = c & 7;
+    *reinterpret_cast<uint4*>(emb_w + row * EMB_WLD + part * 8) =
+        *reinterpret_cast<const uint4*>(wT16 + (size_t)row * 64 + part * 8);
+  }
+  __syncthreads();
+  if (!__any(need_h)) return;  // wave-uniform; no barrier follows
   const bool need_x = need_h && flag[n] != 0;
   float v[12];
 #pragma unroll
@@ -224,7 +236,7 @@ __global__ void __launch_bounds__(256) embed_bf16_kernel(Geo g, const float* __r
   float sum = 0.f;
 #pragma unroll
   for (int f = 0; f < FN; ++f) {
-    const bf16* wr = wT16 + (size_t)(16 * f + l16) * 64 + 8 * kg;
+    const bf16* wr = emb_w + (16 * f + l16) * EMB_WLD + 8 * kg;
     const bf16x8_t w0 = *reinterpret_cast<const bf16x8_t*>(wr);
     const bf16x8_t w1 = *reinterpret_cast<const bf16x8_t*>(wr + 32);
     f32x4_t a = {0.f, 0.f, 0.f, 0.f};
@@ -270,11 +282,12 @@ void launch_embed_bf16(const Geo& g, int C, const float* frames, const uint8_t* 
                        const int32_t* wcount, const bf16* wT16, const float* b, float* x, bf16* xh, hipStream_t s) {
   const int blocks = (g.N + 63) / 64;
   if (blocks == 0) return;
+  const size_t wlds = (size_t)C * EMB_WLD * 2;  // at most 55 KB (C = 384)
   switch (C) {
-    case 64: embed_bf16_kernel<64><<<blocks, 256, 0, s>>>(g, frames, masks, flag, wcount, wT16, b, x, xh); break;
-    case 128: embed_bf16_kernel<128><<<blocks, 256, 0, s>>>(g, frames, masks, flag, wcount, wT16, b, x, xh); break;
-    case 256: embed_bf16_kernel<256><<<blocks, 256, 0, s>>>(g, frames, masks, flag, wcount, wT16, b, x, xh); break;
-    case 384: embed_bf16_kernel<384><<<blocks, 256, 0, s>>>(g, frames, masks, flag, wcount, wT16, b, x, xh); break;
+    case 64: embed_bf16_kernel<64><<<blocks, 256, wlds, s>>>(g, frames, masks, flag, wcount, wT16, b, x, xh); break;
+    case 128: embed_bf16_kernel<128><<<blocks, 256, wlds, s>>>(g, frames, masks, flag, wcount, wT16, b, x, xh); break;
+    case 256: embed_bf16_kernel<256><<<blocks, 256, wlds, s>>>(g, frames, masks, flag, wcount, wT16, b, x, xh); break;
+    case 384: embed_bf16_kernel<384><<<blocks, 256, wlds, s>>>(g, frames, masks, flag, wcount, wT16, b, x, xh); break;
     default: break;  // rejected by the caller (resid_ln_supported)
   }
 }
