@@ -159,3 +159,23 @@ def test_decoupled_clip720_network(dev, precision, qs):
     out = run(eng, frames, masks, precision, qs)
     mx, n = compare(out, on.forward(frames, masks, W, cfg, qs), frames, masks, TOL[precision])
     _say(f"    max abs err {mx:.3e} over {n} in-mask values")
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+def test_decoupled_graph_replay_equals_direct_launches(dev, precision):
+    """The decoupled block sequence replayed as a HIP graph gives the bits of direct launches,
+    on every replay, with inputs changing between calls."""
+    from paper_2509_10466_amd import Inpainter
+    cfg, fa, ma = case_inputs("clip240", 0)
+    _, fb, mb = case_inputs("clip240", 1)
+    cfg = dec(cfg)
+    eng = Inpainter(cfg, drsynth.make_weights(cfg, 0))
+    eng.debug_set("graphs", 0)
+    ra = run(eng, fa, ma, precision)
+    rb = run(eng, fb, mb, precision)
+    eng.debug_set("graphs", 1)
+    for rep in range(4):  # eager, capture, replay, replay (per clip)
+        assert np.array_equal(run(eng, fa, ma, precision), ra), ("a", rep)
+        _ = torch.ones(1000, device="cuda").sum().item()  # unrelated eager work + sync
+        assert np.array_equal(run(eng, fb, mb, precision), rb), ("b", rep)
+    eng.close()

@@ -192,3 +192,20 @@ def test_overlap_clip720_network(dev, qs):
     out = run(eng, f, m, "bf16", qs)
     mx, n = compare(out, on.forward(f, m, W, cfg, qs), f, m, TOL["bf16"])
     _say(f"    max abs err {mx:.3e} over {n} in-mask values")
+
+
+def test_overlap_graph_replay_equals_direct_launches(dev):
+    from paper_2509_10466_amd import Inpainter
+    cfg, fa, ma = case_inputs("clip240", 0)
+    _, fb, mb = case_inputs("clip240", 1)
+    cfg = ovl(cfg)
+    eng = Inpainter(cfg, drsynth.make_weights(cfg, 0))
+    eng.debug_set("graphs", 0)
+    ra = run(eng, fa, ma)
+    rb = run(eng, fb, mb)
+    eng.debug_set("graphs", 1)
+    for rep in range(4):
+        assert np.array_equal(run(eng, fa, ma), ra), ("a", rep)
+        _ = torch.ones(1000, device="cuda").sum().item()
+        assert np.array_equal(run(eng, fb, mb), rb), ("b", rep)
+    eng.close()
