@@ -161,3 +161,26 @@ def test_train_precision_rejects_fp8(dev):
     with pytest.raises(DrError, match="DR_EINVAL"):
         eng.train_precision("fp8")
     eng.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_backward_clip720_network(dev, precision):
+    """The 384-dim, 12-block network with 300-key windows (6 x 10 x 5), on a 5 x 48 x 80 clip
+    (2 x 2 windows), against the oracle's FP64 gradient."""
+    from paper_2509_10466_amd import Inpainter
+    cfg = drsynth.NETS["clip720"]
+    frames, masks, _ = drsynth.make_clip(5, 5, 48, 80, cov_range=(0.2, 0.4))
+    W = drsynth.make_weights(cfg, 0)
+    eng = Inpainter(cfg, W)
+    eng.train_precision(precision)
+    L, g, _ = _gpu_grad(eng, frames, masks)
+    Lr, Gr = og.loss_and_grad(frames, masks, W, cfg)
+    gr = _flat(cfg, Gr)
+    rel = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    _say(f"[grad clip720 net] {precision}: loss gpu {L:.7f} oracle {Lr:.7f}; normwise relative error {rel:.3e}")
+    assert abs(L - Lr) <= (1e-5 if precision == "fp32" else 1e-2) * abs(Lr)
+    # 12 blocks put about five bf16-operand products per block on a gradient's path; their
+    # rounding errors (2u = 2^-8 each) are independent, so they add in quadrature:
+    # 2u sqrt(60) ~ 3e-2, held at twice that
+    assert rel <= (1e-3 if precision == "fp32" else 6e-2)
+    eng.close()
