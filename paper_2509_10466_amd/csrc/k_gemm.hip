@@ -218,7 +218,7 @@ void launch_qkv_bf16(const Geo& g, int C, int heads, int Spad, int spv, const bf
   if (g.N <= 0) return;
   const QkvOut out{bias, q, k, vt, C, log2_pow2(C / heads), heads, Spad, g.S, spv};
   if (C % 128 == 0)
-    qkv_list_launch<GemmTile<64, 128, 2, 2, 3>>(g.N, C, xh, tiles, ntiles, w, out, s);
+    qkv_list_launch<GemmTile<64, 128, 2, 2, 2>>(g.N, C, xh, tiles, ntiles, w, out, s);
   else
     qkv_list_launch<GemmTile<64, 64, 2, 2, 3>>(g.N, C, xh, tiles, ntiles, w, out, s);
 }
