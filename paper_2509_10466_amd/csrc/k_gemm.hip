@@ -230,7 +230,7 @@ void launch_qkv_stream(const Geo& g, int C, int heads, const bf16* xh, const uin
   if (C % 128 == 0 && g.N >= BIG_M)
     qkv_launch<GemmTile<256, 128, 4, 2, 2>>(g.N, C, g.S, xh, flag, nullptr, w, out, s);
   else if (C % 128 == 0)
-    qkv_launch<GemmTile<64, 128, 2, 2, 3>>(g.N, C, g.S, xh, flag, nullptr, w, out, s);
+    qkv_launch<GemmTile<64, 128, 2, 2, 2>>(g.N, C, g.S, xh, flag, nullptr, w, out, s);
   else
     qkv_launch<GemmTile<64, 64, 2, 2, 3>>(g.N, C, g.S, xh, flag, nullptr, w, out, s);
 }
@@ -287,7 +287,7 @@ void launch_fc1_bf16(int m_max, const int32_t* m_dev, int C, int R, const bf16* 
   if (m_max >= BIG_M && R % 256 == 0)
     fc1_launch<GemmTile<128, 256, 2, 4, 2>>(m_max, m_dev, C, R, u2, w, bias, h, s);
   else
-    fc1_launch<GemmTile<64, 128, 2, 2, 3>>(m_max, m_dev, C, R, u2, w, bias, h, s);
+    fc1_launch<GemmTile<64, 128, 2, 2, 2>>(m_max, m_dev, C, R, u2, w, bias, h, s);
 }
 
 // ------------------------------------------------------------------------------------------
