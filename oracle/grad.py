@@ -97,11 +97,14 @@ def _attention_backward(q, k, v, do, heads):
 
 def loss_and_grad(frames, masks, W, cfg, query_set="masked", w_in=1.0, w_out=0.1):
     """(L, {name: dL/dname}) for the clip-mode forward on ``frames`` (also the ground truth)."""
+    if getattr(cfg, "overlap", False):
+        raise NotImplementedError("the overlapping embedding/decoder runs in clip mode only")
+    if getattr(cfg, "attn", "joint") != "joint":
+        # the reverse pass below partitions every block into joint windows
+        raise NotImplementedError("the gradient covers joint window attention only")
     d = on.forward_detail(frames, masks, W, cfg, query_set, keep_blocks=True)
     L, dpred = l1_loss(d["pred"], frames, masks, w_in, w_out)
     G = {}
-    if getattr(cfg, "overlap", False):
-        raise NotImplementedError("the overlapping embedding/decoder runs in clip mode only")
     p = cfg.patch
     pred = d["pred"]
     # decoder: pred = sigmoid(y), y[b,t,p*i+ky,p*j+kx,ch] = bd[ch] + sum_c z[b,t,i,j,c] Wd[c,ch,ky,kx]

@@ -57,6 +57,9 @@ def step(state: StreamState, frame, mask, W, cfg, query_set="masked"):
     Returns (out [H, W, 3] FP64, pred [H, W, 3])."""
     if getattr(cfg, "overlap", False):
         raise NotImplementedError("the overlapping embedding/decoder runs in clip mode only")
+    if getattr(cfg, "attn", "joint") != "joint":
+        # every block below attends over the joint per-frame windows of the cache
+        raise NotImplementedError("stream mode covers joint window attention only")
     p = cfg.patch
     H, Wd, _ = frame.shape
     if H % (p * cfg.win_h) or Wd % (p * cfg.win_w):

@@ -102,3 +102,21 @@ def test_decoupled_forward_keeps_the_composite_and_differs_from_joint():
     assert np.array_equal(out[masks == 0], frames[masks == 0].astype(np.float64))
     joint = on.forward(frames, masks, W, dataclasses.replace(cfg, attn="joint"))
     assert not np.allclose(out[masks != 0], joint[masks != 0])
+
+
+def test_gradient_and_stream_reject_decoupled_attention():
+    """The reverse pass and stream mode partition every block into joint windows: a decoupled
+    configuration must raise rather than silently return the joint network's result."""
+    import pytest
+
+    from oracle import grad as og
+    from oracle import stream as ost
+    rng = np.random.default_rng(0)
+    cfg = BASE
+    W = drsynth.make_weights(cfg, 0)
+    frames = rng.random((1, cfg.win_t, 8, 12, 3))
+    masks = (rng.random((1, cfg.win_t, 8, 12)) < 0.3).astype(np.uint8)
+    with pytest.raises(NotImplementedError):
+        og.loss_and_grad(frames, masks, W, cfg)
+    with pytest.raises(NotImplementedError):
+        ost.step(ost.StreamState(cfg), frames[0, 0], masks[0, 0], W, cfg)
