@@ -79,6 +79,31 @@ def time_path(eng, clips, precision, steps, warmup, torch):
     return wall, gpu_ms, lat
 
 
+def latency_pass(eng, clips, precision, calls, torch):
+    """Per-request latency: `calls` calls, each submitted alone and waited for, timed on the
+    host clock from submission to completion (launch overhead included), and on HIP events
+    around the call on the launch stream (device time of that request)."""
+    outs = [torch.empty_like(f) for f, _ in clips]
+    host_ms, dev_ms = [], []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    for i in range(calls):
+        f, m = clips[i % len(clips)]
+        t0 = time.perf_counter()
+        e0.record()
+        eng(f, m, precision, out=outs[i % len(clips)])
+        e1.record()
+        e1.synchronize()
+        host_ms.append((time.perf_counter() - t0) * 1e3)
+        dev_ms.append(e0.elapsed_time(e1))
+    h, d = np.array(host_ms), np.array(dev_ms)
+    pct = lambda a, q: round(float(np.percentile(a, q)), 4)  # noqa: E731
+    return {"samples": calls, "p50_ms": pct(h, 50), "p99_ms": pct(h, 99), "max_ms": round(float(h.max()), 4),
+            "device_p50_ms": pct(d, 50), "device_p99_ms": pct(d, 99),
+            "method": "each call submitted alone and waited for; host clock from submission to completion "
+                      "(device_*: HIP events around the call on its stream)"}
+
+
 def profile_path(eng, clips, precision, steps, torch):
     eng.profile(True)
     for i in range(steps):
@@ -90,16 +115,19 @@ def profile_path(eng, clips, precision, steps, torch):
     return rec
 
 
-def cpu_baseline(cfg, frames, masks, W, n_windows=None):
+def _oracle_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        return len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(cfg, frames, masks, W, n_windows=None, seed_note="clip seed 0"):
     """The FP64 oracle on a bounded sample: `n_windows` windows of one clip (default all of
     them, i.e. the whole clip), each computed from its own pixel footprint (exact, since a
     window's outputs depend only on it)."""
     from oracle import network as on
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:  # pragma: no cover
-        threads = len(os.sched_getaffinity(0))
     B, T, H, Wd, _ = frames.shape
     ph, pw = cfg.patch * cfg.win_h, cfg.patch * cfg.win_w
     wins = [(u, v) for u in range(H // ph) for v in range(Wd // pw)]
@@ -112,9 +140,26 @@ def cpu_baseline(cfg, frames, masks, W, n_windows=None):
         on.forward(frames[:1, :, rs, cs], masks[:1, :, rs, cs], W, cfg)
     dt = time.perf_counter() - t0
     frac = n_windows / len(wins)
-    return {"value": round(T * frac / dt, 4), "unit": "frames/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{n_windows} of {len(wins)} windows of clip seed 0 (all {T} frames, footprint "
+    return {"value": round(T * frac / dt, 4), "unit": "frames/s", "cores": int(_oracle_threads()), "kind": "oracle",
+            "sample": f"{n_windows} of {len(wins)} windows of {seed_note} (all {T} frames, footprint "
                       f"{ph}x{pw} px each), {dt:.1f} s; frames/s scaled by the window fraction"}
+
+
+def cpu_baseline_small():
+    """The oracle on the 64x64 single-frame network (one frame, whole), median of 10 runs."""
+    import drsynth
+    from oracle import network as on
+    cfg = drsynth.NETS["tiny64"]
+    f, m = drsynth.tiny_frame(0)
+    W = drsynth.make_weights(cfg, 0)
+    ts = []
+    for _ in range(10):
+        t0 = time.perf_counter()
+        on.forward(f, m, W, cfg)
+        ts.append(time.perf_counter() - t0)
+    med = float(np.median(ts))
+    return {"value": round(1.0 / med, 3), "unit": "frames/s", "cores": int(_oracle_threads()), "kind": "oracle",
+            "sample": f"1x64x64 frame, tiny64 network (dim 64, 2 blocks), median of 10 runs: {med * 1e3:.1f} ms"}
 
 
 def main():
@@ -124,6 +169,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--fp32-steps", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--latency-calls", type=int, default=1000,
+                    help="calls of the per-request latency pass (independent of --steps)")
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp8"])
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
@@ -162,6 +209,7 @@ def main():
     wall32, gpu32, lat32 = time_path(eng, clips, "fp32", args.fp32_steps, 5, torch)
     fps = T * args.steps / wall
     fps32 = T * args.fp32_steps / wall32
+    latency = latency_pass(eng, clips, args.precision, args.latency_calls, torch)
 
     # per-kernel events over the same workload -> roofline of the dominant kernel
     prof = profile_path(eng, clips, args.precision, len(clips) * 2, torch)
@@ -203,10 +251,17 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
 
-    cpu = None
+    cpu = cpu_other = None
     if not args.no_cpu:
         f0, m0, _ = host[0]
         cpu = cpu_baseline(cfg, f0, m0, W)
+        # the oracle on the other single-GPU workloads: the 64x64 frame, and a sample of
+        # windows of a 5x720x1280 clip on the 384-dim, 12-block network
+        cfg720 = drsynth.NETS["clip720"]
+        f7, m7, _ = drsynth.make_clip(0, 5, 720, 1280)
+        cpu_other = {"tiny64": cpu_baseline_small(),
+                     "clip720": cpu_baseline(cfg720, f7, m7, drsynth.make_weights(cfg720, 0), n_windows=12,
+                                             seed_note="a 5x720x1280 clip (seed 0)")}
 
     line = {
         "metric": METRIC,
@@ -229,10 +284,14 @@ def main():
             "token_coverage_mean": round(float(np.mean(tok_cov)), 4),
             "active_window_fraction_mean": round(float(np.mean(act_cov)), 4),
         },
-        "p50_ms_per_clip": round(float(np.percentile(lat, 50)), 4),
-        "p99_ms_per_clip": round(float(np.percentile(lat, 99)), 4),
-        "p99_ms_per_frame": round(float(np.percentile(lat, 99)), 4),
+        "p50_ms_per_clip": latency["p50_ms"],
+        "p99_ms_per_clip": latency["p99_ms"],
+        "p99_ms_per_frame": latency["p99_ms"],
         "p99_ms_per_frame_note": "all 5 frames of a clip complete together, so a frame's latency is its clip's",
+        "latency": latency,
+        "pipelined_gap_ms": {"samples": args.steps, "p50": round(float(np.percentile(lat, 50)), 4),
+                             "p99": round(float(np.percentile(lat, 99)), 4),
+                             "note": "HIP-event gaps between back-to-back calls of the throughput pass"},
         "fp32_plain": {"value": round(fps32, 2), "unit": "frames/s",
                        "p50_ms_per_clip": round(float(np.percentile(lat32, 50)), 4),
                        "p99_ms_per_clip": round(float(np.percentile(lat32, 99)), 4),
@@ -241,6 +300,7 @@ def main():
         "roofline": roof,
         "stages": stages,
         "cpu_baseline": cpu,
+        "cpu_baseline_other": cpu_other,
     }
     print(json.dumps(line), flush=True)
 

@@ -54,8 +54,9 @@ typedef enum {
  * DR_BF16: BF16 operands on MFMA with FP32 accumulation.  DR_FP8: the Q/K/V, projection and
  * MLP GEMMs take OCP e4m3 operands with per-tensor scales (amax/448; weights fixed at load,
  * activations from the current call) and FP32 accumulation, attention stays BF16; needs dim
- * and hidden width multiples of 128.  LayerNorm statistics, softmax max/sum, the residual
- * stream, patch embedding and decoder stay FP32 in every mode. */
+ * and hidden width multiples of 128.  LayerNorm statistics, softmax max/sum and the residual
+ * stream stay FP32 in every mode.  The patch embedding and the decoder run in FP32 in DR_FP32
+ * and DR_FP8, and take bf16 operands on MFMA (FP32 accumulation) in DR_BF16. */
 typedef enum { DR_FP32 = 0, DR_BF16 = 1, DR_FP8 = 2 } dr_precision;
 
 /* Which tokens are attention queries and get updated.  DR_QUERY_MASKED: tokens whose patch
@@ -223,14 +224,20 @@ dr_status dr_post_frame(dr_ctx* ctx, const uint8_t* bgra, const float* pred_low,
  * class it launches the oldest pending requests (at most one per stream, up to max_batch)
  * whenever that class's executor (own workspace and HIP stream) is idle, so classes overlap
  * on the device and new requests join as soon as their class frees up.  Latency of a request
- * = completion (event observed by the loop) - submission. */
+ * = completion (event observed by the loop) - entry into dr_server_submit. */
 typedef struct dr_server dr_server;
+/* Start a server on `ctx` batching up to max_batch (1..16) requests.  The executors (HIP
+ * stream, event, workspace for max_batch frames) of the resolutions of the streams open at
+ * this call are created here, so serving them allocates nothing; a resolution first seen
+ * later gets its executor when its first request is launched (its requests fail with
+ * DR_ENOMEM if that allocation fails).  DR_ENOMEM if an executor cannot be created. */
 dr_status dr_server_create(dr_ctx* ctx, int max_batch, dr_server** out);
 /* Queue one frame of an open stream; device buffers must stay valid until it completes. */
 dr_status dr_server_submit(dr_server* srv, int32_t sid, const float* frame,
                            const uint8_t* mask, float* out, uint64_t* ticket);
 /* Move up to `max` completed requests into host arrays (status may be NULL; a nonzero status
- * is the dr_status of a failed batch, latency -1).  *n_done receives the count. */
+ * is the dr_status of a failed batch -- DR_EHIP when its completion event reports a device
+ * error -- with latency -1).  *n_done receives the count. */
 dr_status dr_server_poll(dr_server* srv, uint64_t* tickets, double* latency_ms,
                          int32_t* status, int max, int* n_done);
 /* Batches launched, requests launched, requests still pending (any pointer may be NULL). */
@@ -242,24 +249,54 @@ void dr_server_destroy(dr_server* srv);
  * Parameters are addressed as one flat f32 vector in the blob order of dr_load_weights
  * (embed.w OIHW, embed.b, per block ln1.g ... b2, lnf.g, lnf.b, dec.w IOHW, dec.b). */
 size_t dr_param_count(dr_ctx* ctx);
+
+/* Replace the weights from `params`: device f32 [dr_param_count] in that flat order (the
+ * non-overlapping network).  Every layout the kernels read -- transposes, the bf16 copies,
+ * the LayerNorm affine parts folded into the following linear, the e4m3 copies and their
+ * per-tensor scales -- is derived from it on the device, enqueued on `stream`: nothing goes
+ * through host memory, and after the first load of a context nothing is allocated.  The
+ * caller keeps `params` valid until that work has run.  Enqueued forwards that read the
+ * weights run with the new values if they are ordered after this call on the device.
+ * DR_EINVAL for a null pointer or a context whose weights use the overlapping embedding. */
+dr_status dr_load_params(dr_ctx* ctx, const float* params, void* stream);
+
 /* Precision of the training passes (the reverse pass of the thesis's L1-trained network,
  * Methods, "Model Training"): DR_FP32 (default) or DR_BF16, mixed precision -- the weight
  * products of the forward (Q/K/V, projection, MLP) and of the reverse pass (input and weight
  * gradients) take operands rounded to bf16 and accumulate in FP32; weights, activations,
  * LayerNorm, attention, the loss and every gradient stay FP32.  Applies from the next
- * dr_train_forward (its dr_train_backward uses the same precision).  DR_EINVAL otherwise. */
+ * dr_train_forward (its handle's dr_train_backward uses the same precision).  DR_EINVAL
+ * otherwise. */
 dr_status dr_train_set_precision(dr_ctx* ctx, dr_precision prec);
-/* Forward of B clips (as dr_inpaint, masked queries) keeping the activations the reverse
- * pass needs (per block: block input, LN1 output, K/V, Q, attention output and row max/sum,
- * post-projection rows, LN2 output, MLP pre-activation) in the context.  pred: device f32
- * [B,T,H,W,3], the sigmoid output of the decoder at every pixel (before the composite). */
+
+/* Saved activations of one training forward (opaque, owned by the context). */
+typedef struct dr_saved dr_saved;
+
+/* Forward of B clips (as dr_inpaint, masked queries) that keeps what the reverse pass needs
+ * in a new handle *saved: per block the block input, LN1 output, K/V, Q, attention output
+ * and row max/sum, post-projection rows, LN2 output and MLP pre-activation, and a copy of
+ * the FP32 weights the forward ran with (so a later dr_load_params does not change this
+ * forward's gradient).  pred: device f32 [B,T,H,W,3], the sigmoid output of the decoder at
+ * every pixel (before the composite).  Several handles may be live at once; each is released
+ * with dr_saved_free.  A handle's buffers are reused by a later forward after it is freed, so
+ * free it only once the work reading it is ordered before that forward (same stream, or the
+ * caller synchronised).  DR_ENOMEM if its buffers cannot be allocated. */
 dr_status dr_train_forward(dr_ctx* ctx, const float* frames, const uint8_t* masks, float* pred,
-                           int B, int T, int H, int W, void* stream);
-/* Reverse pass of the last dr_train_forward: dpred = dL/dpred (device, layout of pred);
- * grads: device f32 [dr_param_count] receives dL/dparams.  Attention probabilities are
- * recomputed from Q, K and the saved row statistics.  Token reductions run in fixed chunks,
- * so the result is deterministic. */
-dr_status dr_train_backward(dr_ctx* ctx, const float* dpred, float* grads, void* stream);
+                           int B, int T, int H, int W, dr_saved** saved, void* stream);
+
+/* Reverse pass of the forward that produced `saved`: dpred = dL/dpred (device, layout of its
+ * pred); grads: device f32 [dr_param_count] receives dL/dparams at that forward's weights.
+ * Attention probabilities are recomputed from Q, K and the saved row statistics.  Token
+ * reductions run in fixed chunks, so the result is deterministic.  The handle stays live
+ * (the pass may be repeated).  DR_EINVAL for a handle that is not live on this context. */
+dr_status dr_train_backward(dr_ctx* ctx, dr_saved* saved, const float* dpred, float* grads,
+                            void* stream);
+
+/* Release a handle of dr_train_forward (its buffers go back to the context for reuse; the
+ * context keeps at most two such idle sets and frees the rest).  DR_EINVAL if `saved` is not
+ * a live handle of `ctx`.  dr_destroy releases every handle of the context. */
+dr_status dr_saved_free(dr_ctx* ctx, dr_saved* saved);
+
 /* Training loss (thesis, Methods, "Model Training -- Loss"): loss[0] = w_in * mean over
  * masked pixel-channel values |pred - gt| + w_out * mean over the others (an empty region adds
  * 0); dpred (may be NULL) receives dL/dpred with sign(0) = 0.  Device pointers; npix pixels. */

@@ -71,11 +71,13 @@ def load():
         "dr_server_stats": (I, [P, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64), ct.POINTER(I)]),
         "dr_server_destroy": (None, [P]),
         "dr_param_count": (Z, [P]),
-        "dr_train_forward": (I, [P, P, P, P, I, I, I, I, P]),
-        "dr_train_backward": (I, [P, P, P, P]),
+        "dr_load_params": (I, [P, P, P]),
+        "dr_train_forward": (I, [P, P, P, P, I, I, I, I, ct.POINTER(P), P]),
+        "dr_train_backward": (I, [P, P, P, P, P]),
+        "dr_saved_free": (I, [P, P]),
         "dr_l1_loss": (I, [P, P, P, P, Z, ct.c_float, ct.c_float, P, P, P]),
         "dr_set_attention_pattern": (I, [P, I]),
-    "dr_train_set_precision": (I, [P, I]),
+        "dr_train_set_precision": (I, [P, I]),
         "dr_prep_frame": (I, [P, P, P, I, ct.c_uint32, I, I, I, P, P, P, P]),
         "dr_post_frame": (I, [P, P, P, P, I, I, P, P]),
         "dr_last_error": (ct.c_char_p, [P]),

@@ -172,19 +172,14 @@ class Inpainter:
     def param_count(self) -> int:
         return int(self.lib.dr_param_count(self._ctx))
 
-    def load_params(self, flat: torch.Tensor):
-        """Replace the weights from a flat FP32 parameter vector (blob order)."""
-        names = wblob.param_names(self.cfg)
-        shapes = dict(_shapes(self.cfg))
-        host = flat.detach().float().cpu().numpy()
-        W, o = {}, 0
-        for n in names:
-            size = int(np.prod(shapes[n]))
-            W[n] = host[o:o + size].reshape(shapes[n])
-            o += size
-        blob = wblob.pack(self.cfg, W)
-        buf = ct.create_string_buffer(blob, len(blob))
-        _lib.check(self.lib, self._ctx, self.lib.dr_load_weights(self._ctx, buf, len(blob)))
+    def load_params(self, flat: torch.Tensor, stream=None):
+        """Replace the weights from a flat FP32 parameter vector on this context's device (blob
+        order).  The library derives every layout it needs on the device, on ``stream``; no
+        data passes through host memory."""
+        if not flat.is_cuda or flat.dtype != torch.float32 or not flat.is_contiguous() \
+                or flat.numel() != self.param_count():
+            raise ValueError("params must be a contiguous float32 device tensor of param_count() values")
+        _lib.check(self.lib, self._ctx, self.lib.dr_load_params(self._ctx, _ptr(flat), _stream(stream)))
 
     def train_precision(self, precision: str):
         """"fp32" (default) or "bf16": bf16 operands with FP32 accumulation for the weight
@@ -192,21 +187,25 @@ class Inpainter:
         gradients); takes effect at the next train_forward."""
         _lib.check(self.lib, self._ctx, self.lib.dr_train_set_precision(self._ctx, _lib.PRECISION[precision]))
 
-    def train_forward(self, frames: torch.Tensor, masks: torch.Tensor, stream=None) -> torch.Tensor:
-        """Decoder prediction at every pixel [B,T,H,W,3] (before the composite), keeping the
-        activations for train_backward."""
+    def train_forward(self, frames: torch.Tensor, masks: torch.Tensor, stream=None):
+        """(pred, saved): the decoder prediction at every pixel [B,T,H,W,3] (before the
+        composite) and the handle of the activations (and weights) its reverse pass needs."""
         self._check_inputs(frames, masks)
         pred = torch.empty_like(frames)
         B, T, H, W, _ = frames.shape
-        st = self.lib.dr_train_forward(self._ctx, _ptr(frames), _ptr(masks), _ptr(pred), B, T, H, W, _stream(stream))
+        h = ct.c_void_p()
+        st = self.lib.dr_train_forward(self._ctx, _ptr(frames), _ptr(masks), _ptr(pred), B, T, H, W, ct.byref(h),
+                                       _stream(stream))
         _lib.check(self.lib, self._ctx, st)
-        return pred
+        return pred, Saved(self, h)
 
-    def train_backward(self, dpred: torch.Tensor, stream=None) -> torch.Tensor:
-        """dL/dparams (flat FP32, blob order) of the last train_forward."""
+    def train_backward(self, saved: "Saved", dpred: torch.Tensor, stream=None) -> torch.Tensor:
+        """dL/dparams (flat FP32, blob order) of the forward that produced ``saved``."""
+        if saved.eng is not self or not saved.handle:
+            raise ValueError("saved activations of another context, or already released")
         dpred = dpred.contiguous().float()
         grads = torch.empty(self.param_count(), dtype=torch.float32, device=dpred.device)
-        st = self.lib.dr_train_backward(self._ctx, _ptr(dpred), _ptr(grads), _stream(stream))
+        st = self.lib.dr_train_backward(self._ctx, saved.handle, _ptr(dpred), _ptr(grads), _stream(stream))
         _lib.check(self.lib, self._ctx, st)
         return grads
 
@@ -262,7 +261,7 @@ class Inpainter:
 
     def close(self):
         if self._ctx:
-            self.lib.dr_destroy(self._ctx)
+            self.lib.dr_destroy(self._ctx)  # releases every saved-activation handle too
             self._ctx = ct.c_void_p()
 
     def __del__(self):
@@ -351,19 +350,50 @@ def unflatten_params(cfg, flat):
     return out
 
 
+class Saved:
+    """Handle of one training forward's saved activations; released by ``close`` (or when
+    garbage-collected).  Work already enqueued that reads it must be ordered before the next
+    training forward on the same context, which may reuse its buffers."""
+
+    def __init__(self, eng: Inpainter, handle: ct.c_void_p):
+        self.eng = eng
+        self.handle = handle
+
+    def close(self):
+        if self.handle and self.eng._ctx:
+            _lib.check(self.eng.lib, self.eng._ctx, self.eng.lib.dr_saved_free(self.eng._ctx, self.handle))
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class InpaintFn(torch.autograd.Function):
     """pred = network(frames, masks; params) with the library's hand-written backward.
 
-    ``params`` is the flat FP32 parameter vector (blob order); the prediction is the decoder
-    output at every pixel, before the composite (the training loss is taken on it)."""
+    ``params`` is the flat FP32 parameter vector (blob order) on the context's device; the
+    prediction is the decoder output at every pixel, before the composite (the training loss
+    is taken on it).  Each application keeps its own saved activations, so several forwards
+    may precede their backwards.  The parameters are loaded on the device, and only when the
+    tensor object, or its contents by torch's version counter, differs from the last load (the
+    last loaded tensor is kept referenced, so its memory cannot be handed to another tensor)."""
 
     @staticmethod
     def forward(ctx, frames, masks, params, eng):
-        eng.load_params(params)
-        pred = eng.train_forward(frames.contiguous(), masks.contiguous())
+        last = getattr(eng, "_params_last", None)
+        if last is None or last[0] is not params or last[1] != params._version:
+            eng.load_params(params.detach().contiguous())
+            eng._params_last = (params, params._version)
+        pred, saved = eng.train_forward(frames.contiguous(), masks.contiguous())
         ctx.eng = eng
+        ctx.saved = saved
         return pred
 
     @staticmethod
     def backward(ctx, dpred):
-        return None, None, ctx.eng.train_backward(dpred), None
+        grads = ctx.eng.train_backward(ctx.saved, dpred)
+        ctx.saved.close()
+        return None, None, grads, None

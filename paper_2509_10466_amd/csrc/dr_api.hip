@@ -15,11 +15,6 @@ namespace dr {
 bool attn_bf16_supported(int dh, int spad);
 }
 
-static float host_amax(const float* p, size_t n) {
-  float m = 0.f;
-  for (size_t i = 0; i < n; ++i) m = std::max(m, std::fabs(p[i]));
-  return m;
-}
 
 using namespace dr;
 
@@ -64,13 +59,6 @@ const char* const dr::kStageNames[ST_COUNT] = {"tokens", "embed", "ln1",  "qkv",
 // ------------------------------------------------------------------------------------------
 // small host helpers
 // ------------------------------------------------------------------------------------------
-static uint16_t host_f2bf(float f) {
-  uint32_t u;
-  std::memcpy(&u, &f, 4);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
 
 static bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
   const char* pa = (const char*)a;
@@ -149,7 +137,7 @@ void dr::dr_free_work(Work& w) {
 // attention mode of block l (see launch_attn_clip)
 static int attn_mode(const dr_ctx* c, int l) { return c->attn_pattern == 0 ? 0 : (l % 2 == 0 ? 1 : 2); }
 
-static void invalidate_graphs(dr_ctx* c) {
+void dr::dr_invalidate_graphs(dr_ctx* c) {
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   c->graphs.clear();
   c->graph_seen.clear();
@@ -157,7 +145,7 @@ static void invalidate_graphs(dr_ctx* c) {
 }
 
 static void free_work(dr_ctx* c) {
-  invalidate_graphs(c);
+  dr_invalidate_graphs(c);
   dr_free_work(c->work);
 }
 
@@ -176,7 +164,7 @@ extern "C" void dr_destroy(dr_ctx* c) {
     hipFree(kv.second.kc);
     hipFree(kv.second.vc);
   }
-  for (void* p : c->weight_allocs) hipFree(p);
+  dr_weights_release(c);
   for (auto& r : c->recs) {
     hipEventDestroy(r.a);
     hipEventDestroy(r.b);
@@ -191,372 +179,6 @@ extern "C" const char* dr_stage_name(int stage) {
   return (stage >= 0 && stage < ST_COUNT) ? kStageNames[stage] : nullptr;
 }
 
-// ------------------------------------------------------------------------------------------
-// weights
-// ------------------------------------------------------------------------------------------
-struct BlobRec {
-  char name[48];
-  uint32_t dtype, ndim, shape[4];
-  uint64_t offset, nbytes;
-};
-
-extern "C" dr_status dr_load_weights(dr_ctx* c, const void* blob, size_t nbytes) {
-  if (!c || !blob) return fail(c, DR_EINVAL, "dr_load_weights: null argument");
-  const char* b = (const char*)blob;
-  const size_t head = 4 + 4 + sizeof(dr_netcfg) + 4;
-  if (nbytes < head || std::memcmp(b, "DRW1", 4) != 0) return fail(c, DR_EINVAL, "weight blob: bad magic");
-  uint32_t version, count;
-  dr_netcfg bc;
-  std::memcpy(&version, b + 4, 4);
-  std::memcpy(&bc, b + 8, sizeof bc);
-  std::memcpy(&count, b + 8 + sizeof bc, 4);
-  if (version != 1) return fail(c, DR_EINVAL, "weight blob: unsupported version %u", version);
-  if (std::memcmp(&bc, &c->net.cfg, sizeof bc) != 0)
-    return fail(c, DR_EINVAL, "weight blob: network config differs from the context's");
-  const Net& n = c->net;
-  const int C = n.C, R = n.R, L = n.cfg.blocks, P = n.P;
-  // kernel size of the embedding and the decoder: P (non-overlapping) or 2P (overlapping,
-  // stride P, padding P/2), read from the first tensor's shape
-  int K = P;
-  if (nbytes >= head + sizeof(BlobRec)) {
-    BlobRec r0;
-    std::memcpy(&r0, b + head, sizeof r0);
-    if (r0.ndim == 4 && r0.shape[2] == (uint32_t)(2 * P) && r0.shape[3] == (uint32_t)(2 * P)) K = 2 * P;
-  }
-  if (K != P && P != 4) return fail(c, DR_EINVAL, "weight blob: the overlapping embedding needs patch 4");
-  // expected tensors in order
-  struct Want { std::string name; std::vector<uint32_t> shape; };
-  std::vector<Want> want;
-  want.push_back({"embed.w", {(uint32_t)C, 3, (uint32_t)K, (uint32_t)K}});
-  want.push_back({"embed.b", {(uint32_t)C}});
-  for (int l = 0; l < L; ++l) {
-    const std::string p = "blk" + std::to_string(l) + ".";
-    const uint32_t c32 = C, r32 = R;
-    want.push_back({p + "ln1.g", {c32}});
-    want.push_back({p + "ln1.b", {c32}});
-    want.push_back({p + "wq", {c32, c32}});
-    want.push_back({p + "bq", {c32}});
-    want.push_back({p + "wk", {c32, c32}});
-    want.push_back({p + "bk", {c32}});
-    want.push_back({p + "wv", {c32, c32}});
-    want.push_back({p + "bv", {c32}});
-    want.push_back({p + "wo", {c32, c32}});
-    want.push_back({p + "bo", {c32}});
-    want.push_back({p + "ln2.g", {c32}});
-    want.push_back({p + "ln2.b", {c32}});
-    want.push_back({p + "w1", {r32, c32}});
-    want.push_back({p + "b1", {r32}});
-    want.push_back({p + "w2", {c32, r32}});
-    want.push_back({p + "b2", {c32}});
-  }
-  want.push_back({"lnf.g", {(uint32_t)C}});
-  want.push_back({"lnf.b", {(uint32_t)C}});
-  want.push_back({"dec.w", {(uint32_t)C, 3, (uint32_t)K, (uint32_t)K}});
-  want.push_back({"dec.b", {3}});
-  if (count != want.size())
-    return fail(c, DR_EINVAL, "weight blob: %u tensors, expected %zu", count, want.size());
-  const size_t table = head + (size_t)count * sizeof(BlobRec);
-  if (nbytes < table) return fail(c, DR_EINVAL, "weight blob: truncated table");
-  std::vector<const float*> src(count);
-  for (uint32_t i = 0; i < count; ++i) {
-    BlobRec r;
-    std::memcpy(&r, b + head + (size_t)i * sizeof(BlobRec), sizeof r);
-    r.name[47] = 0;
-    if (want[i].name != r.name) return fail(c, DR_EINVAL, "weight blob: tensor %u is '%s', expected '%s'", i, r.name, want[i].name.c_str());
-    if (r.dtype != 0) return fail(c, DR_EINVAL, "weight blob: '%s' is not f32", r.name);
-    if (r.ndim != want[i].shape.size()) return fail(c, DR_EINVAL, "weight blob: '%s' has wrong rank", r.name);
-    size_t elems = 1;
-    for (uint32_t d = 0; d < r.ndim; ++d) {
-      if (r.shape[d] != want[i].shape[d]) return fail(c, DR_EINVAL, "weight blob: '%s' has wrong shape", r.name);
-      elems *= r.shape[d];
-    }
-    if (r.nbytes != elems * 4 || table + r.offset + r.nbytes > nbytes || r.offset % 4)
-      return fail(c, DR_EINVAL, "weight blob: '%s' has a bad extent", r.name);
-    src[i] = reinterpret_cast<const float*>(b + table + r.offset);
-  }
-
-  // Host-side layout: f32 arena and bf16 arena, then one copy each.
-  std::vector<float> f;
-  std::vector<uint16_t> h16;
-  auto put = [&](const float* p, size_t nel) {
-    size_t off = f.size();
-    f.insert(f.end(), p, p + nel);
-    while (f.size() % 64) f.push_back(0.f);  // 256-byte alignment
-    return off;
-  };
-  auto put16 = [&](const std::vector<const float*>& parts, const std::vector<size_t>& nels) {
-    size_t off = h16.size();
-    for (size_t k = 0; k < parts.size(); ++k)
-      for (size_t e = 0; e < nels[k]; ++e) h16.push_back(host_f2bf(parts[k][e]));
-    while (h16.size() % 128) h16.push_back(0);
-    return off;
-  };
-  const size_t CC = (size_t)C * C, RC = (size_t)R * C;
-  // embed weight transposed to [48][C], row (ky*4+kx)*3+c
-  std::vector<float> ewT((size_t)48 * C), dw((size_t)C * 48);
-  const float* ew = src[0];
-  const float* dws = src[count - 2];
-  if (K == P) {
-    for (int o = 0; o < C; ++o)
-      for (int ch = 0; ch < 3; ++ch)
-        for (int ky = 0; ky < P; ++ky)
-          for (int kx = 0; kx < P; ++kx)
-            ewT[(size_t)((ky * P + kx) * 3 + ch) * C + o] = ew[((o * 3 + ch) * P + ky) * P + kx];
-    for (int ci = 0; ci < C; ++ci)
-      for (int ch = 0; ch < 3; ++ch)
-        for (int ky = 0; ky < P; ++ky)
-          for (int kx = 0; kx < P; ++kx)
-            dw[(size_t)ci * 48 + (ky * P + kx) * 3 + ch] = dws[((ci * 3 + ch) * P + ky) * P + kx];
-  }
-  // overlapping variant: embedding weight [C][192] in the slot order of the overlapping MFMA
-  // embedding (slot 32 s + 8 g + e holds footprint row ky = g + 4 (s / 3), value m = 8 (s % 3)
-  // + e = 3 kx + c), decoder [192][C] (k = (ky*8 + kx)*3 + ch) with the final LayerNorm gain
-  // folded in, its shift through the decoder per token, and the decoder bias per pixel
-  std::vector<float> eo, dwo, dbo;
-  if (K != P) {
-    eo.assign((size_t)C * 192, 0.f);
-    for (int o = 0; o < C; ++o)
-      for (int sl = 0; sl < 6; ++sl)
-        for (int gq = 0; gq < 4; ++gq)
-          for (int e = 0; e < 8; ++e) {
-            const int ky = gq + 4 * (sl / 3), m = 8 * (sl % 3) + e, kx = m / 3, ch = m % 3;
-            eo[(size_t)o * 192 + 32 * sl + 8 * gq + e] = ew[((o * 3 + ch) * K + ky) * K + kx];
-          }
-    dwo.assign((size_t)192 * C, 0.f);
-    dbo.assign(192, 0.f);
-    const float* gf = src[count - 4];
-    const float* btf = src[count - 3];
-    for (int k = 0; k < 192; ++k) {
-      const int ky = (k / 3) / 8, kx = (k / 3) % 8, ch = k % 3;
-      double acc = 0.0;
-      for (int ci = 0; ci < C; ++ci) {
-        const float wv = dws[((ci * 3 + ch) * K + ky) * K + kx];
-        dwo[(size_t)k * C + ci] = gf[ci] * wv;
-        acc += (double)btf[ci] * wv;
-      }
-      dbo[k] = (float)acc;
-    }
-  }
-  struct Off { size_t v[32]; };
-  const size_t o_ewT = put(ewT.data(), ewT.size());
-  const size_t o_eb = put(src[1], C);
-  std::vector<Off> bo(L), b16(L);
-  for (int l = 0; l < L; ++l) {
-    const float* const* s = &src[2 + 16 * l];
-    Off& O = bo[l];
-    O.v[0] = put(s[0], C);   // ln1.g
-    O.v[1] = put(s[1], C);   // ln1.b
-    O.v[2] = put(s[2], CC);  // wq
-    O.v[3] = put(s[3], C);   // bq
-    O.v[4] = put(s[4], CC);  // wk
-    O.v[5] = put(s[5], C);   // bk
-    O.v[6] = put(s[6], CC);  // wv
-    O.v[7] = put(s[7], C);   // bv
-    O.v[8] = put(s[8], CC);  // wo
-    O.v[9] = put(s[9], C);   // bo
-    O.v[10] = put(s[10], C); // ln2.g
-    O.v[11] = put(s[11], C); // ln2.b
-    O.v[12] = put(s[12], RC);// w1
-    O.v[13] = put(s[13], R); // b1
-    O.v[14] = put(s[14], RC);// w2
-    O.v[15] = put(s[15], C); // b2
-    // [Wk; Wv] and [bq; bk; bv]
-    O.v[16] = f.size();
-    f.insert(f.end(), s[4], s[4] + CC);
-    f.insert(f.end(), s[6], s[6] + CC);
-    while (f.size() % 64) f.push_back(0.f);
-    O.v[17] = f.size();
-    f.insert(f.end(), s[5], s[5] + C);
-    f.insert(f.end(), s[7], s[7] + C);
-    while (f.size() % 64) f.push_back(0.f);
-    O.v[18] = f.size();
-    f.insert(f.end(), s[3], s[3] + C);
-    f.insert(f.end(), s[5], s[5] + C);
-    f.insert(f.end(), s[7], s[7] + C);
-    while (f.size() % 64) f.push_back(0.f);
-    // transposes: T[i][o] = W[o][i] for W [out][in]
-    auto putT = [&](std::initializer_list<const float*> parts, int out_each, int in) {
-      const size_t off = f.size();
-      const int nparts = (int)parts.size();
-      const int out_total = out_each * nparts;
-      f.resize(off + (size_t)in * out_total);
-      int pi = 0;
-      for (const float* wsrc : parts) {
-        for (int o = 0; o < out_each; ++o)
-          for (int i = 0; i < in; ++i) f[off + (size_t)i * out_total + pi * out_each + o] = wsrc[(size_t)o * in + i];
-        ++pi;
-      }
-      while (f.size() % 64) f.push_back(0.f);
-      return off;
-    };
-    O.v[19] = putT({s[2]}, C, C);         // Wq^T
-    O.v[20] = putT({s[4], s[6]}, C, C);   // [Wk; Wv]^T  [C][2C]
-    O.v[21] = putT({s[8]}, C, C);         // Wo^T
-    O.v[22] = putT({s[12]}, R, C);        // W1^T [C][R]
-    O.v[23] = putT({s[14]}, C, R);        // W2^T [R][C]
-    Off& H = b16[l];
-    H.v[0] = put16({s[2], s[4], s[6]}, {CC, CC, CC});
-    H.v[1] = put16({s[8]}, {CC});
-    H.v[2] = put16({s[12]}, {RC});
-    H.v[3] = put16({s[14]}, {RC});
-    // LayerNorm affine parts folded into the next linear: appends sc * W diag(g) to wf and
-    // sc * (b + W beta) to bf for W [outs][in] (double precision, rounded once)
-    auto fold = [](const float* wsrc, const float* bias, int outs, int in, const float* g, const float* beta,
-                   double sc, std::vector<float>& wf, std::vector<float>& bf) {
-      for (int o = 0; o < outs; ++o) {
-        double acc = bias[o];
-        for (int i = 0; i < in; ++i) {
-          wf.push_back((float)(sc * wsrc[(size_t)o * in + i] * g[i]));
-          acc += (double)wsrc[(size_t)o * in + i] * beta[i];
-        }
-        bf.push_back((float)(sc * acc));
-      }
-    };
-    std::vector<float> wf, bf;
-    // Q also carries the softmax scale in base 2, log2(e) / sqrt(dh): the attention kernels
-    // of the BF16 path exponentiate the scores with exp2 directly
-    const double qscale = 1.4426950408889634 / std::sqrt((double)n.dh);
-    fold(s[2], s[3], C, C, s[0], s[1], qscale, wf, bf);  // Q
-    fold(s[4], s[5], C, C, s[0], s[1], 1.0, wf, bf);     // K
-    fold(s[6], s[7], C, C, s[0], s[1], 1.0, wf, bf);     // V
-    H.v[4] = put16({wf.data()}, {wf.size()});
-    O.v[24] = put(bf.data(), bf.size());
-    wf.clear();
-    bf.clear();
-    fold(s[12], s[13], R, C, s[10], s[11], 1.0, wf, bf);  // first MLP linear
-    H.v[5] = put16({wf.data()}, {wf.size()});
-    O.v[25] = put(bf.data(), bf.size());
-  }
-  // embedding weight [C][64] in the k slot order of the MFMA embedding's patch operand (slot
-  // 32 s + 8 g + e holds patch value k = 12 g + 8 s + e for e < 8 - 4 s, zero otherwise; patch
-  // value k = (ky*P + kx)*3 + c) and the decoder with the final LayerNorm folded in:
-  // Wd'[k][c] = gf[c] Wd[c][k], bd'[k] = bd[k % 3] + sum_c bf[c] Wd[c][k]
-  std::vector<float> ew64((size_t)C * 64, 0.f), dwf((size_t)48 * C), dbf(48);
-  for (int o = 0; o < C; ++o)
-    for (int sl = 0; sl < 2; ++sl)
-      for (int gq = 0; gq < 4; ++gq)
-        for (int e = 0; e < (sl ? 4 : 8); ++e)
-          ew64[(size_t)o * 64 + 32 * sl + 8 * gq + e] = ewT[(size_t)(12 * gq + 8 * sl + e) * C + o];
-  {
-    const float* gf = src[count - 4];
-    const float* btf = src[count - 3];
-    const float* db = src[count - 1];
-    for (int k = 0; k < 48; ++k) {
-      double acc = db[k % 3];
-      for (int ci = 0; ci < C; ++ci) {
-        dwf[(size_t)k * C + ci] = gf[ci] * dw[(size_t)ci * 48 + k];
-        acc += (double)btf[ci] * dw[(size_t)ci * 48 + k];
-      }
-      dbf[k] = (float)acc;
-    }
-  }
-  const size_t o16_ew = put16({ew64.data()}, {ew64.size()});
-  const size_t o16_dw = put16({dwf.data()}, {dwf.size()});
-  const size_t o_dbf = put(dbf.data(), dbf.size());
-  const size_t o_lnfg = put(src[count - 4], C);
-  const size_t o_lnfb = put(src[count - 3], C);
-  const size_t o_dw = put(dw.data(), dw.size());
-  const size_t o_db = put(src[count - 1], 3);
-  size_t o16_eo = 0, o16_dwo = 0, o_dbo = 0;
-  if (K != P) {
-    o16_eo = put16({eo.data()}, {eo.size()});
-    o16_dwo = put16({dwo.data()}, {dwo.size()});
-    o_dbo = put(dbo.data(), dbo.size());
-  }
-
-  HIP_OK(c, hipSetDevice(c->device));
-  HIP_OK(c, hipDeviceSynchronize());
-  invalidate_graphs(c);
-  for (void* p : c->weight_allocs) hipFree(p);
-  c->weight_allocs.clear();
-  c->have_weights = false;
-  void *df = nullptr, *dh16 = nullptr;
-  if (dmalloc(c, &df, f.size() * 4, c->weight_allocs) != hipSuccess ||
-      dmalloc(c, &dh16, h16.size() * 2, c->weight_allocs) != hipSuccess)
-    return fail(c, DR_ENOMEM, "weights: device allocation failed");
-  HIP_OK(c, hipMemcpy(df, f.data(), f.size() * 4, hipMemcpyHostToDevice));
-  HIP_OK(c, hipMemcpy(dh16, h16.data(), h16.size() * 2, hipMemcpyHostToDevice));
-  const float* F = (const float*)df;
-  const bf16* B16 = (const bf16*)dh16;
-  Net& nn = c->net;
-  nn.embed_wT = F + o_ewT;
-  nn.embed_b = F + o_eb;
-  nn.blk.assign(L, BlockW());
-  for (int l = 0; l < L; ++l) {
-    BlockW& w = nn.blk[l];
-    const Off& O = bo[l];
-    w.ln1g = F + O.v[0]; w.ln1b = F + O.v[1];
-    w.wq = F + O.v[2]; w.bq = F + O.v[3];
-    w.wk = F + O.v[4]; w.bk = F + O.v[5];
-    w.wv = F + O.v[6]; w.bv = F + O.v[7];
-    w.wo = F + O.v[8]; w.bo = F + O.v[9];
-    w.ln2g = F + O.v[10]; w.ln2b = F + O.v[11];
-    w.w1 = F + O.v[12]; w.b1 = F + O.v[13];
-    w.w2 = F + O.v[14]; w.b2 = F + O.v[15];
-    w.wkv = F + O.v[16]; w.bkv = F + O.v[17]; w.bqkv = F + O.v[18];
-    w.wqT = F + O.v[19]; w.wkvT = F + O.v[20]; w.woT = F + O.v[21]; w.w1T = F + O.v[22]; w.w2T = F + O.v[23];
-    w.wqkv16 = B16 + b16[l].v[0];
-    w.wo16 = B16 + b16[l].v[1];
-    w.w116 = B16 + b16[l].v[2];
-    w.w216 = B16 + b16[l].v[3];
-    w.wqkvf16 = B16 + b16[l].v[4];
-    w.w1f16 = B16 + b16[l].v[5];
-    w.bqkvf = F + O.v[24];
-    w.b1f = F + O.v[25];
-  }
-  nn.embed_wT16 = B16 + o16_ew;
-  nn.dec_wf16 = B16 + o16_dw;
-  nn.dec_bf = F + o_dbf;
-  nn.lnfg = F + o_lnfg;
-  nn.lnfb = F + o_lnfb;
-  nn.dec_w = F + o_dw;
-  nn.dec_b = F + o_db;
-  nn.K = K;
-  nn.embed_ovl16 = K != P ? B16 + o16_eo : nullptr;
-  nn.dec_ovl16 = K != P ? B16 + o16_dwo : nullptr;
-  nn.dec_ovl_bf = K != P ? F + o_dbo : nullptr;
-  nn.dec_ovl_b = K != P ? F + o_db : nullptr;
-
-  // FP8 e4m3 copies of the GEMM weights, one scale per tensor (amax / 448)
-  if (fp8_supported(C, R)) {
-    const size_t per_blk = 3 * CC + CC + RC + RC;
-    void *d8 = nullptr, *dsc = nullptr;
-    if (dmalloc(c, &d8, per_blk * L, c->weight_allocs) != hipSuccess ||
-        dmalloc(c, &dsc, (size_t)L * 8 * 4, c->weight_allocs) != hipSuccess)
-      return fail(c, DR_ENOMEM, "weights: device allocation failed");
-    std::vector<float> sc((size_t)L * 8, 1.f);
-    uint8_t* q8 = (uint8_t*)d8;
-    for (int l = 0; l < L; ++l) {
-      const float* const* sp = &src[2 + 16 * l];
-      BlockW& w = nn.blk[l];
-      uint8_t* base = q8 + per_blk * l;
-      const float* dev[6] = {w.wq, w.wk, w.wv, w.wo, w.w1, w.w2};
-      const float* hst[6] = {sp[2], sp[4], sp[6], sp[8], sp[12], sp[14]};
-      const size_t nel[6] = {CC, CC, CC, CC, RC, RC};
-      size_t off = 0;
-      for (int k = 0; k < 6; ++k) {
-        const float am = host_amax(hst[k], nel[k]);
-        const float s8 = am > 0.f ? am / 448.0f : 1.0f;
-        sc[(size_t)l * 8 + k] = s8;
-        launch_quantize_fp8(dev[k], base + off, nel[k], 1.0f / s8, nullptr);
-        off += nel[k];
-      }
-      w.wqkv8 = base;
-      w.wo8 = base + 3 * CC;
-      w.w18 = base + 4 * CC;
-      w.w28 = base + 4 * CC + RC;
-      w.wscale8 = (const float*)dsc + (size_t)l * 8;
-      w.so8 = sc[(size_t)l * 8 + 3];
-      w.s18 = sc[(size_t)l * 8 + 4];
-      w.s28 = sc[(size_t)l * 8 + 5];
-    }
-    HIP_OK(c, hipGetLastError());
-    HIP_OK(c, hipMemcpy(dsc, sc.data(), sc.size() * 4, hipMemcpyHostToDevice));
-    HIP_OK(c, hipDeviceSynchronize());
-  }
-  c->have_weights = true;
-  return DR_OK;
-}
 
 // ------------------------------------------------------------------------------------------
 // shapes and workspace
@@ -619,6 +241,11 @@ dr_status dr::dr_reserve_work(dr_ctx* c, Work& w, const Geo& g, bool stream_mode
   ALLOC(u16, N * C * 2);
   ALLOC(xh, N * C * 2);
   ALLOC(amax, (size_t)n.cfg.blocks * 4 * 4);
+  if (mlp_split_supported((int)C, (int)R)) {
+    ALLOC(mlp_part, mlp_split_part_floats((int)C, (int)N) * 4);
+    ALLOC(mlp_cnt, mlp_split_counters((int)N) * 4);
+    HIP_OK(c, hipMemset(w.mlp_cnt, 0, mlp_split_counters((int)N) * 4));
+  }
   if (stream_mode) {
     const size_t npix = N * 16;  // 4 x 4 pixels per token
     ALLOC(fst, npix * 12);
@@ -649,7 +276,7 @@ dr_status dr::dr_reserve_work(dr_ctx* c, Work& w, const Geo& g, bool stream_mode
 static dr_status reserve_geo(dr_ctx* c, const Geo& g) {
   const bool grows = !((size_t)g.N <= c->work.cap_tokens && (size_t)g.nwin <= c->work.cap_windows &&
                        !c->work.stream_mode && (c->net.K == c->net.P || c->work.contrib));
-  if (grows) invalidate_graphs(c);
+  if (grows) dr_invalidate_graphs(c);
   return dr_reserve_work(c, c->work, g, false);
 }
 
@@ -725,16 +352,18 @@ static dr_status run_blocks(dr_ctx* c, const Geo& g, dr_precision prec, hipStrea
       LAUNCH(ST_LN1, launch_ln_rows_amax(w.x, nullptr, nullptr, N, w.wcount, g.S, C, b.ln1g, b.ln1b, w.u16, am + 0, s));
       LAUNCH(ST_QKV, launch_qkv_fp8(g, C, n.cfg.heads, n.Spad, attn_clip_vt_stride(n.Spad), w.u16, w.tiles, w.ntiles, b.wqkv8, b.wscale8, b.bqkv, am + 0, (float)(1.4426950408889634 / std::sqrt((double)n.dh)), w.q16, w.k16, w.vt16, s));
       LAUNCH(ST_ATTN, launch_attn_clip(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.vt16, w.idx, w.woff, w.worder, w.o16, am + 1, attn_mode(c, l), s));
-      LAUNCH(ST_PROJ, launch_gemm_fp8_resid(w.o16, w.nq, N, C, b.wo8, b.so8, am + 1, b.bo, C, w.x, w.idx, s));
+      LAUNCH(ST_PROJ, launch_gemm_fp8_resid(w.o16, w.nq, N, C, b.wo8, b.wscale8 + 3, am + 1, b.bo, C, w.x, w.idx, s));
       LAUNCH(ST_LN2, launch_ln_rows_amax(w.x, w.idx, w.nq, N, nullptr, g.S, C, b.ln2g, b.ln2b, w.u16, am + 2, s));
-      LAUNCH(ST_FC1, launch_fc1_fp8(N, w.nq, C, R, w.u16, b.w18, b.s18, b.b1, am + 2, w.h16, am + 3, s));
-      LAUNCH(ST_FC2, launch_gemm_fp8_resid(w.h16, w.nq, N, R, b.w28, b.s28, am + 3, b.b2, C, w.x, w.idx, s));
+      LAUNCH(ST_FC1, launch_fc1_fp8(N, w.nq, C, R, w.u16, b.w18, b.wscale8 + 4, b.b1, am + 2, w.h16, am + 3, s));
+      LAUNCH(ST_FC2, launch_gemm_fp8_resid(w.h16, w.nq, N, R, b.w28, b.wscale8 + 5, am + 3, b.b2, C, w.x, w.idx, s));
     } else {
       // x^ (normalised rows) feeds Q/K/V; the projection leaves x1^ of the query rows in u16
       // for the MLP; the second MLP linear refreshes x^ of the query rows
       LAUNCH(ST_QKV, launch_qkv_bf16(g, C, n.cfg.heads, n.Spad, attn_clip_vt_stride(n.Spad), w.xh, w.tiles, w.ntiles, b.wqkvf16, b.bqkvf, w.q16, w.k16, w.vt16, s));
       LAUNCH(ST_ATTN, launch_attn_clip(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.vt16, w.idx, w.woff, w.worder, w.o16, nullptr, attn_mode(c, l), s));
-      if (mlp_block_supported(C, R)) {
+      if (mlp_split_supported(C, R)) {
+        LAUNCH(ST_MLP, launch_mlp_split_bf16(N, w.nq, C, w.o16, w.idx, b.wo16, b.bo, b.w1f16, b.b1f, b.w216, b.b2, w.x, w.xh, w.mlp_part, w.mlp_cnt, s));
+      } else if (mlp_block_supported(C, R)) {
         LAUNCH(ST_MLP, launch_mlp_block_bf16(N, w.nq, C, w.o16, w.idx, b.wo16, b.bo, b.w1f16, b.b1f, b.w216, b.b2, w.x, w.xh, s));
       } else {
         LAUNCH(ST_PROJ, launch_resid_ln_bf16(N, w.nq, C, C, w.o16, b.wo16, b.bo, w.x, w.idx, w.u16, nullptr, s));
@@ -908,7 +537,7 @@ extern "C" dr_status dr_set_attention_pattern(dr_ctx* c, int pattern) {
   if (c->attn_pattern != pattern) {
     HIP_OK(c, hipSetDevice(c->device));
     HIP_OK(c, hipDeviceSynchronize());
-    invalidate_graphs(c);  // captured block sequences hold the previous attention kernels
+    dr_invalidate_graphs(c);  // captured block sequences hold the previous attention kernels
     c->attn_pattern = pattern;
   }
   return DR_OK;

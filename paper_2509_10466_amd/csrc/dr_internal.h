@@ -56,8 +56,7 @@ struct BlockW {
   const float *bqkvf, *b1f;                  // f32 [3C], [R]
   const uint8_t* wqkv8;                      // e4m3 [3C, C] (Wq, Wk, Wv each / own scale)
   const uint8_t *wo8, *w18, *w28;            // e4m3 [out, in]
-  const float* wscale8;                      // device: s_q, s_k, s_v
-  float so8, s18, s28;                       // host copies of the other weight scales
+  const float* wscale8;                      // device: s_q, s_k, s_v, s_o, s_1, s_2
   // transposed FP32 copies for the input gradients of the backward pass ([in, out])
   const float *wqT, *wkvT, *woT, *w1T, *w2T;  // [C,C], [C,2C], [C,C], [C,R], [R,C]
 };
@@ -109,6 +108,8 @@ struct Work {
   bf16* vt16 = nullptr;  // V^T [win][head][dh][vt stride] (BF16 clip mode)
   float* amax = nullptr;  // FP8 activation amax slots [blocks][4]
   float* contrib = nullptr;  // overlapping decoder: per-token logit patches [N][192]
+  float* mlp_part = nullptr;    // split MLP: per-slice partial products [slices][N][C]
+  int32_t* mlp_cnt = nullptr;   // split MLP: arrival counters per 64-row tile (zero between launches)
   // stream mode: contiguous staging of the batch's frames, masks and outputs
   float* fst = nullptr;
   uint8_t* mst = nullptr;
@@ -162,11 +163,26 @@ struct StreamSt {
 };
 }  // namespace dr
 
+struct dr_wplan;  // per-shape weight derivation plan (dr_weights.hip)
+
 struct dr_ctx {
   int device = 0;
   dr::Net net;
   bool have_weights = false;
+  // weights: the flat FP32 parameters (blob order) and the arenas derived from them on the
+  // device, with the plan's index maps (all in weight_allocs)
   std::vector<void*> weight_allocs;
+  dr_wplan* wplan = nullptr;
+  float* params = nullptr;
+  float* wf32 = nullptr;
+  size_t wf32_elems = 0;
+  dr::bf16* wb16 = nullptr;
+  uint8_t* w8 = nullptr;
+  float* wscale8 = nullptr;
+  int32_t *wmaps32 = nullptr, *wmaps16a = nullptr, *wmaps16b = nullptr;
+  void* wfolds = nullptr;
+  const float** wjob_ptrs = nullptr;
+  size_t* wjob_counts = nullptr;
   dr::Work work;
   std::string err;
   // profiling
@@ -242,6 +258,8 @@ void launch_attn_f32(const Geo& g, int C, int heads, const float* q, const float
 // FP8 path (OCP e4m3 operands, per-tensor scales s = amax/448, FP32 accumulation)
 bool fp8_supported(int C, int R);
 void launch_quantize_fp8(const float* in, uint8_t* out, size_t n, float inv_scale, hipStream_t s);
+// as launch_quantize_fp8 with the scale read from device memory (values / *scale)
+void launch_quantize_fp8_dev(const float* in, uint8_t* out, size_t n, const float* scale, hipStream_t s);
 void launch_zero_f32(float* p, int n, hipStream_t s);
 // LayerNorm of rows (affine) into bf16 rows plus the call's amax: rows given -> compact output
 // rows r < *nrows_dev from x[rows[r]]; else rows r < nrows_max of windows with queries.
@@ -254,10 +272,10 @@ void launch_qkv_fp8(const Geo& g, int C, int heads, int Spad, int spv, const bf1
                     const int32_t* ntiles, const uint8_t* w, const float* wscale, const float* bias,
                     const float* amax_u, float qscale, bf16* q, bf16* k, bf16* vt, hipStream_t s);
 // first MLP linear + GELU over compact rows u [*m_dev][C] -> h [.][R], amax of h
-void launch_fc1_fp8(int m_max, const int32_t* m_dev, int C, int R, const bf16* u, const uint8_t* w, float s_w,
+void launch_fc1_fp8(int m_max, const int32_t* m_dev, int C, int R, const bf16* u, const uint8_t* w, const float* s_w,
                     const float* bias, const float* amax_u, bf16* h, float* amax_h, hipStream_t s);
 void launch_gemm_fp8_resid(const bf16* A, const int32_t* m_dev, int m_max, int K,
-                           const uint8_t* W, float s_w, const float* amax_a, const float* bias,
+                           const uint8_t* W, const float* s_w, const float* amax_a, const float* bias,
                            int Nout, float* x, const int32_t* res_rows, hipStream_t s);
 
 // weight preparation
@@ -302,6 +320,14 @@ void launch_fc1_bf16(int m_max, const int32_t* m_dev, int C, int R, const bf16* 
                      const float* bias, bf16* h, hipStream_t s);
 bool resid_ln_supported(int C);
 bool mlp_block_supported(int C, int R);
+// fused projection + MLP with the hidden dimension split over several workgroups per row tile
+// (partials in `part`, per-tile arrival counters in `cnt`, zero between launches)
+bool mlp_split_supported(int C, int R);
+size_t mlp_split_part_floats(int C, int m_max);
+size_t mlp_split_counters(int m_max);
+void launch_mlp_split_bf16(int m_max, const int32_t* m_dev, int C, const bf16* o, const int32_t* rows,
+                           const bf16* wo, const float* bo, const bf16* w1, const float* b1, const bf16* w2,
+                           const float* b2, float* x, bf16* xh, float* part, int32_t* cnt, hipStream_t s);
 void launch_mlp_block_bf16(int m_max, const int32_t* m_dev, int C, const bf16* o, const int32_t* rows,
                            const bf16* wo, const float* bo, const bf16* w1, const float* b1, const bf16* w2,
                            const float* b2, float* x, bf16* xh, hipStream_t s);
@@ -323,6 +349,11 @@ dr_status dr_make_geo(dr_ctx* c, int B, int T, int H, int W, int wt, Geo& g);
 dr_status dr_reserve_work(dr_ctx* c, Work& w, const Geo& g, bool stream_mode);
 void dr_free_work(Work& w);
 void dr_train_release(dr_ctx* c);
+void dr_invalidate_graphs(dr_ctx* c);
+// weights (dr_weights.hip)
+void dr_weights_release(dr_ctx* c);
+void dr_wplan_free(dr_wplan* p);
+size_t dr_nparams(const Net& n, int K);
 void dr_prof_begin(dr_ctx* c, hipStream_t s, hipEvent_t* a, hipEvent_t* b);
 void dr_prof_end(dr_ctx* c, int stage, hipStream_t s, hipEvent_t a, hipEvent_t b);
 extern const char* const kStageNames[];

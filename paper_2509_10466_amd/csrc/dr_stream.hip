@@ -198,7 +198,9 @@ static dr_status stream_step_locked(dr_ctx* c, Work& w, int n, const int32_t* si
     tab.sfp = ring_vt_frame_stride(g.S);
     LAUNCH(ST_QKV, launch_qkv_stream(g, C, net.cfg.heads, w.xh, w.flag, b.wqkvf16, b.bqkvf, w.q16, tab, s));
     LAUNCH(ST_ATTN, launch_attn_ring(tab, g, C, net.cfg.heads, net.cfg.win_t, w.q16, w.idx, w.woff, w.worder, w.o16, s));
-    if (mlp_block_supported(C, R)) {
+    if (mlp_split_supported(C, R)) {
+      LAUNCH(ST_MLP, launch_mlp_split_bf16(N, w.nq, C, w.o16, w.idx, b.wo16, b.bo, b.w1f16, b.b1f, b.w216, b.b2, w.x, w.xh, w.mlp_part, w.mlp_cnt, s));
+    } else if (mlp_block_supported(C, R)) {
       LAUNCH(ST_MLP, launch_mlp_block_bf16(N, w.nq, C, w.o16, w.idx, b.wo16, b.bo, b.w1f16, b.b1f, b.w216, b.b2, w.x, w.xh, s));
     } else {
       LAUNCH(ST_PROJ, launch_resid_ln_bf16(N, w.nq, C, C, w.o16, b.wo16, b.bo, w.x, w.idx, w.u16, nullptr, s));
@@ -278,40 +280,94 @@ struct dr_server {
   int64_t batches = 0, batched_requests = 0;
 };
 
+// An executor for frames of H x W: its own HIP stream, completion event and workspace (sized
+// for max_batch frames).  Null on failure, with the reason in *why.
+static Exec* new_exec(dr_server* sv, int H, int W, const char** why) {
+  dr_ctx* c = sv->ctx;
+  Exec* e = new Exec();
+  e->H = H;
+  e->W = W;
+  *why = nullptr;
+  if (hipStreamCreateWithFlags(&e->s, hipStreamNonBlocking) != hipSuccess) {
+    e->s = nullptr;
+    *why = "executor stream creation failed";
+  } else if (hipEventCreateWithFlags(&e->ev, hipEventDisableTiming) != hipSuccess) {
+    e->ev = nullptr;
+    *why = "executor event creation failed";
+  } else {
+    Geo g;
+    std::lock_guard<std::mutex> slk(c->smu);
+    if (dr_make_geo(c, sv->max_batch, 1, H, W, 1, g) != DR_OK || dr_reserve_work(c, e->work, g, true) != DR_OK)
+      *why = "executor workspace allocation failed";
+  }
+  if (*why) {
+    dr_free_work(e->work);
+    if (e->ev) (void)hipEventDestroy(e->ev);
+    if (e->s) (void)hipStreamDestroy(e->s);
+    delete e;
+    return nullptr;
+  }
+  return e;
+}
+
+static Exec* find_exec(dr_server* sv, int H, int W) {
+  for (Exec* x : sv->execs)
+    if (x->H == H && x->W == W) return x;
+  return nullptr;
+}
+
+// Server thread.  sv->mu guards the queues and counters; it is released while a batch's
+// launches are enqueued, so submissions and polls are never held up by a launch.
 static void server_loop(dr_server* sv) {
   dr_ctx* c = sv->ctx;
   (void)hipSetDevice(c->device);
   std::unique_lock<std::mutex> lk(sv->mu);
   while (true) {
     bool progressed = false;
-    // completions
+    // completions: a batch whose event reports an error fails its requests with DR_EHIP
     for (Exec* e : sv->execs) {
-      if (e->busy && hipEventQuery(e->ev) == hipSuccess) {
-        const double t = now_s();
-        for (const Req& r : e->inflight) {
-          sv->done.push_back({r.ticket, (t - r.t_arrive) * 1e3, 0});
-          sv->busy_streams.erase(r.sid);
-        }
-        e->inflight.clear();
-        e->busy = false;
-        progressed = true;
+      if (!e->busy) continue;
+      const hipError_t q = hipEventQuery(e->ev);
+      if (q == hipErrorNotReady) continue;
+      const double t = now_s();
+      for (const Req& r : e->inflight) {
+        if (q == hipSuccess)
+          sv->done.push_back({r.ticket, (t - r.t_arrive) * 1e3, DR_OK});
+        else
+          sv->done.push_back({r.ticket, -1.0, DR_EHIP});
+        sv->busy_streams.erase(r.sid);
       }
+      e->inflight.clear();
+      e->busy = false;
+      progressed = true;
     }
-    // launches: per resolution class, the oldest pending requests, one per stream
-    bool any_busy = false;
-    for (auto it = sv->pending.begin(); it != sv->pending.end(); ++it) {
-      Exec* e = nullptr;
-      for (Exec* x : sv->execs)
-        if (x->H == it->H && x->W == it->W) e = x;
-      if (!e) {
-        e = new Exec();
-        e->H = it->H;
-        e->W = it->W;
-        (void)hipStreamCreateWithFlags(&e->s, hipStreamNonBlocking);
-        (void)hipEventCreateWithFlags(&e->ev, hipEventDisableTiming);
+    // an executor for every resolution class with pending requests (the classes of the
+    // streams open at dr_server_create already have one)
+    for (auto it = sv->pending.begin(); it != sv->pending.end();) {
+      if (find_exec(sv, it->H, it->W)) {
+        ++it;
+        continue;
+      }
+      const char* why = nullptr;
+      Exec* e = new_exec(sv, it->H, it->W, &why);
+      if (e) {
         sv->execs.push_back(e);
+        ++it;
+        continue;
       }
+      const int H = it->H, W = it->W;
+      for (auto jt = sv->pending.begin(); jt != sv->pending.end();) {
+        if (jt->H == H && jt->W == W) {
+          sv->done.push_back({jt->ticket, -1.0, DR_ENOMEM});
+          jt = sv->pending.erase(jt);
+        } else {
+          ++jt;
+        }
+      }
+      it = sv->pending.begin();
+      progressed = true;
     }
+    // launches: per idle executor, the oldest pending requests of its class, one per stream
     for (Exec* e : sv->execs) {
       if (e->busy) continue;
       std::vector<Req> batch;
@@ -326,6 +382,8 @@ static void server_loop(dr_server* sv) {
         }
       }
       if (batch.empty()) continue;
+      for (const Req& r : batch) sv->busy_streams.insert(r.sid);
+      e->busy = true;
       const int n = (int)batch.size();
       std::vector<int32_t> sids(n);
       std::vector<const float*> fr(n);
@@ -337,23 +395,28 @@ static void server_loop(dr_server* sv) {
         ms[r] = batch[r].m;
         os[r] = batch[r].o;
       }
+      lk.unlock();
       dr_status st;
       {
         std::lock_guard<std::mutex> slk(c->smu);
         st = stream_step_locked(c, e->work, n, sids.data(), fr.data(), ms.data(), os.data(), DR_QUERY_MASKED, e->s);
       }
+      if (st == DR_OK && hipEventRecord(e->ev, e->s) != hipSuccess) st = DR_EHIP;
+      lk.lock();
       if (st != DR_OK) {
-        for (const Req& r : batch) sv->done.push_back({r.ticket, -1.0, (int32_t)st});
-        continue;
+        for (const Req& r : batch) {
+          sv->done.push_back({r.ticket, -1.0, (int32_t)st});
+          sv->busy_streams.erase(r.sid);
+        }
+        e->busy = false;
+      } else {
+        e->inflight = std::move(batch);
+        sv->batches += 1;
+        sv->batched_requests += n;
       }
-      (void)hipEventRecord(e->ev, e->s);
-      for (const Req& r : batch) sv->busy_streams.insert(r.sid);
-      e->inflight = std::move(batch);
-      e->busy = true;
-      sv->batches += 1;
-      sv->batched_requests += n;
       progressed = true;
     }
+    bool any_busy = false;
     for (Exec* e : sv->execs) any_busy = any_busy || e->busy;
     if (sv->stop && sv->pending.empty() && !any_busy) break;
     if (!progressed) {
@@ -367,10 +430,34 @@ static void server_loop(dr_server* sv) {
 
 extern "C" dr_status dr_server_create(dr_ctx* c, int max_batch, dr_server** out) {
   if (!c || !out) return dr_fail(c, DR_EINVAL, "dr_server_create: null argument");
+  *out = nullptr;
   if (max_batch < 1 || max_batch > STREAM_MAXB) return dr_fail(c, DR_EINVAL, "max_batch must be 1..%d", STREAM_MAXB);
+  HIP_OK(c, hipSetDevice(c->device));
   dr_server* sv = new dr_server();
   sv->ctx = c;
   sv->max_batch = max_batch;
+  // executors (stream, event, workspace for max_batch frames) for the resolutions of the
+  // streams already open, so that serving them allocates nothing
+  std::set<std::pair<int, int>> classes;
+  {
+    std::lock_guard<std::mutex> slk(c->smu);
+    for (const auto& kv : c->streams) classes.insert({kv.second.H, kv.second.W});
+  }
+  for (const auto& hw : classes) {
+    const char* why = nullptr;
+    Exec* e = new_exec(sv, hw.first, hw.second, &why);
+    if (!e) {
+      for (Exec* x : sv->execs) {
+        dr_free_work(x->work);
+        (void)hipEventDestroy(x->ev);
+        (void)hipStreamDestroy(x->s);
+        delete x;
+      }
+      delete sv;
+      return dr_fail(c, DR_ENOMEM, "dr_server_create: %s", why);
+    }
+    sv->execs.push_back(e);
+  }
   sv->th = std::thread(server_loop, sv);
   *out = sv;
   return DR_OK;
@@ -379,6 +466,7 @@ extern "C" dr_status dr_server_create(dr_ctx* c, int max_batch, dr_server** out)
 extern "C" dr_status dr_server_submit(dr_server* sv, int32_t sid, const float* frame, const uint8_t* mask, float* out,
                                       uint64_t* ticket) {
   if (!sv || !frame || !mask || !out || !ticket) return DR_EINVAL;
+  const double t_arrive = now_s();  // latency counts from here, before any lock is taken
   dr_ctx* c = sv->ctx;
   int H = 0, W = 0;
   {
@@ -391,7 +479,7 @@ extern "C" dr_status dr_server_submit(dr_server* sv, int32_t sid, const float* f
   std::lock_guard<std::mutex> lk(sv->mu);
   if (sv->stop) return DR_EBUSY;
   const uint64_t t = sv->next_ticket++;
-  sv->pending.push_back({t, sid, frame, mask, out, now_s(), H, W});
+  sv->pending.push_back({t, sid, frame, mask, out, t_arrive, H, W});
   *ticket = t;
   sv->cv.notify_one();
   return DR_OK;

@@ -64,7 +64,8 @@ __device__ __forceinline__ float wave_max_abs(float v) { return wave_max(fabsf(v
 // elementwise quantisation (weights at load, and the test hook)
 // ------------------------------------------------------------------------------------------
 __global__ void quantize_fp8_kernel(const float* __restrict__ in, uint8_t* __restrict__ out, size_t n,
-                                    float inv_scale) {
+                                    float inv_scale, const float* __restrict__ scale) {
+  if (scale) inv_scale = 1.0f / *scale;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; 2 * i < n; i += (size_t)gridDim.x * blockDim.x) {
     const float a = in[2 * i] * inv_scale;
     const float b = (2 * i + 1 < n) ? in[2 * i + 1] * inv_scale : 0.f;
@@ -77,7 +78,13 @@ __global__ void quantize_fp8_kernel(const float* __restrict__ in, uint8_t* __res
 void launch_quantize_fp8(const float* in, uint8_t* out, size_t n, float inv_scale, hipStream_t s) {
   size_t grid = (n / 2 + 256) / 256;
   if (grid > 8192) grid = 8192;
-  if (grid) quantize_fp8_kernel<<<(unsigned)grid, 256, 0, s>>>(in, out, n, inv_scale);
+  if (grid) quantize_fp8_kernel<<<(unsigned)grid, 256, 0, s>>>(in, out, n, inv_scale, nullptr);
+}
+
+void launch_quantize_fp8_dev(const float* in, uint8_t* out, size_t n, const float* scale, hipStream_t s) {
+  size_t grid = (n / 2 + 256) / 256;
+  if (grid > 8192) grid = 8192;
+  if (grid) quantize_fp8_kernel<<<(unsigned)grid, 256, 0, s>>>(in, out, n, 1.f, scale);
 }
 
 __global__ void zero_f32_kernel(float* p, int n) {
@@ -333,14 +340,14 @@ constexpr int F8_BIG_M = 32768;
 // x[res_rows[m], n] += s_a s_w Y + bias[n]
 struct F8ResidEpi {
   const float* bias;
-  float s_w;
+  const float* s_w;  // device: the weight's scale
   float* x;
   const int32_t* res_rows;
   int Nout;
   __device__ __forceinline__ int need(int, int) const { return 1; }
   __device__ __forceinline__ int list(int) const { return 0; }
   __device__ __forceinline__ void operator()(int m, int n, const f32x4_t& a, float sa) const {
-    const float sc = sa * s_w;
+    const float sc = sa * *s_w;
     const float4 b4 = *reinterpret_cast<const float4*>(bias + n);
     float4* p = reinterpret_cast<float4*>(x + (size_t)res_rows[m] * Nout + n);
     float4 xv = *p;
@@ -353,7 +360,7 @@ struct F8ResidEpi {
   __device__ __forceinline__ void finish() const {}
 };
 
-void launch_gemm_fp8_resid(const bf16* A, const int32_t* m_dev, int m_max, int K, const uint8_t* W, float s_w,
+void launch_gemm_fp8_resid(const bf16* A, const int32_t* m_dev, int m_max, int K, const uint8_t* W, const float* s_w,
                            const float* amax_a, const float* bias, int Nout, float* x, const int32_t* res_rows,
                            hipStream_t s) {
   // (a 128 x 128 tile on 8 wavefronts measured slower here at 720p)
@@ -412,7 +419,7 @@ void launch_qkv_fp8(const Geo& g, int C, int heads, int Spad, int spv, const bf1
 // h = GELU(s_a s_w Y + b1) in bf16, amax |h| of the call into *amax_h (one atomic per wave)
 struct F8GeluEpi {
   const float* bias;
-  float s_w;
+  const float* s_w;  // device: the weight's scale
   bf16* h;
   float* amax_h;
   int R;
@@ -420,7 +427,7 @@ struct F8GeluEpi {
   __device__ __forceinline__ int need(int, int) const { return 1; }
   __device__ __forceinline__ int list(int) const { return 0; }
   __device__ __forceinline__ void operator()(int m, int n, const f32x4_t& a, float sa) {
-    const float sc = sa * s_w;
+    const float sc = sa * *s_w;
     const float4 b4 = *reinterpret_cast<const float4*>(bias + n);
     const float y0 = gelu_fast(a[0] * sc + b4.x), y1 = gelu_fast(a[1] * sc + b4.y);
     const float y2 = gelu_fast(a[2] * sc + b4.z), y3 = gelu_fast(a[3] * sc + b4.w);
@@ -436,7 +443,7 @@ struct F8GeluEpi {
   }
 };
 
-void launch_fc1_fp8(int m_max, const int32_t* m_dev, int C, int R, const bf16* u, const uint8_t* w, float s_w,
+void launch_fc1_fp8(int m_max, const int32_t* m_dev, int C, int R, const bf16* u, const uint8_t* w, const float* s_w,
                     const float* bias, const float* amax_u, bf16* h, float* amax_h, hipStream_t s) {
   const F8GeluEpi epi{bias, s_w, h, amax_h, R, 0.f};
   if (m_max >= F8_BIG_M && R % 256 == 0)

@@ -48,7 +48,6 @@ def main():
 
     nets = {"clip240": drsynth.NETS["clip240"], "clip720": drsynth.NETS["clip720"]}
     engines = {k: Inpainter(cfg, drsynth.make_weights(cfg, 0)) for k, cfg in nets.items()}
-    servers = {k: Server(e, max_batch=args.max_batch) for k, e in engines.items()}
 
     rng = np.random.default_rng(args.seed)
     streams = []
@@ -64,6 +63,9 @@ def main():
         streams.append(dict(i=i, H=H, W=W, net=net, sid=sid, frames=frames, masks=masks, outs=outs,
                             cov=sc.coverage, k=0))
     torch.cuda.synchronize()
+    # servers start after the streams are open, so every executor's workspace is allocated
+    # before the first request
+    servers = {k: Server(e, max_batch=args.max_batch) for k, e in engines.items()}
     t_gen = time.time() - t_gen
 
     # arrival timeline: per stream exponential gaps at `fps`

@@ -49,13 +49,14 @@ def main():
     for step in range(args.steps + 1):
         e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         e[0].record()
-        pred = eng.train_forward(frames, masks)
+        pred, saved = eng.train_forward(frames, masks)
         e[1].record()
         loss, dpred = eng.l1_loss(pred, gt, masks)
         e[2].record()
-        grads = eng.train_backward(dpred)
+        grads = eng.train_backward(saved, dpred)
         e[3].record()
         torch.cuda.synchronize()
+        saved.close()
         if step == 0:
             continue  # first step allocates the training workspace
         t_f.append(e[0].elapsed_time(e[1]))

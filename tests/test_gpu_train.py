@@ -28,10 +28,11 @@ def dev():
 def _gpu_grad(eng, frames, masks):
     f = torch.from_numpy(frames).cuda()
     m = torch.from_numpy(masks).cuda()
-    pred = eng.train_forward(f, m)
+    pred, saved = eng.train_forward(f, m)
     loss, dpred = eng.l1_loss(pred, f, m)
-    g = eng.train_backward(dpred)
+    g = eng.train_backward(saved, dpred)
     torch.cuda.synchronize()
+    saved.close()
     return float(loss.item()), g.cpu().numpy().astype(np.float64), pred.cpu().numpy()
 
 
@@ -96,8 +97,10 @@ def test_autograd_function_and_sgd_step(dev):
     pred = InpaintFn.apply(f, m, params, eng)
     loss = loss_of(pred)
     loss.backward()
-    direct = eng.train_backward(eng.l1_loss(eng.train_forward(f, m), f, m)[1])
+    pred_d, saved = eng.train_forward(f, m)
+    direct = eng.train_backward(saved, eng.l1_loss(pred_d, f, m)[1])
     torch.cuda.synchronize()
+    saved.close()
     rel = float((params.grad - direct).norm() / direct.norm())
     assert rel < 1e-5, rel
     with torch.no_grad():
@@ -184,3 +187,137 @@ def test_backward_clip720_network(dev, precision):
     # 2u sqrt(60) ~ 3e-2, held at twice that
     assert rel <= (1e-3 if precision == "fp32" else 6e-2)
     eng.close()
+
+
+# ------------------------------------------------------------------------------------------
+# the training boundary: saved-activation handles and parameters loaded on the device
+# ------------------------------------------------------------------------------------------
+def test_two_forwards_then_one_backward_sum_gradients(dev):
+    """Two InpaintFn applications (different clips) before a single backward: the gradient is
+    the sum of the two separate gradients, because each application keeps its own handle."""
+    from paper_2509_10466_amd import Inpainter
+    from paper_2509_10466_amd.api import InpaintFn, flatten_params
+    cfg = MID
+    fa, ma, _ = drsynth.make_clip(3, 5, 40, 72, cov_range=(0.2, 0.4))
+    fb, mb, _ = drsynth.make_clip(4, 5, 40, 72, cov_range=(0.2, 0.4))
+    W = drsynth.make_weights(cfg, 0)
+    eng = Inpainter(cfg, W)
+    sep = []
+    for f, m in ((fa, ma), (fb, mb)):
+        _, g, _ = _gpu_grad(eng, f, m)
+        sep.append(g)
+    params = flatten_params(cfg, W).cuda().requires_grad_(True)
+    losses = []
+    for f, m in ((fa, ma), (fb, mb)):
+        ft, mt = torch.from_numpy(f).cuda(), torch.from_numpy(m).cuda()
+        pred = InpaintFn.apply(ft, mt, params, eng)
+        inside = (mt != 0).unsqueeze(-1).expand_as(ft)
+        e = (pred - ft).abs()
+        losses.append(e[inside].mean() + 0.1 * e[~inside].mean())
+    (losses[0] + losses[1]).backward()
+    torch.cuda.synchronize()
+    got = params.grad.cpu().numpy().astype(np.float64)
+    want = sep[0] + sep[1]
+    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+    _say(f"[two forwards] relative difference to the summed gradients {rel:.3e}")
+    assert rel < 1e-5
+    eng.close()
+
+
+def test_handle_keeps_the_weights_of_its_forward(dev):
+    """A forward, then new parameters loaded, then that forward's backward: the gradient is the
+    one at the forward's weights."""
+    from paper_2509_10466_amd import Inpainter
+    from paper_2509_10466_amd.api import flatten_params
+    cfg, frames, masks = case_inputs("mid")
+    W0 = drsynth.make_weights(cfg, 0)
+    W1 = drsynth.make_weights(cfg, 1)
+    eng = Inpainter(cfg, W0)
+    _, g_ref, _ = _gpu_grad(eng, frames, masks)
+    f = torch.from_numpy(frames).cuda()
+    m = torch.from_numpy(masks).cuda()
+    pred, saved = eng.train_forward(f, m)
+    eng.load_params(flatten_params(cfg, W1).cuda())
+    g = eng.train_backward(saved, eng.l1_loss(pred, f, m)[1])
+    torch.cuda.synchronize()
+    saved.close()
+    assert np.array_equal(g.cpu().numpy().astype(np.float64), g_ref)
+    eng.close()
+
+
+def test_device_parameter_load_equals_blob_load(dev):
+    """Inference after dr_load_params (flat parameters already on the device) is bitwise the
+    inference after dr_load_weights of the same values, in every precision."""
+    from paper_2509_10466_amd import Inpainter
+    from paper_2509_10466_amd.api import flatten_params
+    cfg, frames, masks = case_inputs("mid")
+    W0 = drsynth.make_weights(cfg, 0)
+    W1 = drsynth.make_weights(cfg, 1)
+    a = Inpainter(cfg, W1)
+    b = Inpainter(cfg, W0)
+    b.load_params(flatten_params(cfg, W1).cuda())
+    f = torch.from_numpy(frames).cuda()
+    m = torch.from_numpy(masks).cuda()
+    for prec in ("fp32", "bf16", "fp8"):
+        oa = a(f, m, prec)
+        ob = b(f, m, prec)
+        torch.cuda.synchronize()
+        assert torch.equal(oa, ob), prec
+    a.close()
+    b.close()
+
+
+def test_training_step_copies_nothing_to_the_host(dev, monkeypatch):
+    """An InpaintFn forward and backward with new parameters every step moves no tensor to host
+    memory: the parameters go to the library as a device pointer."""
+    from paper_2509_10466_amd import Inpainter
+    from paper_2509_10466_amd.api import InpaintFn, flatten_params
+    cfg, frames, masks = case_inputs("tiny64")
+    W = drsynth.make_weights(cfg, 0)
+    eng = Inpainter(cfg, W)
+    f = torch.from_numpy(frames).cuda()
+    m = torch.from_numpy(masks).cuda()
+    params = flatten_params(cfg, W).cuda().requires_grad_(True)
+    opt = torch.optim.SGD([params], lr=1e-3)
+
+    def no_host(*a, **k):
+        raise AssertionError("a tensor was copied to host memory")
+
+    monkeypatch.setattr(torch.Tensor, "cpu", no_host)
+    monkeypatch.setattr(torch.Tensor, "numpy", no_host)
+    monkeypatch.setattr(torch.Tensor, "tolist", no_host)
+    for _ in range(3):
+        opt.zero_grad()
+        pred = InpaintFn.apply(f, m, params, eng)
+        (pred - f).abs().mean().backward()
+        opt.step()
+    monkeypatch.undo()
+    torch.cuda.synchronize()
+    assert torch.isfinite(params).all().item()
+    eng.close()
+
+
+def test_saved_handle_misuse_is_an_error(dev):
+    from paper_2509_10466_amd import Inpainter
+    cfg, frames, masks = case_inputs("tiny64")
+    eng = Inpainter(cfg, drsynth.make_weights(cfg, 0))
+    other = Inpainter(cfg, drsynth.make_weights(cfg, 0))
+    f = torch.from_numpy(frames).cuda()
+    m = torch.from_numpy(masks).cuda()
+    pred, saved = eng.train_forward(f, m)
+    dpred = eng.l1_loss(pred, f, m)[1]
+    grads = torch.empty(eng.param_count(), dtype=torch.float32, device=f.device)
+    # another context's handle is refused before any work is enqueued
+    assert other.lib.dr_train_backward(other._ctx, saved.handle, dpred.data_ptr(), grads.data_ptr(), None) == 1
+    st = other.lib.dr_saved_free(other._ctx, saved.handle)
+    assert st == 1  # DR_EINVAL: not a handle of that context
+    g1 = eng.train_backward(saved, dpred)
+    g2 = eng.train_backward(saved, dpred)  # a live handle can be used again
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g2)
+    h = saved.handle
+    saved.close()
+    assert eng.lib.dr_saved_free(eng._ctx, h) == 1  # double free
+    assert eng.lib.dr_train_backward(eng._ctx, h, dpred.data_ptr(), g1.data_ptr(), None) == 1
+    eng.close()
+    other.close()
