@@ -7,11 +7,14 @@
 // the sum, so any k permutation applied to both operands alike is legal; the kernel uses
 // that to feed P straight from the score registers.
 //
-// The kernel uses the single-rate v_mfma_f32_16x16x16_bf16, whose operands are read at
-// issue: the double-rate 16x16x32 form keeps reading its source VGPRs for a few cycles, and a
-// VALU write to one of them right after the issue corrupts the product (seen as run-to-run
-// differences of single output elements), a case the compiler does not pad.  The GEMMs,
-// which use the double-rate form, fence every MFMA group instead.
+// The score and output products (S^T = K Q^T, O^T = V^T P^T) use the double-rate
+// v_mfma_f32_16x16x32_bf16 in fenced groups: that form keeps reading its source VGPRs for a
+// few cycles after issue, and a VALU write to one of them right after the issue corrupts the
+// product (seen as run-to-run differences of single output elements), a case the compiler
+// does not pad; each group is therefore bracketed by scheduling barriers and followed by
+// s_nop 7, with the next group's operands loaded into other registers beforehand.  The last
+// key tile of an odd tile count, which has no partner for a 32-wide k step, uses the
+// single-rate v_mfma_f32_16x16x16_bf16, whose operands are read at issue.
 #include "dr_device.h"
 #include "dr_internal.h"
 
