@@ -124,6 +124,17 @@ dr_status dr_gather_tokens(dr_ctx* ctx, const uint8_t* masks, int B, int T, int 
                            dr_query_set qs, uint8_t* flag, int32_t* idx, int32_t* woff,
                            int32_t* nq, void* stream);
 
+/* dr_gather_tokens for callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: same arguments, outputs and
+ * errors, but it allocates nothing (no workspace is reserved).  Its only scratch, the
+ * per-window query counts, is a static device array of 65,536 entries (256 KB) that every
+ * device the library runs on holds until the process ends; more windows than that
+ * (B*T*H*W / (p^2 * window tokens)) give DR_EINVAL.  The array is shared by every call on a
+ * device, so calls that overlap in time on one device (any context, any stream) race. */
+dr_status dr_gather_tokens_noalloc(dr_ctx* ctx, const uint8_t* masks, int B, int T, int H, int W,
+                                   dr_query_set qs, uint8_t* flag, int32_t* idx, int32_t* woff,
+                                   int32_t* nq, void* stream);
+
 /* Per-kernel timing.  dr_profile(ctx, 1) makes every later launch record a HIP event pair
  * on its stream; dr_profile_read synchronises on those events, writes the summed time in
  * milliseconds and the launch count per stage into ms[] / count[] (host arrays of

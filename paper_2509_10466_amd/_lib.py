@@ -53,6 +53,7 @@ def load():
         "dr_reserve": (I, [P, I, I, I, I, I]),
         "dr_inpaint": (I, [P, P, P, P, I, I, I, I, I, I, P]),
         "dr_gather_tokens": (I, [P, P, I, I, I, I, I, P, P, P, P, P]),
+        "dr_gather_tokens_noalloc": (I, [P, P, I, I, I, I, I, P, P, P, P, P]),
         "dr_profile": (I, [P, I]),
         "dr_profile_read": (I, [P, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64), I]),
         "dr_stage_name": (ct.c_char_p, [I]),

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -98,6 +99,28 @@ void dr::dr_prof_end(dr_ctx* c, int stage, hipStream_t s, hipEvent_t a, hipEvent
 // ------------------------------------------------------------------------------------------
 // create / destroy
 // ------------------------------------------------------------------------------------------
+// ------------------------------------------------------------------------------------------
+// static scratch of the allocation-free token gather (dr_gather_tokens_noalloc): per-window
+// query counts.  Every device the library runs on holds one copy until the process ends; its
+// device address is resolved once per device, at the first dr_create there.
+// ------------------------------------------------------------------------------------------
+static constexpr int kScratchWindows = 1 << 16;
+static __device__ __align__(256) int32_t scratch[kScratchWindows];
+static std::mutex g_scratch_mu;
+static int32_t* g_scratch_dev[64];  // device address of `scratch` per HIP device
+
+static int32_t* scratch_address(int device) {
+  if (device < 0 || device >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    // the device must be current: each device holds its own copy at its own address
+    if (hipSetDevice(device) == hipSuccess && hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess)
+      g_scratch_dev[device] = static_cast<int32_t*>(p);
+  }
+  return g_scratch_dev[device];
+}
+
 extern "C" dr_status dr_create(dr_ctx** out, int device, const dr_netcfg* cfg) {
   if (!out || !cfg) return fail(nullptr, DR_EINVAL, "dr_create: null argument");
   *out = nullptr;
@@ -115,8 +138,11 @@ extern "C" dr_status dr_create(dr_ctx** out, int device, const dr_netcfg* cfg) {
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
     return fail(nullptr, DR_EINVAL, "no HIP device %d", device);
+  int32_t* scr = scratch_address(device);
+  if (!scr) return fail(nullptr, DR_EHIP, "dr_create: cannot resolve the static scratch array on device %d", device);
   dr_ctx* c = new dr_ctx();
   c->device = device;
+  c->scratch_wcount = scr;
   Net& n = c->net;
   n.cfg = k;
   n.C = k.dim;
@@ -326,6 +352,28 @@ extern "C" dr_status dr_gather_tokens(dr_ctx* c, const uint8_t* masks, int B, in
   hipStream_t s = (hipStream_t)stream;
   LAUNCH(ST_TOKENS, launch_token_flags(g, masks, qs == DR_QUERY_ALL, flag, c->work.wcount, s, c->net.K != c->net.P));
   LAUNCH(ST_TOKENS, launch_token_gather(g, flag, c->work.wcount, idx, woff, nq, s));
+  return DR_OK;
+}
+
+extern "C" dr_status dr_gather_tokens_noalloc(dr_ctx* c, const uint8_t* masks, int B, int T, int H, int W,
+                                              dr_query_set qs, uint8_t* flag, int32_t* idx, int32_t* woff,
+                                              int32_t* nq, void* stream) {
+  if (!c || !masks || !flag || !idx || !woff || !nq)
+    return fail(c, DR_EINVAL, "dr_gather_tokens_noalloc: null argument");
+  if (qs != DR_QUERY_MASKED && qs != DR_QUERY_ALL) return fail(c, DR_EINVAL, "bad query set");
+  Geo g;
+  dr_status st = make_geo(c, B, T, H, W, g);
+  if (st != DR_OK) return st;
+  if (g.nwin > kScratchWindows)
+    return fail(c, DR_EINVAL, "dr_gather_tokens_noalloc: %d windows exceed the static scratch of %d", g.nwin,
+                kScratchWindows);
+  HIP_OK(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  // no profiling brackets here: they may create events.  Every count in scratch[0, nwin) is
+  // written by the flag kernel before the gather kernel reads it, so nothing is cleared.
+  launch_token_flags(g, masks, qs == DR_QUERY_ALL, flag, c->scratch_wcount, s, c->net.K != c->net.P);
+  launch_token_gather(g, flag, c->scratch_wcount, idx, woff, nq, s);
+  HIP_OK(c, hipGetLastError());
   return DR_OK;
 }
 

@@ -167,6 +167,7 @@ struct dr_wplan;  // per-shape weight derivation plan (dr_weights.hip)
 
 struct dr_ctx {
   int device = 0;
+  int32_t* scratch_wcount = nullptr;  // this device's static gather scratch (device address)
   dr::Net net;
   bool have_weights = false;
   // weights: the flat FP32 parameters (blob order) and the arenas derived from them on the
