@@ -267,11 +267,6 @@ dr_status dr::dr_reserve_work(dr_ctx* c, Work& w, const Geo& g, bool stream_mode
   ALLOC(u16, N * C * 2);
   ALLOC(xh, N * C * 2);
   ALLOC(amax, (size_t)n.cfg.blocks * 4 * 4);
-  if (mlp_split_supported((int)C, (int)R)) {
-    ALLOC(mlp_part, mlp_split_part_floats((int)C, (int)N) * 4);
-    ALLOC(mlp_cnt, mlp_split_counters((int)N) * 4);
-    HIP_OK(c, hipMemset(w.mlp_cnt, 0, mlp_split_counters((int)N) * 4));
-  }
   if (stream_mode) {
     const size_t npix = N * 16;  // 4 x 4 pixels per token
     ALLOC(fst, npix * 12);
@@ -409,9 +404,7 @@ static dr_status run_blocks(dr_ctx* c, const Geo& g, dr_precision prec, hipStrea
       // for the MLP; the second MLP linear refreshes x^ of the query rows
       LAUNCH(ST_QKV, launch_qkv_bf16(g, C, n.cfg.heads, n.Spad, attn_clip_vt_stride(n.Spad), w.xh, w.tiles, w.ntiles, b.wqkvf16, b.bqkvf, w.q16, w.k16, w.vt16, s));
       LAUNCH(ST_ATTN, launch_attn_clip(g, C, n.cfg.heads, n.Spad, w.q16, w.k16, w.vt16, w.idx, w.woff, w.worder, w.o16, nullptr, attn_mode(c, l), s));
-      if (mlp_split_supported(C, R)) {
-        LAUNCH(ST_MLP, launch_mlp_split_bf16(N, w.nq, C, w.o16, w.idx, b.wo16, b.bo, b.w1f16, b.b1f, b.w216, b.b2, w.x, w.xh, w.mlp_part, w.mlp_cnt, s));
-      } else if (mlp_block_supported(C, R)) {
+      if (mlp_block_supported(C, R)) {
         LAUNCH(ST_MLP, launch_mlp_block_bf16(N, w.nq, C, w.o16, w.idx, b.wo16, b.bo, b.w1f16, b.b1f, b.w216, b.b2, w.x, w.xh, s));
       } else {
         LAUNCH(ST_PROJ, launch_resid_ln_bf16(N, w.nq, C, C, w.o16, b.wo16, b.bo, w.x, w.idx, w.u16, nullptr, s));

@@ -108,8 +108,6 @@ struct Work {
   bf16* vt16 = nullptr;  // V^T [win][head][dh][vt stride] (BF16 clip mode)
   float* amax = nullptr;  // FP8 activation amax slots [blocks][4]
   float* contrib = nullptr;  // overlapping decoder: per-token logit patches [N][192]
-  float* mlp_part = nullptr;    // split MLP: per-slice partial products [slices][N][C]
-  int32_t* mlp_cnt = nullptr;   // split MLP: arrival counters per 64-row tile (zero between launches)
   // stream mode: contiguous staging of the batch's frames, masks and outputs
   float* fst = nullptr;
   uint8_t* mst = nullptr;
@@ -321,14 +319,6 @@ void launch_fc1_bf16(int m_max, const int32_t* m_dev, int C, int R, const bf16* 
                      const float* bias, bf16* h, hipStream_t s);
 bool resid_ln_supported(int C);
 bool mlp_block_supported(int C, int R);
-// fused projection + MLP with the hidden dimension split over several workgroups per row tile
-// (partials in `part`, per-tile arrival counters in `cnt`, zero between launches)
-bool mlp_split_supported(int C, int R);
-size_t mlp_split_part_floats(int C, int m_max);
-size_t mlp_split_counters(int m_max);
-void launch_mlp_split_bf16(int m_max, const int32_t* m_dev, int C, const bf16* o, const int32_t* rows,
-                           const bf16* wo, const float* bo, const bf16* w1, const float* b1, const bf16* w2,
-                           const float* b2, float* x, bf16* xh, float* part, int32_t* cnt, hipStream_t s);
 void launch_mlp_block_bf16(int m_max, const int32_t* m_dev, int C, const bf16* o, const int32_t* rows,
                            const bf16* wo, const float* bo, const bf16* w1, const float* b1, const bf16* w2,
                            const float* b2, float* x, bf16* xh, hipStream_t s);

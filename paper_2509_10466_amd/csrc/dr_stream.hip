@@ -198,9 +198,7 @@ static dr_status stream_step_locked(dr_ctx* c, Work& w, int n, const int32_t* si
     tab.sfp = ring_vt_frame_stride(g.S);
     LAUNCH(ST_QKV, launch_qkv_stream(g, C, net.cfg.heads, w.xh, w.flag, b.wqkvf16, b.bqkvf, w.q16, tab, s));
     LAUNCH(ST_ATTN, launch_attn_ring(tab, g, C, net.cfg.heads, net.cfg.win_t, w.q16, w.idx, w.woff, w.worder, w.o16, s));
-    if (mlp_split_supported(C, R)) {
-      LAUNCH(ST_MLP, launch_mlp_split_bf16(N, w.nq, C, w.o16, w.idx, b.wo16, b.bo, b.w1f16, b.b1f, b.w216, b.b2, w.x, w.xh, w.mlp_part, w.mlp_cnt, s));
-    } else if (mlp_block_supported(C, R)) {
+    if (mlp_block_supported(C, R)) {
       LAUNCH(ST_MLP, launch_mlp_block_bf16(N, w.nq, C, w.o16, w.idx, b.wo16, b.bo, b.w1f16, b.b1f, b.w216, b.b2, w.x, w.xh, s));
     } else {
       LAUNCH(ST_PROJ, launch_resid_ln_bf16(N, w.nq, C, C, w.o16, b.wo16, b.bo, w.x, w.idx, w.u16, nullptr, s));

@@ -780,332 +780,4 @@ void launch_mlp_block_bf16(int m_max, const int32_t* m_dev, int C, const bf16* o
   }
 }
 
-// ------------------------------------------------------------------------------------------
-// Fused projection + MLP with the hidden dimension split over NSL workgroups per row tile
-// ------------------------------------------------------------------------------------------
-// A 64-row tile of query tokens is handled by NSL workgroups, workgroup sl owning hidden units
-// [sl HS, (sl+1) HS): each computes the projection x1 = x + o Wo^T + bo of its rows (the same
-// values in every slice) and u2 = normalise(x1), then its slice of h = GELU(u2 W1'^T + b1')
-// and the partial product h_sl W2[:, slice]^T.  The partials go to a workspace; the last
-// workgroup of the tile to finish (an agent-scope counter per tile) adds them in slice order
-// -- so the result does not depend on which one finishes last -- with x1 and b2, and writes
-// x2 = x1 + sum + b2 and x^ = normalise(x2).  Nothing is written to x before every slice of
-// the tile has read it.  Against one workgroup per tile this spreads the tile's work over
-// NSL compute units and shortens each workgroup's chain of weight stages from
-// NKC + NCH (NW1 + NKH) to 2 NKC + HS / 64.
-template <int C_, int HS_, int ST_>
-struct SplitCfg {
-  static constexpr int C = C_, HS = HS_, R = 4 * C, NSL = R / HS, BM = 64, ST = ST_;
-  static constexpr int WM = 2, WN = 4, TM = BM / WM, FM = TM / 16;
-  static constexpr int FN_C = C / 64, FN_H = HS / 64;   // 16-wide fragments per wavefront
-  static constexpr int NKC = C / 64, NKH = HS / 64;     // 64-wide k blocks of C and HS
-  static constexpr int SLOT_ROWS = C > HS ? C : HS, SLOT = SLOT_ROWS * 64;
-  static constexpr int NSTAGE = 2 * NKC + NKH;          // projection, first and second linear
-  static constexpr size_t RING = (size_t)ST * SLOT;
-  static constexpr size_t ACT = (size_t)(NKC > NKH ? NKC : NKH) * BM * 64;  // o, then u2, then h
-  static constexpr size_t FLOATS = (size_t)C + HS + C + 2 * WN * BM + 4;   // biases, row sums, flag
-  static constexpr size_t LDS_BYTES = (RING + ACT) * 2 + FLOATS * 4;
-  // u2 fragments held in registers through the first linear (C <= 256), else read from LDS
-  static constexpr bool UA_REGS = C <= 256;
-  static_assert(R % HS == 0 && HS % 64 == 0 && C % 64 == 0 && (ST == 2 || ST == 3), "shapes");
-  static_assert(LDS_BYTES <= 160 * 1024, "LDS");
-};
-
-// First linear with the hidden fragments dealt round robin over the column wavefronts:
-// fragment j of wavefront wn holds hidden units 16 (WN j + wn) .. +15 of the slice, so every
-// wavefront owns part of every 64-wide k block of h.
-template <class MC>
-__device__ __forceinline__ void mfma_fc1_rr(const bf16x8_t (&af)[2][MC::FM], const bf16* Ws,
-                                            f32x4_t (&acc)[MC::FM][MC::FN_H]) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int wn = wv % MC::WN;
-  const int l16 = lane & 15, kg = lane >> 4;
-  bf16x8_t wf[2][MC::FN_H];
-  static_for<2>([&](auto kk) {
-    static_for<MC::FN_H>([&](auto j) {
-      const int row = 16 * (MC::WN * j + wn) + l16;
-      wf[kk][j] = *reinterpret_cast<const bf16x8_t*>(Ws + row * 64 + (((4 * kk + kg) ^ lds_swz(row)) * 8));
-    });
-  });
-  static_for<2>([&](auto kk) {
-    mfma_fence_begin();
-    static_for<MC::FM>([&](auto i) {
-      static_for<MC::FN_H>([&](auto j) { acc[i][j] = mfma_bf16_16x16x32(wf[kk][j], af[kk][i], acc[i][j]); });
-    });
-    mfma_fence_end();
-  });
-}
-
-// As mfma_fc1_rr with the u2 fragments read from LDS (k block at As).
-template <class MC>
-__device__ __forceinline__ void mfma_fc1_rr_lds(const bf16* As, const bf16* Ws, f32x4_t (&acc)[MC::FM][MC::FN_H]) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int wm = wv / MC::WN;
-  const int l16 = lane & 15, kg = lane >> 4;
-  bf16x8_t af[2][MC::FM];
-  static_for<2>([&](auto kk) {
-    static_for<MC::FM>([&](auto i) {
-      const int row = wm * MC::TM + 16 * i + l16;
-      af[kk][i] = *reinterpret_cast<const bf16x8_t*>(As + row * 64 + (((4 * kk + kg) ^ lds_swz(row)) * 8));
-    });
-  });
-  mfma_fc1_rr<MC>(af, Ws, acc);
-}
-
-template <class MC>
-__global__ void __launch_bounds__(MLP_THREADS) mlp_split_kernel(
-    const int32_t* __restrict__ m_dev, const bf16* __restrict__ o, const int32_t* __restrict__ rows,
-    const bf16* __restrict__ Wo, const float* __restrict__ bo, const bf16* __restrict__ W1,
-    const float* __restrict__ b1, const bf16* __restrict__ W2, const float* __restrict__ b2, float* __restrict__ x,
-    bf16* __restrict__ xh, float* __restrict__ part, int part_rows, int32_t* __restrict__ cnt) {
-  constexpr int C = MC::C, HS = MC::HS, R = MC::R, BM = MC::BM, NW = MLP_THREADS / 64, NSL = MC::NSL;
-  extern __shared__ __align__(16) bf16 lds[];
-  bf16* ring = lds;
-  bf16* act = lds + MC::RING;
-  float* sbo = reinterpret_cast<float*>(act + MC::ACT);
-  float* sb1 = sbo + C;
-  float* sb2 = sb1 + HS;
-  float(*red)[MC::WN][64] = reinterpret_cast<float(*)[MC::WN][64]>(sb2 + C);
-  int* sflag = reinterpret_cast<int*>(sb2 + C + 2 * MC::WN * 64);
-
-  // workgroup b runs on XCD b % 8; the NSL slices of a row tile are b, b + 8, ... on one XCD
-  const int b = blockIdx.x, kq = b >> 3;
-  const int sl = kq % NSL, rt = (kq / NSL) * 8 + (b & 7);
-  const int M = m_dev[0];
-  const int m0 = rt * BM;
-  if (m0 >= M) return;
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int wm = wv / MC::WN, wn = wv % MC::WN;
-  const int l16 = lane & 15, kg = lane >> 4;
-
-  for (int i = t; i < C; i += MLP_THREADS) {
-    sbo[i] = bo[i];
-    sb2[i] = b2[i];
-  }
-  for (int i = t; i < HS; i += MLP_THREADS) sb1[i] = b1[sl * HS + i];
-  // o rows -> act (rows >= M read row M-1; their results are never stored)
-  static_for<MC::NKC>([&](auto kb) {
-    const int row = wv * 8 + (lane >> 3);
-    const int m = min(m0 + row, M - 1);
-    dma16(o + (size_t)m * C + 64 * kb + ((lane & 7) ^ lds_swz(row)) * 8, act + kb * BM * 64 + wv * 512);
-  });
-  // stage s: 64 k columns of `rows_of(s)` weight rows
-  auto rows_of = [](int s) { return (s >= MC::NKC && s < 2 * MC::NKC) ? HS : C; };
-  auto issue = [&](int s) {
-    const bf16* base;
-    int ld;
-    if (s < MC::NKC) {
-      base = Wo + 64 * s;
-      ld = C;
-    } else if (s < 2 * MC::NKC) {
-      base = W1 + (size_t)sl * HS * C + 64 * (s - MC::NKC);
-      ld = C;
-    } else {
-      base = W2 + sl * HS + 64 * (s - 2 * MC::NKC);
-      ld = R;
-    }
-    const int rows_s = rows_of(s);
-    bf16* dst = ring + (s % MC::ST) * MC::SLOT;
-    static_for<MC::SLOT_ROWS / (8 * NW)>([&](auto c) {
-      const int g8 = wv + NW * c;
-      if (g8 * 8 < rows_s) {  // uniform per wavefront
-        const int row = g8 * 8 + (lane >> 3);
-        dma16(base + (size_t)row * ld + ((lane & 7) ^ lds_swz(row)) * 8, dst + g8 * 512);
-      }
-    });
-  };
-  static_for<MC::ST - 1>([&](auto s0) { issue(s0); });
-
-  int dst[MC::FM];
-  static_for<MC::FM>([&](auto i) {
-    const int m = m0 + wm * MC::TM + 16 * i + l16;
-    dst[i] = m < M ? rows[m] : -1;
-  });
-  // Before multiplying stage s: wait until it has landed (the next stage's loads may stay in
-  // flight with a 3-stage ring; none after other vector-memory traffic), then queue s + ST - 1.
-  bool drained = true;
-  auto enter = [&](int s) {
-    if (MC::ST == 2 || drained || s + 1 >= MC::NSTAGE)
-      vm_wait_barrier<0>();
-    else if (rows_of(s + 1) == C)
-      vm_wait_barrier<(MC::ST == 3 ? C / (8 * NW) : 0)>();
-    else
-      vm_wait_barrier<(MC::ST == 3 ? HS / (8 * NW) : 0)>();
-    drained = false;
-    if (s + MC::ST - 1 < MC::NSTAGE) issue(s + MC::ST - 1);
-    return ring + (s % MC::ST) * MC::SLOT;
-  };
-
-  f32x4_t x1[MC::FM][MC::FN_C];
-  static_for<MC::FM>([&](auto i) {
-    static_for<MC::FN_C>([&](auto j) { x1[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f}; });
-  });
-  float mean[MC::FM], rstd[MC::FM];
-  int s = 0;
-  {
-    float4 xo[MC::FM][MC::FN_C];
-    static_for<MC::NKC>([&](auto kb) {
-      const bf16* ws = enter(s);
-      if (kb == MC::NKC - 1) load_resid<MC>(x, dst, xo);
-      mfma_block<MC, MC::FN_C>(act + kb * BM * 64, ws, x1);
-      ++s;
-    });
-    // x1 = x + o Wo^T + bo stays in registers (no slice writes x before the tile is done)
-    resid_rows<MC>(x1, sbo, x, dst, xo, red, mean, rstd, false);
-  }
-  static_for<MC::FM>([&](auto i) {
-    const int r = wm * MC::TM + 16 * i + l16;
-    static_for<MC::FN_C>([&](auto j) {
-      const int n = wn * 16 * MC::FN_C + 16 * j + 4 * kg;
-      const f32x4_t& a = x1[i][j];
-      uint2 pk;
-      pk.x = pack_bf2((a[0] - mean[i]) * rstd[i], (a[1] - mean[i]) * rstd[i]);
-      pk.y = pack_bf2((a[2] - mean[i]) * rstd[i], (a[3] - mean[i]) * rstd[i]);
-      *reinterpret_cast<uint2*>(act + res_off(r, n)) = pk;
-    });
-  });
-  drained = true;  // x was read
-  lds_barrier();
-  f32x4_t hacc[MC::FM][MC::FN_H];
-  static_for<MC::FM>([&](auto i) {
-    static_for<MC::FN_H>([&](auto j) { hacc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f}; });
-  });
-  if constexpr (MC::UA_REGS) {
-    bf16x8_t ua[MC::NKC][2][MC::FM];
-    static_for<MC::NKC>([&](auto kb) {
-      static_for<2>([&](auto kk) {
-        static_for<MC::FM>([&](auto i) {
-          const int row = wm * MC::TM + 16 * i + l16;
-          ua[kb][kk][i] = *reinterpret_cast<const bf16x8_t*>(act + kb * BM * 64 + row * 64 +
-                                                             (((4 * kk + kg) ^ lds_swz(row)) * 8));
-        });
-      });
-    });
-    static_for<MC::NKC>([&](auto tt) {
-      const bf16* ws = enter(s);
-      mfma_fc1_rr<MC>(ua[tt], ws, hacc);
-      ++s;
-    });
-  } else {
-    static_for<MC::NKC>([&](auto tt) {
-      const bf16* ws = enter(s);
-      mfma_fc1_rr_lds<MC>(act + tt * BM * 64, ws, hacc);
-      ++s;
-    });
-    lds_barrier();  // every wavefront has read u2 before h overwrites it
-  }
-  // h = GELU(.) into act (with u2 in registers, every wavefront read its fragments before the
-  // first stage of the first linear, so act is free)
-  static_for<MC::FM>([&](auto i) {
-    const int r = wm * MC::TM + 16 * i + l16;
-    static_for<MC::FN_H>([&](auto jj) {
-      const int c = 16 * (MC::WN * jj + wn) + 4 * kg;
-      const float* bb = sb1 + c;
-      const f32x4_t& a = hacc[i][jj];
-      uint2 pk;
-      pk.x = pack_bf2(gelu_fast(a[0] + bb[0]), gelu_fast(a[1] + bb[1]));
-      pk.y = pack_bf2(gelu_fast(a[2] + bb[2]), gelu_fast(a[3] + bb[3]));
-      *reinterpret_cast<uint2*>(act + res_off(r, c)) = pk;
-    });
-  });
-  f32x4_t acc[MC::FM][MC::FN_C];
-  static_for<MC::FM>([&](auto i) {
-    static_for<MC::FN_C>([&](auto j) { acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f}; });
-  });
-  static_for<MC::NKH>([&](auto kb) {
-    const bf16* ws = enter(s);
-    mfma_block<MC, MC::FN_C>(act + kb * BM * 64, ws, acc);
-    ++s;
-  });
-  if constexpr (NSL > 1) {
-    // this slice's partial product -> workspace; the tile's counter says who finishes
-    float* mine = part + (size_t)sl * part_rows * C;
-    static_for<MC::FM>([&](auto i) {
-      const int m = m0 + wm * MC::TM + 16 * i + l16;
-      if (m < M)
-        static_for<MC::FN_C>([&](auto j) {
-          const int n = wn * 16 * MC::FN_C + 16 * j + 4 * kg;
-          const f32x4_t& a = acc[i][j];
-          *reinterpret_cast<float4*>(mine + (size_t)m * C + n) = make_float4(a[0], a[1], a[2], a[3]);
-        });
-    });
-    vm_wait_barrier<0>();  // every wavefront's stores have completed
-    if (t == 0) *sflag = __hip_atomic_fetch_add(cnt + rt, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    lds_barrier();
-    if (*sflag != NSL - 1) return;
-    // the last slice to arrive: sum the partials in slice order
-    static_for<MC::FM>([&](auto i) {
-      const int m = min(m0 + wm * MC::TM + 16 * i + l16, M - 1);
-      static_for<MC::FN_C>([&](auto j) {
-        const int n = wn * 16 * MC::FN_C + 16 * j + 4 * kg;
-        f32x4_t sum = f32x4_t{0.f, 0.f, 0.f, 0.f};
-        for (int q = 0; q < NSL; ++q) {
-          f32x4_t v;
-          if (q == sl) {
-            v = acc[i][j];
-          } else {
-            const float4 p4 = *reinterpret_cast<const float4*>(part + ((size_t)q * part_rows + m) * C + n);
-            v = f32x4_t{p4.x, p4.y, p4.z, p4.w};
-          }
-          if (q == 0)
-            sum = v;
-          else
-            sum = f32x4_t{sum[0] + v[0], sum[1] + v[1], sum[2] + v[2], sum[3] + v[3]};
-        }
-        acc[i][j] = sum;
-      });
-    });
-    if (t == 0) __hip_atomic_store(cnt + rt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // for the next launch
-  }
-  // x2 = x1 + sum + b2; x^ = normalise(x2)
-  float4 x1v[MC::FM][MC::FN_C];
-  static_for<MC::FM>([&](auto i) {
-    static_for<MC::FN_C>([&](auto j) { x1v[i][j] = make_float4(x1[i][j][0], x1[i][j][1], x1[i][j][2], x1[i][j][3]); });
-  });
-  resid_rows<MC>(acc, sb2, x, dst, x1v, red, mean, rstd, true);
-  static_for<MC::FM>([&](auto i) {
-    if (dst[i] >= 0)
-      static_for<MC::FN_C>([&](auto j) {
-        const int n = wn * 16 * MC::FN_C + 16 * j + 4 * kg;
-        const f32x4_t& a = acc[i][j];
-        uint2 pk;
-        pk.x = pack_bf2((a[0] - mean[i]) * rstd[i], (a[1] - mean[i]) * rstd[i]);
-        pk.y = pack_bf2((a[2] - mean[i]) * rstd[i], (a[3] - mean[i]) * rstd[i]);
-        *reinterpret_cast<uint2*>(xh + (size_t)dst[i] * C + n) = pk;
-      });
-  });
-}
-
-template <class MC>
-static void split_launch(int m_max, const int32_t* m_dev, const bf16* o, const int32_t* rows, const bf16* wo,
-                         const float* bo, const bf16* w1, const float* b1, const bf16* w2, const float* b2, float* x,
-                         bf16* xh, float* part, int32_t* cnt, hipStream_t s) {
-  static bool attr = false;
-  if (!attr) {
-    allow_lds(mlp_split_kernel<MC>, MC::LDS_BYTES);
-    attr = true;
-  }
-  const int mt = (m_max + MC::BM - 1) / MC::BM;
-  mlp_split_kernel<MC><<<xcd_grid(mt, MC::NSL), MLP_THREADS, MC::LDS_BYTES, s>>>(m_dev, o, rows, wo, bo, w1, b1, w2,
-                                                                                 b2, x, xh, part, m_max, cnt);
-}
-
-// (dim 384 keeps the three-kernel path: six slices of FP32 partials would move several times
-// the block's algorithmic bytes)
-bool mlp_split_supported(int C, int R) { return R == 4 * C && (C == 128 || C == 256); }
-
-size_t mlp_split_part_floats(int C, int m_max) { return (size_t)(4 * C / 256) * m_max * C; }
-size_t mlp_split_counters(int m_max) { return (size_t)(m_max + 63) / 64; }
-
-void launch_mlp_split_bf16(int m_max, const int32_t* m_dev, int C, const bf16* o, const int32_t* rows,
-                           const bf16* wo, const float* bo, const bf16* w1, const float* b1, const bf16* w2,
-                           const float* b2, float* x, bf16* xh, float* part, int32_t* cnt, hipStream_t s) {
-  if (m_max <= 0) return;
-  switch (C) {
-    case 128: split_launch<SplitCfg<128, 256, 3>>(m_max, m_dev, o, rows, wo, bo, w1, b1, w2, b2, x, xh, part, cnt, s); break;
-    case 256: split_launch<SplitCfg<256, 256, 3>>(m_max, m_dev, o, rows, wo, bo, w1, b1, w2, b2, x, xh, part, cnt, s); break;
-    default: break;  // rejected by the caller (mlp_split_supported)
-  }
-}
-
 }  // namespace dr

@@ -3,6 +3,8 @@
     python -m paper_2509_10466_amd.profile_summary kernels RESULTS_DB --command "CMD"
     python -m paper_2509_10466_amd.profile_summary traffic --fetch FETCH_DB --write WRITE_DB \\
         --kernel SUBSTRING --command-fetch "CMD" --command-write "CMD"
+    python -m paper_2509_10466_amd.profile_summary counters DB [DB ...] --kernel SUB [--kernel SUB] \\
+        --command "CMD" [--command "CMD"]
 
 ``kernels`` tabulates a --kernel-trace run: calls, average / min / max duration and share of
 the traced GPU time per kernel.  ``traffic`` turns two --pmc runs (FETCH_SIZE, then
@@ -119,6 +121,76 @@ def traffic(fetch_db, write_db, kernel, cmd_f, cmd_w) -> str:
     return "\n".join(lines)
 
 
+def _counters_all(db: str):
+    """kernel name -> counter -> list of per-dispatch values.  SQ counters are summed over
+    their instances (shader engines, XCDs); GRBM counters, one per XCD for the same kernel
+    interval, take the maximum (as rocprofv3's derived MfmaUtil does)."""
+    c = sqlite3.connect(db)
+    acc = defaultdict(lambda: defaultdict(float))
+    names = {}
+    for name, ctr, val, did in c.execute("select kernel_name, counter_name, value, dispatch_id from counters_collection"):
+        key = (did, ctr)
+        if ctr.startswith("GRBM_"):
+            acc[did][ctr] = max(acc[did][ctr], val)
+        else:
+            acc[did][ctr] += val
+        names[did] = name
+    out = defaultdict(lambda: defaultdict(list))
+    for did, d in acc.items():
+        for ctr, v in d.items():
+            out[names[did]][ctr].append(v)
+    return out
+
+
+SIMDS = 1024          # MI355X: 256 CUs x 4 SIMDs
+CUS = 256
+CLOCK_GHZ = 2.4
+
+
+def counters(dbs, kernels, commands) -> str:
+    """Per-kernel averages of the counters of one or more --pmc runs, with the derived figures:
+    MFMA busy = sum SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x SIMDs) (rocprofv3's
+    MfmaUtil), BF16 MFMA rate = 512 SQ_INSTS_VALU_MFMA_MOPS_BF16 per GRBM_GUI_ACTIVE cycle at
+    2.4 GHz, VALU busy = 4 SQ_ACTIVE_INST_VALU / (GRBM_GUI_ACTIVE x SIMDs) (quad-cycles),
+    LDS bank-conflict cycles per CU-cycle."""
+    merged = defaultdict(lambda: defaultdict(list))
+    for db in dbs:
+        for k, d in _counters_all(db).items():
+            for ctr, vals in d.items():
+                merged[k][ctr] += vals
+    lines = [f"command: {cmd}" for cmd in commands]
+    lines.append("per-dispatch averages; derived figures from the averages")
+    for sub in kernels:
+        hits = [k for k in merged if sub in k]
+        if not hits:
+            lines.append(f"{sub}: no dispatch")
+            continue
+        name = max(hits, key=lambda k: len(next(iter(merged[k].values()))))
+        d = {ctr: sum(v) / len(v) for ctr, v in merged[name].items()}
+        n = max(len(v) for v in merged[name].values())
+        lines.append(f"kernel: {short(name)}  (dispatches: {n})")
+        for ctr in sorted(d):
+            lines.append(f"  {ctr:32s} {d[ctr]:16.1f}")
+        gui = d.get("GRBM_GUI_ACTIVE")
+        if gui:
+            lines.append(f"  kernel time from GRBM_GUI_ACTIVE: {gui / CLOCK_GHZ / 1e3:.2f} us")
+            if "SQ_VALU_MFMA_BUSY_CYCLES" in d:
+                lines.append(f"  MFMA busy: {100 * d['SQ_VALU_MFMA_BUSY_CYCLES'] / (gui * SIMDS):.1f} % of SIMD cycles")
+            if "SQ_INSTS_VALU_MFMA_MOPS_BF16" in d:
+                tf = 512 * d["SQ_INSTS_VALU_MFMA_MOPS_BF16"] / (gui / (CLOCK_GHZ * 1e9)) / 1e12
+                lines.append(f"  BF16 MFMA rate: {tf:.1f} TFLOP/s ({100 * tf / 2500:.1f} % of 2.5 PFLOP/s), "
+                             f"{512 * d['SQ_INSTS_VALU_MFMA_MOPS_BF16'] / 1e9:.3f} GFLOP issued")
+            if "SQ_ACTIVE_INST_VALU" in d:
+                lines.append(f"  VALU busy: {100 * 4 * d['SQ_ACTIVE_INST_VALU'] / (gui * SIMDS):.1f} % of SIMD cycles")
+            if "SQ_VALU_MFMA_COEXEC_CYCLES" in d:
+                lines.append(f"  VALU/MFMA co-execution: {100 * d['SQ_VALU_MFMA_COEXEC_CYCLES'] / (gui * SIMDS):.1f} % of SIMD cycles")
+            if "SQ_LDS_BANK_CONFLICT" in d:
+                lines.append(f"  LDS bank-conflict cycles: {100 * d['SQ_LDS_BANK_CONFLICT'] / (gui * CUS):.2f} % of CU cycles")
+            if "SQ_ACTIVE_INST_LDS" in d:
+                lines.append(f"  LDS instruction issue: {100 * 4 * d['SQ_ACTIVE_INST_LDS'] / (gui * SIMDS):.1f} % of SIMD cycles")
+    return "\n".join(lines)
+
+
 def read_traffic(path: str):
     """(kernel, bytes per launch) from a ``traffic`` summary if it was taken from the current
     sources, else None."""
@@ -149,9 +221,15 @@ def main():
     t.add_argument("--kernel", required=True)
     t.add_argument("--command-fetch", required=True)
     t.add_argument("--command-write", required=True)
+    cc = sub.add_parser("counters")
+    cc.add_argument("dbs", nargs="+")
+    cc.add_argument("--kernel", action="append", required=True)
+    cc.add_argument("--command", action="append", required=True)
     a = ap.parse_args()
     if a.cmd == "kernels":
         print(kernels(a.db, a.command))
+    elif a.cmd == "counters":
+        print(counters(a.dbs, a.kernel, a.command))
     else:
         print(traffic(a.fetch, a.write, a.kernel, a.command_fetch, a.command_write))
 
