@@ -22,12 +22,13 @@ void launch_gather_rows(const float* X, const int32_t* rows, const int32_t* n_de
 void launch_scatter_rows(const float* Y, const int32_t* rows, const int32_t* n_dev, int n_max, int C, float* X, hipStream_t s);
 void launch_gelu_fwd(const float* h, const int32_t* n_dev, int n_max, int R, float* a, hipStream_t s);
 void launch_gelu_bwd(const float* h, const float* da, const int32_t* n_dev, int n_max, int R, float* dh, hipStream_t s);
-void launch_attn_f32_save(const Geo& g, int C, int heads, const float* q, const float* kv, const int32_t* woff,
-                          float* o, float2* stats, hipStream_t s);
-void launch_attn_bwd_q(const Geo& g, int C, int heads, const float* q, const float* kv, const float* dout,
-                       const float2* stats, const int32_t* woff, float* dq, float* P, float* dS, hipStream_t s);
-void launch_attn_bwd_kv(const Geo& g, int C, int heads, const float* q, const float* dout, const float* P,
-                        const float* dS, const int32_t* woff, float* dkv, hipStream_t s);
+bool attn_train_supported(int dh, int S);
+void launch_attn_train_fwd(const Geo& g, int C, int heads, const float* q, const float* kv, const int32_t* woff,
+                           float* o, float2* stats, hipStream_t s);
+void launch_attn_train_dq(const Geo& g, int C, int heads, const float* q, const float* kv, const float* dout,
+                          const float2* stats, const int32_t* woff, float* dq, float* dsum, hipStream_t s);
+void launch_attn_train_dkv(const Geo& g, int C, int heads, const float* q, const float* kv, const float* dout,
+                           const float2* stats, const float* dsum, const int32_t* woff, float* dkv, hipStream_t s);
 void launch_ln_bwd(const float* x, const int32_t* rows, const int32_t* n_dev, int n_max, int C, const float* g,
                    const float* dy, float* dx, int accumulate, int dst_compact, float* part, hipStream_t s);
 int ln_bwd_blocks(int n_max);
@@ -96,7 +97,7 @@ struct dr_train {
   float* x = nullptr;
   // reverse-pass scratch
   float *a = nullptr, *dx = nullptr, *dx2 = nullptr, *dx1 = nullptr, *da = nullptr, *dh = nullptr, *dn2 = nullptr,
-        *dout = nullptr, *dq = nullptr, *dkv = nullptr, *du = nullptr, *P = nullptr, *dS = nullptr, *dyt = nullptr,
+        *dout = nullptr, *dq = nullptr, *dkv = nullptr, *du = nullptr, *dsum = nullptr, *dyt = nullptr,
         *dz = nullptr, *part = nullptr, *lnpart = nullptr, *zeros = nullptr, *tmp = nullptr;
   // loss scratch (allocated once)
   float *lpart = nullptr, *lacc = nullptr;
@@ -110,7 +111,7 @@ static void free_list(std::vector<void*>& l) {
 
 static void scratch_free(dr_train* t) {
   free_list(t->allocs);
-  t->x = t->a = t->dx = t->dx2 = t->dx1 = t->da = t->dh = t->dn2 = t->dout = t->dq = t->dkv = t->du = t->P = t->dS =
+  t->x = t->a = t->dx = t->dx2 = t->dx1 = t->da = t->dh = t->dn2 = t->dout = t->dq = t->dkv = t->du = t->dsum =
       t->dyt = t->dz = t->part = t->lnpart = t->zeros = t->tmp = nullptr;
   t->cap = 0;
 }
@@ -180,8 +181,7 @@ static dr_status scratch_reserve(dr_ctx* c, dr_train* t, const Geo& g) {
     t->dq = (float*)A(N * C * 4);
     t->dkv = (float*)A(N * 2 * C * 4);
     t->du = (float*)A(N * C * 4);
-    t->P = (float*)A(N * H * g.S * 4);
-    t->dS = (float*)A(N * H * g.S * 4);
+    t->dsum = (float*)A(N * H * 4);
     t->dyt = (float*)A(N * 48 * 4);
     t->dz = (float*)A(N * C * 4);
     t->part = (float*)A((size_t)tn_chunks((int)N) * R * C * 4);
@@ -319,7 +319,7 @@ static dr_status train_forward_into(dr_ctx* c, dr_train* t, dr_saved* sv, const 
     launch_ln_f32(t->x, nullptr, nullptr, N, C, b.ln1g, b.ln1b, tb.u, s);
     train_gemm(b16, tb.u, nullptr, nullptr, N, C, b.wkv, b.bkv, 2 * C, EPI_STORE, tb.kv, nullptr, s);
     train_gemm(b16, tb.u, sv->idx, sv->nq, N, C, b.wq, b.bq, C, EPI_STORE, tb.q, nullptr, s);
-    launch_attn_f32_save(g, C, heads, tb.q, tb.kv, sv->woff, tb.o, tb.stats, s);
+    launch_attn_train_fwd(g, C, heads, tb.q, tb.kv, sv->woff, tb.o, tb.stats, s);
     train_gemm(b16, tb.o, nullptr, sv->nq, N, C, b.wo, b.bo, C, EPI_RESID, t->x, sv->idx, s);
     launch_gather_rows(t->x, sv->idx, sv->nq, N, C, tb.x1, s);
     launch_ln_f32(tb.x1, nullptr, sv->nq, N, C, b.ln2g, b.ln2b, tb.n2, s);
@@ -343,6 +343,8 @@ extern "C" dr_status dr_train_forward(dr_ctx* c, const float* frames, const uint
   if (!c->have_weights) return dr_fail(c, DR_EINVAL, "no weights loaded");
   if (c->attn_pattern != 0) return dr_fail(c, DR_EINVAL, "training runs the joint-attention network");
   if (c->net.K != c->net.P) return dr_fail(c, DR_EINVAL, "training runs the non-overlapping embedding");
+  if (!attn_train_supported(c->net.dh, c->net.S))
+    return dr_fail(c, DR_ESHAPE, "training attention holds windows of at most 304 tokens, head dim 32 or 64");
   Geo g;
   dr_status st = dr_make_geo(c, B, T, H, W, c->net.cfg.win_t, g);
   if (st != DR_OK) return st;
@@ -476,8 +478,8 @@ extern "C" dr_status dr_train_backward(dr_ctx* c, dr_saved* sv, const float* dpr
     launch_scatter_rows(t->dx1, sv->idx, sv->nq, N, C, t->dx, s);
     KCHECK("mlp/proj backward");
     // attention
-    launch_attn_bwd_q(g, C, heads, tb.q, tb.kv, t->dout, tb.stats, sv->woff, t->dq, t->P, t->dS, s);
-    launch_attn_bwd_kv(g, C, heads, tb.q, t->dout, t->P, t->dS, sv->woff, t->dkv, s);
+    launch_attn_train_dq(g, C, heads, tb.q, tb.kv, t->dout, tb.stats, sv->woff, t->dq, t->dsum, s);
+    launch_attn_train_dkv(g, C, heads, tb.q, tb.kv, t->dout, tb.stats, t->dsum, sv->woff, t->dkv, s);
     KCHECK("attention backward");
     // Q, K, V projections
     tn_grad(t, b16, t->dq, nullptr, C, tb.u, sv->idx, C, sv->nq, N, C, C, G + pb.wq, s);

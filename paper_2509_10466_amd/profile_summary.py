@@ -147,12 +147,28 @@ CUS = 256
 CLOCK_GHZ = 2.4
 
 
-def counters(dbs, kernels, commands) -> str:
-    """Per-kernel averages of the counters of one or more --pmc runs, with the derived figures:
-    MFMA busy = sum SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x SIMDs) (rocprofv3's
-    MfmaUtil), BF16 MFMA rate = 512 SQ_INSTS_VALU_MFMA_MOPS_BF16 per GRBM_GUI_ACTIVE cycle at
-    2.4 GHz, VALU busy = 4 SQ_ACTIVE_INST_VALU / (GRBM_GUI_ACTIVE x SIMDs) (quad-cycles),
-    LDS bank-conflict cycles per CU-cycle."""
+def trace_durations(summary: str):
+    """kernel (short name) -> average duration in us, from a ``kernels`` summary file."""
+    out = {}
+    for ln in open(summary).read().splitlines():
+        parts = ln.split()
+        if len(parts) >= 7 and parts[-6].isdigit():
+            try:
+                out[" ".join(parts[:-6])] = float(parts[-5])
+            except ValueError:
+                pass
+    return out
+
+
+def counters(dbs, kernels, commands, trace_summary=None) -> str:
+    """Per-kernel averages of the counters of one or more --pmc runs, with the derived figures
+    normalised by the kernel's duration: its average in a kernel-trace summary of the same
+    workload when given (a --pmc run serialises dispatches, so GRBM_GUI_ACTIVE there also
+    counts the counter collection around each one), else GRBM_GUI_ACTIVE.  MFMA busy = sum
+    SQ_VALU_MFMA_BUSY_CYCLES / (cycles x SIMDs) (rocprofv3's MfmaUtil); BF16 MFMA rate = 512
+    SQ_INSTS_VALU_MFMA_MOPS_BF16 per second; VALU busy = 4 SQ_ACTIVE_INST_VALU / (cycles x
+    SIMDs) (quad-cycles); LDS bank-conflict cycles per CU-cycle."""
+    dur = trace_durations(trace_summary) if trace_summary else {}
     merged = defaultdict(lambda: defaultdict(list))
     for db in dbs:
         for k, d in _counters_all(db).items():
@@ -172,8 +188,13 @@ def counters(dbs, kernels, commands) -> str:
         for ctr in sorted(d):
             lines.append(f"  {ctr:32s} {d[ctr]:16.1f}")
         gui = d.get("GRBM_GUI_ACTIVE")
-        if gui:
+        us = next((v for k, v in dur.items() if k[:60] == short(name)[:60]), None)
+        if us:
+            gui = us * 1e3 * CLOCK_GHZ
+            lines.append(f"  kernel time from the trace summary: {us:.2f} us")
+        elif gui:
             lines.append(f"  kernel time from GRBM_GUI_ACTIVE: {gui / CLOCK_GHZ / 1e3:.2f} us")
+        if gui:
             if "SQ_VALU_MFMA_BUSY_CYCLES" in d:
                 lines.append(f"  MFMA busy: {100 * d['SQ_VALU_MFMA_BUSY_CYCLES'] / (gui * SIMDS):.1f} % of SIMD cycles")
             if "SQ_INSTS_VALU_MFMA_MOPS_BF16" in d:
@@ -225,11 +246,12 @@ def main():
     cc.add_argument("dbs", nargs="+")
     cc.add_argument("--kernel", action="append", required=True)
     cc.add_argument("--command", action="append", required=True)
+    cc.add_argument("--trace-summary", default=None, help="kernels summary of the same workload (durations)")
     a = ap.parse_args()
     if a.cmd == "kernels":
         print(kernels(a.db, a.command))
     elif a.cmd == "counters":
-        print(counters(a.dbs, a.kernel, a.command))
+        print(counters(a.dbs, a.kernel, a.command, a.trace_summary))
     else:
         print(traffic(a.fetch, a.write, a.kernel, a.command_fetch, a.command_write))
 

@@ -321,3 +321,25 @@ def test_saved_handle_misuse_is_an_error(dev):
     assert eng.lib.dr_train_backward(eng._ctx, h, dpred.data_ptr(), g1.data_ptr(), None) == 1
     eng.close()
     other.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_backward_clip240_network_batch2(dev, precision):
+    """The training network of the 4-clip workload (dim 256, 4 heads, 8 blocks, 225-key
+    windows) on a batch of two 5 x 40 x 72 clips (2 x 2 windows each), against the oracle's
+    FP64 gradient."""
+    from paper_2509_10466_amd import Inpainter
+    cfg = drsynth.NETS["clip240"]
+    frames, masks = drsynth.make_clip_batch([7, 8], 5, 40, 72)
+    W = drsynth.make_weights(cfg, 0)
+    eng = Inpainter(cfg, W)
+    eng.train_precision(precision)
+    L, g, _ = _gpu_grad(eng, frames, masks)
+    Lr, Gr = og.loss_and_grad(frames, masks, W, cfg)
+    gr = _flat(cfg, Gr)
+    rel = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    _say(f"[grad clip240 net, batch 2] {precision}: loss gpu {L:.7f} oracle {Lr:.7f}; normwise relative error {rel:.3e}")
+    assert abs(L - Lr) <= (1e-5 if precision == "fp32" else 1e-2) * abs(Lr)
+    # eight blocks: about forty bf16-operand products on a gradient's path, 2u sqrt(40) ~ 2.5e-2
+    assert rel <= (1e-3 if precision == "fp32" else 5e-2)
+    eng.close()
