@@ -11,6 +11,10 @@ mode realises that memory for the windowed network:
 * for a new frame, block l computes Q/K/V of the new frame's tokens; the queries (flagged
   tokens of the new frame) attend to the keys/values of their spatial window in the cached
   frames followed by the new frame (win_h x win_w tokens per frame, no key mask);
+* decoupled networks (``cfg.attn == "decoupled"``; even blocks within one frame of a
+  window, odd blocks across its frames at one token position, as in clip mode): a spatial
+  block's queries attend to their spatial window in the new frame only, a temporal block's
+  to their own token position in the cached frames followed by the new frame;
 * the projection, MLP, final LayerNorm, decoder and composite act on the new frame only;
 * then the new frame's K/V of every block enter the cache, dropping the oldest frame.
 
@@ -57,9 +61,6 @@ def step(state: StreamState, frame, mask, W, cfg, query_set="masked"):
     Returns (out [H, W, 3] FP64, pred [H, W, 3])."""
     if getattr(cfg, "overlap", False):
         raise NotImplementedError("the overlapping embedding/decoder runs in clip mode only")
-    if getattr(cfg, "attn", "joint") != "joint":
-        # every block below attends over the joint per-frame windows of the cache
-        raise NotImplementedError("stream mode covers joint window attention only")
     p = cfg.patch
     H, Wd, _ = frame.shape
     if H % (p * cfg.win_h) or Wd % (p * cfg.win_w):
@@ -80,11 +81,18 @@ def step(state: StreamState, frame, mask, W, cfg, query_set="masked"):
         k = on.linear(u, w("wk"), w("bk"))
         v = on.linear(u, w("wv"), w("bv"))
         past = state.kv[l]
-        keys = np.concatenate([_windows2d(kk, cfg) for kk, _ in past] + [_windows2d(k, cfg)], axis=2)
-        vals = np.concatenate([_windows2d(vv, cfg) for _, vv in past] + [_windows2d(v, cfg)], axis=2)
-        qw = _windows2d(q, cfg)
-        o_w = _cross_attention(qw, keys, vals, heads)
-        o = _unwindows2d(o_w, cfg)
+        kind = on.block_attention_kind(l, cfg)
+        if kind == "temporal":
+            # one token position across the cached frames and the new one: [Ht, Wt, F, C]
+            keys = np.stack([kk for kk, _ in past] + [k], axis=2)
+            vals = np.stack([vv for _, vv in past] + [v], axis=2)
+            o = _cross_attention(q[:, :, None, :], keys, vals, heads)[:, :, 0, :]
+        else:
+            frames_kv = [] if kind == "spatial" else past
+            keys = np.concatenate([_windows2d(kk, cfg) for kk, _ in frames_kv] + [_windows2d(k, cfg)], axis=2)
+            vals = np.concatenate([_windows2d(vv, cfg) for _, vv in frames_kv] + [_windows2d(v, cfg)], axis=2)
+            o_w = _cross_attention(_windows2d(q, cfg), keys, vals, heads)
+            o = _unwindows2d(o_w, cfg)
         x1 = x + on.linear(o, w("wo"), w("bo"))
         h = on.linear(on.layer_norm(x1, w("ln2.g"), w("ln2.b")), w("w1"), w("b1"))
         x2 = x1 + on.linear(on.gelu(h), w("w2"), w("b2"))

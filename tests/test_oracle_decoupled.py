@@ -104,13 +104,12 @@ def test_decoupled_forward_keeps_the_composite_and_differs_from_joint():
     assert not np.allclose(out[masks != 0], joint[masks != 0])
 
 
-def test_gradient_and_stream_reject_decoupled_attention():
-    """The reverse pass and stream mode partition every block into joint windows: a decoupled
-    configuration must raise rather than silently return the joint network's result."""
+def test_gradient_rejects_decoupled_attention():
+    """The reverse pass partitions every block into joint windows: a decoupled configuration
+    must raise rather than silently return the joint network's gradient."""
     import pytest
 
     from oracle import grad as og
-    from oracle import stream as ost
     rng = np.random.default_rng(0)
     cfg = BASE
     W = drsynth.make_weights(cfg, 0)
@@ -118,5 +117,80 @@ def test_gradient_and_stream_reject_decoupled_attention():
     masks = (rng.random((1, cfg.win_t, 8, 12)) < 0.3).astype(np.uint8)
     with pytest.raises(NotImplementedError):
         og.loss_and_grad(frames, masks, W, cfg)
-    with pytest.raises(NotImplementedError):
-        ost.step(ost.StreamState(cfg), frames[0, 0], masks[0, 0], W, cfg)
+
+
+# ------------------------------------------------------------------------------------------
+# stream mode with the decoupled pattern
+# ------------------------------------------------------------------------------------------
+def _stream_frames(seed, T, H=8, W=12):
+    rng = np.random.default_rng(seed)
+    return rng.random((T, H, W, 3)), np.zeros((T, H, W), np.uint8)
+
+
+def test_stream_decoupled_equals_clip_mode_when_past_frames_are_unmasked():
+    """Past frames without private pixels are never updated in either mode, so their keys and
+    values are the same; the newest frame's spatial blocks see its own frame and its temporal
+    blocks its position in every frame, in both modes."""
+    from oracle import stream as ost
+    cfg = BASE
+    W = drsynth.make_weights(cfg, 1, std=0.2)
+    f, m = _stream_frames(2, cfg.win_t)
+    m[-1, 1:7, 2:10] = 1
+    outs = ost.run_stream(f, m, W, cfg)
+    clip = on.forward(f[None], m[None], W, cfg)[0]
+    np.testing.assert_allclose(outs[-1], clip[-1], rtol=1e-12, atol=1e-13)
+    assert not np.allclose(outs[-1], ost.run_stream(f, m, W, dataclasses.replace(cfg, attn="joint"))[-1])
+
+
+def test_stream_decoupled_identical_frames_equal_clip_mode():
+    """A stream of identical frames (and masks) gives the clip-mode result of a clip of those
+    frames: every frame's activations agree at every block in both modes, so a temporal block
+    averages identical values either way."""
+    from oracle import stream as ost
+    cfg = BASE
+    W = drsynth.make_weights(cfg, 2, std=0.2)
+    f1, m1 = _stream_frames(3, 1)
+    m1[0, 2:6, 1:9] = 1
+    f = np.repeat(f1, cfg.win_t, axis=0)
+    m = np.repeat(m1, cfg.win_t, axis=0)
+    outs = ost.run_stream(f, m, W, cfg)
+    clip = on.forward(f[None], m[None], W, cfg)[0]
+    for t in range(cfg.win_t):
+        np.testing.assert_allclose(outs[t], clip[t], rtol=1e-11, atol=1e-12)
+
+
+def test_stream_decoupled_spatial_blocks_ignore_the_cache_and_history_is_bounded():
+    """With one block (spatial only) the stream is per-frame; with two, a frame older than
+    the memory slots no longer matters."""
+    from oracle import stream as ost
+    one = dataclasses.replace(BASE, blocks=1)
+    W1 = drsynth.make_weights(one, 3, std=0.2)
+    f, m = _stream_frames(4, 3)
+    m[:, 2:6, 1:9] = 1
+    f2 = f.copy()
+    f2[0] = 0.3
+    assert np.array_equal(ost.run_stream(f, m, W1, one)[-1], ost.run_stream(f2, m, W1, one)[-1])
+    W = drsynth.make_weights(BASE, 3, std=0.2)
+    a = ost.run_stream(f, m, W, BASE, slots=1)
+    b = ost.run_stream(f2, m, W, BASE, slots=1)
+    assert np.array_equal(a[-1], b[-1])   # frame 0 dropped by frame 2 (one memory slot)
+    assert not np.array_equal(ost.run_stream(f, m, W, BASE, slots=2)[-1], ost.run_stream(f2, m, W, BASE, slots=2)[-1])
+
+
+def test_stream_decoupled_planted_mistake_is_caught():
+    """A temporal block that forgot the cache (attending to the new frame only) breaks the
+    unmasked-history equivalence above."""
+    from oracle import stream as ost
+    cfg = BASE
+    W = drsynth.make_weights(cfg, 1, std=0.2)
+    f, m = _stream_frames(5, cfg.win_t)
+    m[-1, 1:7, 2:10] = 1
+    clip = on.forward(f[None], m[None], W, cfg)[0]
+    orig = on.block_attention_kind
+    try:
+        # temporal blocks computed as spatial ones without the cache
+        on.block_attention_kind = lambda l, c: "spatial" if orig(l, c) == "temporal" else orig(l, c)
+        bad = ost.run_stream(f, m, W, cfg)
+    finally:
+        on.block_attention_kind = orig
+    assert not np.allclose(bad[-1], clip[-1], atol=1e-6)
