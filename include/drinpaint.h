@@ -172,7 +172,8 @@ dr_status dr_fp8_encode(dr_ctx* ctx, const float* in, uint8_t* out, size_t n, fl
  * the device (the thesis's memory tensors kept from previous outputs, Methods, "Inpainting
  * Manager"); a new frame's flagged tokens attend to their spatial window (win_h x win_w
  * tokens) in those frames and in the new frame, then the new frame's K/V replace the oldest.
- * The first frames of a stream use the frames available.  BF16 only. */
+ * The first frames of a stream use the frames available (a decoupled network's blocks attend
+ * as dr_set_attention_pattern states).  BF16 only. */
 
 /* Footprint budget in bytes for all open streams' caches (0 = unlimited, the default). */
 dr_status dr_set_budget(dr_ctx* ctx, size_t bytes);
@@ -198,9 +199,11 @@ dr_status dr_stream_step(dr_ctx* ctx, int n, const int32_t* sids, const float* c
  * 0 (default) every block attends over its whole window; 1 decoupled, in the manner of the
  * DSTT network the thesis builds on (Background, "Decoupled Spatial-Temporal Transformer"):
  * even blocks attend within one frame of the window, odd blocks across the window's frames
- * at one token position.  Pattern 1 runs on the BF16 and FP8 paths of dr_inpaint (FP32,
- * stream mode and training return DR_EINVAL) with at most 8 frames per window.  Waits for the
- * device when the pattern changes. */
+ * at one token position.  Pattern 1 runs on the BF16 and FP8 paths of dr_inpaint (FP32 and
+ * training return DR_EINVAL) with at most 8 frames per window, and in stream mode, where an
+ * even block attends within the new frame's window only and an odd block to its token
+ * position in the cached frames and the new one.  Waits for the device when the pattern
+ * changes. */
 dr_status dr_set_attention_pattern(dr_ctx* ctx, int pattern);
 
 /* ---- Camera-resolution pre/post-processing ----------------------------------------------

@@ -333,6 +333,10 @@ int ring_vt_frame_stride(int sf);
 bool attn_ring_supported(int dh, int sf, int nf);
 void launch_attn_ring(const StreamTable& tab, const Geo& g, int C, int heads, int nf, const bf16* q, const int32_t* idx,
                       const int32_t* woff, const int32_t* worder, bf16* o, hipStream_t s);
+bool attn_ring_temporal_supported(int dh);
+void launch_attn_ring_temporal(const StreamTable& tab, const Geo& g, int C, int heads, const bf16* q,
+                               const int32_t* idx, const int32_t* woff, const int32_t* worder, bf16* o,
+                               hipStream_t s);
 
 // host helpers shared by the API translation units
 dr_status dr_fail(dr_ctx* c, dr_status st, const char* fmt, ...);

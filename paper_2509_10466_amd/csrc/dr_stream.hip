@@ -144,10 +144,12 @@ static dr_status stream_step_locked(dr_ctx* c, Work& w, int n, const int32_t* si
                                     hipStream_t s) {
   if (n < 1 || n > STREAM_MAXB) return dr_fail(c, DR_EINVAL, "batch of %d requests (1..%d)", n, STREAM_MAXB);
   if (!c->have_weights) return dr_fail(c, DR_EINVAL, "no weights loaded");
-  if (c->attn_pattern != 0) return dr_fail(c, DR_EINVAL, "stream mode runs the joint-attention network");
   if (c->net.K != c->net.P) return dr_fail(c, DR_EINVAL, "stream mode runs the non-overlapping embedding");
   const Net& net = c->net;
-  if (!attn_ring_supported(net.dh, net.cfg.win_h * net.cfg.win_w, net.cfg.win_t))
+  const bool decoupled = c->attn_pattern != 0;
+  const int sf = net.cfg.win_h * net.cfg.win_w;
+  if (decoupled ? !(attn_ring_supported(net.dh, sf, 1) && attn_ring_temporal_supported(net.dh))
+                : !attn_ring_supported(net.dh, sf, net.cfg.win_t))
     return dr_fail(c, DR_ESHAPE, "no stream attention kernel for this window");
   if (!resid_ln_supported(net.C) || net.cfg.patch != 4)
     return dr_fail(c, DR_ESHAPE, "stream mode needs dim 64, 128, 256 or 384 and patch 4");
@@ -197,7 +199,15 @@ static dr_status stream_step_locked(dr_ctx* c, Work& w, int n, const int32_t* si
     tab.vslot_stride = (long long)L * vblk_elems;
     tab.sfp = ring_vt_frame_stride(g.S);
     LAUNCH(ST_QKV, launch_qkv_stream(g, C, net.cfg.heads, w.xh, w.flag, b.wqkvf16, b.bqkvf, w.q16, tab, s));
-    LAUNCH(ST_ATTN, launch_attn_ring(tab, g, C, net.cfg.heads, net.cfg.win_t, w.q16, w.idx, w.woff, w.worder, w.o16, s));
+    if (!decoupled) {
+      LAUNCH(ST_ATTN, launch_attn_ring(tab, g, C, net.cfg.heads, net.cfg.win_t, w.q16, w.idx, w.woff, w.worder, w.o16, s));
+    } else if (l % 2 == 0) {
+      // spatial block: the new frame's window only (its K/V sit in the head slot)
+      for (int r = 0; r < n; ++r) tab.npast[r] = 0;
+      LAUNCH(ST_ATTN, launch_attn_ring(tab, g, C, net.cfg.heads, 1, w.q16, w.idx, w.woff, w.worder, w.o16, s));
+    } else {
+      LAUNCH(ST_ATTN, launch_attn_ring_temporal(tab, g, C, net.cfg.heads, w.q16, w.idx, w.woff, w.worder, w.o16, s));
+    }
     if (mlp_block_supported(C, R)) {
       LAUNCH(ST_MLP, launch_mlp_block_bf16(N, w.nq, C, w.o16, w.idx, b.wo16, b.bo, b.w1f16, b.b1f, b.w216, b.b2, w.x, w.xh, s));
     } else {

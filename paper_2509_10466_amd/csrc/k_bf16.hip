@@ -547,7 +547,7 @@ __global__ void __launch_bounds__(ATT_THREADS) attn_ring_kernel(StreamTable tab,
 int ring_vt_frame_stride(int sf) { return (sf + 15) / 16 * 16; }
 
 bool attn_ring_supported(int dh, int sf, int nf) {
-  return (dh == 32 || dh == 64) && ((sf == 45 && nf == 5) || (sf == 60 && nf == 5) || (sf == 64 && nf == 1));
+  return (dh == 32 || dh == 64) && (((sf == 45 || sf == 60) && (nf == 5 || nf == 1)) || (sf == 64 && nf == 1));
 }
 
 void launch_attn_ring(const StreamTable& tab, const Geo& g, int C, int heads, int nf, const bf16* q, const int32_t* idx,
@@ -575,7 +575,92 @@ void launch_attn_ring(const StreamTable& tab, const Geo& g, int C, int heads, in
   DR_ATTN_RING(32, 60, 5)
   DR_ATTN_RING(32, 64, 1)
   DR_ATTN_RING(64, 64, 1)
+  DR_ATTN_RING(64, 45, 1)
+  DR_ATTN_RING(64, 60, 1)
+  DR_ATTN_RING(32, 45, 1)
+  DR_ATTN_RING(32, 60, 1)
 #undef DR_ATTN_RING
+}
+
+// Stream mode, temporal block of a decoupled network: the query at position p of window
+// (request r, window wl) attends to the keys at position p of that window in the request's
+// cached frames (oldest first) and in the new frame.  A handful of keys per query, so no
+// matrix cores: four lanes per query, DH/4 channels each, an online softmax over the frames.
+// K rows of a position are contiguous in the ring; V^T is read at stride sfp, which the
+// neighbouring queries of a wave share cache lines of.
+template <int DH>
+__global__ void __launch_bounds__(ATT_THREADS) attn_ring_temporal_kernel(StreamTable tab, int C, int heads, int nwin_f,
+                                                                         int sf, const bf16* __restrict__ q,
+                                                                         const int32_t* __restrict__ idx,
+                                                                         const int32_t* __restrict__ woff,
+                                                                         const int32_t* __restrict__ worder,
+                                                                         bf16* __restrict__ o) {
+  constexpr int DPL = DH / 4, NV = DPL / 8;
+  const int rank = blockIdx.x / heads, h = blockIdx.x - rank * heads;
+  const int w = worder[rank];
+  const int q0 = woff[w], nqw = woff[w + 1] - q0;
+  if (nqw == 0) return;
+  const int r = w / nwin_f, wl = w - r * nwin_f;
+  const int np = pick(tab.npast, r), hd = pick(tab.head, r), nT = pick(tab.T, r);
+  const int part = threadIdx.x & 3;
+  const bf16* kb = pick(tab.k, r) + ((size_t)wl * heads + h) * sf * DH + part * DPL;
+  const bf16* vb = pick(tab.v, r) + (((size_t)wl * heads + h) * DH + part * DPL) * tab.sfp;
+  for (int qi = threadIdx.x >> 2; qi < nqw; qi += ATT_THREADS / 4) {  // uniform per 4 lanes
+    const int row = q0 + qi;
+    const int n = idx[row];
+    const int p = n - w * sf;
+    u16x8_t qu[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      qu[v] = *reinterpret_cast<const u16x8_t*>(q + (size_t)n * C + h * DH + part * DPL + 8 * v);
+    float m = -INFINITY, l = 0.f, ov[DPL];
+#pragma unroll
+    for (int e = 0; e < DPL; ++e) ov[e] = 0.f;
+    for (int f = 0; f <= np; ++f) {
+      const int slot = (hd - np + f + nT) % nT;
+      const bf16* kf = kb + (size_t)slot * tab.slot_stride + (size_t)p * DH;
+      float acc = 0.f;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const u16x8_t ku = *reinterpret_cast<const u16x8_t*>(kf + 8 * v);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc = fmaf(bf2f(qu[v][e]), bf2f(ku[e]), acc);
+      }
+      acc += __shfl_xor(acc, 1, 64);
+      acc += __shfl_xor(acc, 2, 64);
+      const float mn = fmaxf(m, acc);
+      const float a = __builtin_amdgcn_exp2f(m - mn), pe = __builtin_amdgcn_exp2f(acc - mn);
+      l = fmaf(l, a, pe);
+      m = mn;
+      const bf16* vf = vb + (size_t)slot * tab.vslot_stride + p;
+#pragma unroll
+      for (int e = 0; e < DPL; ++e) ov[e] = fmaf(pe, bf2f(vf[(size_t)e * tab.sfp]), ov[e] * a);
+    }
+    const float inv = 1.0f / l;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      uint4 pk;
+      pk.x = pack_bf2(ov[8 * v + 0] * inv, ov[8 * v + 1] * inv);
+      pk.y = pack_bf2(ov[8 * v + 2] * inv, ov[8 * v + 3] * inv);
+      pk.z = pack_bf2(ov[8 * v + 4] * inv, ov[8 * v + 5] * inv);
+      pk.w = pack_bf2(ov[8 * v + 6] * inv, ov[8 * v + 7] * inv);
+      *reinterpret_cast<uint4*>(o + (size_t)row * C + h * DH + part * DPL + 8 * v) = pk;
+    }
+  }
+}
+
+bool attn_ring_temporal_supported(int dh) { return dh == 32 || dh == 64; }
+
+void launch_attn_ring_temporal(const StreamTable& tab, const Geo& g, int C, int heads, const bf16* q,
+                               const int32_t* idx, const int32_t* woff, const int32_t* worder, bf16* o,
+                               hipStream_t s) {
+  const int dh = C / heads, nwin_f = g.nwh * g.nww;
+  if (dh == 64)
+    attn_ring_temporal_kernel<64><<<g.nwin * heads, ATT_THREADS, 0, s>>>(tab, C, heads, nwin_f, g.S, q, idx, woff,
+                                                                         worder, o);
+  else if (dh == 32)
+    attn_ring_temporal_kernel<32><<<g.nwin * heads, ATT_THREADS, 0, s>>>(tab, C, heads, nwin_f, g.S, q, idx, woff,
+                                                                         worder, o);
 }
 
 int attn_clip_vt_stride(int spad) { return attn_vt_stride(spad); }
