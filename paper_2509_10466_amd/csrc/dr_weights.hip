@@ -46,7 +46,7 @@ struct dr_wplan {
   int K = 0;                        // embedding / decoder kernel size of this plan
   size_t nparams = 0;
   std::vector<int32_t> m32;         // f32 arena: source parameter, -1 = 0
-  std::vector<int32_t> m16a, m16b;  // bf16 arena: value = a * b (see gather16_kernel)
+  std::vector<int32_t> m16a, m16b;  // bf16 arena: value = a * b * scale (see gather16_kernel)
   std::vector<FoldRow> folds;
   // arena offsets (elements)
   size_t ewT, eb, dbf, lnfg, lnfb, dw, db, dbo;
@@ -92,7 +92,7 @@ static dr_wplan* build_plan(const Net& n, int K) {
   auto pad16 = [&] {
     while (a16.size() % 128) {
       a16.push_back(-1);
-      b16.push_back(-1);
+      b16.push_back((int32_t)0x80000000u);
     }
   };
   auto copy = [&](size_t src, size_t nel) {
@@ -115,22 +115,28 @@ static dr_wplan* build_plan(const Net& n, int K) {
     pad32();
     return off;
   };
-  auto cast16 = [&](std::initializer_list<std::pair<size_t, size_t>> parts) {
+  // second-factor code of the bf16 map: bit 31 set = no factor, bits 29-30 = scale class
+  // (0: 1, 1: the softmax scale of Q, 2: 1/sqrt 2 of the GELU), bits 0-28 = factor index
+  auto fcode = [](int64_t factor, int cls) -> int32_t {
+    const uint32_t c = (uint32_t)cls << 29;
+    return (int32_t)(factor < 0 ? (0x80000000u | c) : (c | (uint32_t)factor));
+  };
+  auto cast16 = [&](std::initializer_list<std::pair<size_t, size_t>> parts, int cls = 0) {
     const size_t off = a16.size();
     for (auto pr : parts)
       for (size_t e = 0; e < pr.second; ++e) {
         a16.push_back((int32_t)(pr.first + e));
-        b16.push_back(-1);
+        b16.push_back(fcode(-1, cls));
       }
     pad16();
     return off;
   };
-  // W diag(g) for W [outs][in]; qs marks the rows that also carry the softmax scale
-  auto fold16 = [&](size_t w, int outs, int in, size_t g, bool qs) {
+  // W diag(g) for W [outs][in], scaled by class cls
+  auto fold16 = [&](size_t w, int outs, int in, size_t g, int cls) {
     for (int oo = 0; oo < outs; ++oo)
       for (int i = 0; i < in; ++i) {
         a16.push_back((int32_t)(w + (size_t)oo * in + i));
-        b16.push_back(qs ? -2 - (int32_t)(g + i) : (int32_t)(g + i));
+        b16.push_back(fcode((int64_t)(g + i), cls));
       }
   };
   auto foldb = [&](size_t dst, size_t w, int outs, int in, size_t bias, size_t beta, double sc) {
@@ -179,14 +185,15 @@ static dr_wplan* build_plan(const Net& n, int K) {
     B.h[0] = cast16({{s[2], CC}, {s[4], CC}, {s[6], CC}});
     B.h[1] = cast16({{s[8], CC}});
     B.h[2] = cast16({{s[12], RC}});
-    B.h[3] = cast16({{s[14], RC}});
+    // W2 carries one 1/sqrt 2 of the GELU (gelu_scaled)
+    B.h[3] = cast16({{s[14], RC}}, 2);
     // LayerNorm affine parts folded into the next linear: W diag(g) and b + W beta; Q also
     // carries the softmax scale in base 2, log2(e) / sqrt(dh): the attention kernels of the
     // BF16 path exponentiate the scores with exp2 directly
     B.h[4] = a16.size();
-    fold16(s[2], C, C, s[0], true);
-    fold16(s[4], C, C, s[0], false);
-    fold16(s[6], C, C, s[0], false);
+    fold16(s[2], C, C, s[0], 1);
+    fold16(s[4], C, C, s[0], 0);
+    fold16(s[6], C, C, s[0], 0);
     pad16();
     B.f[24] = f.size();
     f.resize(f.size() + 3 * (size_t)C, -1);
@@ -194,13 +201,14 @@ static dr_wplan* build_plan(const Net& n, int K) {
     foldb(B.f[24], s[2], C, C, s[3], s[1], qscale);
     foldb(B.f[24] + C, s[4], C, C, s[5], s[1], 1.0);
     foldb(B.f[24] + 2 * C, s[6], C, C, s[7], s[1], 1.0);
+    // the first MLP linear also carries the other 1/sqrt 2 of the GELU (gelu_scaled)
     B.h[5] = a16.size();
-    fold16(s[12], R, C, s[10], false);
+    fold16(s[12], R, C, s[10], 2);
     pad16();
     B.f[25] = f.size();
     f.resize(f.size() + (size_t)R, -1);
     pad32();
-    foldb(B.f[25], s[12], R, C, s[13], s[11], 1.0);
+    foldb(B.f[25], s[12], R, C, s[13], s[11], 0.70710678118654752440);
   }
   // embedding weight [C][64] in the k slot order of the MFMA embedding's patch operand (slot
   // 32 s + 8 g + e holds patch value k = 12 g + 8 s + e for e < 8 - 4 s, zero otherwise), and
@@ -213,14 +221,14 @@ static dr_wplan* build_plan(const Net& n, int K) {
         for (int e = 0; e < 8; ++e) {
           const bool on = K == P && e < (sl ? 4 : 8);
           a16.push_back(on ? ew_idx(oc, 12 * gq + 8 * sl + e) : -1);
-          b16.push_back(-1);
+          b16.push_back(fcode(-1, 0));
         }
   pad16();
   pl->d16 = a16.size();
   for (int k = 0; k < 48; ++k)
     for (int ci = 0; ci < C; ++ci) {
       a16.push_back(K == P ? dw_idx(ci, k) : -1);
-      b16.push_back(K == P ? (int32_t)(pl->p_lnfg + ci) : -1);
+      b16.push_back(fcode(K == P ? (int64_t)(pl->p_lnfg + ci) : -1, 0));
     }
   pad16();
   pl->dbf = f.size();
@@ -250,7 +258,7 @@ static dr_wplan* build_plan(const Net& n, int K) {
           for (int e = 0; e < 8; ++e) {
             const int ky = gq + 4 * (sl / 3), m = 8 * (sl % 3) + e, kx = m / 3, ch = m % 3;
             a16.push_back((int32_t)(pl->p_ew + ((size_t)(oc * 3 + ch) * K + ky) * K + kx));
-            b16.push_back(-1);
+            b16.push_back(fcode(-1, 0));
           }
     pad16();
     auto dwo_idx = [&](int ci, int k) {
@@ -261,7 +269,7 @@ static dr_wplan* build_plan(const Net& n, int K) {
     for (int k = 0; k < 192; ++k)
       for (int ci = 0; ci < C; ++ci) {
         a16.push_back(dwo_idx(ci, k));
-        b16.push_back((int32_t)(pl->p_lnfg + ci));
+        b16.push_back(fcode((int64_t)(pl->p_lnfg + ci), 0));
       }
     pad16();
     pl->dbo = f.size();
@@ -284,17 +292,21 @@ __global__ void gather32_kernel(const float* __restrict__ src, const int32_t* __
   }
 }
 
-// dst = bf16(a) when b == -1; bf16(a * g) with g = src[b] when b >= 0; bf16(qscale * a * g)
-// with g = src[-2 - b] when b <= -2 (products in double, rounded once to f32, then to bf16)
+// dst = bf16(scale * a [* g]): a = src[ma] (0 when ma < 0); mb bit 31 clear: g = src[mb & (2^29 - 1)];
+// mb bits 29-30: scale 1, qscale or hscale.  Products in double, rounded once to f32, then
+// to bf16.
 __global__ void gather16_kernel(const float* __restrict__ src, const int32_t* __restrict__ ma,
-                                const int32_t* __restrict__ mb, double qscale, size_t n, bf16* __restrict__ dst) {
+                                const int32_t* __restrict__ mb, double qscale, double hscale, size_t n,
+                                bf16* __restrict__ dst) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-    const int32_t a = ma[e], b = mb[e];
+    const int32_t a = ma[e];
+    const uint32_t b = (uint32_t)mb[e];
     float v = 0.f;
     if (a >= 0) {
-      v = src[a];
-      if (b >= 0) v = (float)((double)v * (double)src[b]);
-      else if (b <= -2) v = (float)(qscale * (double)v * (double)src[-2 - b]);
+      const int cls = (b >> 29) & 3;
+      const double sc = cls == 1 ? qscale : (cls == 2 ? hscale : 1.0);
+      const double g = (b >> 31) ? 1.0 : (double)src[b & 0x1FFFFFFFu];
+      v = (float)(sc * (double)src[a] * g);
     }
     dst[e] = f2bf(v);
   }
@@ -480,8 +492,8 @@ static dr_status derive(dr_ctx* c, hipStream_t s) {
   const size_t n32 = pl.m32.size(), n16 = pl.m16a.size();
   const double qscale = 1.4426950408889634 / std::sqrt((double)n.dh);
   gather32_kernel<<<(unsigned)std::min<size_t>((n32 + 255) / 256, 8192), 256, 0, s>>>(c->params, c->wmaps32, n32, c->wf32);
-  gather16_kernel<<<(unsigned)std::min<size_t>((n16 + 255) / 256, 8192), 256, 0, s>>>(c->params, c->wmaps16a, c->wmaps16b,
-                                                                                    qscale, n16, c->wb16);
+  gather16_kernel<<<(unsigned)std::min<size_t>((n16 + 255) / 256, 8192), 256, 0, s>>>(
+      c->params, c->wmaps16a, c->wmaps16b, qscale, 0.70710678118654752440, n16, c->wb16);
   const int nf = (int)pl.folds.size();
   fold_kernel<<<(nf + 127) / 128, 128, 0, s>>>(c->params, (const FoldRow*)c->wfolds, nf, c->wf32);
   HIP_OK(c, hipGetLastError());

@@ -6,7 +6,10 @@
 // next to the FP32 residual.  Their affine part is folded into the linear that follows:
 // LN(x) W^T + b = x^ (W diag(g))^T + (b + W beta), so Q/K/V, the first MLP linear and the
 // decoder read x^ directly.  In exact arithmetic this is the same network (the folded weights
-// are prepared once, on the host, in double precision).
+// are derived on the device at load, in double precision).  The first MLP linear's folded
+// weight and bias and the second's weight each also carry a factor 1/sqrt 2, so that the
+// GELU epilogue evaluates x (1 + erf x) on x = z / sqrt 2 (gelu_scaled) without the two
+// constant multiplications of 0.5 z (1 + erf(z / sqrt 2)).
 //
 //   qkv:   [Q | K | V] = x^ Wqkv'^T + bqkv'      all tokens of windows holding a query (K, V);
 //                                                row tiles holding a flagged token (Q)
@@ -245,8 +248,9 @@ struct GeluOut {
   __device__ __forceinline__ void operator()(int m, int n, const f32x4_t& a) const {
     const float4 b4 = *reinterpret_cast<const float4*>(bias + n);
     uint2 pk;
-    pk.x = pack_bf2(gelu_fast(a[0] + b4.x), gelu_fast(a[1] + b4.y));
-    pk.y = pack_bf2(gelu_fast(a[2] + b4.z), gelu_fast(a[3] + b4.w));
+    // the first and second linears' weights carry GELU's constant factors (gelu_scaled)
+    pk.x = pack_bf2(gelu_scaled(a[0] + b4.x), gelu_scaled(a[1] + b4.y));
+    pk.y = pack_bf2(gelu_scaled(a[2] + b4.z), gelu_scaled(a[3] + b4.w));
     *reinterpret_cast<uint2*>(h + (size_t)m * R + n) = pk;
   }
 };
@@ -419,9 +423,9 @@ void launch_resid_ln_bf16(int m_max, const int32_t* m_dev, int C, int K, const b
 // ------------------------------------------------------------------------------------------
 constexpr int MLP_THREADS = 512;
 
-template <int C_, int HC_>
+template <int C_, int HC_, int BM_ = 64, int ST_ = 3>
 struct MlpCfg {
-  static constexpr int C = C_, HC = HC_, BM = 64, R = 4 * C, ST = 3;
+  static constexpr int C = C_, HC = HC_, BM = BM_, R = 4 * C, ST = ST_;
   static constexpr int WM = 2, WN = 4, TM = BM / WM;   // wavefront grid; rows per wavefront
   static constexpr int FM = TM / 16;
   static constexpr int SLOT_ROWS = C > HC ? C : HC;
@@ -439,6 +443,10 @@ struct MlpCfg {
   static constexpr size_t FLOATS = 2 * (size_t)C + R + 2 * WN * BM;  // b_o, b1', b_2, row sums
   static constexpr size_t LDS_BYTES = (RING + ARES + HRES) * 2 + FLOATS * 4;
   static_assert(C % 64 == 0 && HC % 64 == 0 && R % HC == 0 && NKC % KB1 == 0, "shapes");
+  static_assert((BM == 32 || BM == 64) && (ST == 2 || ST == 3), "row tile and ring depth");
+  // x1 (the residual after the projection) kept in registers for the second residual, rather
+  // than stored to x and read back, where the registers allow it
+  static constexpr bool X1_REGS = C <= 256;
   static_assert(LDS_BYTES <= 160 * 1024, "LDS");
 };
 
@@ -493,9 +501,10 @@ __device__ __forceinline__ void mfma_block_ra(const bf16x8_t (&af)[2][MC::FM], c
   });
 }
 
-// Element offset of (row r, column c) in a resident [k block][64 rows][64] swizzled tile.
+// Element offset of (row r, column c) in a resident [k block][BM rows][64] swizzled tile.
+template <int BM = 64>
 __device__ __forceinline__ int res_off(int r, int c) {
-  return (c >> 6) * (64 * 64) + r * 64 + ((((c & 63) >> 3) ^ lds_swz(r)) << 3) + (c & 7);
+  return (c >> 6) * (BM * 64) + r * 64 + ((((c & 63) >> 3) ^ lds_swz(r)) << 3) + (c & 7);
 }
 
 // This thread's residual values x[dst] for the [64][C] accumulators (zero for rows past M),
@@ -516,11 +525,11 @@ __device__ __forceinline__ void load_resid(const float* __restrict__ x, const in
 
 // Residual + row normalisation for the [64][C] accumulators: acc += bias + xo (= x[dst]);
 // x[dst] = acc; the row statistics come back through mean/rstd.  The four column
-// wavefronts of a row group exchange partial sums through red[2][WN][64].
+// wavefronts of a row group exchange partial sums through red[2][WN][BM].
 template <class MC>
 __device__ __forceinline__ void resid_rows(f32x4_t (&acc)[MC::FM][MC::FN_C], const float* sbias,
                                            float* __restrict__ x, const int (&dst)[MC::FM],
-                                           const float4 (&xo_in)[MC::FM][MC::FN_C], float (*red)[MC::WN][64],
+                                           const float4 (&xo_in)[MC::FM][MC::FN_C], float (*red)[MC::WN][MC::BM],
                                            float (&mean)[MC::FM], float (&rstd)[MC::FM], bool store = true) {
   constexpr int C = MC::C, FN = MC::FN_C;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -586,7 +595,7 @@ __global__ void __launch_bounds__(MLP_THREADS) mlp_block_kernel(const int32_t* _
   float* sbo = reinterpret_cast<float*>(hres + MC::HRES);
   float* sb1 = sbo + C;
   float* sb2 = sb1 + R;
-  float(*red)[MC::WN][64] = reinterpret_cast<float(*)[MC::WN][64]>(sb2 + C);
+  float(*red)[MC::WN][MC::BM] = reinterpret_cast<float(*)[MC::WN][MC::BM]>(sb2 + C);
 
   const int M = m_dev[0];
   const int m0 = blockIdx.x * BM;
@@ -601,12 +610,13 @@ __global__ void __launch_bounds__(MLP_THREADS) mlp_block_kernel(const int32_t* _
   }
   for (int i = t; i < R; i += MLP_THREADS) sb1[i] = b1[i];
   // o rows -> resident A tile (rows >= M read row M-1; their results are never stored):
-  // 8 rows per load, 8 row groups per k block, one group per wavefront
-  static_for<MC::NKC>([&](auto kb) {
-    const int row = wv * 8 + (lane >> 3);
-    const int m = min(m0 + row, M - 1);
-    dma16(o + (size_t)m * C + 64 * kb + ((lane & 7) ^ lds_swz(row)) * 8, ares + kb * BM * 64 + wv * 512);
-  });
+  // 8 rows per load, BM / 8 row groups per k block, one group per wavefront
+  if (wv * 8 < BM)
+    static_for<MC::NKC>([&](auto kb) {
+      const int row = wv * 8 + (lane >> 3);
+      const int m = min(m0 + row, M - 1);
+      dma16(o + (size_t)m * C + 64 * kb + ((lane & 7) ^ lds_swz(row)) * 8, ares + kb * BM * 64 + wv * 512);
+    });
   // weight stages: stage s holds rows [0, stage_rows(s)) of 64 k columns; a W1' stage holds
   // KB1 blocks of HC rows, k block b of the stage at rows [b HC, (b+1) HC)
   auto stage_rows = [](int s) {
@@ -646,8 +656,7 @@ __global__ void __launch_bounds__(MLP_THREADS) mlp_block_kernel(const int32_t* _
       }
     });
   };
-  issue(0);
-  issue(1);
+  static_for<MC::ST - 1>([&](auto s0) { issue(s0); });
 
   int dst[MC::FM];
   static_for<MC::FM>([&](auto i) {
@@ -657,21 +666,22 @@ __global__ void __launch_bounds__(MLP_THREADS) mlp_block_kernel(const int32_t* _
   f32x4_t acc[MC::FM][MC::FN_C], hacc[MC::FM][MC::FN_H];
   static_for<MC::FM>([&](auto i) {
     static_for<MC::FN_C>([&](auto j) { acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f}; });
-    static_for<MC::FN_H>([&](auto j) { hacc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f}; });
+    static_for<MC::FN_H>([&](auto j) { hacc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f}; });  // set per chunk below
   });
   float mean[MC::FM], rstd[MC::FM];
-  // Before multiplying stage s: wait until it has landed (at most the next stage's loads
-  // outstanding, or none after a stretch of other vector-memory traffic), then queue s + 2.
+  // Before multiplying stage s: wait until it has landed (with a 3-stage ring at most the next
+  // stage's loads outstanding, or none after a stretch of other vector-memory traffic), then
+  // queue s + ST - 1.
   bool drained = true;  // the bias loads and row indices above are vector-memory reads
   auto enter = [&](int s) {
-    if (drained || s + 1 >= MC::NSTAGE)
+    if (MC::ST == 2 || drained || s + 1 >= MC::NSTAGE)
       vm_wait_barrier<0>();
     else if (stage_rows(s + 1) == C)
-      vm_wait_barrier<C / (8 * NW)>();
+      vm_wait_barrier<(MC::ST == 3 ? C / (8 * NW) : 0)>();
     else
-      vm_wait_barrier<HC * MC::KB1 / (8 * NW)>();
+      vm_wait_barrier<(MC::ST == 3 ? HC * MC::KB1 / (8 * NW) : 0)>();
     drained = false;
-    if (s + 2 < MC::NSTAGE) issue(s + 2);
+    if (s + MC::ST - 1 < MC::NSTAGE) issue(s + MC::ST - 1);
     return ring + (s % MC::ST) * MC::SLOT;
   };
   int s = 0;
@@ -684,7 +694,12 @@ __global__ void __launch_bounds__(MLP_THREADS) mlp_block_kernel(const int32_t* _
   });
   // x1 = x + o W_o^T + b_o; u2 = normalise(x1) into the resident tile (every wavefront has
   // finished reading o there: resid_rows passes two block barriers)
-  resid_rows<MC>(acc, sbo, x, dst, xo, red, mean, rstd);
+  // x1 stays in registers (xo) for the second residual (or goes to x and is read back)
+  resid_rows<MC>(acc, sbo, x, dst, xo, red, mean, rstd, !MC::X1_REGS);
+  if constexpr (MC::X1_REGS)
+    static_for<MC::FM>([&](auto i) {
+      static_for<MC::FN_C>([&](auto j) { xo[i][j] = make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]); });
+    });
   static_for<MC::FM>([&](auto i) {
     const int r = wm * MC::TM + 16 * i + l16;
     static_for<MC::FN_C>([&](auto j) {
@@ -693,7 +708,7 @@ __global__ void __launch_bounds__(MLP_THREADS) mlp_block_kernel(const int32_t* _
       uint2 pk;
       pk.x = pack_bf2((a[0] - mean[i]) * rstd[i], (a[1] - mean[i]) * rstd[i]);
       pk.y = pack_bf2((a[2] - mean[i]) * rstd[i], (a[3] - mean[i]) * rstd[i]);
-      *reinterpret_cast<uint2*>(ares + res_off(r, n)) = pk;
+      *reinterpret_cast<uint2*>(ares + res_off<MC::BM>(r, n)) = pk;
       acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
     });
   });
@@ -711,24 +726,27 @@ __global__ void __launch_bounds__(MLP_THREADS) mlp_block_kernel(const int32_t* _
     });
   });
   for (int j = 0; j < MC::NCH; ++j) {
+    // the chunk's accumulators start at its bias b1' (the GELU epilogue then adds nothing)
+    static_for<MC::FN_H>([&](auto jj) {
+      const float4 b4 = *reinterpret_cast<const float4*>(sb1 + j * HC + wn * 16 * MC::FN_H + 16 * jj + 4 * kg);
+      static_for<MC::FM>([&](auto i) { hacc[i][jj] = f32x4_t{b4.x, b4.y, b4.z, b4.w}; });
+    });
     static_for<MC::NW1>([&](auto tt) {
       const bf16* ws = enter(s);
       static_for<MC::KB1>([&](auto b) { mfma_block_ra<MC, MC::FN_H>(ua[tt * MC::KB1 + b], ws + b * HC * 64, hacc); });
       ++s;
     });
     // hidden chunk j: GELU into the H tile (its previous contents were consumed before this
-    // stage's barrier)
+    // stage's barrier); the weights carry GELU's constant factors (gelu_scaled)
     static_for<MC::FM>([&](auto i) {
       const int r = wm * MC::TM + 16 * i + l16;
       static_for<MC::FN_H>([&](auto jj) {
         const int c = wn * 16 * MC::FN_H + 16 * jj + 4 * kg;
-        const float* bb = sb1 + j * HC + c;
         const f32x4_t& a = hacc[i][jj];
         uint2 pk;
-        pk.x = pack_bf2(gelu_fast(a[0] + bb[0]), gelu_fast(a[1] + bb[1]));
-        pk.y = pack_bf2(gelu_fast(a[2] + bb[2]), gelu_fast(a[3] + bb[3]));
-        *reinterpret_cast<uint2*>(hres + res_off(r, c)) = pk;
-        hacc[i][jj] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        pk.x = pack_bf2(gelu_scaled(a[0]), gelu_scaled(a[1]));
+        pk.y = pack_bf2(gelu_scaled(a[2]), gelu_scaled(a[3]));
+        *reinterpret_cast<uint2*>(hres + res_off<MC::BM>(r, c)) = pk;
       });
     });
     static_for<MC::NKH>([&](auto kb) {
@@ -737,8 +755,8 @@ __global__ void __launch_bounds__(MLP_THREADS) mlp_block_kernel(const int32_t* _
       ++s;
     });
   }
-  // x2 = x1 + h W_2^T + b_2 (x1 was stored by this thread above, an L2 hit); x^ = normalise(x2)
-  load_resid<MC>(x, dst, xo);
+  // x2 = x1 + h W_2^T + b_2; x^ = normalise(x2)
+  if constexpr (!MC::X1_REGS) load_resid<MC>(x, dst, xo);  // this thread's own stores, an L2 hit
   resid_rows<MC>(acc, sb2, x, dst, xo, red, mean, rstd);
   static_for<MC::FM>([&](auto i) {
     if (dst[i] >= 0)
@@ -766,7 +784,7 @@ static void mlp_launch(int m_max, const int32_t* m_dev, const bf16* o, const int
                                                                                           b1, w2, b2, x, xh);
 }
 
-bool mlp_block_supported(int C, int R) { return R == 4 * C && (C == 64 || C == 128 || C == 256); }
+bool mlp_block_supported(int C, int R) { return R == 4 * C && (C == 64 || C == 128 || C == 256 || C == 384); }
 
 void launch_mlp_block_bf16(int m_max, const int32_t* m_dev, int C, const bf16* o, const int32_t* rows,
                            const bf16* wo, const float* bo, const bf16* w1, const float* b1, const bf16* w2,
@@ -776,6 +794,8 @@ void launch_mlp_block_bf16(int m_max, const int32_t* m_dev, int C, const bf16* o
     case 64: mlp_launch<MlpCfg<64, 128>>(m_max, m_dev, o, rows, wo, bo, w1, b1, w2, b2, x, xh, s); break;
     case 128: mlp_launch<MlpCfg<128, 128>>(m_max, m_dev, o, rows, wo, bo, w1, b1, w2, b2, x, xh, s); break;
     case 256: mlp_launch<MlpCfg<256, 128>>(m_max, m_dev, o, rows, wo, bo, w1, b1, w2, b2, x, xh, s); break;
+    // dim 384: 32-row tiles on a 2-stage ring (384-row weight slots) fit the LDS
+    case 384: mlp_launch<MlpCfg<384, 128, 32, 2>>(m_max, m_dev, o, rows, wo, bo, w1, b1, w2, b2, x, xh, s); break;
     default: break;  // rejected by the caller (mlp_block_supported)
   }
 }

@@ -80,205 +80,6 @@ void launch_gelu_bwd(const float* h, const float* da, const int32_t* n_dev, int 
 }
 
 // ------------------------------------------------------------------------------------------
-// Window attention forward (FP32) that also saves each query row's max m and sum l of
-// exp(s - m) per head: stats[r * heads + h] = (m, l).  Same arithmetic as the inference
-// kernel of the FP32 path.
-// ------------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) attn_f32_save_kernel(Geo g, int C, int heads, const float* __restrict__ q,
-                                                            const float* __restrict__ kv,
-                                                            const int32_t* __restrict__ woff, float* __restrict__ o,
-                                                            float2* __restrict__ stats) {
-  __shared__ __align__(16) float qs[4][64];
-  __shared__ float ps[4][320];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int w = blockIdx.x / heads, h = blockIdx.x - w * heads;
-  const int j = blockIdx.y * 4 + wv;
-  const int q0 = woff[w], nqw = woff[w + 1] - q0;
-  if (j >= nqw) return;
-  const int dh = C / heads;
-  const int r = q0 + j;
-  const float scale = rsqrtf((float)dh);
-  if (lane < dh) qs[wv][lane] = q[(size_t)r * C + h * dh + lane];
-  __builtin_amdgcn_wave_barrier();
-  const float* kbase = kv + (size_t)w * g.S * 2 * C + h * dh;
-  float mx = -INFINITY;
-  for (int s = lane; s < g.S; s += 64) {
-    const float* kr = kbase + (size_t)s * 2 * C;
-    float d = 0.f;
-    // the lane's key row in 16-byte pieces (dh % 4 == 0; rows and head offsets are 16-byte
-    // aligned), summed in channel order
-    for (int e = 0; e < dh; e += 4) {
-      const float4 k4 = *reinterpret_cast<const float4*>(kr + e);
-      const float4 q4 = *reinterpret_cast<const float4*>(&qs[wv][e]);
-      d = fmaf(q4.x, k4.x, d);
-      d = fmaf(q4.y, k4.y, d);
-      d = fmaf(q4.z, k4.z, d);
-      d = fmaf(q4.w, k4.w, d);
-    }
-    d *= scale;
-    ps[wv][s] = d;
-    mx = fmaxf(mx, d);
-  }
-  mx = wave_max(mx);
-  float sum = 0.f;
-  for (int s = lane; s < g.S; s += 64) {
-    const float e = expf(ps[wv][s] - mx);
-    ps[wv][s] = e;
-    sum += e;
-  }
-  sum = wave_sum(sum);
-  __builtin_amdgcn_wave_barrier();
-  if (lane < dh) {
-    const float* vbase = kbase + C + lane;
-    // eight interleaved partial sums keep eight loads in flight; fixed combination order
-    float a8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    int s = 0;
-    for (; s + 7 < g.S; s += 8)
-#pragma unroll
-      for (int u = 0; u < 8; ++u) a8[u] = fmaf(ps[wv][s + u], vbase[(size_t)(s + u) * 2 * C], a8[u]);
-    for (; s < g.S; ++s) a8[0] = fmaf(ps[wv][s], vbase[(size_t)s * 2 * C], a8[0]);
-    const float acc = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
-    o[(size_t)r * C + h * dh + lane] = acc / sum;
-  }
-  if (lane == 0) stats[(size_t)r * heads + h] = make_float2(mx, sum);
-}
-
-void launch_attn_f32_save(const Geo& g, int C, int heads, const float* q, const float* kv, const int32_t* woff,
-                          float* o, float2* stats, hipStream_t s) {
-  dim3 grid(g.nwin * heads, (g.S + 3) / 4);
-  attn_f32_save_kernel<<<grid, 256, 0, s>>>(g, C, heads, q, kv, woff, o, stats);
-}
-
-// ------------------------------------------------------------------------------------------
-// Attention backward, part 1: one wavefront per (query, head).  P is recomputed from Q, K and
-// the saved row statistics, P_s = exp(q.k_s / sqrt(dh) - m) / l.  Then dP_s = dO . v_s,
-// D = sum_s P_s dP_s (= dO . O), dS_s = P_s (dP_s - D), dq = sum_s dS_s k_s / sqrt(dh).
-// P and dS are written for part 2 ([Nq][heads][S]).
-// ------------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) attn_bwd_q_kernel(Geo g, int C, int heads, const float* __restrict__ q,
-                                                         const float* __restrict__ kv, const float* __restrict__ dout,
-                                                         const float2* __restrict__ stats,
-                                                         const int32_t* __restrict__ woff, float* __restrict__ dq,
-                                                         float* __restrict__ P, float* __restrict__ dS) {
-  __shared__ __align__(16) float qs[4][64];
-  __shared__ __align__(16) float dos[4][64];
-  __shared__ float ds_[4][320];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int w = blockIdx.x / heads, h = blockIdx.x - w * heads;
-  const int j = blockIdx.y * 4 + wv;
-  const int q0 = woff[w], nqw = woff[w + 1] - q0;
-  if (j >= nqw) return;
-  const int dh = C / heads;
-  const int r = q0 + j;
-  const float scale = rsqrtf((float)dh);
-  if (lane < dh) {
-    qs[wv][lane] = q[(size_t)r * C + h * dh + lane];
-    dos[wv][lane] = dout[(size_t)r * C + h * dh + lane];
-  }
-  __builtin_amdgcn_wave_barrier();
-  const float2 st = stats[(size_t)r * heads + h];
-  const float* kbase = kv + (size_t)w * g.S * 2 * C + h * dh;
-  float* prow = P + ((size_t)r * heads + h) * g.S;
-  float* dsrow = dS + ((size_t)r * heads + h) * g.S;
-  float dsum = 0.f;
-  for (int s = lane; s < g.S; s += 64) {
-    const float* kr = kbase + (size_t)s * 2 * C;
-    const float* vr = kr + C;
-    float d = 0.f, dp = 0.f;
-    for (int e = 0; e < dh; e += 4) {  // 16-byte pieces of the key and value rows, channel order
-      const float4 k4 = *reinterpret_cast<const float4*>(kr + e);
-      const float4 v4 = *reinterpret_cast<const float4*>(vr + e);
-      const float4 q4 = *reinterpret_cast<const float4*>(&qs[wv][e]);
-      const float4 o4 = *reinterpret_cast<const float4*>(&dos[wv][e]);
-      d = fmaf(q4.x, k4.x, d);
-      d = fmaf(q4.y, k4.y, d);
-      d = fmaf(q4.z, k4.z, d);
-      d = fmaf(q4.w, k4.w, d);
-      dp = fmaf(o4.x, v4.x, dp);
-      dp = fmaf(o4.y, v4.y, dp);
-      dp = fmaf(o4.z, v4.z, dp);
-      dp = fmaf(o4.w, v4.w, dp);
-    }
-    const float p = expf(d * scale - st.x) / st.y;
-    prow[s] = p;
-    ds_[wv][s] = dp;
-    dsum += p * dp;
-  }
-  dsum = wave_sum(dsum);
-  __builtin_amdgcn_wave_barrier();
-  for (int s = lane; s < g.S; s += 64) {
-    const float v = prow[s] * (ds_[wv][s] - dsum);
-    ds_[wv][s] = v;
-    dsrow[s] = v;
-  }
-  __builtin_amdgcn_wave_barrier();
-  if (lane < dh) {
-    // eight interleaved partial sums keep eight loads in flight; fixed combination order
-    float a8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    int s = 0;
-    for (; s + 7 < g.S; s += 8)
-#pragma unroll
-      for (int u = 0; u < 8; ++u) a8[u] = fmaf(ds_[wv][s + u], kbase[(size_t)(s + u) * 2 * C + lane], a8[u]);
-    for (; s < g.S; ++s) a8[0] = fmaf(ds_[wv][s], kbase[(size_t)s * 2 * C + lane], a8[0]);
-    const float acc = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
-    dq[(size_t)r * C + h * dh + lane] = acc * scale;
-  }
-}
-
-void launch_attn_bwd_q(const Geo& g, int C, int heads, const float* q, const float* kv, const float* dout,
-                       const float2* stats, const int32_t* woff, float* dq, float* P, float* dS, hipStream_t s) {
-  dim3 grid(g.nwin * heads, (g.S + 3) / 4);
-  attn_bwd_q_kernel<<<grid, 256, 0, s>>>(g, C, heads, q, kv, dout, stats, woff, dq, P, dS);
-}
-
-// ------------------------------------------------------------------------------------------
-// Attention backward, part 2: per (window, head), thread per (key s, channel d):
-//   dK[s, d] = sum_j dS[j, s] q[j, d] / sqrt(dh),  dV[s, d] = sum_j P[j, s] dO[j, d]
-// over the window's queries j (in order).  dkv rows [N][2C]: dK in [0, C), dV in [C, 2C);
-// windows without queries get zeros.
-// ------------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) attn_bwd_kv_kernel(Geo g, int C, int heads, const float* __restrict__ q,
-                                                          const float* __restrict__ dout, const float* __restrict__ P,
-                                                          const float* __restrict__ dS,
-                                                          const int32_t* __restrict__ woff, float* __restrict__ dkv) {
-  const int w = blockIdx.x / heads, h = blockIdx.x - w * heads;
-  const int dh = C / heads;
-  const int q0 = woff[w], nqw = woff[w + 1] - q0;
-  const float scale = rsqrtf((float)dh);
-  for (int e = blockIdx.y * blockDim.x + threadIdx.x; e < g.S * dh; e += gridDim.y * blockDim.x) {
-    const int s = e / dh, d = e - s * dh;
-    // four interleaved partial sums per output (loads of four queries in flight), fixed order
-    float ak4[4] = {0.f, 0.f, 0.f, 0.f}, av4[4] = {0.f, 0.f, 0.f, 0.f};
-    int j = 0;
-    for (; j + 3 < nqw; j += 4)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const size_t r = (size_t)(q0 + j + u);
-        const size_t pi = (r * heads + h) * g.S + s;
-        ak4[u] = fmaf(dS[pi], q[r * C + h * dh + d], ak4[u]);
-        av4[u] = fmaf(P[pi], dout[r * C + h * dh + d], av4[u]);
-      }
-    for (; j < nqw; ++j) {
-      const size_t r = (size_t)(q0 + j);
-      const size_t pi = (r * heads + h) * g.S + s;
-      ak4[0] = fmaf(dS[pi], q[r * C + h * dh + d], ak4[0]);
-      av4[0] = fmaf(P[pi], dout[r * C + h * dh + d], av4[0]);
-    }
-    const float ak = (ak4[0] + ak4[1]) + (ak4[2] + ak4[3]), av = (av4[0] + av4[1]) + (av4[2] + av4[3]);
-    float* row = dkv + ((size_t)w * g.S + s) * 2 * C + h * dh + d;
-    row[0] = ak * scale;
-    row[C] = av;
-  }
-}
-
-void launch_attn_bwd_kv(const Geo& g, int C, int heads, const float* q, const float* dout, const float* P,
-                        const float* dS, const int32_t* woff, float* dkv, hipStream_t s) {
-  const int dh = C / heads;
-  dim3 grid(g.nwin * heads, (g.S * dh + 255) / 256);
-  attn_bwd_kv_kernel<<<grid, 256, 0, s>>>(g, C, heads, q, dout, P, dS, woff, dkv);
-}
-
-// ------------------------------------------------------------------------------------------
 // LayerNorm backward, one wavefront per row r < *n (or n_max): rows of x at rows[r] (or r);
 // dx[r] = rstd * (dxh - mean(dxh) - xh * mean(dxh * xh)), dxh = dy * gamma, written or added
 // (accumulate) at dst row (rows ? rows[r] : r) or compact r (dst_compact).  dgamma/dbeta
