@@ -423,26 +423,34 @@ void launch_resid_ln_bf16(int m_max, const int32_t* m_dev, int C, int K, const b
 // ------------------------------------------------------------------------------------------
 constexpr int MLP_THREADS = 512;
 
-template <int C_, int HC_, int BM_ = 64, int ST_ = 3>
+template <int C_, int HC_, int BM_ = 64, int ST_ = 3, int SR_ = 0>
 struct MlpCfg {
   static constexpr int C = C_, HC = HC_, BM = BM_, R = 4 * C, ST = ST_;
   static constexpr int WM = 2, WN = 4, TM = BM / WM;   // wavefront grid; rows per wavefront
   static constexpr int FM = TM / 16;
-  static constexpr int SLOT_ROWS = C > HC ? C : HC;
+  static constexpr int SLOT_ROWS = SR_ ? SR_ : (C > HC ? C : HC);
   static constexpr int SLOT = SLOT_ROWS * 64;          // bf16 elements per ring slot
   static constexpr int NKC = C / 64, NKH = HC / 64;    // k blocks of C- and HC-wide operands
   static constexpr int NCH = R / HC;                   // hidden chunks
+  // a k block of a C-row weight (W_o, W_2) moves in NHALF stages of CS rows when a slot
+  // holds fewer than C rows
+  static constexpr int CS = C < SLOT_ROWS ? C : SLOT_ROWS, NHALF = C / CS;
   // k blocks of W1' per stage: as many HC-row blocks as a ring slot holds, so that every
   // stage moves a full slot (fewer stages, each with the same fixed wait + barrier cost)
   static constexpr int KB1 = (SLOT_ROWS / HC < NKC) ? SLOT_ROWS / HC : NKC;
   static constexpr int NW1 = NKC / KB1;                // W1' stages per hidden chunk
-  static constexpr int PER_CHUNK = NW1 + NKH;
-  static constexpr int NSTAGE = NKC + NCH * PER_CHUNK;
+  static constexpr int PER_CHUNK = NW1 + NKH * NHALF;
+  static constexpr int NSTAGE = NKC * NHALF + NCH * PER_CHUNK;
   static constexpr int FN_C = C / 64, FN_H = HC / 64;  // 16-wide fragments per wavefront
+  static constexpr int FPH = FN_C / NHALF;             // of them per C-row stage
+  // output column of wavefront wn's fragment j (lane group kg adds 4 kg): the wavefront's
+  // columns are spread over the NHALF row ranges of a C-row stage, FPH fragments in each
+  __device__ static constexpr int col(int wn, int j) { return (j / FPH) * CS + wn * 16 * FPH + 16 * (j % FPH); }
   static constexpr size_t RING = (size_t)ST * SLOT, ARES = (size_t)NKC * BM * 64, HRES = (size_t)NKH * BM * 64;
   static constexpr size_t FLOATS = 2 * (size_t)C + R + 2 * WN * BM;  // b_o, b1', b_2, row sums
   static constexpr size_t LDS_BYTES = (RING + ARES + HRES) * 2 + FLOATS * 4;
   static_assert(C % 64 == 0 && HC % 64 == 0 && R % HC == 0 && NKC % KB1 == 0, "shapes");
+  static_assert(C % CS == 0 && FN_C % NHALF == 0 && CS % (16 * WN) == 0 && SLOT_ROWS >= HC, "C-row stages");
   static_assert((BM == 32 || BM == 64) && (ST == 2 || ST == 3), "row tile and ring depth");
   // x1 (the residual after the projection) kept in registers for the second residual, rather
   // than stored to x and read back, where the registers allow it
@@ -452,8 +460,8 @@ struct MlpCfg {
 
 // One 64-wide k block: acc[i][j] += A[wm*TM + 16i + l16][k] W[wn*16*FN + 16j + l16][k], A and
 // W in the swizzled 64-column LDS layout.
-template <class MC, int FN>
-__device__ __forceinline__ void mfma_block(const bf16* As, const bf16* Ws, f32x4_t (&acc)[MC::FM][FN]) {
+template <class MC, int FN, int J0 = 0, int NA = FN>
+__device__ __forceinline__ void mfma_block(const bf16* As, const bf16* Ws, f32x4_t (&acc)[MC::FM][NA]) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int wm = wv / MC::WN, wn = wv % MC::WN;
   const int l16 = lane & 15, kg = lane >> 4;
@@ -471,7 +479,7 @@ __device__ __forceinline__ void mfma_block(const bf16* As, const bf16* Ws, f32x4
   static_for<2>([&](auto kk) {
     mfma_fence_begin();
     static_for<MC::FM>([&](auto i) {
-      static_for<FN>([&](auto j) { acc[i][j] = mfma_bf16_16x16x32(wf[kk][j], af[kk][i], acc[i][j]); });
+      static_for<FN>([&](auto j) { acc[i][J0 + j] = mfma_bf16_16x16x32(wf[kk][j], af[kk][i], acc[i][J0 + j]); });
     });
     mfma_fence_end();
   });
@@ -516,7 +524,7 @@ __device__ __forceinline__ void load_resid(const float* __restrict__ x, const in
   const int wn = wv % MC::WN, kg = lane >> 4;
   static_for<MC::FM>([&](auto i) {
     static_for<MC::FN_C>([&](auto j) {
-      const int n = wn * 16 * MC::FN_C + 16 * j + 4 * kg;
+      const int n = MC::col(wn, j) + 4 * kg;
       xo[i][j] = dst[i] >= 0 ? *reinterpret_cast<const float4*>(x + (size_t)dst[i] * MC::C + n)
                              : make_float4(0.f, 0.f, 0.f, 0.f);
     });
@@ -532,14 +540,18 @@ __device__ __forceinline__ void resid_rows(f32x4_t (&acc)[MC::FM][MC::FN_C], con
                                            const float4 (&xo_in)[MC::FM][MC::FN_C], float (*red)[MC::WN][MC::BM],
                                            float (&mean)[MC::FM], float (&rstd)[MC::FM], bool store = true) {
   constexpr int C = MC::C, FN = MC::FN_C;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // the thread index passes through an empty asm so that the column addresses below are
+  // recomputed per call rather than kept live (or spilled) from an earlier call
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  const int lane = tid & 63, wv = tid >> 6;
   const int wm = wv / MC::WN, wn = wv % MC::WN;
   const int l16 = lane & 15, kg = lane >> 4;
   float part[MC::FM];
   static_for<MC::FM>([&](auto i) {
     float sum = 0.f;
     static_for<FN>([&](auto j) {
-      const int n = wn * 16 * FN + 16 * j + 4 * kg;
+      const int n = MC::col(wn, j) + 4 * kg;
       const float4 xo = xo_in[i][j];
       f32x4_t& a = acc[i][j];
       a[0] += sbias[n] + xo.x;
@@ -620,30 +632,32 @@ __global__ void __launch_bounds__(MLP_THREADS) mlp_block_kernel(const int32_t* _
   // weight stages: stage s holds rows [0, stage_rows(s)) of 64 k columns; a W1' stage holds
   // KB1 blocks of HC rows, k block b of the stage at rows [b HC, (b+1) HC)
   auto stage_rows = [](int s) {
-    if (s < MC::NKC) return C;
-    const int tt = (s - MC::NKC) % MC::PER_CHUNK;
-    return tt < MC::NW1 ? HC * MC::KB1 : C;
+    if (s < MC::NKC * MC::NHALF) return MC::CS;
+    const int tt = (s - MC::NKC * MC::NHALF) % MC::PER_CHUNK;
+    return tt < MC::NW1 ? HC * MC::KB1 : MC::CS;
   };
   auto issue = [&](int s) {
     const bf16* base;
     int rows_s, ld, blk_rows;  // slot rows; source row stride; rows per k block in the slot
-    if (s < MC::NKC) {
-      base = Wo + 64 * s;
-      rows_s = C;
+    if (s < MC::NKC * MC::NHALF) {
+      const int kb = s / MC::NHALF, h = s - kb * MC::NHALF;
+      base = Wo + (size_t)h * MC::CS * C + 64 * kb;
+      rows_s = MC::CS;
       ld = C;
-      blk_rows = C;
+      blk_rows = MC::CS;
     } else {
-      const int q = s - MC::NKC, j = q / MC::PER_CHUNK, tt = q - j * MC::PER_CHUNK;
+      const int q = s - MC::NKC * MC::NHALF, j = q / MC::PER_CHUNK, tt = q - j * MC::PER_CHUNK;
       if (tt < MC::NW1) {
         base = W1 + (size_t)j * HC * C + 64 * MC::KB1 * tt;
         rows_s = HC * MC::KB1;
         ld = C;
         blk_rows = HC;
       } else {
-        base = W2 + j * HC + 64 * (tt - MC::NW1);
-        rows_s = C;
+        const int u = tt - MC::NW1, kb = u / MC::NHALF, h = u - kb * MC::NHALF;
+        base = W2 + (size_t)h * MC::CS * R + j * HC + 64 * kb;
+        rows_s = MC::CS;
         ld = R;
-        blk_rows = C;
+        blk_rows = MC::CS;
       }
     }
     bf16* dst = ring + (s % MC::ST) * MC::SLOT;
@@ -676,8 +690,8 @@ __global__ void __launch_bounds__(MLP_THREADS) mlp_block_kernel(const int32_t* _
   auto enter = [&](int s) {
     if (MC::ST == 2 || drained || s + 1 >= MC::NSTAGE)
       vm_wait_barrier<0>();
-    else if (stage_rows(s + 1) == C)
-      vm_wait_barrier<(MC::ST == 3 ? C / (8 * NW) : 0)>();
+    else if (stage_rows(s + 1) == MC::CS)
+      vm_wait_barrier<(MC::ST == 3 ? MC::CS / (8 * NW) : 0)>();
     else
       vm_wait_barrier<(MC::ST == 3 ? HC * MC::KB1 / (8 * NW) : 0)>();
     drained = false;
@@ -686,10 +700,11 @@ __global__ void __launch_bounds__(MLP_THREADS) mlp_block_kernel(const int32_t* _
   };
   int s = 0;
   float4 xo[MC::FM][MC::FN_C];
-  static_for<MC::NKC>([&](auto kb) {
+  static_for<MC::NKC * MC::NHALF>([&](auto sk) {
+    constexpr int kb = sk / MC::NHALF, h = sk % MC::NHALF;
     const bf16* ws = enter(s);
-    if (kb == MC::NKC - 1) load_resid<MC>(x, dst, xo);  // youngest loads: no stage waits for them
-    mfma_block<MC, MC::FN_C>(ares + kb * BM * 64, ws, acc);
+    if (sk == MC::NKC * MC::NHALF - 1) load_resid<MC>(x, dst, xo);  // youngest loads: no stage waits for them
+    mfma_block<MC, MC::FPH, h * MC::FPH, MC::FN_C>(ares + kb * BM * 64, ws, acc);
     ++s;
   });
   // x1 = x + o W_o^T + b_o; u2 = normalise(x1) into the resident tile (every wavefront has
@@ -703,7 +718,7 @@ __global__ void __launch_bounds__(MLP_THREADS) mlp_block_kernel(const int32_t* _
   static_for<MC::FM>([&](auto i) {
     const int r = wm * MC::TM + 16 * i + l16;
     static_for<MC::FN_C>([&](auto j) {
-      const int n = wn * 16 * MC::FN_C + 16 * j + 4 * kg;
+      const int n = MC::col(wn, j) + 4 * kg;
       const f32x4_t& a = acc[i][j];
       uint2 pk;
       pk.x = pack_bf2((a[0] - mean[i]) * rstd[i], (a[1] - mean[i]) * rstd[i]);
@@ -749,9 +764,10 @@ __global__ void __launch_bounds__(MLP_THREADS) mlp_block_kernel(const int32_t* _
         *reinterpret_cast<uint2*>(hres + res_off<MC::BM>(r, c)) = pk;
       });
     });
-    static_for<MC::NKH>([&](auto kb) {
+    static_for<MC::NKH * MC::NHALF>([&](auto sk) {
+      constexpr int kb = sk / MC::NHALF, h = sk % MC::NHALF;
       const bf16* ws = enter(s);
-      mfma_block<MC, MC::FN_C>(hres + kb * BM * 64, ws, acc);
+      mfma_block<MC, MC::FPH, h * MC::FPH, MC::FN_C>(hres + kb * BM * 64, ws, acc);
       ++s;
     });
   }
@@ -761,7 +777,7 @@ __global__ void __launch_bounds__(MLP_THREADS) mlp_block_kernel(const int32_t* _
   static_for<MC::FM>([&](auto i) {
     if (dst[i] >= 0)
       static_for<MC::FN_C>([&](auto j) {
-        const int n = wn * 16 * MC::FN_C + 16 * j + 4 * kg;
+        const int n = MC::col(wn, j) + 4 * kg;
         const f32x4_t& a = acc[i][j];
         uint2 pk;
         pk.x = pack_bf2((a[0] - mean[i]) * rstd[i], (a[1] - mean[i]) * rstd[i]);
@@ -794,8 +810,9 @@ void launch_mlp_block_bf16(int m_max, const int32_t* m_dev, int C, const bf16* o
     case 64: mlp_launch<MlpCfg<64, 128>>(m_max, m_dev, o, rows, wo, bo, w1, b1, w2, b2, x, xh, s); break;
     case 128: mlp_launch<MlpCfg<128, 128>>(m_max, m_dev, o, rows, wo, bo, w1, b1, w2, b2, x, xh, s); break;
     case 256: mlp_launch<MlpCfg<256, 128>>(m_max, m_dev, o, rows, wo, bo, w1, b1, w2, b2, x, xh, s); break;
-    // dim 384: 32-row tiles on a 2-stage ring (384-row weight slots) fit the LDS
-    case 384: mlp_launch<MlpCfg<384, 128, 32, 2>>(m_max, m_dev, o, rows, wo, bo, w1, b1, w2, b2, x, xh, s); break;
+    // dim 384: 64-row tiles with 192-row weight slots (W_o and W_2 k blocks in two halves) and
+    // 192-wide hidden chunks fit the LDS (155 KB)
+    case 384: mlp_launch<MlpCfg<384, 192, 64, 3, 192>>(m_max, m_dev, o, rows, wo, bo, w1, b1, w2, b2, x, xh, s); break;
     default: break;  // rejected by the caller (mlp_block_supported)
   }
 }
