@@ -31,7 +31,7 @@ COPY_BYTES = 64 * 1024 * 1024 * 4  # bench.py --calib-copy: 64 Mi float32 elemen
 # includes); a traffic figure stays valid while these files are unchanged.
 KERNEL_SOURCES = {
     "mlp_block_kernel": ["k_gemm.hip", "gemm_core.h", "dr_device.h", "dr_internal.h"],
-    "qkv_kernel": ["k_gemm.hip", "gemm_core.h", "dr_device.h", "dr_internal.h"],
+    "qkv_list_kernel": ["k_gemm.hip", "gemm_core.h", "dr_device.h", "dr_internal.h"],
     "attn_clip_kernel": ["k_bf16.hip", "dr_device.h", "dr_internal.h"],
 }
 
