@@ -456,14 +456,19 @@ extern "C" dr_status dr_inpaint(dr_ctx* c, const float* frames, const uint8_t* m
   hipStream_t s = (hipStream_t)stream;
   Work& w = c->work;
   const int C = n.C, R = n.R, N = g.N;
-  st = run_tokens(c, g, masks, qs == DR_QUERY_ALL, s);
-  if (st != DR_OK) return st;
-  if (ovl)
-    LAUNCH(ST_EMBED, launch_embed_ovl_bf16(g, C, frames, masks, w.flag, w.wcount, n.embed_ovl16, n.embed_b, w.x, w.xh, s));
-  else if (prec == DR_BF16)
-    LAUNCH(ST_EMBED, launch_embed_bf16(g, C, frames, masks, w.flag, w.wcount, n.embed_wT16, n.embed_b, w.x, w.xh, s));
-  else
-    LAUNCH(ST_EMBED, launch_embed(g, C, frames, masks, n.embed_wT, n.embed_b, w.x, s));
+  if (prec == DR_BF16 && !ovl) {
+    // token lists, window order and the embedding in one launch after the flags
+    LAUNCH(ST_TOKENS, launch_token_flags(g, masks, qs == DR_QUERY_ALL, w.flag, w.wcount, s, 0));
+    LAUNCH(ST_TOKENS, launch_tokens_embed_bf16(g, C, frames, masks, w.flag, w.wcount, w.wcount, n.embed_wT16, n.embed_b,
+                                               w.x, w.xh, w.idx, w.woff, w.nq, w.worder, w.tiles, w.ntiles, s));
+  } else {
+    st = run_tokens(c, g, masks, qs == DR_QUERY_ALL, s);
+    if (st != DR_OK) return st;
+    if (ovl)
+      LAUNCH(ST_EMBED, launch_embed_ovl_bf16(g, C, frames, masks, w.flag, w.wcount, n.embed_ovl16, n.embed_b, w.x, w.xh, s));
+    else
+      LAUNCH(ST_EMBED, launch_embed(g, C, frames, masks, n.embed_wT, n.embed_b, w.x, s));
+  }
   if (prec == DR_FP8) LAUNCH(ST_LN1, launch_zero_f32(w.amax, 4 * n.cfg.blocks, s));
   dr_status br = DR_OK;
   const bool graphable = c->use_graphs && !c->prof && c->debug_blocks < 0;

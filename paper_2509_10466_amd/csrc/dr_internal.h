@@ -279,6 +279,10 @@ void launch_gemm_fp8_resid(const bf16* A, const int32_t* m_dev, int m_max, int K
 
 // weight preparation
 // x (f32) of flagged tokens, x^ (bf16) of tokens in windows with queries (wcount null: all)
+void launch_tokens_embed_bf16(const Geo& g, int C, const float* frames, const uint8_t* masks, const uint8_t* flag,
+                              const int32_t* wcount, const int32_t* emb_wcount, const bf16* wT16, const float* b,
+                              float* x, bf16* xh, int32_t* idx, int32_t* woff, int32_t* nq, int32_t* order,
+                              int32_t* tiles, int32_t* ntiles, hipStream_t s);
 void launch_embed_bf16(const Geo& g, int C, const float* frames, const uint8_t* masks, const uint8_t* flag,
                        const int32_t* wcount, const bf16* wT16, const float* b, float* x, bf16* xh, hipStream_t s);
 void launch_decode_bf16(const Geo& g, int C, const bf16* xh, const int32_t* idx, const int32_t* nq,

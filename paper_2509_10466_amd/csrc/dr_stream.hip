@@ -182,9 +182,9 @@ static dr_status stream_step_locked(dr_ctx* c, Work& w, int n, const int32_t* si
   ring_elems(c, H, Wd, blk_elems, vblk_elems);
   LAUNCH(ST_COPY, launch_gather_frames(fp, npix, w.fst, w.mst, s));
   LAUNCH(ST_TOKENS, launch_token_flags(g, w.mst, qs == DR_QUERY_ALL, w.flag, w.wcount, s));
-  LAUNCH(ST_TOKENS, launch_token_gather(g, w.flag, w.wcount, w.idx, w.woff, w.nq, s));
-  LAUNCH(ST_TOKENS, launch_window_order(g, w.wcount, w.flag, w.worder, w.tiles, w.ntiles, s));
-  LAUNCH(ST_EMBED, launch_embed_bf16(g, C, w.fst, w.mst, w.flag, nullptr, net.embed_wT16, net.embed_b, w.x, w.xh, s));
+  // token lists, window order and the embedding of every token in one launch
+  LAUNCH(ST_TOKENS, launch_tokens_embed_bf16(g, C, w.fst, w.mst, w.flag, w.wcount, nullptr, net.embed_wT16, net.embed_b,
+                                             w.x, w.xh, w.idx, w.woff, w.nq, w.worder, w.tiles, w.ntiles, s));
   for (int l = 0; l < L; ++l) {
     const BlockW& b = net.blk[l];
     StreamTable tab{};

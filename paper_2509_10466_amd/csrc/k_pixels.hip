@@ -7,6 +7,8 @@
 // together they are well under 1 % of the path's arithmetic.
 #include "dr_device.h"
 #include "dr_internal.h"
+#include "gemm_core.h"
+#include "tokens_dev.h"
 
 namespace dr {
 
@@ -182,49 +184,53 @@ void launch_decode(const Geo& g, int C, const float* x, const int32_t* idx, cons
 // lane's MFMA operands come straight from its own loads.
 // Only what later steps read is stored: x^ of tokens in windows with queries (of every token
 // when wcount is null: stream mode keeps K/V of all tokens), x of flagged tokens.
-constexpr int EMB_WLD = 72;  // LDS row stride (bf16) of the staged embedding weight
-
+// The kernel is a chain of memory round trips, so every load a token needs (its window's query
+// count, its flag, the patch row and mask bytes) is issued at once at the start, and the
+// weight [C][64] is staged once per block by direct global->LDS loads in 128-byte rows with
+// 16-byte chunk c at c ^ (row & 7) (loads into VGPRs move a quarter of the bytes per cycle).
+// (the body for 64-token group blk; a block of 256 threads; emb_w holds C x 64 bf16 of LDS)
 template <int C>
-__global__ void __launch_bounds__(256) embed_bf16_kernel(Geo g, const float* __restrict__ frames,
-                                                         const uint8_t* __restrict__ masks,
-                                                         const uint8_t* __restrict__ flag,
-                                                         const int32_t* __restrict__ wcount,
-                                                         const bf16* __restrict__ wT16, const float* __restrict__ bias,
-                                                         float* __restrict__ x, bf16* __restrict__ xh) {
+__device__ __forceinline__ void embed_tokens(const Geo& g, int blk, const float* __restrict__ frames,
+                                             const uint8_t* __restrict__ masks, const uint8_t* __restrict__ flag,
+                                             const int32_t* __restrict__ wcount, const bf16* __restrict__ wT16,
+                                             const float* __restrict__ bias, float* __restrict__ x,
+                                             bf16* __restrict__ xh, bf16* emb_w) {
   constexpr int FN = C / 16;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int l16 = lane & 15, kg = lane >> 4;
-  const int n = (blockIdx.x * 4 + wv) * 16 + l16;
-  const bool need_h = n < g.N && (wcount == nullptr || wcount[n / g.S] > 0);
-  // the weight [C][64] staged once per block in LDS (rows padded to EMB_WLD) for the four
-  // wavefronts, instead of each reading it from L2
-  if (!__syncthreads_or(need_h)) return;  // uniform per block
-  extern __shared__ __align__(16) bf16 emb_w[];
-  for (int c = threadIdx.x; c < C * 8; c += blockDim.x) {
-    const int row = c >> 3, part = c & 7;
-    *reinterpret_cast<uint4*>(emb_w + row * EMB_WLD + part * 8) =
-        *reinterpret_cast<const uint4*>(wT16 + (size_t)row * 64 + part * 8);
-  }
-  __syncthreads();
-  if (!__any(need_h)) return;  // wave-uniform; no barrier follows
-  const bool need_x = need_h && flag[n] != 0;
+  const int n = (blk * 4 + wv) * 16 + l16;
+  const bool in = n < g.N;
   float v[12];
 #pragma unroll
   for (int e = 0; e < 12; ++e) v[e] = 0.f;
-  if (need_h) {
+  uint32_t m = 0;
+  int wc = 0, fl = 0;
+  if (in) {
+    wc = wcount == nullptr ? 1 : wcount[n / g.S];
+    fl = flag[n];
     int b, t, i, j;
     token_coords(g, n, b, t, i, j);
     const size_t px = (((size_t)b * g.T + t) * g.H + 4 * i + kg) * g.W + 4 * j;
     const float4* src = reinterpret_cast<const float4*>(frames + px * 3);
     const float4 f0 = src[0], f1 = src[1], f2 = src[2];
-    const uint32_t m = *reinterpret_cast<const uint32_t*>(masks + px);
+    m = *reinterpret_cast<const uint32_t*>(masks + px);
     v[0] = f0.x; v[1] = f0.y; v[2] = f0.z; v[3] = f0.w;
     v[4] = f1.x; v[5] = f1.y; v[6] = f1.z; v[7] = f1.w;
     v[8] = f2.x; v[9] = f2.y; v[10] = f2.z; v[11] = f2.w;
-#pragma unroll
-    for (int kx = 0; kx < 4; ++kx)
-      if ((m >> (8 * kx)) & 0xffu) v[3 * kx] = v[3 * kx + 1] = v[3 * kx + 2] = 0.f;
   }
+  const bool need_h = in && wc > 0;
+  if (!__syncthreads_or(need_h)) return;  // uniform per block
+  static_for<C / 32>([&](auto c) {  // C rows, 8 per load, over the four wavefronts
+    const int g8 = wv + 4 * c;
+    const int row = g8 * 8 + (lane >> 3);
+    dma16(wT16 + (size_t)row * 64 + ((lane & 7) ^ lds_swz(row)) * 8, emb_w + g8 * 512);
+  });
+  vm_wait_barrier<0>();
+  if (!__any(need_h)) return;  // wave-uniform; no barrier follows
+  const bool need_x = need_h && fl != 0;
+#pragma unroll
+  for (int kx = 0; kx < 4; ++kx)
+    if ((m >> (8 * kx)) & 0xffu) v[3 * kx] = v[3 * kx + 1] = v[3 * kx + 2] = 0.f;
   bf16x8_t p0, p1;
 #pragma unroll
   for (int e = 0; e < 8; ++e) p0[e] = (__bf16)v[e];
@@ -236,9 +242,9 @@ __global__ void __launch_bounds__(256) embed_bf16_kernel(Geo g, const float* __r
   float sum = 0.f;
 #pragma unroll
   for (int f = 0; f < FN; ++f) {
-    const bf16* wr = emb_w + (16 * f + l16) * EMB_WLD + 8 * kg;
-    const bf16x8_t w0 = *reinterpret_cast<const bf16x8_t*>(wr);
-    const bf16x8_t w1 = *reinterpret_cast<const bf16x8_t*>(wr + 32);
+    const int row = 16 * f + l16;
+    const bf16x8_t w0 = *reinterpret_cast<const bf16x8_t*>(emb_w + row * 64 + ((kg ^ lds_swz(row)) * 8));
+    const bf16x8_t w1 = *reinterpret_cast<const bf16x8_t*>(emb_w + row * 64 + (((4 + kg) ^ lds_swz(row)) * 8));
     f32x4_t a = {0.f, 0.f, 0.f, 0.f};
     __builtin_amdgcn_sched_barrier(0);
     a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, p0, a, 0, 0, 0);
@@ -278,11 +284,69 @@ __global__ void __launch_bounds__(256) embed_bf16_kernel(Geo g, const float* __r
   }
 }
 
+template <int C>
+__global__ void __launch_bounds__(256) embed_bf16_kernel(Geo g, const float* __restrict__ frames,
+                                                         const uint8_t* __restrict__ masks,
+                                                         const uint8_t* __restrict__ flag,
+                                                         const int32_t* __restrict__ wcount,
+                                                         const bf16* __restrict__ wT16, const float* __restrict__ bias,
+                                                         float* __restrict__ x, bf16* __restrict__ xh) {
+  extern __shared__ __align__(16) bf16 emb_w[];
+  embed_tokens<C>(g, blockIdx.x, frames, masks, flag, wcount, wT16, bias, x, xh, emb_w);
+}
+
+// One launch for the three steps of the BF16 path that need only the token flags and window
+// counts: block 0 orders the windows and lists the Q/K/V row tiles, blocks 1 .. nwin gather
+// each window's query tokens, the rest embed 64 tokens each.  They run side by side instead of
+// one after the other with a launch gap between.  emb_wcount: window counts for the
+// embedding's skip test (null: embed every token, as stream mode needs).
+template <int C>
+__global__ void __launch_bounds__(256) tokens_embed_bf16_kernel(
+    Geo g, const float* __restrict__ frames, const uint8_t* __restrict__ masks, const uint8_t* __restrict__ flag,
+    const int32_t* __restrict__ wcount, const int32_t* __restrict__ emb_wcount, const bf16* __restrict__ wT16,
+    const float* __restrict__ bias, float* __restrict__ x, bf16* __restrict__ xh, int32_t* __restrict__ idx,
+    int32_t* __restrict__ woff, int32_t* __restrict__ nq, int32_t* __restrict__ order, int32_t* __restrict__ tiles,
+    int32_t* __restrict__ ntiles) {
+  extern __shared__ __align__(16) int tok_lds[];
+  const int b = blockIdx.x;
+  if (b == 0) {
+    order_windows(g.nwin, g.S, g.N, wcount, flag, order, tiles, ntiles, tok_lds, tok_lds + (ORDER_MAX_S + 1),
+                  tok_lds + 2 * (ORDER_MAX_S + 1));
+  } else if (b <= g.nwin) {
+    gather_window(g, b - 1, flag, wcount, idx, woff, nq);
+  } else {
+    embed_tokens<C>(g, b - 1 - g.nwin, frames, masks, flag, emb_wcount, wT16, bias, x, xh,
+                    reinterpret_cast<bf16*>(tok_lds));
+  }
+}
+
+void launch_tokens_embed_bf16(const Geo& g, int C, const float* frames, const uint8_t* masks, const uint8_t* flag,
+                              const int32_t* wcount, const int32_t* emb_wcount, const bf16* wT16, const float* b,
+                              float* x, bf16* xh, int32_t* idx, int32_t* woff, int32_t* nq, int32_t* order,
+                              int32_t* tiles, int32_t* ntiles, hipStream_t s) {
+  const int grid = 1 + g.nwin + (g.N + 63) / 64;
+  const size_t order_lds = (2 * (size_t)(ORDER_MAX_S + 1) + 2) * 4;
+  const size_t lds = std::max((size_t)C * 64 * 2, order_lds);  // at most 48 KB
+#define DR_TOK_EMB(C_)                                                                                        \
+  case C_:                                                                                                    \
+    tokens_embed_bf16_kernel<C_><<<grid, 256, lds, s>>>(g, frames, masks, flag, wcount, emb_wcount, wT16, b, x, \
+                                                       xh, idx, woff, nq, order, tiles, ntiles);             \
+    break;
+  switch (C) {
+    DR_TOK_EMB(64)
+    DR_TOK_EMB(128)
+    DR_TOK_EMB(256)
+    DR_TOK_EMB(384)
+    default: break;  // rejected by the caller (resid_ln_supported)
+  }
+#undef DR_TOK_EMB
+}
+
 void launch_embed_bf16(const Geo& g, int C, const float* frames, const uint8_t* masks, const uint8_t* flag,
                        const int32_t* wcount, const bf16* wT16, const float* b, float* x, bf16* xh, hipStream_t s) {
   const int blocks = (g.N + 63) / 64;
   if (blocks == 0) return;
-  const size_t wlds = (size_t)C * EMB_WLD * 2;  // at most 55 KB (C = 384)
+  const size_t wlds = (size_t)C * 64 * 2;  // at most 48 KB (C = 384)
   switch (C) {
     case 64: embed_bf16_kernel<64><<<blocks, 256, wlds, s>>>(g, frames, masks, flag, wcount, wT16, b, x, xh); break;
     case 128: embed_bf16_kernel<128><<<blocks, 256, wlds, s>>>(g, frames, masks, flag, wcount, wT16, b, x, xh); break;
