@@ -507,9 +507,11 @@ extern "C" dr_status dr_inpaint(dr_ctx* c, const float* frames, const uint8_t* m
   if (ovl) {
     LAUNCH(ST_DECODE, launch_decode_ovl_bf16(g, C, w.xh, w.idx, w.nq, n.dec_ovl16, n.dec_ovl_bf, w.contrib, s));
     LAUNCH(ST_DECODE, launch_fold_ovl(g, w.contrib, n.dec_ovl_b, masks, out, s));
-  } else if (prec == DR_BF16)
-    LAUNCH(ST_DECODE, launch_decode_bf16(g, C, w.xh, w.idx, w.nq, n.dec_wf16, n.dec_bf, masks, out, s));
-  else
+  } else if (prec == DR_BF16) {  // decoder and unmasked copy in one launch
+    LAUNCH(ST_DECODE, launch_decode_copy_bf16(g, C, w.xh, w.idx, w.nq, n.dec_wf16, n.dec_bf, masks, frames, out,
+                                              npix, s));
+    return DR_OK;
+  } else
     LAUNCH(ST_DECODE, launch_decode(g, C, w.x, w.idx, w.nq, n.lnfg, n.lnfb, n.dec_w, n.dec_b, masks, out, s));
   if (out != frames) LAUNCH(ST_COPY, launch_copy_unmasked(npix, frames, masks, out, s));
   return DR_OK;

@@ -277,16 +277,19 @@ void launch_gemm_fp8_resid(const bf16* A, const int32_t* m_dev, int m_max, int K
                            const uint8_t* W, const float* s_w, const float* amax_a, const float* bias,
                            int Nout, float* x, const int32_t* res_rows, hipStream_t s);
 
-// weight preparation
-// x (f32) of flagged tokens, x^ (bf16) of tokens in windows with queries (wcount null: all)
+// BF16 path after the token flags, in one launch: the window order and Q/K/V row tiles, each
+// window's query list, and the embedding: x (f32) of flagged tokens, x^ (bf16) of tokens in
+// windows with queries (emb_wcount null: all)
 void launch_tokens_embed_bf16(const Geo& g, int C, const float* frames, const uint8_t* masks, const uint8_t* flag,
                               const int32_t* wcount, const int32_t* emb_wcount, const bf16* wT16, const float* b,
                               float* x, bf16* xh, int32_t* idx, int32_t* woff, int32_t* nq, int32_t* order,
                               int32_t* tiles, int32_t* ntiles, hipStream_t s);
-void launch_embed_bf16(const Geo& g, int C, const float* frames, const uint8_t* masks, const uint8_t* flag,
-                       const int32_t* wcount, const bf16* wT16, const float* b, float* x, bf16* xh, hipStream_t s);
-void launch_decode_bf16(const Geo& g, int C, const bf16* xh, const int32_t* idx, const int32_t* nq,
-                        const bf16* wd16, const float* bd, const uint8_t* masks, float* out, hipStream_t s);
+// decoder from x^ (Wd' [48][C] with the final LayerNorm's affine part folded in) writing the
+// masked pixels of the flagged tokens, and out = frames at every unmasked pixel of the npix
+// pixels (no copy when out == frames), in one launch
+void launch_decode_copy_bf16(const Geo& g, int C, const bf16* xh, const int32_t* idx, const int32_t* nq,
+                             const bf16* wd16, const float* bd, const uint8_t* masks, const float* frames,
+                             float* out, size_t npix, hipStream_t s);
 // overlapping variant (kernel 8, stride 4, padding 2): the embedding with wT16 [C][192] in
 // the slot order of embed_ovl_bf16_kernel; the decoder as per-token logit patches
 // contrib [N][192] of the flagged tokens (k = (ky*8 + kx)*3 + ch, wd16 [192][C] with the final

@@ -216,8 +216,8 @@ static dr_status stream_step_locked(dr_ctx* c, Work& w, int n, const int32_t* si
       LAUNCH(ST_FC2, launch_resid_ln_bf16(N, w.nq, C, R, w.h16, b.w216, b.b2, w.x, w.idx, w.xh, w.idx, s));
     }
   }
-  LAUNCH(ST_DECODE, launch_decode_bf16(g, C, w.xh, w.idx, w.nq, net.dec_wf16, net.dec_bf, w.mst, w.ost, s));
-  LAUNCH(ST_COPY, launch_copy_unmasked(npix * n, w.fst, w.mst, w.ost, s));
+  LAUNCH(ST_DECODE, launch_decode_copy_bf16(g, C, w.xh, w.idx, w.nq, net.dec_wf16, net.dec_bf, w.mst, w.fst, w.ost,
+                                            npix * n, s));
   LAUNCH(ST_COPY, launch_scatter_frames(fp, npix, w.ost, s));
   // the new frame now occupies the head slot
   for (int r = 0; r < n; ++r) {

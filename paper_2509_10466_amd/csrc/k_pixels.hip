@@ -284,17 +284,6 @@ __device__ __forceinline__ void embed_tokens(const Geo& g, int blk, const float*
   }
 }
 
-template <int C>
-__global__ void __launch_bounds__(256) embed_bf16_kernel(Geo g, const float* __restrict__ frames,
-                                                         const uint8_t* __restrict__ masks,
-                                                         const uint8_t* __restrict__ flag,
-                                                         const int32_t* __restrict__ wcount,
-                                                         const bf16* __restrict__ wT16, const float* __restrict__ bias,
-                                                         float* __restrict__ x, bf16* __restrict__ xh) {
-  extern __shared__ __align__(16) bf16 emb_w[];
-  embed_tokens<C>(g, blockIdx.x, frames, masks, flag, wcount, wT16, bias, x, xh, emb_w);
-}
-
 // One launch for the three steps of the BF16 path that need only the token flags and window
 // counts: block 0 orders the windows and lists the Q/K/V row tiles, blocks 1 .. nwin gather
 // each window's query tokens, the rest embed 64 tokens each.  They run side by side instead of
@@ -342,49 +331,49 @@ void launch_tokens_embed_bf16(const Geo& g, int C, const float* frames, const ui
 #undef DR_TOK_EMB
 }
 
-void launch_embed_bf16(const Geo& g, int C, const float* frames, const uint8_t* masks, const uint8_t* flag,
-                       const int32_t* wcount, const bf16* wT16, const float* b, float* x, bf16* xh, hipStream_t s) {
-  const int blocks = (g.N + 63) / 64;
-  if (blocks == 0) return;
-  const size_t wlds = (size_t)C * 64 * 2;  // at most 48 KB (C = 384)
-  switch (C) {
-    case 64: embed_bf16_kernel<64><<<blocks, 256, wlds, s>>>(g, frames, masks, flag, wcount, wT16, b, x, xh); break;
-    case 128: embed_bf16_kernel<128><<<blocks, 256, wlds, s>>>(g, frames, masks, flag, wcount, wT16, b, x, xh); break;
-    case 256: embed_bf16_kernel<256><<<blocks, 256, wlds, s>>>(g, frames, masks, flag, wcount, wT16, b, x, xh); break;
-    case 384: embed_bf16_kernel<384><<<blocks, 256, wlds, s>>>(g, frames, masks, flag, wcount, wT16, b, x, xh); break;
-    default: break;  // rejected by the caller (resid_ln_supported)
-  }
-}
-
 // Decoder on x^ with the final LayerNorm's affine part folded in: logits[k] = bd'[k] +
 // sum_c x^[c] Wd'[k][c] (Wd' [48][C] bf16, bd' [48] FP32), sigmoid, and the masked pixels of
 // each flagged token written.  Output fragment f of lane l holds k = 16 f + 4 (l / 16) + e of
-// token l % 16.
+// token l % 16.  Blocks blk of nblk, 256 threads; wl holds 48 x C bf16 of LDS.  The weight is
+// staged once per block by direct loads ([C/64][48][64], swizzled 128-byte rows) and every x^
+// fragment of a 16-token group is requested before its MFMAs: with the loads inside the
+// fenced k loop each slice waited for its own round trip.
 template <int C>
-__global__ void __launch_bounds__(256) decode_bf16_kernel(Geo g, const bf16* __restrict__ xh,
-                                                          const int32_t* __restrict__ idx,
-                                                          const int32_t* __restrict__ nq,
-                                                          const bf16* __restrict__ wd16, const float* __restrict__ bd,
-                                                          const uint8_t* __restrict__ masks, float* __restrict__ out) {
+__device__ __forceinline__ void decode_rows(const Geo& g, int blk, int nblk, const bf16* __restrict__ xh,
+                                            const int32_t* __restrict__ idx, const int32_t* __restrict__ nq,
+                                            const bf16* __restrict__ wd16, const float* __restrict__ bd,
+                                            const uint8_t* __restrict__ masks, float* __restrict__ out, bf16* wl) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int l16 = lane & 15, kg = lane >> 4;
   const int total = nq[0];
-  for (int r0 = (blockIdx.x * 4 + wv) * 16; r0 < total; r0 += gridDim.x * 64) {
+  if (blk * 64 >= total) return;  // no rows here: skip the weight
+  constexpr int NG = (C / 64) * 6;  // 8-row groups of the staged weight
+  for (int gi = wv; gi < NG; gi += 4) {  // uniform per wavefront
+    const int kb = gi / 6, g8 = gi - kb * 6;
+    const int row = g8 * 8 + (lane >> 3);
+    dma16(wd16 + (size_t)row * C + 64 * kb + ((lane & 7) ^ lds_swz(row)) * 8, wl + (kb * 48 + g8 * 8) * 64);
+  }
+  vm_wait_barrier<0>();
+  for (int r0 = (blk * 4 + wv) * 16; r0 < total; r0 += nblk * 64) {
     const int r = r0 + l16;
     const bool ok = r < total;
     const int n = ok ? idx[r] : 0;
+    bf16x8_t z[C / 32];
+#pragma unroll
+    for (int kk = 0; kk < C / 32; ++kk)
+      z[kk] = ok ? *reinterpret_cast<const bf16x8_t*>(xh + (size_t)n * C + kk * 32 + 8 * kg) : bf16x8_t{};
     f32x4_t acc[3] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
     for (int kk = 0; kk < C / 32; ++kk) {
-      const bf16x8_t z = ok ? *reinterpret_cast<const bf16x8_t*>(xh + (size_t)n * C + kk * 32 + 8 * kg)
-                            : bf16x8_t{};
       bf16x8_t w[3];
 #pragma unroll
-      for (int f = 0; f < 3; ++f)
-        w[f] = *reinterpret_cast<const bf16x8_t*>(wd16 + (size_t)(16 * f + l16) * C + kk * 32 + 8 * kg);
+      for (int f = 0; f < 3; ++f) {
+        const int row = 16 * f + l16;
+        w[f] = *reinterpret_cast<const bf16x8_t*>(wl + ((kk >> 1) * 48 + row) * 64 + ((((kk & 1) * 4 + kg) ^ lds_swz(row)) * 8));
+      }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int f = 0; f < 3; ++f) acc[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[f], z, acc[f], 0, 0, 0);
+      for (int f = 0; f < 3; ++f) acc[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[f], z[kk], acc[f], 0, 0, 0);
       __builtin_amdgcn_sched_barrier(0);
       asm volatile("s_nop 7" ::: "memory");
       __builtin_amdgcn_sched_barrier(0);
@@ -402,20 +391,6 @@ __global__ void __launch_bounds__(256) decode_bf16_kernel(Geo g, const bf16* __r
         const size_t px = (((size_t)b * g.T + t) * g.H + 4 * i + ky) * g.W + 4 * j + kx;
         if (masks[px]) out[px * 3 + ch] = 1.0f / (1.0f + expf(-(acc[f][e] + bd[k])));
       }
-  }
-}
-
-void launch_decode_bf16(const Geo& g, int C, const bf16* xh, const int32_t* idx, const int32_t* nq,
-                        const bf16* wd16, const float* bd, const uint8_t* masks, float* out, hipStream_t s) {
-  int grid = (g.N + 63) / 64;
-  if (grid > DEC_GRID) grid = DEC_GRID;
-  if (grid == 0) return;
-  switch (C) {
-    case 64: decode_bf16_kernel<64><<<grid, 256, 0, s>>>(g, xh, idx, nq, wd16, bd, masks, out); break;
-    case 128: decode_bf16_kernel<128><<<grid, 256, 0, s>>>(g, xh, idx, nq, wd16, bd, masks, out); break;
-    case 256: decode_bf16_kernel<256><<<grid, 256, 0, s>>>(g, xh, idx, nq, wd16, bd, masks, out); break;
-    case 384: decode_bf16_kernel<384><<<grid, 256, 0, s>>>(g, xh, idx, nq, wd16, bd, masks, out); break;
-    default: break;
   }
 }
 
@@ -672,10 +647,10 @@ void launch_fold_ovl(const Geo& g, const float* contrib, const float* db, const 
 // ------------------------------------------------------------------------------------------
 // out = frames wherever the mask is 0 (4 pixels per thread, vector loads and stores).
 // ------------------------------------------------------------------------------------------
-__global__ void copy_unmasked_kernel(size_t nquad, const float4* __restrict__ frames,
-                                     const uint32_t* __restrict__ masks, float4* __restrict__ out) {
-  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < nquad;
-       q += (size_t)gridDim.x * blockDim.x) {
+// (quads q0, q0 + stride, ...)
+__device__ __forceinline__ void copy_quads(size_t q0, size_t stride, size_t nquad, const float4* __restrict__ frames,
+                                           const uint32_t* __restrict__ masks, float4* __restrict__ out) {
+  for (size_t q = q0; q < nquad; q += stride) {
     const uint32_t m = masks[q];
     if (m == 0x01010101u) continue;
     const float4 a = frames[3 * q], b = frames[3 * q + 1], c = frames[3 * q + 2];
@@ -696,6 +671,56 @@ __global__ void copy_unmasked_kernel(size_t nquad, const float4* __restrict__ fr
       }
     }
   }
+}
+
+__global__ void copy_unmasked_kernel(size_t nquad, const float4* __restrict__ frames,
+                                     const uint32_t* __restrict__ masks, float4* __restrict__ out) {
+  copy_quads(blockIdx.x * (size_t)blockDim.x + threadIdx.x, (size_t)gridDim.x * blockDim.x, nquad, frames, masks,
+             out);
+}
+
+// The BF16 decoder (blocks below gd) and the copy of the unmasked pixels (the rest) in one
+// launch: they write disjoint pixels.
+template <int C>
+__global__ void __launch_bounds__(256) decode_copy_bf16_kernel(Geo g, const bf16* __restrict__ xh,
+                                                               const int32_t* __restrict__ idx,
+                                                               const int32_t* __restrict__ nq,
+                                                               const bf16* __restrict__ wd16,
+                                                               const float* __restrict__ bd,
+                                                               const uint8_t* __restrict__ masks,
+                                                               float* __restrict__ out, int gd, size_t nquad,
+                                                               const float4* __restrict__ frames) {
+  extern __shared__ __align__(16) bf16 dec_w[];
+  if ((int)blockIdx.x < gd)
+    decode_rows<C>(g, blockIdx.x, gd, xh, idx, nq, wd16, bd, masks, out, dec_w);
+  else
+    copy_quads((blockIdx.x - gd) * (size_t)blockDim.x + threadIdx.x, (size_t)(gridDim.x - gd) * blockDim.x, nquad,
+               frames, reinterpret_cast<const uint32_t*>(masks), reinterpret_cast<float4*>(out));
+}
+
+void launch_decode_copy_bf16(const Geo& g, int C, const bf16* xh, const int32_t* idx, const int32_t* nq,
+                             const bf16* wd16, const float* bd, const uint8_t* masks, const float* frames,
+                             float* out, size_t npix, hipStream_t s) {
+  int gd = (g.N + 63) / 64;
+  if (gd > DEC_GRID) gd = DEC_GRID;
+  const size_t nquad = out != frames ? npix / 4 : 0;  // in place: nothing to copy
+  size_t gc = (nquad + 255) / 256;
+  if (gc > 4096) gc = 4096;
+  const unsigned grid = (unsigned)(gd + gc);
+  if (grid == 0) return;
+  const float4* f4 = reinterpret_cast<const float4*>(frames);
+#define DR_DEC_COPY(C_)                                                                                        \
+  case C_:                                                                                                     \
+    decode_copy_bf16_kernel<C_><<<grid, 256, 48 * C_ * 2, s>>>(g, xh, idx, nq, wd16, bd, masks, out, gd, nquad, f4); \
+    break;
+  switch (C) {
+    DR_DEC_COPY(64)
+    DR_DEC_COPY(128)
+    DR_DEC_COPY(256)
+    DR_DEC_COPY(384)
+    default: break;
+  }
+#undef DR_DEC_COPY
 }
 
 void launch_copy_unmasked(size_t npix, const float* frames, const uint8_t* masks, float* out,
