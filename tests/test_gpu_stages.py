@@ -58,7 +58,9 @@ def test_residual_stream_per_block(dev, case, precision, tol):
         ref = _window_major(d["blocks"][l]["x2"], cfg)
         ref = np.where(flags[:, None], ref, ref0)  # unflagged tokens keep their embedding
         x = _x_after(eng, cfg, frames, masks, l + 1, precision)
-        assert np.array_equal(x[~flags], x0[~flags]), "unflagged tokens changed"
+        # bitwise: in the BF16 path these rows are never written, so they hold whatever the
+        # allocation held, NaN bit patterns included
+        assert np.array_equal(x[~flags].view(np.uint32), x0[~flags].view(np.uint32)), "unflagged tokens changed"
         scale = np.abs(ref[flags]).max()
         err = np.abs(x[flags] - ref[flags]).max()
         assert err <= tol * max(scale, 1.0), (l, err, scale)
