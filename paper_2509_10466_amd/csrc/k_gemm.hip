@@ -108,6 +108,11 @@ struct QkvOut {
     const float4 b4 = *reinterpret_cast<const float4*>(bias + n);
     qkv_store(r, n - r.part * C, C, dsh, Spad << dsh, spv, b4, a);
   }
+  // (the bias of channels n .. n + 3, and a store with it fetched beforehand)
+  __device__ __forceinline__ float4 bias4(int n) const { return *reinterpret_cast<const float4*>(bias + n); }
+  __device__ __forceinline__ void store_b(const QkvRow& r, int n, const float4& b4, const f32x4_t& a) const {
+    qkv_store(r, n - r.part * C, C, dsh, Spad << dsh, spv, b4, a);
+  }
 };
 
 // Stream mode: Q rows into the batch buffer; K [win_f][head][S_f][dh] and V^T
@@ -159,10 +164,12 @@ __global__ void __launch_bounds__(TL::THREADS) qkv_kernel(int M, int C, int S, c
   for_rows<TL>(M, m0, n0, acc, out);
 }
 
-// Clip mode: blocks run only the listed row tiles (computed with the window order): the first
-// xcd_grid(mt, C/BN) blocks take Q column tiles over the tiles with a flagged token, the rest
-// K/V column tiles over the tiles touching a window with queries.  Slots past a list's length
-// exit; they come last in dispatch order.
+// Clip mode: blocks run only the listed row tiles (computed with the window order).  Block b
+// takes, in dispatch order, the Q column tiles of the tiles holding a flagged token, then the
+// K/V column tiles of the tiles touching a window with queries (each part XCD-ordered as
+// xcd_tile), and the slots past both lists exit, last.  The epilogue's per-row destinations
+// and this lane's bias values are fetched before the product, so that their latency hides
+// behind it.
 template <class TL, class Out>
 __global__ void __launch_bounds__(TL::THREADS) qkv_list_kernel(int M, int C, const bf16* __restrict__ xh,
                                                        const int32_t* __restrict__ tiles,
@@ -171,16 +178,28 @@ __global__ void __launch_bounds__(TL::THREADS) qkv_list_kernel(int M, int C, con
   static_assert(TL::BM == ROW_TILE, "row tiles are listed in ROW_TILE units");
   extern __shared__ __align__(16) bf16 ring[];
   const int mt = (M + TL::BM - 1) / TL::BM;
-  const int ntq = C / TL::BN, gq = xcd_grid(mt, ntq);
+  const int ntq = C / TL::BN, gq = xcd_grid(ntiles[0], ntq);
   const bool is_q = (int)blockIdx.x < gq;
   const int b = is_q ? blockIdx.x : blockIdx.x - gq;
   int i, ct;
   xcd_tile(b, is_q ? ntq : 2 * ntq, i, ct);
   if (i >= ntiles[is_q ? 0 : 1]) return;
   const int m0 = tiles[(is_q ? 0 : mt) + i] * TL::BM, n0 = (is_q ? 0 : C) + ct * TL::BN;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wm = wv / TL::WN, wn = wv % TL::WN, l16 = lane & 15, kg = lane >> 4;
+  QkvRow rr[TL::FM];
+  static_for<TL::FM>([&](auto f) {
+    const int m = min(m0 + wm * TL::TM + 16 * f + l16, M - 1);
+    rr[f] = out.row(m, n0);
+  });
+  float4 b4[TL::FN];
+  static_for<TL::FN>([&](auto j) { b4[j] = out.bias4(n0 + wn * TL::TN + 16 * j + 4 * kg); });
   f32x4_t acc[TL::FM][TL::FN];
   gemm_core<TL>(xh, M, m0, W, n0, C, ring, acc);
-  for_rows<TL>(M, m0, n0, acc, out);
+  static_for<TL::FM>([&](auto f) {
+    if (m0 + wm * TL::TM + 16 * f + l16 < M)
+      static_for<TL::FN>([&](auto j) { out.store_b(rr[f], n0 + wn * TL::TN + 16 * j + 4 * kg, b4[j], acc[f][j]); });
+  });
 }
 
 template <class TL, class Out>
