@@ -135,7 +135,30 @@ struct StreamQkvOut {
     const float4 b4 = *reinterpret_cast<const float4*>(bias + n);
     qkv_store(r, n - r.part * C, C, dsh, Sf << dsh, tab.sfp, b4, a);
   }
+  __device__ __forceinline__ float4 bias4(int n) const { return *reinterpret_cast<const float4*>(bias + n); }
+  __device__ __forceinline__ void store_b(const QkvRow& r, int n, const float4& b4, const f32x4_t& a) const {
+    qkv_store(r, n - r.part * C, C, dsh, Sf << dsh, tab.sfp, b4, a);
+  }
 };
+
+// The Q/K/V epilogue with its per-row destinations and this lane's bias values fetched before
+// the product (their latency hides behind it): rows m0 .. of the tile at column n0.
+template <class TL, class Out>
+__device__ __forceinline__ void qkv_tile(int M, int m0, int n0, int C, const bf16* __restrict__ xh,
+                                         const bf16* __restrict__ W, bf16* ring, const Out& out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wm = wv / TL::WN, wn = wv % TL::WN, l16 = lane & 15, kg = lane >> 4;
+  QkvRow rr[TL::FM];
+  static_for<TL::FM>([&](auto f) { rr[f] = out.row(min(m0 + wm * TL::TM + 16 * f + l16, M - 1), n0); });
+  float4 b4[TL::FN];
+  static_for<TL::FN>([&](auto j) { b4[j] = out.bias4(n0 + wn * TL::TN + 16 * j + 4 * kg); });
+  f32x4_t acc[TL::FM][TL::FN];
+  gemm_core<TL>(xh, M, m0, W, n0, C, ring, acc);
+  static_for<TL::FM>([&](auto f) {
+    if (m0 + wm * TL::TM + 16 * f + l16 < M)
+      static_for<TL::FN>([&](auto j) { out.store_b(rr[f], n0 + wn * TL::TN + 16 * j + 4 * kg, b4[j], acc[f][j]); });
+  });
+}
 
 // Tile skipping: a Q column tile runs only for row tiles holding a flagged token; a K/V
 // column tile only for row tiles touching a window with queries (clip mode) -- keys and
@@ -159,17 +182,13 @@ __global__ void __launch_bounds__(TL::THREADS) qkv_kernel(int M, int C, int S, c
     need = is_q ? flag[m] != 0 : (wcount ? wcount[m / S] > 0 : 1);
   }
   if (!__syncthreads_or(need)) return;
-  f32x4_t acc[TL::FM][TL::FN];
-  gemm_core<TL>(xh, M, m0, W, n0, C, ring, acc);
-  for_rows<TL>(M, m0, n0, acc, out);
+  qkv_tile<TL>(M, m0, n0, C, xh, W, ring, out);
 }
 
 // Clip mode: blocks run only the listed row tiles (computed with the window order).  Block b
 // takes, in dispatch order, the Q column tiles of the tiles holding a flagged token, then the
 // K/V column tiles of the tiles touching a window with queries (each part XCD-ordered as
-// xcd_tile), and the slots past both lists exit, last.  The epilogue's per-row destinations
-// and this lane's bias values are fetched before the product, so that their latency hides
-// behind it.
+// xcd_tile), and the slots past both lists exit, last.
 template <class TL, class Out>
 __global__ void __launch_bounds__(TL::THREADS) qkv_list_kernel(int M, int C, const bf16* __restrict__ xh,
                                                        const int32_t* __restrict__ tiles,
@@ -185,21 +204,7 @@ __global__ void __launch_bounds__(TL::THREADS) qkv_list_kernel(int M, int C, con
   xcd_tile(b, is_q ? ntq : 2 * ntq, i, ct);
   if (i >= ntiles[is_q ? 0 : 1]) return;
   const int m0 = tiles[(is_q ? 0 : mt) + i] * TL::BM, n0 = (is_q ? 0 : C) + ct * TL::BN;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int wm = wv / TL::WN, wn = wv % TL::WN, l16 = lane & 15, kg = lane >> 4;
-  QkvRow rr[TL::FM];
-  static_for<TL::FM>([&](auto f) {
-    const int m = min(m0 + wm * TL::TM + 16 * f + l16, M - 1);
-    rr[f] = out.row(m, n0);
-  });
-  float4 b4[TL::FN];
-  static_for<TL::FN>([&](auto j) { b4[j] = out.bias4(n0 + wn * TL::TN + 16 * j + 4 * kg); });
-  f32x4_t acc[TL::FM][TL::FN];
-  gemm_core<TL>(xh, M, m0, W, n0, C, ring, acc);
-  static_for<TL::FM>([&](auto f) {
-    if (m0 + wm * TL::TM + 16 * f + l16 < M)
-      static_for<TL::FN>([&](auto j) { out.store_b(rr[f], n0 + wn * TL::TN + 16 * j + 4 * kg, b4[j], acc[f][j]); });
-  });
+  qkv_tile<TL>(M, m0, n0, C, xh, W, ring, out);
 }
 
 template <class TL, class Out>
