@@ -640,11 +640,25 @@ __global__ void __launch_bounds__(MLP_THREADS) mlp_block_kernel(const int32_t* _
   const int wm = wv / MC::WN, wn = wv % MC::WN;
   const int l16 = lane & 15, kg = lane >> 4;
 
-  for (int i = t; i < C; i += MLP_THREADS) {
-    sbo[i] = bo[i];
-    sb2[i] = b2[i];
-  }
-  for (int i = t; i < R; i += MLP_THREADS) sb1[i] = b1[i];
+  // the rows' token indices first: the residual loads below need them
+  int dst[MC::FM];
+  static_for<MC::FM>([&](auto i) {
+    const int m = m0 + wm * MC::TM + 16 * i + l16;
+    dst[i] = m < M ? rows[m] : -1;
+  });
+  // the biases into registers now, into LDS after the loads below are queued: one round trip
+  // for all of them instead of one per loop iteration
+  constexpr int NBC = (C + MLP_THREADS - 1) / MLP_THREADS, NBR = (R + MLP_THREADS - 1) / MLP_THREADS;
+  float vbo[NBC], vb2[NBC], vb1[NBR];
+  static_for<NBC>([&](auto k) {
+    const int i = t + MLP_THREADS * k;
+    vbo[k] = i < C ? bo[i] : 0.f;
+    vb2[k] = i < C ? b2[i] : 0.f;
+  });
+  static_for<NBR>([&](auto k) {
+    const int i = t + MLP_THREADS * k;
+    vb1[k] = i < R ? b1[i] : 0.f;
+  });
   // o rows -> resident A tile (rows >= M read row M-1; their results are never stored):
   // 8 rows per load, BM / 8 row groups per k block, one group per wavefront
   if (wv * 8 < BM)
@@ -695,11 +709,22 @@ __global__ void __launch_bounds__(MLP_THREADS) mlp_block_kernel(const int32_t* _
     });
   };
   static_for<MC::ST - 1>([&](auto s0) { issue(s0); });
-
-  int dst[MC::FM];
-  static_for<MC::FM>([&](auto i) {
-    const int m = m0 + wm * MC::TM + 16 * i + l16;
-    dst[i] = m < M ? rows[m] : -1;
+  // the residual rows x[dst] for the projection's epilogue, requested now (after the first
+  // stages) so that their latency hides behind the projection: the first two stage waits
+  // leave these NX loads outstanding, the third covers them
+  float4 xo[MC::FM][MC::FN_C];
+  load_resid<MC>(x, dst, xo);
+  constexpr int NX = MC::FM * MC::FN_C;
+  static_for<NBC>([&](auto k) {
+    const int i = t + MLP_THREADS * k;
+    if (i < C) {
+      sbo[i] = vbo[k];
+      sb2[i] = vb2[k];
+    }
+  });
+  static_for<NBR>([&](auto k) {
+    const int i = t + MLP_THREADS * k;
+    if (i < R) sb1[i] = vb1[k];
   });
   f32x4_t acc[MC::FM][MC::FN_C], hacc[MC::FM][MC::FN_H];
   static_for<MC::FM>([&](auto i) {
@@ -723,11 +748,24 @@ __global__ void __launch_bounds__(MLP_THREADS) mlp_block_kernel(const int32_t* _
     return ring + (s % MC::ST) * MC::SLOT;
   };
   int s = 0;
-  float4 xo[MC::FM][MC::FN_C];
+  static_assert(MC::ST == 3, "the counted waits below assume a 3-stage ring");
+  // stage s + 1's loads per wavefront (s = 0, 1): the counts of the first two waits
+  constexpr int L1 = stage_rows(1) / (8 * NW), L2 = stage_rows(2) / (8 * NW);
   static_for<MC::NKC * MC::NHALF>([&](auto sk) {
     constexpr int kb = sk / MC::NHALF, h = sk % MC::NHALF;
-    const bf16* ws = enter(s);
-    if (sk == MC::NKC * MC::NHALF - 1) load_resid<MC>(x, dst, xo);  // youngest loads: no stage waits for them
+    const bf16* ws;
+    if constexpr (sk == 0) {  // outstanding: stage 0, stage 1, x rows
+      vm_wait_barrier<L1 + NX>();
+      drained = false;
+      issue(s + MC::ST - 1);
+      ws = ring;
+    } else if constexpr (sk == 1) {  // outstanding: stage 1, x rows, stage 2
+      vm_wait_barrier<NX + L2>();
+      issue(s + MC::ST - 1);
+      ws = ring + MC::SLOT;
+    } else {
+      ws = enter(s);
+    }
     mfma_block<MC, MC::FPH, h * MC::FPH, MC::FN_C>(ares + kb * BM * 64, ws, acc);
     ++s;
   });
