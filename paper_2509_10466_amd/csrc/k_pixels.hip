@@ -299,7 +299,7 @@ __global__ void __launch_bounds__(256) tokens_embed_bf16_kernel(
   extern __shared__ __align__(16) int tok_lds[];
   const int b = blockIdx.x;
   if (b == 0) {
-    order_windows(g.nwin, g.S, g.N, wcount, flag, order, tiles, ntiles, tok_lds, tok_lds + (ORDER_MAX_S + 1),
+    order_windows<256>(g.nwin, g.S, g.N, wcount, flag, order, tiles, ntiles, tok_lds, tok_lds + (ORDER_MAX_S + 1),
                   tok_lds + 2 * (ORDER_MAX_S + 1));
   } else if (b <= g.nwin) {
     gather_window(g, b - 1, flag, wcount, idx, woff, nq);

@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(1024) window_order_kernel(int nwin, int S, int
   __shared__ int hist[ORDER_MAX_S + 1];
   __shared__ int start[ORDER_MAX_S + 1];
   __shared__ int nlist[2];
-  order_windows(nwin, S, N, wcount, flag, order, tiles, ntiles, hist, start, nlist);
+  order_windows<1024>(nwin, S, N, wcount, flag, order, tiles, ntiles, hist, start, nlist);
 }
 
 bool window_order_supported(int S) { return S <= ORDER_MAX_S; }

@@ -58,8 +58,9 @@ constexpr int ORDER_MAX_S = 2048;
 // (their K/V rows are read), so that the GEMM launches no block for the others.
 static_assert(ROW_TILE == 64, "the flag scan reads a tile as four 16-byte words");
 
-// (the body of the one-block kernel, any block size; hist and start hold S + 1 ints each in
-// LDS, nlist 2)
+// (the body of the one-block kernel, at most MAXT threads; hist and start hold S + 1 ints
+// each in LDS, nlist 2)
+template <int MAXT>
 __device__ __forceinline__ void order_windows(int nwin, int S, int N, const int32_t* __restrict__ wcount,
                                               const uint8_t* __restrict__ flag, int32_t* __restrict__ order,
                                               int32_t* __restrict__ tiles, int32_t* __restrict__ ntiles, int* hist,
@@ -85,11 +86,32 @@ __device__ __forceinline__ void order_windows(int nwin, int S, int N, const int3
   }
   for (int w = threadIdx.x; w < nwin; w += blockDim.x) atomicAdd(&hist[wcount[w]], 1);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int run = 0;
-    for (int c = S; c >= 0; --c) {
-      start[c] = run;
-      run += hist[c];
+  // start[c] = number of windows with more than c queries: an exclusive scan of the counts
+  // taken from c = S down.  Thread t sums a run of `per` consecutive positions of that order,
+  // the run totals are scanned in LDS (log2(blockDim) steps), then each thread writes its
+  // run's starts -- one serial pass over S + 1 counts had been the longest thread of the
+  // launch.
+  __shared__ int runsum[MAXT];
+  const int n = S + 1, per = (n + (int)blockDim.x - 1) / (int)blockDim.x;
+  int tot = 0;
+  for (int k = 0; k < per; ++k) {
+    const int p = (int)threadIdx.x * per + k;
+    if (p < n) tot += hist[S - p];
+  }
+  runsum[threadIdx.x] = tot;
+  __syncthreads();
+  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+    const int v = (int)threadIdx.x >= off ? runsum[threadIdx.x - off] : 0;
+    __syncthreads();
+    runsum[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int run = threadIdx.x ? runsum[threadIdx.x - 1] : 0;
+  for (int k = 0; k < per; ++k) {
+    const int p = (int)threadIdx.x * per + k;
+    if (p < n) {
+      start[S - p] = run;
+      run += hist[S - p];
     }
   }
   __syncthreads();
