@@ -278,6 +278,15 @@ __global__ void __launch_bounds__(TL::THREADS) gemm_fp8_kernel(const bf16* __res
   for (int i = 0; i < TL::FM; ++i)
 #pragma unroll
     for (int j = 0; j < TL::FN; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  // what the epilogue reads from memory (the residual rows), requested before the product so
+  // that its latency hides behind it
+  typename Epi::Pre pre[TL::FM][TL::FN];
+#pragma unroll
+  for (int i = 0; i < TL::FM; ++i) {
+    const int m = m0 + wm * TL::TM + i * 16 + l16;
+#pragma unroll
+    for (int j = 0; j < TL::FN; ++j) pre[i][j] = epi.pre(min(m, M - 1), n0 + wn * TL::TN + j * 16 + kg * 4);
+  }
   load(0);
   stash(0);
   __syncthreads();
@@ -314,7 +323,7 @@ __global__ void __launch_bounds__(TL::THREADS) gemm_fp8_kernel(const bf16* __res
     const int m = m0 + wm * TL::TM + i * 16 + l16;
     if (m >= M) continue;
 #pragma unroll
-    for (int j = 0; j < TL::FN; ++j) epi(m, n0 + wn * TL::TN + j * 16 + kg * 4, acc[i][j], sa);
+    for (int j = 0; j < TL::FN; ++j) epi(m, n0 + wn * TL::TN + j * 16 + kg * 4, acc[i][j], sa, pre[i][j]);
   }
   epi.finish();
 }
@@ -346,11 +355,15 @@ struct F8ResidEpi {
   int Nout;
   __device__ __forceinline__ int need(int, int) const { return 1; }
   __device__ __forceinline__ int list(int) const { return 0; }
-  __device__ __forceinline__ void operator()(int m, int n, const f32x4_t& a, float sa) const {
+  using Pre = float4;  // x[res_rows[m], n .. n + 3]
+  __device__ __forceinline__ Pre pre(int m, int n) const {
+    return *reinterpret_cast<const float4*>(x + (size_t)res_rows[m] * Nout + n);
+  }
+  __device__ __forceinline__ void operator()(int m, int n, const f32x4_t& a, float sa, const Pre& xin) const {
     const float sc = sa * *s_w;
     const float4 b4 = *reinterpret_cast<const float4*>(bias + n);
     float4* p = reinterpret_cast<float4*>(x + (size_t)res_rows[m] * Nout + n);
-    float4 xv = *p;
+    float4 xv = xin;
     xv.x += a[0] * sc + b4.x;
     xv.y += a[1] * sc + b4.y;
     xv.z += a[2] * sc + b4.z;
@@ -379,7 +392,9 @@ struct F8QkvEpi {
   int C, dh, heads, Spad, S, spv;
   __device__ __forceinline__ int need(int, int) const { return 1; }
   __device__ __forceinline__ int list(int n0) const { return n0 < C ? 0 : 1; }
-  __device__ __forceinline__ void operator()(int m, int n, const f32x4_t& a, float sa) const {
+  struct Pre {};
+  __device__ __forceinline__ Pre pre(int, int) const { return {}; }
+  __device__ __forceinline__ void operator()(int m, int n, const f32x4_t& a, float sa, const Pre&) const {
     const int part = n < C ? 0 : (n < 2 * C ? 1 : 2);
     const float sc = sa * wscale[part];
     const float4 b4 = *reinterpret_cast<const float4*>(bias + n);
@@ -426,7 +441,9 @@ struct F8GeluEpi {
   float mx;
   __device__ __forceinline__ int need(int, int) const { return 1; }
   __device__ __forceinline__ int list(int) const { return 0; }
-  __device__ __forceinline__ void operator()(int m, int n, const f32x4_t& a, float sa) {
+  struct Pre {};
+  __device__ __forceinline__ Pre pre(int, int) const { return {}; }
+  __device__ __forceinline__ void operator()(int m, int n, const f32x4_t& a, float sa, const Pre&) {
     const float sc = sa * *s_w;
     const float4 b4 = *reinterpret_cast<const float4*>(bias + n);
     const float y0 = gelu_fast(a[0] * sc + b4.x), y1 = gelu_fast(a[1] * sc + b4.y);
