@@ -392,12 +392,18 @@ struct F8QkvEpi {
   int C, dh, heads, Spad, S, spv;
   __device__ __forceinline__ int need(int, int) const { return 1; }
   __device__ __forceinline__ int list(int n0) const { return n0 < C ? 0 : 1; }
-  struct Pre {};
-  __device__ __forceinline__ Pre pre(int, int) const { return {}; }
-  __device__ __forceinline__ void operator()(int m, int n, const f32x4_t& a, float sa, const Pre&) const {
+  struct Pre {  // the bias of the fragment's channels and the token's window and slot
+    float4 b4;
+    int w, s;
+  };
+  __device__ __forceinline__ Pre pre(int m, int n) const {
+    const int w = m / S;
+    return {*reinterpret_cast<const float4*>(bias + n), w, m - w * S};
+  }
+  __device__ __forceinline__ void operator()(int m, int n, const f32x4_t& a, float sa, const Pre& pr) const {
     const int part = n < C ? 0 : (n < 2 * C ? 1 : 2);
     const float sc = sa * wscale[part];
-    const float4 b4 = *reinterpret_cast<const float4*>(bias + n);
+    const float4 b4 = pr.b4;
     const float y0 = a[0] * sc + b4.x, y1 = a[1] * sc + b4.y, y2 = a[2] * sc + b4.z, y3 = a[3] * sc + b4.w;
     if (part == 0) {
       uint2 pk;
@@ -407,7 +413,7 @@ struct F8QkvEpi {
       return;
     }
     const int c = n - part * C, hh = c / dh, d = c - hh * dh;
-    const int w = m / S, s = m - w * S;
+    const int w = pr.w, s = pr.s;
     if (part == 1) {
       uint2 pk;
       pk.x = pack_bf2(y0, y1);
