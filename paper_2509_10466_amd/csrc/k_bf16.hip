@@ -63,11 +63,11 @@ __host__ __device__ constexpr int attn_vt_stride(int spad) { return (spad / 8) %
 
 // Copies `bytes` (a multiple of 16) from global to LDS, 1 KB per wavefront load; the
 // K tile is swizzled on the way (dh/8 chunks per row), the V^T tile copied as is.
-template <int CH, bool SWZ>
+template <int CH, bool SWZ, int NTHR = ATT_THREADS>
 __device__ __forceinline__ void attn_dma(const bf16* __restrict__ src, bf16* dst, int bytes) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int chunks = bytes / 16;
-  for (int c0 = wv * 64; c0 < chunks; c0 += ATT_THREADS) {
+  for (int c0 = wv * 64; c0 < chunks; c0 += NTHR) {
     const int c = c0 + lane;
     if (c < chunks) {
       int sc = c;
@@ -339,9 +339,14 @@ __device__ __forceinline__ float attn_query_tiles(const bf16* Ks, const bf16* Vt
 // key masks of the decoupled patterns take a few more registers at 240 keys and dh = 64.
 template <int NT, int MODE>
 constexpr int attn_clip_waves_per_simd() { return NT <= 4 || (NT <= 15 && MODE == 0) ? 4 : 3; }
+// Threads of a clip attention block: 16 wavefronts where the kernel fits 4 per SIMD and a
+// window has more query tiles than 8 wavefronts take in one pass, so that a full window's
+// tiles (the longest blocks of the launch) run in one pass; otherwise 8.
+template <int NT, int MODE>
+constexpr int attn_clip_threads() { return attn_clip_waves_per_simd<NT, MODE>() == 4 && NT > 8 ? 1024 : ATT_THREADS; }
 
 template <int DH, int NT, int MODE>
-__global__ void __launch_bounds__(ATT_THREADS, (attn_clip_waves_per_simd<NT, MODE>())) attn_clip_kernel(Geo g, int C, int heads, const bf16* __restrict__ q,
+__global__ void __launch_bounds__((attn_clip_threads<NT, MODE>()), (attn_clip_waves_per_simd<NT, MODE>())) attn_clip_kernel(Geo g, int C, int heads, const bf16* __restrict__ q,
                                                                 const bf16* __restrict__ kmat,
                                                                 const bf16* __restrict__ vtmat,
                                                                 const int32_t* __restrict__ idx,
@@ -359,13 +364,13 @@ __global__ void __launch_bounds__(ATT_THREADS, (attn_clip_waves_per_simd<NT, MOD
   const int rank = wh_ / heads, h = wh_ - rank * heads;
   const int w = worder[rank];
   const int q0 = woff[w], nqw = woff[w + 1] - q0;
-  constexpr int QW = ATT_THREADS / 64;  // query tiles per pass of the block
+  constexpr int NTHR = attn_clip_threads<NT, MODE>(), QW = NTHR / 64;  // query tiles per pass
   if (QW * part * 16 >= nqw) return;    // uniform per block
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   bf16x8_t qnext[DH / 32];
   if ((QW * part + wv) * 16 < nqw) attn_load_q<DH>(q, idx, q0, nqw, C, h, QW * part + wv, qnext);
-  attn_dma<CH, true>(kmat + ((size_t)w * heads + h) * SP * DH, Ks, SP * DH * 2);
-  attn_dma<CH, false>(vtmat + ((size_t)w * heads + h) * DH * SPV, Vt, DH * SPV * 2);
+  attn_dma<CH, true, NTHR>(kmat + ((size_t)w * heads + h) * SP * DH, Ks, SP * DH * 2);
+  attn_dma<CH, false, NTHR>(vtmat + ((size_t)w * heads + h) * DH * SPV, Vt, DH * SPV * 2);
   asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
   const float wmx = attn_query_tiles<DH, NT, ClipKeys<NT, SPV>, MODE, QW * ATT_SPLIT>(
       Ks, Vt, ClipKeys<NT, SPV>{g.S}, C, h, q, idx, q0, nqw, o, qnext, amax_o != nullptr,
@@ -374,12 +379,12 @@ __global__ void __launch_bounds__(ATT_THREADS, (attn_clip_waves_per_simd<NT, MOD
     // max |O| of the block into the per-call slot that scales O for an FP8 projection: one
     // atomic per block, skipped when the slot already holds more (non-negative floats order
     // like their bits)
-    __shared__ float wred[ATT_THREADS / 64];
+    __shared__ float wred[NTHR / 64];
     if ((threadIdx.x & 63) == 0) wred[wv] = wmx;
     __syncthreads();
     if (threadIdx.x == 0) {
       float m = 0.f;
-      for (int i = 0; i < ATT_THREADS / 64; ++i) m = fmaxf(m, wred[i]);
+      for (int i = 0; i < NTHR / 64; ++i) m = fmaxf(m, wred[i]);
       if (m > 0.f && m > *reinterpret_cast<volatile float*>(amax_o))
         atomicMax(reinterpret_cast<unsigned int*>(amax_o), __float_as_uint(m));
     }
@@ -690,7 +695,7 @@ void launch_attn_clip(const Geo& g, int C, int heads, int Spad, const bf16* q, c
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
       attr = true;                                                                                      \
     }                                                                                                   \
-    attn_clip_kernel<DH_, NT_, MODE_><<<g.nwin * heads * ATT_SPLIT, ATT_THREADS, lds, s>>>(g, C, heads, q, k, vt, idx, woff, \
+    attn_clip_kernel<DH_, NT_, MODE_><<<g.nwin * heads * ATT_SPLIT, attn_clip_threads<NT_, MODE_>(), lds, s>>>(g, C, heads, q, k, vt, idx, woff, \
                                                                                worder, o, amax_o);      \
     return;                                                                                             \
   }
