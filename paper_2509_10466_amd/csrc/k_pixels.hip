@@ -188,7 +188,8 @@ void launch_decode(const Geo& g, int C, const float* x, const int32_t* idx, cons
 // count, its flag, the patch row and mask bytes) is issued at once at the start, and the
 // weight [C][64] is staged once per block by direct global->LDS loads in 128-byte rows with
 // 16-byte chunk c at c ^ (row & 7) (loads into VGPRs move a quarter of the bytes per cycle).
-// (the body for 64-token group blk; a block of 256 threads; emb_w holds C x 64 bf16 of LDS)
+// (the body for 64-token group blk; a block of 256 threads; emb_w holds C x 64 bf16 of LDS
+// and then the C bias floats)
 template <int C>
 __device__ __forceinline__ void embed_tokens(const Geo& g, int blk, const float* __restrict__ frames,
                                              const uint8_t* __restrict__ masks, const uint8_t* __restrict__ flag,
@@ -225,6 +226,10 @@ __device__ __forceinline__ void embed_tokens(const Geo& g, int blk, const float*
     const int row = g8 * 8 + (lane >> 3);
     dma16(wT16 + (size_t)row * 64 + ((lane & 7) ^ lds_swz(row)) * 8, emb_w + g8 * 512);
   });
+  // the bias (C floats, 256-byte aligned) after the weight, 64 16-byte chunks per wavefront
+  float* emb_b = reinterpret_cast<float*>(emb_w + C * 64);
+  if (wv * 64 < C / 4 && wv * 64 + lane < C / 4)
+    dma16(bias + 4 * (wv * 64 + lane), reinterpret_cast<bf16*>(emb_b + wv * 256));
   vm_wait_barrier<0>();
   if (!__any(need_h)) return;  // wave-uniform; no barrier follows
   const bool need_x = need_h && fl != 0;
@@ -238,25 +243,40 @@ __device__ __forceinline__ void embed_tokens(const Geo& g, int blk, const float*
   for (int e = 0; e < 4; ++e) p1[e] = (__bf16)v[8 + e];
 #pragma unroll
   for (int e = 4; e < 8; ++e) p1[e] = (__bf16)0.f;
+  // each fragment's weight slices and bias are read from LDS one fragment ahead of its fenced
+  // MFMA pair (inside the fences every fragment had waited for its own round trips in turn)
   f32x4_t acc[FN];
   float sum = 0.f;
-#pragma unroll
-  for (int f = 0; f < FN; ++f) {
+  auto wslice = [&](int f, bf16x8_t& w0, bf16x8_t& w1, float4& b4) {
     const int row = 16 * f + l16;
-    const bf16x8_t w0 = *reinterpret_cast<const bf16x8_t*>(emb_w + row * 64 + ((kg ^ lds_swz(row)) * 8));
-    const bf16x8_t w1 = *reinterpret_cast<const bf16x8_t*>(emb_w + row * 64 + (((4 + kg) ^ lds_swz(row)) * 8));
+    w0 = *reinterpret_cast<const bf16x8_t*>(emb_w + row * 64 + ((kg ^ lds_swz(row)) * 8));
+    w1 = *reinterpret_cast<const bf16x8_t*>(emb_w + row * 64 + (((4 + kg) ^ lds_swz(row)) * 8));
+    b4 = *reinterpret_cast<const float4*>(emb_b + 16 * f + 4 * kg);
+  };
+  bf16x8_t wa0, wa1, wb0, wb1;
+  float4 ba, bb;
+  wslice(0, wa0, wa1, ba);
+  static_for<FN>([&](auto f) {
+    bf16x8_t& c0 = (f & 1) ? wb0 : wa0;
+    bf16x8_t& c1 = (f & 1) ? wb1 : wa1;
+    const float4& b4 = (f & 1) ? bb : ba;
+    if constexpr (f + 1 < FN) {
+      if constexpr (f & 1)
+        wslice(f + 1, wa0, wa1, ba);
+      else
+        wslice(f + 1, wb0, wb1, bb);
+    }
     f32x4_t a = {0.f, 0.f, 0.f, 0.f};
     __builtin_amdgcn_sched_barrier(0);
-    a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, p0, a, 0, 0, 0);
-    a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, p1, a, 0, 0, 0);
+    a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c0, p0, a, 0, 0, 0);
+    a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c1, p1, a, 0, 0, 0);
     __builtin_amdgcn_sched_barrier(0);
     asm volatile("s_nop 7" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
-    const float4 b4 = *reinterpret_cast<const float4*>(bias + 16 * f + 4 * kg);
     a[0] += b4.x; a[1] += b4.y; a[2] += b4.z; a[3] += b4.w;
     acc[f] = a;
     sum += (a[0] + a[1]) + (a[2] + a[3]);
-  }
+  });
   sum += __shfl_xor(sum, 16, 64);
   sum += __shfl_xor(sum, 32, 64);
   const float mean = sum * (1.0f / C);
@@ -315,7 +335,7 @@ void launch_tokens_embed_bf16(const Geo& g, int C, const float* frames, const ui
                               int32_t* tiles, int32_t* ntiles, hipStream_t s) {
   const int grid = 1 + g.nwin + (g.N + 63) / 64;
   const size_t order_lds = (2 * (size_t)(ORDER_MAX_S + 1) + 2) * 4;
-  const size_t lds = std::max((size_t)C * 64 * 2, order_lds);  // at most 48 KB
+  const size_t lds = std::max((size_t)C * 64 * 2 + (size_t)C * 4, order_lds);  // weight + bias, at most 49.5 KB
 #define DR_TOK_EMB(C_)                                                                                        \
   case C_:                                                                                                    \
     tokens_embed_bf16_kernel<C_><<<grid, 256, lds, s>>>(g, frames, masks, flag, wcount, emb_wcount, wT16, b, x, \
