@@ -45,22 +45,6 @@ __device__ __forceinline__ void for_fragments(int M, int m0, int n0, f32x4_t (&a
 // MLP linear shapes: from ~50k rows they run 13-17 % faster, at 16k rows 10 % slower).
 constexpr int BIG_M = 32768;
 
-// Row-then-column epilogue: epi.row(m, n0) computes the destination of token m once (the
-// column tile's part of the output is uniform over the tile), epi.store(row, n, a) then adds
-// the fragment's channel offset.  Keeps per-token address arithmetic (divisions, table
-// selects) out of the per-fragment path.
-template <class TL, class Epi>
-__device__ __forceinline__ void for_rows(int M, int m0, int n0, f32x4_t (&acc)[TL::FM][TL::FN], const Epi& epi) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int wm = wv / TL::WN, wn = wv % TL::WN, l16 = lane & 15, kg = lane >> 4;
-  static_for<TL::FM>([&](auto i) {
-    const int m = m0 + wm * TL::TM + 16 * i + l16;
-    if (m < M) {
-      const auto row = epi.row(m, n0);
-      static_for<TL::FN>([&](auto j) { epi.store(row, n0 + wn * TL::TN + 16 * j + 4 * kg, acc[i][j]); });
-    }
-  });
-}
 
 // ------------------------------------------------------------------------------------------
 // Q/K/V
@@ -104,11 +88,7 @@ struct QkvOut {
     if (part == 1) return {k + (((size_t)w * heads * Spad + s) << dsh), 1};
     return {vt + (((size_t)w * heads) << dsh) * spv + s, 2};
   }
-  __device__ __forceinline__ void store(const QkvRow& r, int n, const f32x4_t& a) const {
-    const float4 b4 = *reinterpret_cast<const float4*>(bias + n);
-    qkv_store(r, n - r.part * C, C, dsh, Spad << dsh, spv, b4, a);
-  }
-  // (the bias of channels n .. n + 3, and a store with it fetched beforehand)
+  // the bias of channels n .. n + 3, and the store of a fragment of row r with it
   __device__ __forceinline__ float4 bias4(int n) const { return *reinterpret_cast<const float4*>(bias + n); }
   __device__ __forceinline__ void store_b(const QkvRow& r, int n, const float4& b4, const f32x4_t& a) const {
     qkv_store(r, n - r.part * C, C, dsh, Spad << dsh, spv, b4, a);
@@ -131,18 +111,18 @@ struct StreamQkvOut {
     if (part == 1) return {pick(tab.k, r) + slot * tab.slot_stride + (((size_t)wl * heads * Sf + s) << dsh), 1};
     return {pick(tab.v, r) + slot * tab.vslot_stride + (((size_t)wl * heads) << dsh) * tab.sfp + s, 2};
   }
-  __device__ __forceinline__ void store(const QkvRow& r, int n, const f32x4_t& a) const {
-    const float4 b4 = *reinterpret_cast<const float4*>(bias + n);
-    qkv_store(r, n - r.part * C, C, dsh, Sf << dsh, tab.sfp, b4, a);
-  }
   __device__ __forceinline__ float4 bias4(int n) const { return *reinterpret_cast<const float4*>(bias + n); }
   __device__ __forceinline__ void store_b(const QkvRow& r, int n, const float4& b4, const f32x4_t& a) const {
     qkv_store(r, n - r.part * C, C, dsh, Sf << dsh, tab.sfp, b4, a);
   }
 };
 
-// The Q/K/V epilogue with its per-row destinations and this lane's bias values fetched before
-// the product (their latency hides behind it): rows m0 .. of the tile at column n0.
+// One Q/K/V tile (rows m0 .., columns n0 ..).  Row-then-column epilogue: out.row(m, n0)
+// computes the destination of token m once (the column tile's part of the output is uniform
+// over the tile) and out.store_b(row, n, b4, a) adds the fragment's channel offset, which
+// keeps per-token address arithmetic (divisions, table selects) out of the per-fragment
+// path.  The row destinations and this lane's bias values are fetched before the product, so
+// that their latency hides behind it.
 template <class TL, class Out>
 __device__ __forceinline__ void qkv_tile(int M, int m0, int n0, int C, const bf16* __restrict__ xh,
                                          const bf16* __restrict__ W, bf16* ring, const Out& out) {
