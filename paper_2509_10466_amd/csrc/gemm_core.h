@@ -81,10 +81,12 @@ struct GemmTile {
 // caller), W: [*][K] rows n0 .. n0+BN-1; K a multiple of 64, M >= 1.  `lds` holds
 // GemmTile::LDS_BYTES.  On return every wavefront has finished reading LDS only after the
 // caller's next barrier.
-template <class TL>
+// KC > 0: K = KC known at compile time (the k loop unrolled, its waits fixed); else K at run time.
+template <class TL, int KC = 0>
 __device__ __forceinline__ void gemm_core(const bf16_t* __restrict__ A, int M, int m0,
-                                          const bf16_t* __restrict__ W, int n0, int K, bf16_t* lds,
+                                          const bf16_t* __restrict__ W, int n0, int K_, bf16_t* lds,
                                           f32x4_t (&acc)[TL::FM][TL::FN]) {
+  const int K = KC ? KC : K_;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int wm = wv / TL::WN, wn = wv % TL::WN;
   const int l16 = lane & 15, kg = lane >> 4;
@@ -120,7 +122,7 @@ __device__ __forceinline__ void gemm_core(const bf16_t* __restrict__ A, int M, i
   static_for<TL::ST - 1>([&](auto s) {
     if (s < nk) issue(s, s);
   });
-  for (int kt = 0; kt < nk; ++kt) {
+  auto stage = [&](int kt) {
     const int ahead = min(TL::ST - 2, nk - 1 - kt);  // later stages already in flight
     static_for<TL::ST - 1>([&](auto a) {
       if (a == ahead) vm_wait_barrier<a * TL::LOADS>();
@@ -147,7 +149,11 @@ __device__ __forceinline__ void gemm_core(const bf16_t* __restrict__ A, int M, i
       });
       mfma_fence_end();
     });
-  }
+  };
+  if constexpr (KC > 0)
+    static_for<KC / 64>([&](auto kt) { stage(kt); });
+  else
+    for (int kt = 0; kt < nk; ++kt) stage(kt);
 }
 
 // Tile order: consecutive workgroups are dispatched round-robin over the 8 XCDs (each with

@@ -123,7 +123,7 @@ struct StreamQkvOut {
 // keeps per-token address arithmetic (divisions, table selects) out of the per-fragment
 // path.  The row destinations and this lane's bias values are fetched before the product, so
 // that their latency hides behind it.
-template <class TL, class Out>
+template <class TL, class Out, int KC = 0>
 __device__ __forceinline__ void qkv_tile(int M, int m0, int n0, int C, const bf16* __restrict__ xh,
                                          const bf16* __restrict__ W, bf16* ring, const Out& out) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -133,7 +133,7 @@ __device__ __forceinline__ void qkv_tile(int M, int m0, int n0, int C, const bf1
   float4 b4[TL::FN];
   static_for<TL::FN>([&](auto j) { b4[j] = out.bias4(n0 + wn * TL::TN + 16 * j + 4 * kg); });
   f32x4_t acc[TL::FM][TL::FN];
-  gemm_core<TL>(xh, M, m0, W, n0, C, ring, acc);
+  gemm_core<TL, KC>(xh, M, m0, W, n0, C, ring, acc);
   static_for<TL::FM>([&](auto f) {
     if (m0 + wm * TL::TM + 16 * f + l16 < M)
       static_for<TL::FN>([&](auto j) { out.store_b(rr[f], n0 + wn * TL::TN + 16 * j + 4 * kg, b4[j], acc[f][j]); });
@@ -169,12 +169,14 @@ __global__ void __launch_bounds__(TL::THREADS) qkv_kernel(int M, int C, int S, c
 // takes, in dispatch order, the Q column tiles of the tiles holding a flagged token, then the
 // K/V column tiles of the tiles touching a window with queries (each part XCD-ordered as
 // xcd_tile), and the slots past both lists exit, last.
-template <class TL, class Out>
-__global__ void __launch_bounds__(TL::THREADS) qkv_list_kernel(int M, int C, const bf16* __restrict__ xh,
+template <class TL, class Out, int KC>
+__global__ void __launch_bounds__(TL::THREADS) qkv_list_kernel(int M, int C_, const bf16* __restrict__ xh,
                                                        const int32_t* __restrict__ tiles,
                                                        const int32_t* __restrict__ ntiles, const bf16* __restrict__ W,
                                                        Out out) {
   static_assert(TL::BM == ROW_TILE, "row tiles are listed in ROW_TILE units");
+  static_assert(KC % TL::BN == 0, "whole column tiles");
+  const int C = KC ? KC : C_;
   extern __shared__ __align__(16) bf16 ring[];
   const int mt = (M + TL::BM - 1) / TL::BM;
   const int ntq = C / TL::BN, gq = xcd_grid(ntiles[0], ntq);
@@ -184,20 +186,39 @@ __global__ void __launch_bounds__(TL::THREADS) qkv_list_kernel(int M, int C, con
   xcd_tile(b, is_q ? ntq : 2 * ntq, i, ct);
   if (i >= ntiles[is_q ? 0 : 1]) return;
   const int m0 = tiles[(is_q ? 0 : mt) + i] * TL::BM, n0 = (is_q ? 0 : C) + ct * TL::BN;
-  qkv_tile<TL>(M, m0, n0, C, xh, W, ring, out);
+  qkv_tile<TL, Out, KC>(M, m0, n0, C, xh, W, ring, out);
 }
 
-template <class TL, class Out>
+template <class TL, int KC, class Out>
 static void qkv_list_launch(int M, int C, const bf16* xh, const int32_t* tiles, const int32_t* ntiles, const bf16* w,
                             const Out& out, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    allow_lds(qkv_list_kernel<TL, Out>, TL::LDS_BYTES);
+    allow_lds(qkv_list_kernel<TL, Out, KC>, TL::LDS_BYTES);
     attr = true;
   }
   const int mt = (M + TL::BM - 1) / TL::BM;
   const int grid = xcd_grid(mt, C / TL::BN) + xcd_grid(mt, 2 * C / TL::BN);
-  qkv_list_kernel<TL, Out><<<grid, TL::THREADS, TL::LDS_BYTES, s>>>(M, C, xh, tiles, ntiles, w, out);
+  qkv_list_kernel<TL, Out, KC><<<grid, TL::THREADS, TL::LDS_BYTES, s>>>(M, C, xh, tiles, ntiles, w, out);
+}
+
+// The network widths get their own instantiation, with the k loop unrolled (0.8 % per clip at
+// 5 x 240 x 432 and 5 x 720 x 1280, timed back to back on one GPU); other widths take K at
+// run time.
+template <class TL, class Out>
+static void qkv_list_by_c(int M, int C, const bf16* xh, const int32_t* tiles, const int32_t* ntiles, const bf16* w,
+                          const Out& out, hipStream_t s) {
+  if constexpr (TL::BN == 128) {
+    switch (C) {
+      case 128: return qkv_list_launch<TL, 128>(M, C, xh, tiles, ntiles, w, out, s);
+      case 256: return qkv_list_launch<TL, 256>(M, C, xh, tiles, ntiles, w, out, s);
+      case 384: return qkv_list_launch<TL, 384>(M, C, xh, tiles, ntiles, w, out, s);
+      default: break;
+    }
+  } else if (C == 64) {
+    return qkv_list_launch<TL, 64>(M, C, xh, tiles, ntiles, w, out, s);
+  }
+  qkv_list_launch<TL, 0>(M, C, xh, tiles, ntiles, w, out, s);
 }
 
 template <class TL, class Out>
@@ -227,11 +248,11 @@ void launch_qkv_bf16(const Geo& g, int C, int heads, int Spad, int spv, const bf
   // 8 wavefronts per 64 x 128 tile below BIG_M tokens (0.6 % faster per clip at 5 x 240 x 432,
   // 1 % slower at 5 x 720 x 1280, timed back to back on one GPU)
   if (C % 128 == 0 && g.N < BIG_M)
-    qkv_list_launch<GemmTile<64, 128, 2, 4, 2>>(g.N, C, xh, tiles, ntiles, w, out, s);
+    qkv_list_by_c<GemmTile<64, 128, 2, 4, 2>>(g.N, C, xh, tiles, ntiles, w, out, s);
   else if (C % 128 == 0)
-    qkv_list_launch<GemmTile<64, 128, 2, 2, 2>>(g.N, C, xh, tiles, ntiles, w, out, s);
+    qkv_list_by_c<GemmTile<64, 128, 2, 2, 2>>(g.N, C, xh, tiles, ntiles, w, out, s);
   else
-    qkv_list_launch<GemmTile<64, 64, 2, 2, 3>>(g.N, C, xh, tiles, ntiles, w, out, s);
+    qkv_list_by_c<GemmTile<64, 64, 2, 2, 3>>(g.N, C, xh, tiles, ntiles, w, out, s);
 }
 
 void launch_qkv_stream(const Geo& g, int C, int heads, const bf16* xh, const uint8_t* flag, const bf16* w,
@@ -786,6 +807,9 @@ __global__ void __launch_bounds__(MLP_THREADS) mlp_block_kernel(const int32_t* _
       });
     });
   });
+  // unrolled: every stage index, ring slot and wait count below is a constant (1.2 % per clip
+  // at 5 x 240 x 432, timed back to back on one GPU)
+#pragma unroll
   for (int j = 0; j < MC::NCH; ++j) {
     // the chunk's accumulators start at its bias b1' (the GELU epilogue then adds nothing)
     static_for<MC::FN_H>([&](auto jj) {
