@@ -123,6 +123,36 @@ def test_forward_parity_full_size_sampled(dev, case, precision):
     _say(f"    worst sampled max abs err {worst:.3e}")
 
 
+# Widths and MLP ratios outside the four networks above: the FP32 path takes any multiple of
+# 64 and any MLP ratio, the FP8 path multiples of 128; the BF16 path takes dims 64, 128, 256
+# and 384 (with another MLP ratio than 4 it runs the projection, first linear and second
+# linear as three launches instead of the fused block) and refuses the others with DR_ESHAPE.
+OTHER_WIDTHS = {
+    "w128_r2": drsynth.NetCfg(dim=128, heads=4, blocks=2, mlp_ratio=2, patch=4, win_h=5, win_w=9, win_t=5),
+    "w192": drsynth.NetCfg(dim=192, heads=6, blocks=2, mlp_ratio=4, patch=4, win_h=5, win_w=9, win_t=5),
+    "w320_r2": drsynth.NetCfg(dim=320, heads=5, blocks=2, mlp_ratio=2, patch=4, win_h=5, win_w=9, win_t=5),
+    "w512": drsynth.NetCfg(dim=512, heads=8, blocks=2, mlp_ratio=4, patch=4, win_h=5, win_w=9, win_t=5),
+}
+
+
+@pytest.mark.parametrize("name", sorted(OTHER_WIDTHS))
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp8"])
+def test_forward_parity_other_widths(dev, name, precision):
+    from paper_2509_10466_amd._lib import DrError
+    cfg = OTHER_WIDTHS[name]
+    frames, masks, _ = drsynth.make_clip(3, 5, 40, 72, cov_range=(0.2, 0.4))
+    _say(f"[width] net={name} prec={precision} shape={frames.shape}")
+    eng, W = engine(cfg)
+    if (precision == "bf16" and cfg.dim not in (64, 128, 256, 384)) or (precision == "fp8" and cfg.dim % 128):
+        with pytest.raises(DrError, match="DR_ESHAPE"):
+            run(eng, frames, masks, precision)
+        return
+    out = run(eng, frames, masks, precision)
+    ref = on.forward(frames, masks, W, cfg)
+    mx, n = compare(out, ref, frames, masks, TOL[precision])
+    _say(f"    max abs err {mx:.3e} over {n} in-mask values")
+
+
 # ------------------------------------------------------------------------------------------
 # properties that hold at any size
 # ------------------------------------------------------------------------------------------
